@@ -1,0 +1,154 @@
+"""ctypes front end of the C oracle for the query-map renderer.
+
+TEST INFRASTRUCTURE ONLY (tests, smoke check, benchmark CPU-baseline leg).
+See raster_oracle.c for what is computed and which passages it follows.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+from . import build as _build
+
+_lib = None
+
+_f32p = np.ctypeslib.ndpointer(dtype=np.float32, flags="C_CONTIGUOUS")
+_f64p = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = C.CDLL(_build.ensure_built())
+        vp, i32, i64 = C.c_void_p, C.c_int, C.c_int64
+        _lib.orc_project.restype = i64
+        _lib.orc_project.argtypes = [i32, vp, vp, vp, vp, i32, vp] + [vp] * 8
+        _lib.orc_bin.restype = i64
+        _lib.orc_bin.argtypes = [i32, vp, vp, vp, vp, i32, vp, i32, i32, i64, vp, vp, vp, vp]
+        _lib.orc_num_tiles.restype = i64
+        _lib.orc_num_tiles.argtypes = [i32, vp, i32, i32]
+        _lib.orc_render_forward.restype = i32
+        _lib.orc_render_forward.argtypes = [i32, i32, vp, vp, vp, vp, vp, i32, vp, i32, i32] + [vp] * 7
+        _lib.orc_render_bruteforce.restype = i32
+        _lib.orc_render_bruteforce.argtypes = [i32, i32, vp, vp, vp, vp, vp, i32, vp, vp, vp, vp]
+        _lib.orc_render_backward.restype = i32
+        _lib.orc_render_backward.argtypes = [i32, i32, vp, vp, vp, vp, vp, i32, vp, i32, i32, vp] + [vp] * 6
+        _lib.orc_num_threads.restype = i32
+    return _lib
+
+
+def _c(a, dt=np.float32):
+    return np.ascontiguousarray(a, dtype=dt)
+
+
+@dataclass
+class Gaussians:
+    means: np.ndarray
+    log_scales: np.ndarray
+    quats: np.ndarray
+    opacity_logits: np.ndarray
+    queries: np.ndarray
+
+    @classmethod
+    def of(cls, scene) -> "Gaussians":
+        return cls(_c(scene.means), _c(scene.log_scales), _c(scene.quats),
+                   _c(scene.opacity_logits), _c(scene.queries))
+
+    @property
+    def n(self) -> int:
+        return self.means.shape[0]
+
+    @property
+    def d(self) -> int:
+        return self.queries.shape[1]
+
+    def geom_args(self):
+        return [_ptr(self.means), _ptr(self.log_scales), _ptr(self.quats), _ptr(self.opacity_logits)]
+
+
+def n_pixels(cams: np.ndarray) -> int:
+    return int((cams[:, 0].astype(np.int64) * cams[:, 1].astype(np.int64)).sum())
+
+
+def num_tiles(cams, tw=16, th=16) -> int:
+    cams = _c(cams)
+    return int(lib().orc_num_tiles(cams.shape[0], _ptr(cams), tw, th))
+
+
+def project(g: Gaussians, cams):
+    cams = _c(cams)
+    R = cams.shape[0] * g.n
+    out = dict(uv=np.zeros((R, 2)), conic=np.zeros((R, 3)), opacity=np.zeros(R),
+               radius=np.zeros(R), rect=np.zeros((R, 4), np.int32),
+               depth_key=np.zeros(R, np.uint32), vis=np.zeros(R, np.uint8), z=np.zeros(R))
+    nv = lib().orc_project(g.n, *g.geom_args(), cams.shape[0], _ptr(cams), _ptr(out["uv"]),
+                           _ptr(out["conic"]), _ptr(out["opacity"]), _ptr(out["radius"]),
+                           _ptr(out["rect"]), _ptr(out["depth_key"]), _ptr(out["vis"]),
+                           _ptr(out["z"]))
+    out["n_visible"] = int(nv)
+    return out
+
+
+def bin_sort(g: Gaussians, cams, tw=16, th=16):
+    """Tile instances sorted by (tile, depth key, record) and per-tile ranges."""
+    cams = _c(cams)
+    cnt = lib().orc_bin(g.n, *g.geom_args(), cams.shape[0], _ptr(cams), tw, th, 0,
+                        None, None, None, None)
+    tiles = np.zeros(max(cnt, 1), np.uint32)
+    depths = np.zeros(max(cnt, 1), np.uint32)
+    recs = np.zeros(max(cnt, 1), np.uint32)
+    ranges = np.zeros((num_tiles(cams, tw, th), 2), np.uint32)
+    lib().orc_bin(g.n, *g.geom_args(), cams.shape[0], _ptr(cams), tw, th, cnt, _ptr(tiles),
+                  _ptr(depths), _ptr(recs), _ptr(ranges))
+    return dict(count=int(cnt), tiles=tiles[:cnt], depths=depths[:cnt], recs=recs[:cnt],
+                ranges=ranges)
+
+
+def render_forward(g: Gaussians, cams, tw=16, th=16):
+    cams = _c(cams)
+    P = n_pixels(cams)
+    out = dict(Q=np.zeros((P, g.d)), T_final=np.zeros(P), n_contrib=np.zeros(P, np.int32),
+               n_blended=np.zeros(P, np.int32), n_pairs=np.zeros(P, np.int32),
+               margin=np.zeros(P), hash=np.zeros(P, np.uint64))
+    lib().orc_render_forward(g.n, g.d, *g.geom_args(), _ptr(g.queries), cams.shape[0],
+                             _ptr(cams), tw, th, _ptr(out["Q"]), _ptr(out["T_final"]),
+                             _ptr(out["n_contrib"]), _ptr(out["n_blended"]),
+                             _ptr(out["n_pairs"]), _ptr(out["margin"]), _ptr(out["hash"]))
+    return out
+
+
+def render_bruteforce(g: Gaussians, cams):
+    cams = _c(cams)
+    P = n_pixels(cams)
+    out = dict(Q=np.zeros((P, g.d)), T_final=np.zeros(P), n_blended=np.zeros(P, np.int32))
+    lib().orc_render_bruteforce(g.n, g.d, *g.geom_args(), _ptr(g.queries), cams.shape[0],
+                                _ptr(cams), _ptr(out["Q"]), _ptr(out["T_final"]),
+                                _ptr(out["n_blended"]))
+    return out
+
+
+def render_backward(g: Gaussians, cams, dQ, tw=16, th=16, with_rec: bool = False):
+    cams = _c(cams)
+    dQ = _c(dQ, np.float64)
+    n, d = g.n, g.d
+    out = dict(means=np.zeros((n, 3)), log_scales=np.zeros((n, 3)), quats=np.zeros((n, 4)),
+               opacity_logits=np.zeros(n), queries=np.zeros((n, d)))
+    rec = np.zeros((cams.shape[0] * n, 6)) if with_rec else None
+    lib().orc_render_backward(n, d, *g.geom_args(), _ptr(g.queries), cams.shape[0], _ptr(cams),
+                              tw, th, _ptr(dQ), _ptr(out["means"]), _ptr(out["log_scales"]),
+                              _ptr(out["quats"]), _ptr(out["opacity_logits"]),
+                              _ptr(out["queries"]), _ptr(rec))
+    if with_rec:
+        out["rec"] = rec
+    return out
+
+
+def num_threads() -> int:
+    return int(lib().orc_num_threads())
