@@ -1,0 +1,261 @@
+#!/usr/bin/env python3
+"""Throughput of the render + decode hot path (forward and backward).
+
+One step = render_forward (projection, binning, sort, compositing) + the
+decode/loss call (softmax(Q K^T / sqrt d) V, cosine loss with trust region,
+and its gradients) + render_backward, for one keyframe of the 640x480
+workload (100k Gaussians, d=16, M=256, D=512) with a BF16 decode.  Inputs
+are seeded synthetic arrays resident in HBM before timing starts.
+
+Prints one JSON line: feature-pixels/s, per-stage times, the roofline of the
+dominant kernel (timed with HIP events on its launch stream), the FP32 decode
+path for comparison, and the FP64 CPU oracle timed on the host.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAKS = {  # MI355X published peaks
+    "hbm_gbs": 8000.0,
+    "bf16_tflops": 2500.0,
+    "fp8_tflops": 5000.0,
+    "fp32_mfma_tflops": 157.3,
+    "fp32_vector_tflops": 157.3,
+}
+
+
+def _log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(os.path.join(ROOT, "paper_2602_12314_amd", "csrc"))):
+        with open(os.path.join(ROOT, "paper_2602_12314_amd", "csrc", name), "rb") as fh:
+            h.update(name.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_work(spec, pairs_eval: int, pairs_blend: int):
+    """Algorithmic flops / bytes per launch of each main kernel."""
+    n, d, M, D = spec.n_pixels, spec.d, spec.M, spec.D
+    return {
+        # MFMA: S = Q K^T (2Md), F = P V (2MD), dP = G V^T (2MD), dQ = dS K (2Md) per pixel
+        "decode_rows": dict(flops=n * 4.0 * M * (d + D), bound="mfma"),
+        # MFMA: dV = P^T G, 2MD per pixel
+        "decode_tn": dict(flops=n * 2.0 * M * D, bound="mfma"),
+        # VALU: per evaluated pair 20 flops (offset, conic form, exp, opacity, clamp,
+        # transmittance); per blended pair 2d more for the query accumulation
+        "raster_fwd": dict(flops=20.0 * pairs_eval + 2.0 * d * pairs_blend, bound="alu"),
+        # VALU: per blended pair 45 + 9d flops (alpha and transmittance rebuild,
+        # dq, dalpha, behind-sum update, conic/mean/opacity terms)
+        "raster_bwd": dict(flops=(45.0 + 9.0 * d) * pairs_blend, bound="alu"),
+    }
+
+
+def run(args):
+    import numpy as np
+    import torch
+
+    from paper_2602_12314_amd import _lib, ops, scenes
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    spec = scenes.spec(args.workload)
+    prec = args.precision or spec.precision
+    tw, th = (int(v) for v in args.tile.split("x"))
+    _log(f"[bench] generating workload {spec.name}")
+    s = scenes.make_scene(spec, seed=0)
+    g = ops.Gaussians.from_numpy(s, device=dev)
+    K = torch.as_tensor(s.K, device=dev)
+    V = torch.as_tensor(s.V, device=dev)
+    K0 = torch.as_tensor(s.K0, device=dev)
+    tgt = torch.as_tensor(s.target, device=dev)
+    n = spec.n_pixels
+    r = ops.Renderer(s.cams, spec.n_gauss, spec.d, tile=(tw, th))
+    Q = torch.empty((n, spec.d), device=dev)
+    T = torch.empty((n,), device=dev)
+    grads = g.zeros_like()
+
+    def make_step(dec):
+        def step():
+            r.forward(g, Q, T, check=False)
+            loss, dQ, dK, dV = dec.loss_and_grads(Q, K, V, tgt, K0, spec.lambda_tr)
+            r.backward(g, dQ, out=grads)
+            return loss
+        return step
+
+    def timed(dec, steps, warmup, profile):
+        step = make_step(dec)
+        r.forward(g, Q, T, check=True)  # sizes the pair capacity
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        need, over = r.counters()
+        assert not over, "pair capacity overflow after warm-up"
+        L = _lib.lib()
+        if profile:
+            L.lam_profile_enable(1)
+            for name in ("raster_fwd", "raster_bwd", "decode_rows", "decode_tn", "render_sort",
+                         "preprocess", "preprocess_bwd"):
+                _read_prof(L, name)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            loss = step()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        prof = {}
+        if profile:
+            for name in ("raster_fwd", "raster_bwd", "decode_rows", "decode_tn", "render_sort",
+                         "preprocess", "preprocess_bwd"):
+                tot, cnt = _read_prof(L, name)
+                if cnt:
+                    prof[name] = tot / cnt
+            L.lam_profile_enable(0)
+        return (t1 - t0) / steps, float(loss), prof, need
+
+    dec = ops.Decoder(prec, n, spec.d, spec.M, spec.D, device=dev)
+    _log(f"[bench] timing {args.steps} steps ({prec} decode)")
+    sec, loss, prof, pairs = timed(dec, args.steps, args.warmup, profile=True)
+    dec32 = ops.Decoder("fp32", n, spec.d, spec.M, spec.D, device=dev)
+    fp32_steps = max(3, args.steps // 4)
+    _log(f"[bench] timing {fp32_steps} steps (fp32 decode)")
+    sec32, loss32, prof32, _ = timed(dec32, fp32_steps, 2, profile=True)
+    del dec32
+
+    out = {
+        "metric": "feature-pixels/s fwd+bwd",
+        "value": n / sec,
+        "unit": "feature-pixels/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec * 1e3,
+        "ms_per_keyframe": sec * 1e3 / len(spec.cams),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": prec,
+        "data": "synthetic",
+        "config": {"workload": spec.name, "n_gaussians": spec.n_gauss,
+                   "image": f"{s.cams[0, 0]:.0f}x{s.cams[0, 1]:.0f}", "views": len(spec.cams),
+                   "pixels": n, "d": spec.d, "M": spec.M, "D": spec.D, "decode_precision": prec,
+                   "tile": args.tile, "tile_pairs": pairs},
+        "stage_ms": {k: round(v, 4) for k, v in prof.items()},
+        "loss": loss,
+        "fp32_decode_path": {"value": n / sec32, "ms_per_step": sec32 * 1e3,
+                             "stage_ms": {k: round(v, 4) for k, v in prof32.items()},
+                             "speedup_of_reduced_precision": sec32 / sec},
+    }
+
+    # roofline of the dominant kernel, with algorithmic work from the oracle's pair counts
+    cpu = None
+    pairs_eval = pairs_blend = None
+    if not args.no_cpu_baseline:
+        cpu, pairs_eval, pairs_blend = cpu_baseline(s, spec)
+    else:
+        pairs_eval, pairs_blend = oracle_pairs(s)
+    work = algorithmic_work(spec, pairs_eval, pairs_blend)
+    dom = max((k for k in prof if k in work), key=lambda k: prof[k])
+    ms = prof[dom]
+    w = work[dom]
+    achieved = w["flops"] / (ms * 1e-3) / 1e12
+    if w["bound"] == "mfma":
+        peak = PEAKS["bf16_tflops"] if prec in ("bf16",) else (
+            PEAKS["fp8_tflops"] if prec == "fp8" else PEAKS["fp32_mfma_tflops"])
+    else:
+        peak = PEAKS["fp32_vector_tflops"]
+    out["roofline"] = {"kernel": dom, "bound": w["bound"], "achieved": achieved, "peak": peak,
+                       "unit": "TFLOP/s", "frac": achieved / peak, "kernel_ms": ms,
+                       "traffic": traffic_for(dom, spec.name)}
+    out["cpu_baseline"] = cpu
+    print(json.dumps(out), flush=True)
+
+
+def _read_prof(L, name):
+    import ctypes as C
+    tot, cnt = C.c_double(), C.c_int()
+    L.lam_profile_read(name.encode(), C.byref(tot), C.byref(cnt))
+    return tot.value, cnt.value
+
+
+def traffic_for(kernel, workload):
+    """HBM bytes per launch from the committed rocprofv3 --pmc summary, if it
+    was taken on the current kernel sources; otherwise null."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        rec = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    ent = rec.get(workload, {}).get(kernel)
+    if not ent or ent.get("source_hash") != kernel_source_hash():
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def oracle_pairs(s):
+    from oracle import raster as R
+    f = R.render_forward(R.Gaussians.of(s), s.cams)
+    return int(f["n_pairs"].sum()), int(f["n_blended"].sum())
+
+
+def cpu_baseline(s, spec):
+    """The FP64 oracle (render forward, decode + loss + gradients, render
+    backward) on the full frame, timed on the host cores."""
+    import numpy as np
+
+    from oracle import decode_oracle as DO
+    from oracle import raster as R
+    _log("[bench] timing the FP64 CPU oracle on the full frame")
+    g = R.Gaussians.of(s)
+    t0 = time.perf_counter()
+    f = R.render_forward(g, s.cams)
+    t1 = time.perf_counter()
+    r = DO.loss_and_grads(f["Q"], s.K, s.V, s.target, s.K0, spec.lambda_tr)
+    t2 = time.perf_counter()
+    R.render_backward(g, s.cams, r["dQ"])
+    t3 = time.perf_counter()
+    threads = R.num_threads()
+    try:
+        from threadpoolctl import threadpool_info
+        blas = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    except Exception:
+        blas = 1
+    total = t3 - t0
+    n = spec.n_pixels
+    return ({"value": n / total, "unit": "feature-pixels/s", "cores": max(threads, blas),
+             "kind": "oracle",
+             "sample": f"one full {spec.name} step: render fwd {t1 - t0:.2f}s + decode/loss/grads "
+                       f"{t2 - t1:.2f}s + render bwd {t3 - t2:.2f}s (C/OpenMP {threads} threads, "
+                       f"numpy BLAS {blas} threads, FP64)"},
+            int(f["n_pairs"].sum()), int(f["n_blended"].sum()))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", type=int, default=1, help="0..4 (default: the 640x480 keyframe)")
+    ap.add_argument("--precision", default=None, help="decode precision: fp32 | bf16 (default: workload's)")
+    ap.add_argument("--tile", default="16x16")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
+              "(the multi-GPU design is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    run(args)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,206 @@
+/*
+ * latentam.h -- C ABI of the MI355X (gfx950) library for the hot path of
+ * LatentAM online map optimisation (arXiv 2602.12314):
+ *
+ *   render_forward   Q = R_f(G, T)                       Sec. III-B, Eq. 4 (blend of Eq. 2)
+ *   render_backward  dL/dQ -> dL/d(means, log-scales, quaternions, opacity logits, queries)
+ *   decode_loss      F = softmax(Q K^T / sqrt(d)) V, L = mean(1 - cos(F, T)) + lambda ||K - K0||^2,
+ *                    and dL/dQ, dL/dK, dL/dV                    Sec. III-B, Eq. 5 and Eq. 6
+ *   decode_forward   F alone (inference form of Eq. 5)
+ *   decode_backward  the adjoint of decode_forward for a given dL/dF
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Pointers named as "device" are HIP device pointers; "host" pointers are
+ *   read synchronously before the call returns.  Every device buffer belongs
+ *   to the caller.  The library performs no device allocation on these paths:
+ *   scratch and the state the backward pass needs live in a caller-owned
+ *   workspace whose size the *_workspace_size functions report.
+ * - All arrays are float32, C-contiguous (row-major).
+ * - ``stream`` is a hipStream_t (NULL = the null stream).  Calls only enqueue
+ *   work on it and return; there is no host synchronisation except in the
+ *   functions documented as blocking.  Nothing is allocated or freed, and no
+ *   memset node is recorded, so the non-blocking calls can be captured into a
+ *   HIP graph.
+ * - Errors are status codes; nothing is thrown across the ABI.  Invalid
+ *   arguments are rejected on the host before any work is enqueued.
+ *
+ * Gaussians (paper Eq. 1 and Eq. 3): position p (means[N,3]), orientation as
+ * a quaternion (quats[N,4], w x y z, any non-zero norm), scale through its
+ * logarithm (log_scales[N,3]), opacity through its logit (opacity_logits[N];
+ * opacity = sigmoid(logit)), and the compact query vector f_i
+ * (queries[N,d], d in {16, 32}).
+ *
+ * Cameras: host array of n_cams rows of LAM_CAM_FLOATS floats
+ *   [width, height, fx, fy, cx, cy, viewmat[16]]
+ * with viewmat the row-major 4x4 world->camera transform (x right, y down,
+ * z forward).  Pixels sit at integer coordinates.  Views are concatenated in
+ * camera order, each row-major, so pixel arrays have P = sum(width*height)
+ * rows.  1 <= n_cams <= LAM_MAX_CAMS, 1 <= width, height <= 8192.
+ *
+ * Rendering follows 3D Gaussian Splatting, which the paper cites for its
+ * depth-ordered alpha blending (Eq. 2): EWA projection with a 0.3 px^2
+ * dilation, near plane 0.2, 3-sigma square footprint, alpha = min(0.99,
+ * o exp(power)), pairs with alpha < 1/255 skipped, blending stops before the
+ * transmittance would drop below 1e-4.  Gaussians are ordered per pixel by the
+ * float32 camera-space depth of their centre, ties by index; a Gaussian is
+ * blended into exactly the pixels inside its footprint, so the result does not
+ * depend on the tile shape.
+ */
+#ifndef LATENTAM_H
+#define LATENTAM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LAM_CAM_FLOATS 22
+#define LAM_MAX_CAMS 16
+#define LAM_VERSION 1
+
+typedef enum {
+    LAM_OK = 0,
+    LAM_ERR_INVALID_ARG = -1, /* null pointer, negative size, workspace too small, ... */
+    LAM_ERR_UNSUPPORTED = -2, /* shape outside the supported set (listed per call) */
+    LAM_ERR_CAPACITY = -3,    /* reported by lam_render_counters when instances overflowed */
+    LAM_ERR_HIP = -4          /* a HIP runtime call failed (launch error, bad stream) */
+} lam_status;
+
+typedef enum {
+    LAM_FP32 = 0,     /* all products in float32 (MFMA f32) */
+    LAM_BF16 = 1,     /* products on bf16 operands, float32 accumulation and softmax */
+    LAM_FP8_E4M3 = 2  /* forward products on OCP E4M3 operands with per-row float32
+                         scales (K and V per atom, Q and P per pixel); backward products
+                         in bf16; float32 accumulation and softmax */
+} lam_precision;
+
+/* Human-readable name of a status code (static storage). */
+const char* lam_status_string(int status);
+
+/* Library ABI version (LAM_VERSION). */
+int lam_version(void);
+
+/* ------------------------------------------------------------------ render */
+
+/* Bytes of workspace for rendering n_gauss Gaussians with query dimension d
+ * into the given cameras with tile_w x tile_h tiles (tile_w * tile_h in
+ * {64, 128, 256}, both powers of two) and room for ``instance_capacity``
+ * (Gaussian, tile) pairs.  Host-only, never blocks.
+ * Errors: LAM_ERR_INVALID_ARG (null out, bad camera rows), LAM_ERR_UNSUPPORTED
+ * (tile shape, d, more than 2^31 Gaussian-camera records). */
+lam_status lam_render_workspace_size(int n_gauss, int d, const float* cams, int n_cams,
+                                     int tile_w, int tile_h, uint64_t instance_capacity,
+                                     uint64_t* bytes);
+
+/* Forward render of the query map (Eq. 4): projects every (camera, Gaussian)
+ * record, bins it to the tiles its footprint touches, sorts each tile's list
+ * by depth and blends front to back.
+ *   Q        device [P, d]  out: rendered queries
+ *   T_final  device [P]     out: transmittance left after blending
+ *   ws       device, ws_bytes >= lam_render_workspace_size(...); it keeps the
+ *            projected records, sorted tile lists and per-pixel state that
+ *            lam_render_backward reads, so it must stay untouched between the
+ *            two calls.
+ * If the (Gaussian, tile) pairs exceed instance_capacity, the overflow flag in
+ * the workspace is set and Q is incomplete: read it with lam_render_counters
+ * and call again with a larger workspace.
+ * Errors: LAM_ERR_INVALID_ARG, LAM_ERR_UNSUPPORTED, LAM_ERR_HIP. */
+lam_status lam_render_forward(const float* means, const float* log_scales, const float* quats,
+                              const float* opacity_logits, const float* queries, int n_gauss,
+                              int d, const float* cams, int n_cams, int tile_w, int tile_h,
+                              float* Q, float* T_final, void* ws, uint64_t ws_bytes,
+                              uint64_t instance_capacity, void* stream);
+
+/* Backward of lam_render_forward for the upstream gradient dQ (device [P, d]).
+ * Transmittance is rebuilt from T_final in reverse order.  Writes (overwrites)
+ * the gradients with respect to the raw parameters:
+ *   d_means [N,3], d_log_scales [N,3], d_quats [N,4], d_opacity_logits [N],
+ *   d_queries [N,d]   (all device).
+ * Gaussians culled in every camera get zero gradients.  Arguments other than
+ * dQ and the outputs must equal those of the forward call, with the same ws.
+ * Errors: LAM_ERR_INVALID_ARG, LAM_ERR_UNSUPPORTED, LAM_ERR_HIP. */
+lam_status lam_render_backward(const float* means, const float* log_scales, const float* quats,
+                               const float* opacity_logits, const float* queries, int n_gauss,
+                               int d, const float* cams, int n_cams, int tile_w, int tile_h,
+                               const float* dQ, float* d_means, float* d_log_scales,
+                               float* d_quats, float* d_opacity_logits, float* d_queries,
+                               void* ws, uint64_t ws_bytes, uint64_t instance_capacity,
+                               void* stream);
+
+/* BLOCKING: waits for ``stream`` and reads the counters of the last forward
+ * call on ``ws``: the number of (Gaussian, tile) pairs it needed and whether
+ * it exceeded the capacity (then returns LAM_ERR_CAPACITY). */
+lam_status lam_render_counters(const void* ws, void* stream, uint64_t* instances_needed,
+                               int* overflowed);
+
+/* Debug / verification view of the workspace of the last forward call: device
+ * pointers to its sorted tile keys and record ids ([count] uint32 each),
+ * per-tile [start, end) ranges ([tiles, 2] uint32), per-record depth keys
+ * ([n_cams*N] uint32, 0xFFFFFFFF when culled), per-record footprints
+ * ([n_cams*N, 2] uint32: x0 | x1 << 16, y0 | y1 << 16) and per-pixel
+ * contributor counts ([P] uint32).  Any output pointer may be NULL.
+ * Record r = camera * N + Gaussian.  Host-only, never blocks. */
+lam_status lam_render_debug_views(const void* ws, int n_gauss, int d, const float* cams,
+                                  int n_cams, int tile_w, int tile_h, uint64_t instance_capacity,
+                                  const uint32_t** tile_keys, const uint32_t** tile_recs,
+                                  const uint32_t** ranges, const uint32_t** depth_keys,
+                                  const uint32_t** footprints, const uint32_t** n_contrib);
+
+/* ------------------------------------------------------------------ decode */
+
+/* Bytes of decode workspace for n pixel rows, query dimension d, M atoms,
+ * feature dimension D.  Supported: d in {16, 32}; 1 <= M <= 2048; D a multiple
+ * of 64 with 64 <= D <= 2048; n >= 0.  Host-only.
+ * Errors: LAM_ERR_INVALID_ARG (null out), LAM_ERR_UNSUPPORTED (shape). */
+lam_status lam_decode_workspace_size(int precision, int n, int d, int M, int D, uint64_t* bytes);
+
+/* Decode and feature loss, forward and backward in one call (Eq. 5-6):
+ *   F   = softmax(Q K^T / sqrt(d)) V                    (softmax over the M atoms)
+ *   L   = (1/n) sum_p (1 - F_p.T_p / max(|F_p| |T_p|, 1e-8)) + lambda_tr ||K - K0||_F^2
+ * and writes, for dL = 1:
+ *   loss   device [1]      L
+ *   dQ     device [n, d]   dL/dQ         (nullable: skipped when the queries are fixed)
+ *   dK     device [M, d]   dL/dK (includes 2 lambda_tr (K - K0))
+ *   dV     device [M, D]   dL/dV
+ *   row_cos device [n]     per-pixel cosine (nullable)
+ * Q [n,d], K [M,d], V [M,D], target [n,D] and K0 [M,d] are device inputs
+ * (K0 may be NULL when lambda_tr == 0).  F itself is not stored.
+ * Errors: LAM_ERR_INVALID_ARG, LAM_ERR_UNSUPPORTED, LAM_ERR_HIP. */
+lam_status lam_decode_loss(int precision, const float* Q, int n, int d, const float* K,
+                           const float* V, int M, int D, const float* target, const float* K0,
+                           float lambda_tr, float* loss, float* dQ, float* dK, float* dV,
+                           float* row_cos, void* ws, uint64_t ws_bytes, void* stream);
+
+/* Inference decode (Eq. 5): F device [n, D] = softmax(Q K^T / sqrt(d)) V.
+ * Errors: LAM_ERR_INVALID_ARG, LAM_ERR_UNSUPPORTED, LAM_ERR_HIP. */
+lam_status lam_decode_forward(int precision, const float* Q, int n, int d, const float* K,
+                              const float* V, int M, int D, float* F, void* ws,
+                              uint64_t ws_bytes, void* stream);
+
+/* Adjoint of lam_decode_forward: given dF device [n, D] writes dQ [n, d]
+ * (nullable), dK [M, d], dV [M, D] (device, overwritten); the softmax is
+ * recomputed, not stored.  Errors as above. */
+lam_status lam_decode_backward(int precision, const float* Q, int n, int d, const float* K,
+                               const float* V, int M, int D, const float* dF, float* dQ,
+                               float* dK, float* dV, void* ws, uint64_t ws_bytes, void* stream);
+
+/* --------------------------------------------------------------- profiling */
+
+/* Turns per-kernel timing on or off (process-wide, off by default).  While on,
+ * the main kernels (names: "raster_fwd", "raster_bwd", "decode_rows",
+ * "decode_tn", "render_sort", "preprocess", "preprocess_bwd") are bracketed by
+ * HIP events recorded on their launch stream.  Not for use under graph capture. */
+lam_status lam_profile_enable(int on);
+
+/* BLOCKING: waits for the recorded events of kernel ``name``, returns the sum
+ * of their elapsed times (ms) and how many launches were recorded, and clears
+ * them.  Unknown names read as zero launches. */
+lam_status lam_profile_read(const char* name, double* total_ms, int* count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LATENTAM_H */

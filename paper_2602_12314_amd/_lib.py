@@ -1,0 +1,175 @@
+"""ctypes binding of ``liblatentam.so`` -- argument marshalling only.
+
+Every function here forwards to the C ABI of include/latentam.h with the same
+name minus the ``lam_`` prefix.  Tensors are passed as device pointers
+(``data_ptr()``); the stream is torch's current HIP stream unless given.
+There is no fallback: if the library is not built, loading raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblatentam.so")
+
+LAM_OK, LAM_ERR_INVALID_ARG, LAM_ERR_UNSUPPORTED, LAM_ERR_CAPACITY, LAM_ERR_HIP = 0, -1, -2, -3, -4
+LAM_FP32, LAM_BF16, LAM_FP8_E4M3 = 0, 1, 2
+PRECISIONS = {"fp32": LAM_FP32, "bf16": LAM_BF16, "fp8": LAM_FP8_E4M3}
+CAM_FLOATS = 22
+
+_lib = None
+
+
+class LamError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        super().__init__(f"{where}: {status_string(status)} ({status})")
+        self.status = status
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run `python -m paper_2602_12314_amd.build` "
+                               "(or __graft_entry__.build()); there is no fallback path")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, u64, f32 = C.c_void_p, C.c_int, C.c_uint64, C.c_float
+        pu64, pi32 = C.POINTER(C.c_uint64), C.POINTER(C.c_int)
+        sig = {
+            "lam_status_string": (C.c_char_p, [i32]),
+            "lam_version": (i32, []),
+            "lam_render_workspace_size": (i32, [i32, i32, vp, i32, i32, i32, u64, pu64]),
+            "lam_render_forward": (i32, [vp, vp, vp, vp, vp, i32, i32, vp, i32, i32, i32, vp, vp, vp,
+                                         u64, u64, vp]),
+            "lam_render_backward": (i32, [vp, vp, vp, vp, vp, i32, i32, vp, i32, i32, i32, vp, vp, vp,
+                                          vp, vp, vp, vp, u64, u64, vp]),
+            "lam_render_counters": (i32, [vp, vp, pu64, pi32]),
+            "lam_render_debug_views": (i32, [vp, i32, i32, vp, i32, i32, i32, u64] + [C.POINTER(vp)] * 6),
+            "lam_decode_workspace_size": (i32, [i32, i32, i32, i32, i32, pu64]),
+            "lam_decode_loss": (i32, [i32, vp, i32, i32, vp, vp, i32, i32, vp, vp, f32, vp, vp, vp, vp,
+                                      vp, vp, u64, vp]),
+            "lam_decode_forward": (i32, [i32, vp, i32, i32, vp, vp, i32, i32, vp, vp, u64, vp]),
+            "lam_decode_backward": (i32, [i32, vp, i32, i32, vp, vp, i32, i32, vp, vp, vp, vp, vp, u64,
+                                          vp]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def status_string(status: int) -> str:
+    return lib().lam_status_string(int(status)).decode()
+
+
+def check(status: int, where: str):
+    if status != LAM_OK:
+        raise LamError(status, where)
+
+
+def _p(t):
+    """Device pointer of a tensor (None -> NULL)."""
+    if t is None:
+        return None
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is not None:
+        return C.c_void_p(int(stream))
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _cams(cams) -> np.ndarray:
+    a = np.ascontiguousarray(np.asarray(cams, dtype=np.float32).reshape(-1, CAM_FLOATS))
+    return a
+
+
+# ------------------------------------------------------------------ render
+
+def render_workspace_size(n_gauss, d, cams, tile_w, tile_h, capacity) -> int:
+    cams = _cams(cams)
+    out = C.c_uint64()
+    check(lib().lam_render_workspace_size(n_gauss, d, cams.ctypes.data_as(C.c_void_p), cams.shape[0],
+                                          tile_w, tile_h, capacity, C.byref(out)),
+          "lam_render_workspace_size")
+    return int(out.value)
+
+
+def render_forward(g, cams, tile_w, tile_h, Q, T_final, ws, capacity, stream=None):
+    cams = _cams(cams)
+    check(lib().lam_render_forward(_p(g.means), _p(g.log_scales), _p(g.quats), _p(g.opacity_logits),
+                                   _p(g.queries), g.means.shape[0], g.queries.shape[1],
+                                   cams.ctypes.data_as(C.c_void_p), cams.shape[0], tile_w, tile_h,
+                                   _p(Q), _p(T_final), _p(ws), ws.numel() * ws.element_size(),
+                                   capacity, _stream(stream)), "lam_render_forward")
+
+
+def render_backward(g, cams, tile_w, tile_h, dQ, grads, ws, capacity, stream=None):
+    cams = _cams(cams)
+    check(lib().lam_render_backward(_p(g.means), _p(g.log_scales), _p(g.quats), _p(g.opacity_logits),
+                                    _p(g.queries), g.means.shape[0], g.queries.shape[1],
+                                    cams.ctypes.data_as(C.c_void_p), cams.shape[0], tile_w, tile_h,
+                                    _p(dQ), _p(grads.means), _p(grads.log_scales), _p(grads.quats),
+                                    _p(grads.opacity_logits), _p(grads.queries), _p(ws),
+                                    ws.numel() * ws.element_size(), capacity, _stream(stream)),
+          "lam_render_backward")
+
+
+def render_counters(ws, stream=None):
+    """BLOCKING: (pairs needed, overflowed) of the last forward on ``ws``."""
+    need, over = C.c_uint64(), C.c_int()
+    st = lib().lam_render_counters(_p(ws), _stream(stream), C.byref(need), C.byref(over))
+    if st not in (LAM_OK, LAM_ERR_CAPACITY):
+        check(st, "lam_render_counters")
+    return int(need.value), bool(over.value)
+
+
+def render_debug_views(ws, n_gauss, d, cams, tile_w, tile_h, capacity):
+    cams = _cams(cams)
+    ptrs = [C.c_void_p() for _ in range(6)]
+    check(lib().lam_render_debug_views(_p(ws), n_gauss, d, cams.ctypes.data_as(C.c_void_p),
+                                       cams.shape[0], tile_w, tile_h, capacity,
+                                       *[C.byref(p) for p in ptrs]), "lam_render_debug_views")
+    return [p.value for p in ptrs]
+
+
+# ------------------------------------------------------------------ decode
+
+def decode_workspace_size(precision, n, d, M, D) -> int:
+    out = C.c_uint64()
+    check(lib().lam_decode_workspace_size(PRECISIONS.get(precision, precision), n, d, M, D,
+                                          C.byref(out)), "lam_decode_workspace_size")
+    return int(out.value)
+
+
+def decode_loss(precision, Q, K, V, target, K0, lambda_tr, loss, dQ, dK, dV, row_cos, ws, stream=None):
+    n, d = Q.shape
+    M, D = V.shape
+    check(lib().lam_decode_loss(PRECISIONS.get(precision, precision), _p(Q), n, d, _p(K), _p(V), M, D,
+                                _p(target), _p(K0), float(lambda_tr), _p(loss), _p(dQ), _p(dK), _p(dV),
+                                _p(row_cos), _p(ws), ws.numel() * ws.element_size(), _stream(stream)),
+          "lam_decode_loss")
+
+
+def decode_forward(precision, Q, K, V, F, ws, stream=None):
+    n, d = Q.shape
+    M, D = V.shape
+    check(lib().lam_decode_forward(PRECISIONS.get(precision, precision), _p(Q), n, d, _p(K), _p(V), M, D,
+                                   _p(F), _p(ws), ws.numel() * ws.element_size(), _stream(stream)),
+          "lam_decode_forward")
+
+
+def decode_backward(precision, Q, K, V, dF, dQ, dK, dV, ws, stream=None):
+    n, d = Q.shape
+    M, D = V.shape
+    check(lib().lam_decode_backward(PRECISIONS.get(precision, precision), _p(Q), n, d, _p(K), _p(V), M,
+                                    D, _p(dF), _p(dQ), _p(dK), _p(dV), _p(ws),
+                                    ws.numel() * ws.element_size(), _stream(stream)),
+          "lam_decode_backward")

@@ -1,0 +1,877 @@
+// Dictionary decode (paper Eq. 5) and feature loss (Eq. 6) on gfx950 MFMA.
+//
+//   S = Q K^T / sqrt(d),  P = softmax_atoms(S),  F = P V
+//   L = mean_p (1 - cos(F_p, T_p)) + lambda ||K - K0||^2
+//
+// k_dec_rows handles 32 pixels per 256-thread workgroup (4 waves):
+//   S^T tiles (32 atoms x 32 pixels) come from MFMA with the pixel as the
+//   column, so the softmax statistics of a pixel stay inside one lane pair;
+//   pass 1 takes the row max, pass 2 writes the unnormalised weights
+//   P~ = exp(S - m) to LDS, F^T = V^T P~^T runs with each wave owning a quarter
+//   of the D rows, and the epilogue forms 1 - cos and the cosine gradient
+//   G = dL/dF / l (the softmax normaliser l folded in).  Then, per atom tile,
+//   dP = G V^T (G staged in LDS), dS = P~ (dP - delta) and dQ^T += K^T dS^T with
+//   dS^T fed from registers (K^T pre-permuted to match the MFMA lane layout).
+// The pixel reductions dV = P~^T G and dK = dS^T Q are split-K MFMA GEMMs
+// (k_dec_tn) over "pixel-blocked transposed" copies that k_dec_rows writes:
+// X^T_blk[block][row][32 pixels], so every MFMA fragment is one 16-byte load.
+// The softmax is recomputed in the backward part instead of being stored.
+#include "common.h"
+#include "kernels.h"
+
+namespace lam {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef int i32x8 __attribute__((ext_vector_type(8)));
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+
+constexpr float kFp8Max = 448.0f;  // largest finite OCP E4M3 value
+
+constexpr int kPx = 32;          // pixels per row block
+constexpr int kAtomAlign = 64;   // atom padding
+constexpr int kRowsThreads = 256;
+constexpr float kLog2e = 1.4426950408889634f;
+
+// ------------------------------------------------------------ precisions
+
+// A fragment holds 8 consecutive K-values of one MFMA row/column per lane:
+// lane l covers K-indices 8 (l / 32) + 0..7 of a 16-wide K chunk.
+struct TF32 {
+    using T = float;
+    using Frag = f32x8;
+    static constexpr int kBytes = 4;
+    __device__ static Frag load(const T* p)
+    {
+        const float4 a = reinterpret_cast<const float4*>(p)[0];
+        const float4 b = reinterpret_cast<const float4*>(p)[1];
+        Frag f = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+        return f;
+    }
+    __device__ static Frag from_f32(const float* v)
+    {
+        Frag f;
+#pragma unroll
+        for (int t = 0; t < 8; ++t) f[t] = v[t];
+        return f;
+    }
+    __device__ static T cvt(float x) { return x; }
+    __device__ static float to_f32(T x) { return x; }
+    // K = 16 as 8 steps of the 32x32x2 f32 MFMA (K-index 8h + s in step s)
+    __device__ static void mma(f32x16& c, const Frag& a, const Frag& b)
+    {
+#pragma unroll
+        for (int s = 0; s < 8; ++s) c = __builtin_amdgcn_mfma_f32_32x32x2f32(a[s], b[s], c, 0, 0, 0);
+    }
+    __device__ static void store4(T* p, float a, float b, float c, float d)
+    {
+        *reinterpret_cast<float4*>(p) = make_float4(a, b, c, d);
+    }
+};
+
+struct TBF16 {
+    using T = __bf16;
+    using Frag = bf16x8;
+    static constexpr int kBytes = 2;
+    __device__ static Frag load(const T* p) { return *reinterpret_cast<const bf16x8*>(p); }
+    __device__ static Frag from_f32(const float* v)
+    {
+        Frag f;
+#pragma unroll
+        for (int t = 0; t < 8; ++t) f[t] = (__bf16)v[t];
+        return f;
+    }
+    __device__ static T cvt(float x) { return (__bf16)x; }
+    __device__ static float to_f32(T x) { return (float)x; }
+    __device__ static void mma(f32x16& c, const Frag& a, const Frag& b)
+    {
+        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+    }
+    __device__ static void store4(T* p, float a, float b, float c, float d)
+    {
+        bf16x4 v = {(__bf16)a, (__bf16)b, (__bf16)c, (__bf16)d};
+        *reinterpret_cast<bf16x4*>(p) = v;
+    }
+};
+
+// Row of the 32x32 MFMA result held in register r of lane l (column = l % 32).
+__device__ inline int crow(int r, int h) { return 8 * (r >> 2) + 4 * h + (r & 3); }
+
+// Atom slot k (0..15) of a 16-atom chunk as fed from the result registers of
+// the previous MFMA: B fragment element t of lane half h is result register
+// 8c + t, i.e. atom 8 (t / 4) + 4 h + t % 4.
+__host__ __device__ inline int perm16(int k) { return 8 * ((k & 7) >> 2) + 4 * (k >> 3) + (k & 3); }
+
+// ------------------------------------------------------------ prep
+
+// Kb [Mp, d]   K in the compute type, rows >= M zero
+// Vb [Mp, D]   V in the compute type
+// Vt [D, Mp]   V transposed
+// Ktp [32, Mp] K transposed, rows >= d zero, atoms permuted by perm16 in each 16-chunk
+template <class P>
+__global__ __launch_bounds__(256) void k_dec_prep(const float* __restrict__ K, const float* __restrict__ V,
+                                                  int M, int Mp, int d, int D, typename P::T* Kb,
+                                                  typename P::T* Vb, typename P::T* Vt,
+                                                  typename P::T* Ktp)
+{
+    const size_t tid = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = tid; i < (size_t)Mp * D; i += stride) {
+        const int a = (int)(i / D), c = (int)(i % D);
+        const float v = a < M ? V[(size_t)a * D + c] : 0.0f;
+        Vb[i] = P::cvt(v);
+        Vt[(size_t)c * Mp + a] = P::cvt(v);
+    }
+    for (size_t i = tid; i < (size_t)Mp * d; i += stride) {
+        const int a = (int)(i / d);
+        Kb[i] = P::cvt(a < M ? K[i] : 0.0f);
+    }
+    for (size_t i = tid; i < (size_t)32 * Mp; i += stride) {
+        const int row = (int)(i / Mp), slot = (int)(i % Mp);
+        const int a = (slot & ~15) + perm16(slot & 15);
+        Ktp[i] = P::cvt((row < d && a < M) ? K[(size_t)a * d + row] : 0.0f);
+    }
+}
+
+// FP8 dictionary copies.  Per-atom scales s = amax(row) / 448 map each row of
+// K and V onto the E4M3 range; sc = [s^K (Mp) | s^V (Mp) | max_j s^V_j bits].
+__global__ __launch_bounds__(256) void k_dec_scales(const float* __restrict__ K, const float* __restrict__ V,
+                                                    int M, int Mp, int d, int D, float* __restrict__ sc)
+{
+    __shared__ float sk[256], sv[256];
+    const int row = blockIdx.x;
+    float ak = 0.f, av = 0.f;
+    if (row < M) {
+        for (int j = threadIdx.x; j < d; j += 256) ak = fmaxf(ak, fabsf(K[(size_t)row * d + j]));
+        for (int j = threadIdx.x; j < D; j += 256) av = fmaxf(av, fabsf(V[(size_t)row * D + j]));
+    }
+    sk[threadIdx.x] = ak;
+    sv[threadIdx.x] = av;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            sk[threadIdx.x] = fmaxf(sk[threadIdx.x], sk[threadIdx.x + o]);
+            sv[threadIdx.x] = fmaxf(sv[threadIdx.x], sv[threadIdx.x + o]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const float k = sk[0] > 0.f ? sk[0] / kFp8Max : 1.0f;
+        const float v = sv[0] > 0.f ? sv[0] / kFp8Max : 0.0f;
+        sc[row] = k;
+        sc[Mp + row] = v;
+        atomicMax(reinterpret_cast<unsigned*>(sc + 2 * Mp), __float_as_uint(v));
+    }
+}
+
+__device__ inline uint8_t to_e4m3(float x)
+{
+    return (uint8_t)(__builtin_amdgcn_cvt_pk_fp8_f32(x, 0.0f, 0, false) & 0xFF);
+}
+
+__device__ inline float from_e4m3(uint8_t q) { return __builtin_amdgcn_cvt_f32_fp8((int)q, 0); }
+
+// Kb, Ktp and Vb as bf16 of the FP8-rounded K and V (the backward works on the
+// same dictionary values the forward used); Vt8 = E4M3(V / s^V) transposed;
+// sv_fold = s^V * 448 / max s^V and unscale = max s^V / 448.
+__global__ __launch_bounds__(256) void k_dec_prep_fp8(const float* __restrict__ K, const float* __restrict__ V,
+                                                      int M, int Mp, int d, int D, const float* __restrict__ sc,
+                                                      __bf16* Kb, __bf16* Vb, uint8_t* Vt8, __bf16* Ktp,
+                                                      float* sv_fold, float* unscale)
+{
+    const size_t tid = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    const float vmax = __uint_as_float(reinterpret_cast<const unsigned*>(sc)[2 * Mp]);
+    for (size_t i = tid; i < (size_t)Mp * D; i += stride) {
+        const int a = (int)(i / D), c = (int)(i % D);
+        const float s = sc[Mp + a];
+        uint8_t q = 0;
+        if (a < M && s > 0.f) q = to_e4m3(V[(size_t)a * D + c] / s);
+        Vt8[(size_t)c * Mp + a] = q;
+        Vb[i] = (__bf16)(from_e4m3(q) * s);
+    }
+    for (size_t i = tid; i < (size_t)Mp * d; i += stride) {
+        const int a = (int)(i / d);
+        const float s = sc[a];
+        Kb[i] = (__bf16)(a < M ? from_e4m3(to_e4m3(K[i] / s)) * s : 0.0f);
+    }
+    for (size_t i = tid; i < (size_t)32 * Mp; i += stride) {
+        const int row = (int)(i / Mp), slot = (int)(i % Mp);
+        const int a = (slot & ~15) + perm16(slot & 15);
+        float v = 0.0f;
+        if (row < d && a < M) v = from_e4m3(to_e4m3(K[(size_t)a * d + row] / sc[a])) * sc[a];
+        Ktp[i] = (__bf16)v;
+    }
+    for (size_t i = tid; i < (size_t)Mp; i += stride)
+        sv_fold[i] = vmax > 0.f ? sc[Mp + i] * (kFp8Max / vmax) : 0.0f;
+    if (tid == 0) unscale[0] = vmax / kFp8Max;
+}
+
+// ------------------------------------------------------------ rows kernel
+
+enum { MODE_INFER = 0, MODE_LOSS = 1, MODE_ADJ = 2 };
+
+struct RowsArgs {
+    int n, d, M, Mp, D;
+    float scale_log2;   // log2(e) / sqrt(d)
+    float inv_sqrt_d;
+    float inv_n;
+    const float* Q;
+    const float* target;  // MODE_LOSS
+    const float* dF;      // MODE_ADJ
+    float* F;             // MODE_INFER
+    float* dQ;            // nullable
+    float* row_cos;       // nullable
+    float* loss_part;     // [blocks]
+    const void* Kb;
+    const void* Vb;
+    const void* Vt;
+    const void* Ktp;
+    const uint8_t* Vt8;     // FP8 forward: V^T / s^V as E4M3 [D, Mp]
+    const float* sv_fold;   // FP8 forward: s^V_j * 448 / max_j s^V_j   [Mp]
+    const float* fp8_unscale;  // FP8 forward: max_j s^V_j / 448         [1]
+    void* Pt;   // [blocks, Mp, 32]  P~^T
+    void* Gt;   // [blocks, D, 32]   G^T
+    void* St;   // [blocks, Mp, 32]  dS^T
+    void* Qt;   // [blocks, 32, 32]  Q^T (rows >= d zero)
+};
+
+template <class P, int NT, int DQ, int MODE, bool F8>
+__global__ __launch_bounds__(kRowsThreads) void k_dec_rows(RowsArgs a)
+{
+    using T = typename P::T;
+    using Frag = typename P::Frag;
+    extern __shared__ __align__(16) char smem[];
+    // LDS: red [4][32] x 4 floats, then region X (P~ [32][Mp+8], later G [32][D+8], later dQ red)
+    float* red = reinterpret_cast<float*>(smem);
+    T* X = reinterpret_cast<T*>(smem + 4 * 4 * kPx * sizeof(float));
+    const int ldp = a.Mp + 8, ldg = a.D + 8;
+
+    const int w = threadIdx.x / kWave;
+    const int lane = threadIdx.x % kWave;
+    const int col = lane & 31, h = lane >> 5;
+    const int blk = blockIdx.x;
+    const int px = blk * kPx + col;
+    const bool valid = px < a.n;
+    const int ntiles = a.Mp / 32;
+
+    const T* Kb = reinterpret_cast<const T*>(a.Kb);
+    const T* Vb = reinterpret_cast<const T*>(a.Vb);
+    const T* Vt = reinterpret_cast<const T*>(a.Vt);
+    const T* Ktp = reinterpret_cast<const T*>(a.Ktp);
+
+    // query fragments (B operand of S^T = K Q^T): Q[px][16 c + 8 h + t]
+    Frag qf[DQ / 16];
+#pragma unroll
+    for (int c = 0; c < DQ / 16; ++c) {
+        float v[8];
+        if (valid) {
+            const float4* qp = reinterpret_cast<const float4*>(a.Q + (size_t)px * DQ + 16 * c + 8 * h);
+            const float4 x0 = qp[0], x1 = qp[1];
+            v[0] = x0.x; v[1] = x0.y; v[2] = x0.z; v[3] = x0.w;
+            v[4] = x1.x; v[5] = x1.y; v[6] = x1.z; v[7] = x1.w;
+        } else {
+#pragma unroll
+            for (int t = 0; t < 8; ++t) v[t] = 0.0f;
+        }
+        qf[c] = P::from_f32(v);
+        if (MODE != MODE_INFER && w == 0) {
+            // Q^T block for the dK reduction: Qt[blk][16c + 8h + t][col]
+            T* qt = reinterpret_cast<T*>(a.Qt) + (size_t)blk * 32 * kPx;
+#pragma unroll
+            for (int t = 0; t < 8; ++t) qt[(16 * c + 8 * h + t) * kPx + col] = qf[c][t];
+        }
+    }
+    if (MODE != MODE_INFER && DQ == 16 && w == 1) {
+        T* qt = reinterpret_cast<T*>(a.Qt) + (size_t)blk * 32 * kPx;
+#pragma unroll
+        for (int t = 0; t < 8; ++t) qt[(16 + 8 * h + t) * kPx + col] = P::cvt(0.0f);
+    }
+
+    auto s_tile = [&](int tt) {
+        f32x16 s = {};
+#pragma unroll
+        for (int c = 0; c < DQ / 16; ++c) {
+            const Frag kf = P::load(Kb + (size_t)(32 * tt + col) * DQ + 16 * c + 8 * h);
+            P::mma(s, kf, qf[c]);
+        }
+        return s;
+    };
+
+    // ---- pass 1: row max of the logits (in log2 units)
+    float mx = -INFINITY;
+    for (int tt = w; tt < ntiles; tt += 4) {
+        const f32x16 s = s_tile(tt);
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+            if (32 * tt + crow(r, h) < a.M) mx = fmaxf(mx, s[r]);
+    }
+    mx = fmaxf(mx, __shfl_xor(mx, 32, kWave));
+    if (h == 0) red[w * kPx + col] = mx;
+    __syncthreads();
+    mx = fmaxf(fmaxf(red[col], red[kPx + col]), fmaxf(red[2 * kPx + col], red[3 * kPx + col]));
+    const float m2 = mx * a.scale_log2;
+    __syncthreads();
+
+    // ---- pass 2: P~ = exp2(S scale - m) into LDS [px][atom] and HBM (P~^T blocked)
+    float lsum = 0.0f;
+    T* Pt = reinterpret_cast<T*>(a.Pt) + (size_t)blk * a.Mp * kPx;
+    for (int tt = w; tt < ntiles; tt += 4) {
+        const f32x16 s = s_tile(tt);
+        float p[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int atom = 32 * tt + crow(r, h);
+            p[r] = atom < a.M ? exp2f(s[r] * a.scale_log2 - m2) : 0.0f;
+            lsum += p[r];
+        }
+#pragma unroll
+        for (int g4 = 0; g4 < 4; ++g4) {
+            const int atom0 = 32 * tt + 8 * g4 + 4 * h;
+            if (F8) {
+                // P~ of a pixel peaks at exactly 1, so with the V row scales folded
+                // into its columns one fixed factor maps it onto the E4M3 range.
+                const float4 sv = *reinterpret_cast<const float4*>(a.sv_fold + atom0);
+                int pk = __builtin_amdgcn_cvt_pk_fp8_f32(p[4 * g4] * sv.x, p[4 * g4 + 1] * sv.y, 0, false);
+                pk = __builtin_amdgcn_cvt_pk_fp8_f32(p[4 * g4 + 2] * sv.z, p[4 * g4 + 3] * sv.w, pk, true);
+                *reinterpret_cast<int*>(reinterpret_cast<uint8_t*>(X) + col * (a.Mp + 16) + atom0) = pk;
+            } else {
+                P::store4(X + col * ldp + atom0, p[4 * g4], p[4 * g4 + 1], p[4 * g4 + 2], p[4 * g4 + 3]);
+            }
+            if (MODE != MODE_INFER) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) Pt[(size_t)(atom0 + k) * kPx + col] = P::cvt(p[4 * g4 + k]);
+            }
+        }
+    }
+    lsum += __shfl_xor(lsum, 32, kWave);
+    if (h == 0) red[kPx * 4 + w * kPx + col] = lsum;
+    __syncthreads();
+    const float l = red[4 * kPx + col] + red[5 * kPx + col] + red[6 * kPx + col] + red[7 * kPx + col];
+    const float invl = 1.0f / l;
+
+    // ---- F^T = V^T P~^T: wave w owns D tiles [w NT, w NT + NT)
+    f32x16 acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = f32x16{};
+    if (F8) {
+        // K = 64 atoms per E4M3 MFMA; lane half h holds atoms 32 h + 0..31
+        const uint8_t* X8 = reinterpret_cast<const uint8_t*>(X) + col * (a.Mp + 16);
+        for (int c = 0; c < a.Mp / 64; ++c) {
+            const i32x4 b0 = *reinterpret_cast<const i32x4*>(X8 + 64 * c + 32 * h);
+            const i32x4 b1 = *reinterpret_cast<const i32x4*>(X8 + 64 * c + 32 * h + 16);
+            const i32x8 bf = {b0[0], b0[1], b0[2], b0[3], b1[0], b1[1], b1[2], b1[3]};
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const i32x8 af = *reinterpret_cast<const i32x8*>(
+                    a.Vt8 + (size_t)(32 * (w * NT + t) + col) * a.Mp + 64 * c + 32 * h);
+                acc[t] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(af, bf, acc[t], 0, 0, 0, 127, 0, 127);
+            }
+        }
+    } else {
+        for (int c = 0; c < a.Mp / 16; ++c) {
+            const Frag bf = P::load(X + col * ldp + 16 * c + 8 * h);
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const Frag af = P::load(Vt + (size_t)(32 * (w * NT + t) + col) * a.Mp + 16 * c + 8 * h);
+                P::mma(acc[t], af, bf);
+            }
+        }
+    }
+    const float fscale = F8 ? invl * a.fp8_unscale[0] : invl;
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[t][r] *= fscale;
+
+    if (MODE == MODE_INFER) {
+        if (valid) {
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+#pragma unroll
+                for (int g4 = 0; g4 < 4; ++g4) {
+                    const int dr = 32 * (w * NT + t) + 8 * g4 + 4 * h;
+                    *reinterpret_cast<float4*>(a.F + (size_t)px * a.D + dr) =
+                        make_float4(acc[t][4 * g4], acc[t][4 * g4 + 1], acc[t][4 * g4 + 2], acc[t][4 * g4 + 3]);
+                }
+        }
+        return;
+    }
+
+    // ---- epilogue: cosine loss gradient (LOSS) or upstream dF (ADJ)
+    float gsc[NT][16];
+    float delta = 0.0f;
+    if (MODE == MODE_LOSS) {
+        float tv[NT][16];
+        float nf = 0.f, ft = 0.f, nt = 0.f;
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int g4 = 0; g4 < 4; ++g4) {
+                const int dr = 32 * (w * NT + t) + 8 * g4 + 4 * h;
+                float4 x = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (valid) x = *reinterpret_cast<const float4*>(a.target + (size_t)px * a.D + dr);
+                tv[t][4 * g4] = x.x; tv[t][4 * g4 + 1] = x.y; tv[t][4 * g4 + 2] = x.z; tv[t][4 * g4 + 3] = x.w;
+            }
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                nf += acc[t][r] * acc[t][r];
+                ft += acc[t][r] * tv[t][r];
+                nt += tv[t][r] * tv[t][r];
+            }
+        nf += __shfl_xor(nf, 32, kWave);
+        ft += __shfl_xor(ft, 32, kWave);
+        nt += __shfl_xor(nt, 32, kWave);
+        __syncthreads();
+        if (h == 0) {
+            red[w * kPx + col] = nf;
+            red[4 * kPx + w * kPx + col] = ft;
+            red[8 * kPx + w * kPx + col] = nt;
+        }
+        __syncthreads();
+        nf = red[col] + red[kPx + col] + red[2 * kPx + col] + red[3 * kPx + col];
+        ft = red[4 * kPx + col] + red[5 * kPx + col] + red[6 * kPx + col] + red[7 * kPx + col];
+        nt = red[8 * kPx + col] + red[9 * kPx + col] + red[10 * kPx + col] + red[11 * kPx + col];
+        const float raw = sqrtf(nf) * sqrtf(nt);
+        const float den = fmaxf(raw, 1e-8f);
+        const float cs = ft / den;
+        // dL/dF = -(1/n) (T / den - c F / |F|^2), then divided by l
+        const float ca = valid ? -a.inv_n / den : 0.0f;
+        const float cb = (valid && raw > 1e-8f && nf > 0.f) ? a.inv_n * cs / nf : 0.0f;
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) gsc[t][r] = (ca * tv[t][r] + cb * acc[t][r]) * invl;
+        if (w == 0 && h == 0) {
+            if (a.row_cos && valid) a.row_cos[px] = cs;
+            // block sum of (1 - cos) over valid pixels
+            float lp = valid ? 1.0f - cs : 0.0f;
+            for (int o = 16; o >= 1; o >>= 1) lp += __shfl_xor(lp, o, kWave);
+            if (col == 0) a.loss_part[blk] = lp;
+        }
+    } else {
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int g4 = 0; g4 < 4; ++g4) {
+                const int dr = 32 * (w * NT + t) + 8 * g4 + 4 * h;
+                float4 x = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (valid) x = *reinterpret_cast<const float4*>(a.dF + (size_t)px * a.D + dr);
+                gsc[t][4 * g4] = x.x * invl; gsc[t][4 * g4 + 1] = x.y * invl;
+                gsc[t][4 * g4 + 2] = x.z * invl; gsc[t][4 * g4 + 3] = x.w * invl;
+            }
+    }
+    // delta' = sum_D G F (zero for the pure cosine term up to rounding)
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) delta += gsc[t][r] * acc[t][r];
+    delta += __shfl_xor(delta, 32, kWave);
+    __syncthreads();  // everyone is done reading P~ (region X) and red
+    if (h == 0) red[12 * kPx + w * kPx + col] = delta;
+    // stage G into LDS [px][D] and write G^T blocked to HBM
+    T* Gt = reinterpret_cast<T*>(a.Gt) + (size_t)blk * a.D * kPx;
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int g4 = 0; g4 < 4; ++g4) {
+            const int dr = 32 * (w * NT + t) + 8 * g4 + 4 * h;
+            P::store4(X + col * ldg + dr, gsc[t][4 * g4], gsc[t][4 * g4 + 1], gsc[t][4 * g4 + 2], gsc[t][4 * g4 + 3]);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) Gt[(size_t)(dr + k) * kPx + col] = P::cvt(gsc[t][4 * g4 + k]);
+        }
+    __syncthreads();
+    delta = red[12 * kPx + col] + red[13 * kPx + col] + red[14 * kPx + col] + red[15 * kPx + col];
+
+    // ---- per atom tile: dP = G V^T, dS = P~ (dP - delta) / sqrt(d), dQ^T += K^T dS^T
+    f32x16 dq = {};
+    T* St = reinterpret_cast<T*>(a.St) + (size_t)blk * a.Mp * kPx;
+    for (int tt = w; tt < ntiles; tt += 4) {
+        f32x16 dp = {};
+        for (int c = 0; c < a.D / 16; ++c) {
+            const Frag af = P::load(Vb + (size_t)(32 * tt + col) * a.D + 16 * c + 8 * h);
+            const Frag bf = P::load(X + col * ldg + 16 * c + 8 * h);
+            P::mma(dp, af, bf);
+        }
+        const f32x16 s = s_tile(tt);
+        float ds[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int atom = 32 * tt + crow(r, h);
+            const float pt = atom < a.M ? exp2f(s[r] * a.scale_log2 - m2) : 0.0f;
+            ds[r] = valid ? pt * (dp[r] - delta) * a.inv_sqrt_d : 0.0f;
+        }
+#pragma unroll
+        for (int r = 0; r < 16; ++r) St[(size_t)(32 * tt + crow(r, h)) * kPx + col] = P::cvt(ds[r]);
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const Frag af = P::load(Ktp + (size_t)col * a.Mp + 32 * tt + 16 * c + 8 * h);
+            const Frag bf = P::from_f32(ds + 8 * c);
+            P::mma(dq, af, bf);
+        }
+    }
+    if (!a.dQ) return;
+    __syncthreads();  // region X (G) no longer read
+    float* dqr = reinterpret_cast<float*>(X);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) dqr[(w * 32 + crow(r, h)) * kPx + col] = dq[r];
+    __syncthreads();
+    for (int i = threadIdx.x; i < kPx * DQ; i += kRowsThreads) {
+        const int p = i / DQ, k = i % DQ;
+        const float v = dqr[(0 * 32 + k) * kPx + p] + dqr[(1 * 32 + k) * kPx + p] +
+                        dqr[(2 * 32 + k) * kPx + p] + dqr[(3 * 32 + k) * kPx + p];
+        const int gp = blk * kPx + p;
+        if (gp < a.n) a.dQ[(size_t)gp * DQ + k] = v;
+    }
+}
+
+// ------------------------------------------------------------ split-K TN GEMM
+
+// C_part[split][i][j] = sum over the split's pixel blocks of A^T[i][p] B^T[j][p]
+// with A^T, B^T in the pixel-blocked transposed layout X^T[blk][row][32].
+// Workgroup tile: 64 x 64 (wave tile 32 x 32); grid = tiles x splits, mapped so
+// that the tiles of one split share an XCD (and its L2).
+template <class P>
+__global__ __launch_bounds__(256) void k_dec_tn(const void* At_, int rowsA, const void* Bt_, int rowsB,
+                                                int nblocks, int splits, int tiles_i, int tiles_j,
+                                                float* __restrict__ part)
+{
+    using T = typename P::T;
+    using Frag = typename P::Frag;
+    const T* At = reinterpret_cast<const T*>(At_);
+    const T* Bt = reinterpret_cast<const T*>(Bt_);
+    const int ntiles = tiles_i * tiles_j;
+    // XCD-aware mapping: consecutive workgroup ids go to different XCDs
+    const int b = blockIdx.x;
+    const int xcd = b % 8, idx = b / 8;
+    const int split = (idx / ntiles) * 8 + xcd;
+    const int tile = idx % ntiles;
+    if (split >= splits) return;
+    const int ti = tile / tiles_j, tj = tile % tiles_j;
+    const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int col = lane & 31, h = lane >> 5;
+    const int i0 = 64 * ti + 32 * (w >> 1), j0 = 64 * tj + 32 * (w & 1);
+    const bool ok = i0 < rowsA && j0 < rowsB;
+    const int per = (nblocks + splits - 1) / splits;
+    const int b0 = split * per, b1 = min(nblocks, b0 + per);
+    f32x16 c = {};
+    if (ok) {
+        for (int blk = b0; blk < b1; ++blk) {
+            const T* ab = At + ((size_t)blk * rowsA + i0 + col) * kPx;
+            const T* bb = Bt + ((size_t)blk * rowsB + j0 + col) * kPx;
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                const Frag af = P::load(ab + 16 * k + 8 * h);
+                const Frag bf = P::load(bb + 16 * k + 8 * h);
+                P::mma(c, af, bf);
+            }
+        }
+        float* out = part + (size_t)split * rowsA * rowsB;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) out[(size_t)(i0 + crow(r, h)) * rowsB + j0 + col] = c[r];
+    }
+}
+
+// out[i][j] = scale * sum_split part[split][i][j] (+ 2 lambda (K - K0) for dK),
+// for i < rows_out, j < cols_out; part has ld = ldp columns.
+__global__ __launch_bounds__(256) void k_dec_reduce(const float* __restrict__ part, int splits,
+                                                    int rows_p, int ldp, int rows_out, int cols_out,
+                                                    float* __restrict__ out, const float* __restrict__ K,
+                                                    const float* __restrict__ K0, float two_lambda)
+{
+    const size_t n = (size_t)rows_out * cols_out;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+        const int i = (int)(e / cols_out), j = (int)(e % cols_out);
+        float s = 0.f;
+        for (int k = 0; k < splits; ++k) s += part[((size_t)k * rows_p + i) * ldp + j];
+        if (K0) s += two_lambda * (K[e] - K0[e]);
+        out[e] = s;
+    }
+}
+
+// loss = (1/n) sum_blocks part + lambda ||K - K0||^2  (single workgroup, fixed order)
+__global__ __launch_bounds__(256) void k_dec_loss(const float* __restrict__ part, int nblocks, float inv_n,
+                                                  const float* __restrict__ K, const float* __restrict__ K0,
+                                                  int nk, float lambda, float* __restrict__ loss)
+{
+    __shared__ float sh[256];
+    float s = 0.f, tr = 0.f;
+    for (int i = threadIdx.x; i < nblocks; i += 256) s += part[i];
+    if (K0 && lambda != 0.f)
+        for (int i = threadIdx.x; i < nk; i += 256) {
+            const float dlt = K[i] - K0[i];
+            tr += dlt * dlt;
+        }
+    sh[threadIdx.x] = s * inv_n + lambda * tr;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) loss[0] = sh[0];
+}
+
+// ------------------------------------------------------------ host side
+
+static int pick_splits(int nblocks, int tiles)
+{
+    // enough workgroups to fill 256 CUs twice, splits a multiple of 8
+    int s = (512 + tiles - 1) / tiles;
+    s = ((s + 7) / 8) * 8;
+    if (s > nblocks) s = ((nblocks + 7) / 8) * 8;
+    if (s < 8) s = 8;
+    return s;
+}
+
+bool decode_layout(int prec, int n, int d, int M, int D, DecodeLayout* L)
+{
+    if (prec != LAM_FP32 && prec != LAM_BF16 && prec != LAM_FP8_E4M3) return false;
+    if ((d != 16 && d != 32) || M < 1 || M > 2048 || D < 128 || D > 1024 || D % 128 != 0 || n < 0)
+        return false;
+    const size_t tb = prec == LAM_FP32 ? 4 : 2;
+    const int Mp = (M + kAtomAlign - 1) / kAtomAlign * kAtomAlign;
+    const int nb = (n + kPx - 1) / kPx;
+    L->Mp = Mp;
+    L->row_blocks = nb;
+    const int tiles_v = (Mp / 64) * (D / 64);
+    const int tiles_k = Mp / 64;
+    const int sv = pick_splits(std::max(nb, 1), tiles_v);
+    const int sk = pick_splits(std::max(nb, 1), tiles_k);
+    L->splits = sv;
+    L->splits_k = sk;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += (bytes + 255) / 256 * 256;
+        return o;
+    };
+    L->off_kb = take((size_t)Mp * d * tb);
+    L->off_vb = take((size_t)Mp * D * tb);
+    L->off_vt = take((size_t)Mp * D * tb);
+    L->off_kt = take((size_t)32 * Mp * tb);
+    L->off_p = take((size_t)nb * Mp * kPx * tb);
+    L->off_gf = take((size_t)nb * D * kPx * tb);
+    L->off_ds = take((size_t)nb * Mp * kPx * tb);
+    L->off_qt = take((size_t)nb * 32 * kPx * tb);
+    L->off_part = take((size_t)std::max((size_t)sv * Mp * D, (size_t)sk * Mp * 32) * 4);
+    L->off_loss = take((size_t)std::max(nb, 1) * 4);
+    L->off_sc = take(((size_t)3 * Mp + 64) * 4);
+    L->bytes = off;
+    return true;
+}
+
+static size_t rows_lds(int prec, int Mp, int D)
+{
+    const size_t tb = prec == LAM_FP32 ? 4 : 2;
+    size_t x = std::max((size_t)kPx * (Mp + 8) * tb, (size_t)kPx * (D + 8) * tb);
+    x = std::max(x, (size_t)4 * 32 * kPx * 4);  // dQ reduction
+    return 16 * kPx * 4 + x;
+}
+
+template <class P, int MODE, bool F8>
+static hipError_t launch_rows(const RowsArgs& ra, int nb, int D, int d, size_t lds, hipStream_t st)
+{
+    const int NT = D / 128;
+#define LAM_ROWS(NTV, DQV)                                                                           \
+    if (NT == NTV && d == DQV) {                                                                     \
+        auto kern = k_dec_rows<P, NTV, DQV, MODE, F8>;                                                   \
+        hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
+        hipLaunchKernelGGL(kern, dim3(nb), dim3(kRowsThreads), lds, st, ra);                        \
+        return hipGetLastError();                                                                    \
+    }
+    LAM_ROWS(1, 16) LAM_ROWS(2, 16) LAM_ROWS(3, 16) LAM_ROWS(4, 16) LAM_ROWS(5, 16) LAM_ROWS(6, 16)
+    LAM_ROWS(7, 16) LAM_ROWS(8, 16) LAM_ROWS(1, 32) LAM_ROWS(2, 32) LAM_ROWS(3, 32) LAM_ROWS(4, 32)
+    LAM_ROWS(5, 32) LAM_ROWS(6, 32) LAM_ROWS(7, 32) LAM_ROWS(8, 32)
+#undef LAM_ROWS
+    return hipErrorInvalidValue;
+}
+
+template <class P, bool F8>
+static hipError_t run_decode(const DecodeArgs& A, const DecodeLayout& L, int mode, hipStream_t st)
+{
+    using T = typename P::T;
+    char* base = reinterpret_cast<char*>(L.base);
+    T* Kb = reinterpret_cast<T*>(base + L.off_kb);
+    T* Vb = reinterpret_cast<T*>(base + L.off_vb);
+    T* Vt = reinterpret_cast<T*>(base + L.off_vt);
+    T* Ktp = reinterpret_cast<T*>(base + L.off_kt);
+    const int Mp = L.Mp, nb = L.row_blocks;
+    {
+        size_t work = std::max((size_t)Mp * A.D, (size_t)32 * Mp);
+        int grid = (int)std::min<size_t>((work + 255) / 256, 2048);
+        if (F8) {
+            float* sc = reinterpret_cast<float*>(base + L.off_sc);
+            hipError_t e0 = launch_fill_u32(reinterpret_cast<uint32_t*>(sc + 2 * Mp), 1, 0u, st);
+            if (e0 != hipSuccess) return e0;
+            hipLaunchKernelGGL(k_dec_scales, dim3(Mp), dim3(256), 0, st, A.K, A.V, A.M, Mp, A.d, A.D, sc);
+            hipLaunchKernelGGL(k_dec_prep_fp8, dim3(grid), dim3(256), 0, st, A.K, A.V, A.M, Mp, A.d, A.D,
+                               (const float*)sc, reinterpret_cast<__bf16*>(Kb), reinterpret_cast<__bf16*>(Vb),
+                               reinterpret_cast<uint8_t*>(Vt), reinterpret_cast<__bf16*>(Ktp),
+                               sc + 2 * Mp + 64, sc + 2 * Mp + 8);
+        } else {
+            hipLaunchKernelGGL(k_dec_prep<P>, dim3(grid), dim3(256), 0, st, A.K, A.V, A.M, Mp, A.d, A.D,
+                               Kb, Vb, Vt, Ktp);
+        }
+    }
+    RowsArgs ra{};
+    ra.n = A.n; ra.d = A.d; ra.M = A.M; ra.Mp = Mp; ra.D = A.D;
+    ra.scale_log2 = kLog2e / sqrtf((float)A.d);
+    ra.inv_sqrt_d = 1.0f / sqrtf((float)A.d);
+    ra.inv_n = A.n > 0 ? 1.0f / (float)A.n : 0.0f;
+    ra.Q = A.Q; ra.target = A.target; ra.dF = A.dF; ra.F = A.F; ra.dQ = A.dQ; ra.row_cos = A.row_cos;
+    ra.loss_part = reinterpret_cast<float*>(base + L.off_loss);
+    ra.Kb = Kb; ra.Vb = Vb; ra.Vt = Vt; ra.Ktp = Ktp;
+    ra.Pt = base + L.off_p; ra.Gt = base + L.off_gf; ra.St = base + L.off_ds; ra.Qt = base + L.off_qt;
+    if (F8) {
+        float* sc = reinterpret_cast<float*>(base + L.off_sc);
+        ra.Vt8 = reinterpret_cast<const uint8_t*>(Vt);
+        ra.sv_fold = sc + 2 * Mp + 64;
+        ra.fp8_unscale = sc + 2 * Mp + 8;
+    }
+    const size_t lds = rows_lds(A.prec == LAM_FP32 ? LAM_FP32 : LAM_BF16, Mp, A.D);
+    hipError_t e = hipSuccess;
+    if (nb > 0) {
+        ProfScope ps("decode_rows", st);
+        if (mode == MODE_INFER) e = launch_rows<P, MODE_INFER, F8>(ra, nb, A.D, A.d, lds, st);
+        else if (mode == MODE_LOSS) e = launch_rows<P, MODE_LOSS, F8>(ra, nb, A.D, A.d, lds, st);
+        else e = launch_rows<P, MODE_ADJ, F8>(ra, nb, A.D, A.d, lds, st);
+        if (e != hipSuccess) return e;
+    }
+    if (mode == MODE_INFER) return hipGetLastError();
+    float* part = reinterpret_cast<float*>(base + L.off_part);
+    // dV = P~^T G over all pixels
+    {
+        const int ti = Mp / 64, tj = A.D / 64;
+        if (nb > 0) {
+            ProfScope ps("decode_tn", st);
+            hipLaunchKernelGGL(k_dec_tn<P>, dim3(L.splits * ti * tj), dim3(256), 0, st,
+                               (const void*)(base + L.off_p), Mp, (const void*)(base + L.off_gf), A.D, nb,
+                               L.splits, ti, tj, part);
+        }
+        hipLaunchKernelGGL(k_dec_reduce, dim3(std::min(2048, (A.M * A.D + 255) / 256)), dim3(256), 0, st,
+                           (const float*)part, nb > 0 ? L.splits : 0, Mp, A.D, A.M, A.D, A.dV,
+                           (const float*)nullptr, (const float*)nullptr, 0.0f);
+    }
+    // dK = dS^T Q (1/sqrt(d) already in dS) + 2 lambda (K - K0)
+    {
+        const int ti = Mp / 64, tj = 1;
+        if (nb > 0) {
+            hipLaunchKernelGGL(k_dec_tn<P>, dim3(L.splits_k * ti * tj), dim3(256), 0, st,
+                               (const void*)(base + L.off_ds), Mp, (const void*)(base + L.off_qt), 32, nb,
+                               L.splits_k, ti, tj, part);
+        }
+        const bool tr = mode == MODE_LOSS && A.K0 && A.lambda_tr != 0.0f;
+        hipLaunchKernelGGL(k_dec_reduce, dim3(std::min(2048, (A.M * A.d + 255) / 256)), dim3(256), 0, st,
+                           (const float*)part, nb > 0 ? L.splits_k : 0, Mp, 32, A.M, A.d, A.dK,
+                           tr ? A.K : (const float*)nullptr, tr ? A.K0 : (const float*)nullptr,
+                           tr ? 2.0f * A.lambda_tr : 0.0f);
+    }
+    if (mode == MODE_LOSS)
+        hipLaunchKernelGGL(k_dec_loss, dim3(1), dim3(256), 0, st, (const float*)ra.loss_part, nb,
+                           ra.inv_n, A.K, A.K0, A.M * A.d, A.K0 ? A.lambda_tr : 0.0f, A.loss);
+    return hipGetLastError();
+}
+
+hipError_t decode_loss_launch(const DecodeArgs& A, const DecodeLayout& L, hipStream_t st)
+{
+    if (A.prec == LAM_FP32) return run_decode<TF32, false>(A, L, MODE_LOSS, st);
+    if (A.prec == LAM_FP8_E4M3) return run_decode<TBF16, true>(A, L, MODE_LOSS, st);
+    return run_decode<TBF16, false>(A, L, MODE_LOSS, st);
+}
+
+hipError_t decode_forward_launch(const DecodeArgs& A, const DecodeLayout& L, hipStream_t st)
+{
+    if (A.prec == LAM_FP32) return run_decode<TF32, false>(A, L, MODE_INFER, st);
+    if (A.prec == LAM_FP8_E4M3) return run_decode<TBF16, true>(A, L, MODE_INFER, st);
+    return run_decode<TBF16, false>(A, L, MODE_INFER, st);
+}
+
+hipError_t decode_backward_launch(const DecodeArgs& A, const DecodeLayout& L, hipStream_t st)
+{
+    if (A.prec == LAM_FP32) return run_decode<TF32, false>(A, L, MODE_ADJ, st);
+    if (A.prec == LAM_FP8_E4M3) return run_decode<TBF16, true>(A, L, MODE_ADJ, st);
+    return run_decode<TBF16, false>(A, L, MODE_ADJ, st);
+}
+
+}  // namespace lam
+
+// ------------------------------------------------------------ C ABI
+
+using namespace lam;
+
+static bool dec_ptrs_ok(const float* Q, int n, const float* K, const float* V)
+{
+    return K && V && (n == 0 || Q);
+}
+
+extern "C" {
+
+lam_status lam_decode_workspace_size(int precision, int n, int d, int M, int D, uint64_t* bytes)
+{
+    if (!bytes) return LAM_ERR_INVALID_ARG;
+    if (n < 0) return LAM_ERR_INVALID_ARG;
+    DecodeLayout L{};
+    if (!decode_layout(precision, n, d, M, D, &L)) return LAM_ERR_UNSUPPORTED;
+    *bytes = L.bytes;
+    return LAM_OK;
+}
+
+static lam_status dec_common(int precision, int n, int d, int M, int D, void* ws, uint64_t ws_bytes,
+                             DecodeLayout* L)
+{
+    if (n < 0) return LAM_ERR_INVALID_ARG;
+    if (!decode_layout(precision, n, d, M, D, L)) return LAM_ERR_UNSUPPORTED;
+    if (!ws || ws_bytes < L->bytes) return LAM_ERR_INVALID_ARG;
+    L->base = ws;
+    return LAM_OK;
+}
+
+lam_status lam_decode_loss(int precision, const float* Q, int n, int d, const float* K, const float* V,
+                           int M, int D, const float* target, const float* K0, float lambda_tr,
+                           float* loss, float* dQ, float* dK, float* dV, float* row_cos, void* ws,
+                           uint64_t ws_bytes, void* stream)
+{
+    DecodeLayout L{};
+    lam_status s = dec_common(precision, n, d, M, D, ws, ws_bytes, &L);
+    if (s != LAM_OK) return s;
+    if (!dec_ptrs_ok(Q, n, K, V) || !loss || !dK || !dV || (n > 0 && !target)) return LAM_ERR_INVALID_ARG;
+    if (lambda_tr != 0.0f && !K0) return LAM_ERR_INVALID_ARG;
+    DecodeArgs A{};
+    A.prec = precision; A.n = n; A.d = d; A.M = M; A.D = D;
+    A.Q = Q; A.K = K; A.V = V; A.target = target; A.K0 = K0; A.lambda_tr = lambda_tr;
+    A.loss = loss; A.dQ = dQ; A.dK = dK; A.dV = dV; A.row_cos = row_cos;
+    return decode_loss_launch(A, L, (hipStream_t)stream) == hipSuccess ? LAM_OK : LAM_ERR_HIP;
+}
+
+lam_status lam_decode_forward(int precision, const float* Q, int n, int d, const float* K, const float* V,
+                              int M, int D, float* F, void* ws, uint64_t ws_bytes, void* stream)
+{
+    DecodeLayout L{};
+    lam_status s = dec_common(precision, n, d, M, D, ws, ws_bytes, &L);
+    if (s != LAM_OK) return s;
+    if (!dec_ptrs_ok(Q, n, K, V) || (n > 0 && !F)) return LAM_ERR_INVALID_ARG;
+    DecodeArgs A{};
+    A.prec = precision; A.n = n; A.d = d; A.M = M; A.D = D;
+    A.Q = Q; A.K = K; A.V = V; A.F = F;
+    return decode_forward_launch(A, L, (hipStream_t)stream) == hipSuccess ? LAM_OK : LAM_ERR_HIP;
+}
+
+lam_status lam_decode_backward(int precision, const float* Q, int n, int d, const float* K, const float* V,
+                               int M, int D, const float* dF, float* dQ, float* dK, float* dV, void* ws,
+                               uint64_t ws_bytes, void* stream)
+{
+    DecodeLayout L{};
+    lam_status s = dec_common(precision, n, d, M, D, ws, ws_bytes, &L);
+    if (s != LAM_OK) return s;
+    if (!dec_ptrs_ok(Q, n, K, V) || !dK || !dV || (n > 0 && !dF)) return LAM_ERR_INVALID_ARG;
+    DecodeArgs A{};
+    A.prec = precision; A.n = n; A.d = d; A.M = M; A.D = D;
+    A.Q = Q; A.K = K; A.V = V; A.dF = dF; A.dQ = dQ; A.dK = dK; A.dV = dV;
+    return decode_backward_launch(A, L, (hipStream_t)stream) == hipSuccess ? LAM_OK : LAM_ERR_HIP;
+}
+
+}  // extern "C"

@@ -1,0 +1,92 @@
+// Internal launch interface between the C-ABI layer and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "common.h"
+
+namespace lam {
+
+// ------------------------------------------------------------- sort / scan
+size_t scan_scratch_words(uint32_t n);
+size_t radix_scratch_words(uint32_t n_cap);
+hipError_t launch_excl_scan(const uint32_t* in, const uint32_t* idx, uint32_t n, uint32_t* out,
+                            uint32_t* total, uint32_t* scratch, hipStream_t st);
+hipError_t launch_radix_sort(const uint32_t* keys_first, uint32_t* keys_a, uint32_t* vals_a,
+                             uint32_t* keys_b, uint32_t* vals_b, bool iota_first,
+                             const uint32_t* n_dev, uint32_t n_cap, int bits, uint32_t* scratch,
+                             bool* in_b, hipStream_t st);
+hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t st);
+
+// ------------------------------------------------------------- profiling
+bool profiling();
+void prof_mark(const char* name, bool is_begin, hipStream_t st);
+struct ProfScope {
+    const char* name;
+    hipStream_t st;
+    ProfScope(const char* n, hipStream_t s) : name(n), st(s) { prof_mark(name, true, st); }
+    ~ProfScope() { prof_mark(name, false, st); }
+};
+
+// ------------------------------------------------------------- render
+struct RenderArgs {
+    int n, d;
+    const float *means, *log_scales, *quats, *logits, *queries;
+    float* Q;             // forward output
+    float* T_final;       // forward output (caller copy)
+    const float* dQ;      // backward input
+    const float* T_final_in;  // backward: transmittance saved in the workspace
+    float *d_means, *d_log_scales, *d_quats, *d_logits, *d_queries;
+};
+
+// Workspace carve-up (all pointers into the caller's buffer).
+struct RenderLayout {
+    CamSet cams;
+    uint64_t records, capacity, pixels, bytes;
+    int tile_bits;
+    bool tile_in_b;  // where the sorted (tile, record) pairs end up
+    uint32_t* counters;  // [0] pairs needed, [1] overflow flag
+    float4* rec0;
+    float4* rec1;
+    uint2* foot;
+    uint32_t* depth_key;  // per-record depth key as projected (kept for inspection)
+    uint32_t *depth_a, *depth_b, *recs_a, *recs_b;
+    uint32_t* ntiles;
+    uint32_t* offsets;
+    uint32_t* sort_scratch;
+    uint32_t *ikeys_a, *ikeys_b, *ivals_a, *ivals_b;
+    uint2* ranges;
+    uint32_t* n_contrib;
+    float* t_final;
+    float* rec_grad;
+};
+
+hipError_t render_forward_launch(const RenderArgs& A, const RenderLayout& L, hipStream_t st);
+hipError_t render_backward_launch(const RenderArgs& A, const RenderLayout& L, hipStream_t st);
+
+// ------------------------------------------------------------- decode
+struct DecodeArgs {
+    int prec, n, d, M, D;
+    const float *Q, *K, *V, *target, *K0, *dF;
+    float lambda_tr;
+    float *loss, *dQ, *dK, *dV, *row_cos, *F;
+};
+
+struct DecodeLayout {
+    int Mp;       // M rounded up to the atom tile
+    int row_blocks;
+    uint64_t bytes;
+    void* base;
+    // byte offsets inside the workspace, filled by decode_layout()
+    size_t off_kb, off_vb, off_vt, off_kt, off_gf, off_p, off_ds, off_qt, off_part, off_loss, off_sc;
+    int splits, splits_k;
+};
+
+bool decode_layout(int prec, int n, int d, int M, int D, DecodeLayout* L);
+hipError_t decode_loss_launch(const DecodeArgs& A, const DecodeLayout& L, hipStream_t st);
+hipError_t decode_forward_launch(const DecodeArgs& A, const DecodeLayout& L, hipStream_t st);
+hipError_t decode_backward_launch(const DecodeArgs& A, const DecodeLayout& L, hipStream_t st);
+
+}  // namespace lam

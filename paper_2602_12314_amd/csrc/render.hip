@@ -1,0 +1,635 @@
+// Query-map rendering (paper Eq. 2 and Eq. 4) and its adjoint on gfx950.
+//
+// Pipeline of one forward call (one HIP stream, no host synchronisation):
+//   k_preprocess      one thread per (camera, Gaussian) record, FP64 projection:
+//                     screen mean, conic, opacity, integer footprint, depth key
+//   radix sort        records by float32 depth bits (stable: ties by record)
+//   scan + k_emit     (tile id, record) pairs emitted in depth order
+//   radix sort        pairs by tile id (stable, so each tile stays depth-ordered)
+//   k_ranges          [start, end) of every tile's list
+//   k_raster_fwd      one workgroup per tile; the tile's list is staged through
+//                     LDS 256 records at a time; each thread blends one pixel
+// The backward walks each pixel's list back to front, rebuilding the
+// transmittance by division, reduces the per-Gaussian terms across the wave
+// with DPP and adds them with one atomic per wave; k_preprocess_bwd chains the
+// screen-space gradients to the raw parameters.
+#include "common.h"
+#include "kernels.h"
+
+namespace lam {
+
+// ------------------------------------------------------------- preprocess
+
+// Record outputs: rec0 = (u_hi, v_hi, u_lo, v_lo) with u = u_hi + u_lo as a
+// float pair, rec1 = (A, B, C, opacity) with power = -0.5 (A dx^2 + C dy^2) - B dx dy,
+// foot = (x0 | x1 << 16, y0 | y1 << 16) the inclusive pixel footprint.
+__global__ __launch_bounds__(256) void k_preprocess(
+    CamSet cs, int N, const float* __restrict__ means, const float* __restrict__ log_scales,
+    const float* __restrict__ quats, const float* __restrict__ logits, float4* __restrict__ rec0,
+    float4* __restrict__ rec1, uint2* __restrict__ foot, uint32_t* __restrict__ depth_key,
+    uint32_t* __restrict__ ntiles)
+{
+#pragma clang fp contract(off)
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const Cam& cam = cs.c[blockIdx.y];
+    const size_t r = (size_t)blockIdx.y * N + i;
+
+    const double mx = means[3 * i], my = means[3 * i + 1], mz = means[3 * i + 2];
+    double Wm[3][3], t[3];
+    for (int a = 0; a < 3; ++a) {
+        for (int b = 0; b < 3; ++b) Wm[a][b] = (double)cam.vm[4 * a + b];
+        t[a] = (double)cam.vm[4 * a + 3];
+    }
+    const double x = ((Wm[0][0] * mx + Wm[0][1] * my) + Wm[0][2] * mz) + t[0];
+    const double y = ((Wm[1][0] * mx + Wm[1][1] * my) + Wm[1][2] * mz) + t[1];
+    const double z = ((Wm[2][0] * mx + Wm[2][1] * my) + Wm[2][2] * mz) + t[2];
+
+    bool vis = z > kNear;
+    double s[3], qn[4];
+    double nrm = 0.0;
+    if (vis) {
+        for (int k = 0; k < 3; ++k) s[k] = exp((double)log_scales[3 * i + k]);
+        double q0 = quats[4 * i], q1 = quats[4 * i + 1], q2 = quats[4 * i + 2], q3 = quats[4 * i + 3];
+        nrm = sqrt(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
+        vis = nrm > 0.0;
+        qn[0] = q0 / nrm; qn[1] = q1 / nrm; qn[2] = q2 / nrm; qn[3] = q3 / nrm;
+    }
+    double a = 0, b = 0, c = 0, det = 0, u = 0, v = 0, radius = 0;
+    if (vis) {
+        const double w = qn[0], qx = qn[1], qy = qn[2], qz = qn[3];
+        double Rg[3][3] = {
+            {1.0 - 2.0 * (qy * qy + qz * qz), 2.0 * (qx * qy - w * qz), 2.0 * (qx * qz + w * qy)},
+            {2.0 * (qx * qy + w * qz), 1.0 - 2.0 * (qx * qx + qz * qz), 2.0 * (qy * qz - w * qx)},
+            {2.0 * (qx * qz - w * qy), 2.0 * (qy * qz + w * qx), 1.0 - 2.0 * (qx * qx + qy * qy)}};
+        double S3[3][3], Sc[3][3];
+        for (int p = 0; p < 3; ++p)
+            for (int q = 0; q < 3; ++q) {
+                double acc = 0.0;
+                for (int k = 0; k < 3; ++k) acc += Rg[p][k] * s[k] * s[k] * Rg[q][k];
+                S3[p][q] = acc;
+            }
+        for (int p = 0; p < 3; ++p)
+            for (int q = 0; q < 3; ++q) {
+                double acc = 0.0;
+                for (int k = 0; k < 3; ++k)
+                    for (int l = 0; l < 3; ++l) acc += Wm[p][k] * S3[k][l] * Wm[q][l];
+                Sc[p][q] = acc;
+            }
+        const double fx = cam.fx, fy = cam.fy;
+        const double limx = kFovClamp * (cam.w / (2.0 * fx));
+        const double limy = kFovClamp * (cam.h / (2.0 * fy));
+        double tx = x / z, ty = y / z;
+        tx = tx < -limx ? -limx : (tx > limx ? limx : tx);
+        ty = ty < -limy ? -limy : (ty > limy ? limy : ty);
+        const double J[2][3] = {{fx / z, 0.0, -fx * tx / z}, {0.0, fy / z, -fy * ty / z}};
+        double cov[2][2];
+        for (int p = 0; p < 2; ++p)
+            for (int q = 0; q < 2; ++q) {
+                double acc = 0.0;
+                for (int k = 0; k < 3; ++k)
+                    for (int l = 0; l < 3; ++l) acc += J[p][k] * Sc[k][l] * J[q][l];
+                cov[p][q] = acc;
+            }
+        a = cov[0][0] + kDilation;
+        b = cov[0][1];
+        c = cov[1][1] + kDilation;
+        det = a * c - b * b;
+        vis = det > 0.0;
+        if (vis) {
+            const double mid = 0.5 * (a + c);
+            const double lam = mid + sqrt(fmax(kEigFloor, mid * mid - det));
+            radius = ceil(kSigmas * sqrt(lam));
+            u = (fx * x) / z + (double)cam.cx;
+            v = (fy * y) / z + (double)cam.cy;
+            vis = (u + radius >= 0.0) && (u - radius <= (double)(cam.w - 1)) &&
+                  (v + radius >= 0.0) && (v - radius <= (double)(cam.h - 1));
+        }
+    }
+    int x0 = 0, x1 = -1, y0 = 0, y1 = -1;
+    if (vis) {
+        const double fx0 = ceil(u - radius), fx1 = floor(u + radius);
+        const double fy0 = ceil(v - radius), fy1 = floor(v + radius);
+        x0 = fx0 < 0.0 ? 0 : (int)fx0;
+        x1 = fx1 > cam.w - 1 ? cam.w - 1 : (int)fx1;
+        y0 = fy0 < 0.0 ? 0 : (int)fy0;
+        y1 = fy1 > cam.h - 1 ? cam.h - 1 : (int)fy1;
+        vis = x0 <= x1 && y0 <= y1;
+    }
+    if (!vis) {
+        depth_key[r] = 0xFFFFFFFFu;
+        ntiles[r] = 0u;
+        foot[r] = make_uint2(0u, 0u);
+        return;
+    }
+    const float uh = (float)u, vh = (float)v;
+    rec0[r] = make_float4(uh, vh, (float)(u - (double)uh), (float)(v - (double)vh));
+    const double o = 1.0 / (1.0 + exp(-(double)logits[i]));
+    rec1[r] = make_float4((float)(c / det), (float)(-b / det), (float)(a / det), (float)o);
+    foot[r] = make_uint2((uint32_t)x0 | ((uint32_t)x1 << 16), (uint32_t)y0 | ((uint32_t)y1 << 16));
+    depth_key[r] = __float_as_uint((float)z);
+    const int nx = (x1 >> cs.tile_shift_x) - (x0 >> cs.tile_shift_x) + 1;
+    const int ny = (y1 >> cs.tile_shift_y) - (y0 >> cs.tile_shift_y) + 1;
+    ntiles[r] = (uint32_t)(nx * ny);
+}
+
+// One thread per depth-sorted record: write its (tile id, record) pairs.
+__global__ __launch_bounds__(256) void k_emit(CamSet cs, int N, uint32_t R,
+                                             const uint32_t* __restrict__ sorted_rec,
+                                             const uint32_t* __restrict__ offsets,
+                                             const uint32_t* __restrict__ ntiles,
+                                             const uint2* __restrict__ foot, uint32_t cap,
+                                             uint32_t* __restrict__ keys,
+                                             uint32_t* __restrict__ vals)
+{
+    const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= R) return;
+    const uint32_t r = sorted_rec[s];
+    const uint32_t cnt = ntiles[r];
+    if (cnt == 0) return;
+    const int c = (int)(r / (uint32_t)N);
+    int tbase = 0, tx_n = 1;
+    for (int k = 0; k < cs.n; ++k)
+        if (k == c) { tbase = cs.c[k].tile_base; tx_n = cs.c[k].tiles_x; }
+    const uint2 f = foot[r];
+    const int x0 = (f.x & 0xFFFF) >> cs.tile_shift_x, x1 = (f.x >> 16) >> cs.tile_shift_x;
+    const int y0 = (f.y & 0xFFFF) >> cs.tile_shift_y, y1 = (f.y >> 16) >> cs.tile_shift_y;
+    uint32_t off = offsets[s];
+    for (int ty = y0; ty <= y1; ++ty)
+        for (int tx = x0; tx <= x1; ++tx, ++off)
+            if (off < cap) {
+                keys[off] = (uint32_t)(tbase + ty * tx_n + tx);
+                vals[off] = r;
+            }
+}
+
+// counters[0] = pairs needed, counters[1] = 1 if they exceed the capacity.
+__global__ void k_check_capacity(uint32_t* counters, uint32_t cap)
+{
+    counters[1] = counters[0] > cap ? 1u : 0u;
+}
+
+__global__ __launch_bounds__(256) void k_fill_u32(uint32_t* p, size_t n, uint32_t v)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ keys,
+                                               const uint32_t* __restrict__ counters, uint32_t cap,
+                                               uint2* __restrict__ ranges)
+{
+    uint32_t n = counters[0] < cap ? counters[0] : cap;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const uint32_t t = keys[i];
+        if (i == 0 || keys[i - 1] != t) ranges[t].x = i;
+        if (i + 1 == n || keys[i + 1] != t) ranges[t].y = i + 1;
+    }
+}
+
+// ------------------------------------------------------------- raster fwd
+
+constexpr int kChunk = 256;
+
+template <int DQ>
+struct TileStage {
+    float4 r0[kChunk];
+    float4 r1[kChunk];
+    uint2 fp[kChunk];
+    uint32_t rec[kChunk];
+    float q[kChunk * DQ];
+};
+
+template <int DQ>
+__device__ inline void stage_chunk(TileStage<DQ>& st, int k, uint32_t end, int base_tile_c,
+                                   int N, const uint32_t* __restrict__ tile_recs,
+                                   const float4* __restrict__ rec0,
+                                   const float4* __restrict__ rec1,
+                                   const uint2* __restrict__ foot,
+                                   const float* __restrict__ queries)
+{
+    const int t = threadIdx.x;
+    if ((uint32_t)k < end) {
+        const uint32_t r = tile_recs[k];
+        st.r0[t] = rec0[r];
+        st.r1[t] = rec1[r];
+        st.fp[t] = foot[r];
+        st.rec[t] = r;
+        const uint32_t g = r - (uint32_t)base_tile_c * (uint32_t)N;
+        const float4* qs = reinterpret_cast<const float4*>(queries + (size_t)g * DQ);
+        float4* qd = reinterpret_cast<float4*>(st.q + t * DQ);
+#pragma unroll
+        for (int j = 0; j < DQ / 4; ++j) qd[j] = qs[j];
+    }
+}
+
+template <int DQ>
+__global__ __launch_bounds__(256) void k_raster_fwd(
+    CamSet cs, int N, const uint2* __restrict__ ranges, const uint32_t* __restrict__ tile_recs,
+    const float4* __restrict__ rec0, const float4* __restrict__ rec1,
+    const uint2* __restrict__ foot, const float* __restrict__ queries, float* __restrict__ Q,
+    float* __restrict__ T_final, float* __restrict__ T_save, uint32_t* __restrict__ n_contrib)
+{
+    __shared__ TileStage<DQ> st;
+    const int tile = blockIdx.x;
+    const int c = cam_of_tile(cs, tile);
+    const Cam& cam = cs.c[c];
+    const int lt = tile - cam.tile_base;
+    const int tyi = lt / cam.tiles_x, txi = lt - tyi * cam.tiles_x;
+    const int px = (txi << cs.tile_shift_x) + (threadIdx.x & (cs.tile_w - 1));
+    const int py = (tyi << cs.tile_shift_y) + (threadIdx.x >> cs.tile_shift_x);
+    const bool inside = px < cam.w && py < cam.h;
+    const uint2 rg = ranges[tile];
+
+    float acc[DQ];
+#pragma unroll
+    for (int j = 0; j < DQ; ++j) acc[j] = 0.0f;
+    float T = 1.0f;
+    uint32_t last = 0;
+    bool done = !inside;
+    const float fpx = (float)px, fpy = (float)py;
+
+    for (uint32_t base = rg.x; base < rg.y; base += kChunk) {
+        if (__syncthreads_count(done) == (int)blockDim.x) break;
+        stage_chunk<DQ>(st, (int)(base + threadIdx.x), rg.y, c, N, tile_recs, rec0, rec1, foot,
+                        queries);
+        __syncthreads();
+        const int cnt = min((uint32_t)kChunk, rg.y - base);
+        for (int j = 0; j < cnt && !done; ++j) {
+            const uint2 f = st.fp[j];
+            if (px < (int)(f.x & 0xFFFF) || px > (int)(f.x >> 16) || py < (int)(f.y & 0xFFFF) ||
+                py > (int)(f.y >> 16))
+                continue;
+            const float4 a = st.r0[j];
+            const float4 b = st.r1[j];
+            const float dx = (a.x - fpx) + a.z;
+            const float dy = (a.y - fpy) + a.w;
+            const float power = -0.5f * (b.x * dx * dx + b.z * dy * dy) - b.y * dx * dy;
+            const float oG = b.w * __expf(power);
+            const float al = oG < kAlphaMax ? oG : kAlphaMax;
+            if (al < kAlphaMin) continue;
+            const float Tn = T * (1.0f - al);
+            if (Tn < kTStop) {
+                done = true;
+                break;
+            }
+            const float wgt = al * T;
+            const float* q = st.q + j * DQ;
+#pragma unroll
+            for (int k = 0; k < DQ; ++k) acc[k] += wgt * q[k];
+            T = Tn;
+            last = base - rg.x + j + 1;
+        }
+    }
+    if (inside) {
+        const size_t p = (size_t)cam.pix_base + (size_t)py * cam.w + px;
+        float4* qo = reinterpret_cast<float4*>(Q + p * DQ);
+#pragma unroll
+        for (int k = 0; k < DQ / 4; ++k)
+            qo[k] = make_float4(acc[4 * k], acc[4 * k + 1], acc[4 * k + 2], acc[4 * k + 3]);
+        T_final[p] = T;
+        T_save[p] = T;
+        n_contrib[p] = last;
+    }
+}
+
+// ------------------------------------------------------------- raster bwd
+
+// rec_grad[r] = (du, dv, dA, dB, dC, dopacity) accumulated over pixels.
+template <int DQ>
+__global__ __launch_bounds__(256) void k_raster_bwd(
+    CamSet cs, int N, const uint2* __restrict__ ranges, const uint32_t* __restrict__ tile_recs,
+    const float4* __restrict__ rec0, const float4* __restrict__ rec1,
+    const uint2* __restrict__ foot, const float* __restrict__ queries,
+    const float* __restrict__ T_final, const uint32_t* __restrict__ n_contrib,
+    const float* __restrict__ dQ, float* __restrict__ rec_grad, float* __restrict__ d_queries)
+{
+    __shared__ TileStage<DQ> st;
+    __shared__ uint32_t s_max;
+    const int tile = blockIdx.x;
+    const int c = cam_of_tile(cs, tile);
+    const Cam& cam = cs.c[c];
+    const int lt = tile - cam.tile_base;
+    const int tyi = lt / cam.tiles_x, txi = lt - tyi * cam.tiles_x;
+    const int px = (txi << cs.tile_shift_x) + (threadIdx.x & (cs.tile_w - 1));
+    const int py = (tyi << cs.tile_shift_y) + (threadIdx.x >> cs.tile_shift_x);
+    const bool inside = px < cam.w && py < cam.h;
+    const uint2 rg = ranges[tile];
+    const unsigned lane = __lane_id();
+
+    float g[DQ], behind[DQ];
+    float T = 1.0f;
+    uint32_t last = 0;
+    if (inside) {
+        const size_t p = (size_t)cam.pix_base + (size_t)py * cam.w + px;
+        const float4* gi = reinterpret_cast<const float4*>(dQ + p * DQ);
+#pragma unroll
+        for (int k = 0; k < DQ / 4; ++k) {
+            const float4 v = gi[k];
+            g[4 * k] = v.x; g[4 * k + 1] = v.y; g[4 * k + 2] = v.z; g[4 * k + 3] = v.w;
+        }
+        T = T_final[p];
+        last = n_contrib[p];
+    } else {
+#pragma unroll
+        for (int k = 0; k < DQ; ++k) g[k] = 0.0f;
+    }
+#pragma unroll
+    for (int k = 0; k < DQ; ++k) behind[k] = 0.0f;
+    if (threadIdx.x == 0) s_max = 0;
+    __syncthreads();
+    atomicMax(&s_max, last);
+    __syncthreads();
+    const uint32_t maxlast = s_max;
+    const float fpx = (float)px, fpy = (float)py;
+
+    for (int end = (int)maxlast; end > 0; end -= kChunk) {
+        const int start = end > kChunk ? end - kChunk : 0;
+        __syncthreads();
+        stage_chunk<DQ>(st, (int)(rg.x + start + threadIdx.x), rg.x + end, c, N, tile_recs, rec0,
+                        rec1, foot, queries);
+        __syncthreads();
+        for (int j = end - 1; j >= start; --j) {
+            const int sj = j - start;
+            float gu = 0.f, gv = 0.f, gA = 0.f, gB = 0.f, gC = 0.f, gO = 0.f, wq = 0.f;
+            bool hit = false;
+            if ((uint32_t)j < last) {
+                const uint2 f = st.fp[sj];
+                if (px >= (int)(f.x & 0xFFFF) && px <= (int)(f.x >> 16) &&
+                    py >= (int)(f.y & 0xFFFF) && py <= (int)(f.y >> 16)) {
+                    const float4 a = st.r0[sj];
+                    const float4 b = st.r1[sj];
+                    const float dx = (a.x - fpx) + a.z;
+                    const float dy = (a.y - fpy) + a.w;
+                    const float power = -0.5f * (b.x * dx * dx + b.z * dy * dy) - b.y * dx * dy;
+                    const float G = __expf(power);
+                    const float oG = b.w * G;
+                    const float al = oG < kAlphaMax ? oG : kAlphaMax;
+                    if (al >= kAlphaMin) {
+                        hit = true;
+                        T = T / (1.0f - al);
+                        wq = al * T;
+                        const float* q = st.q + sj * DQ;
+                        float dal = 0.0f;
+#pragma unroll
+                        for (int k = 0; k < DQ; ++k) {
+                            dal += (q[k] - behind[k]) * g[k];
+                            behind[k] = al * q[k] + (1.0f - al) * behind[k];
+                        }
+                        dal *= T;
+                        if (oG < kAlphaMax) {
+                            const float dp = dal * oG;
+                            gu = -dp * (b.x * dx + b.y * dy);
+                            gv = -dp * (b.z * dy + b.y * dx);
+                            gA = -0.5f * dp * dx * dx;
+                            gB = -dp * dx * dy;
+                            gC = -0.5f * dp * dy * dy;
+                            gO = dal * G;
+                        }
+                    }
+                }
+            }
+            if (__ballot(hit) == 0ull) continue;
+            const uint32_t r = st.rec[sj];
+            const float s0 = wave_sum_to_last(gu), s1 = wave_sum_to_last(gv);
+            const float s2 = wave_sum_to_last(gA), s3 = wave_sum_to_last(gB);
+            const float s4 = wave_sum_to_last(gC), s5 = wave_sum_to_last(gO);
+            float sq[DQ];
+#pragma unroll
+            for (int k = 0; k < DQ; ++k) sq[k] = wave_sum_to_last(wq * g[k]);
+            if (lane == kWave - 1) {
+                float* rgp = rec_grad + (size_t)r * 6;
+                unsafeAtomicAdd(rgp + 0, s0);
+                unsafeAtomicAdd(rgp + 1, s1);
+                unsafeAtomicAdd(rgp + 2, s2);
+                unsafeAtomicAdd(rgp + 3, s3);
+                unsafeAtomicAdd(rgp + 4, s4);
+                unsafeAtomicAdd(rgp + 5, s5);
+                float* dq = d_queries + (size_t)(r - (uint32_t)c * (uint32_t)N) * DQ;
+#pragma unroll
+                for (int k = 0; k < DQ; ++k) unsafeAtomicAdd(dq + k, sq[k]);
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------ preprocess adjoint
+
+// Chains rec_grad of every camera back to the raw parameters of Gaussian i
+// (FP32, matrix form of the chain rule).  Outputs are overwritten.
+__global__ __launch_bounds__(256) void k_preprocess_bwd(
+    CamSet cs, int N, const float* __restrict__ means, const float* __restrict__ log_scales,
+    const float* __restrict__ quats, const float* __restrict__ logits,
+    const uint32_t* __restrict__ ntiles, const float* __restrict__ rec_grad,
+    float* __restrict__ d_means, float* __restrict__ d_log_scales, float* __restrict__ d_quats,
+    float* __restrict__ d_logits)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const float m0 = means[3 * i], m1 = means[3 * i + 1], m2 = means[3 * i + 2];
+    float s[3];
+    for (int k = 0; k < 3; ++k) s[k] = __expf(log_scales[3 * i + k]);
+    const float q0 = quats[4 * i], q1 = quats[4 * i + 1], q2 = quats[4 * i + 2], q3 = quats[4 * i + 3];
+    const float qnorm = sqrtf(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
+    const float iq = 1.0f / qnorm;
+    const float w = q0 * iq, x = q1 * iq, y = q2 * iq, z = q3 * iq;
+    float Rm[3][3] = {{1.f - 2.f * (y * y + z * z), 2.f * (x * y - w * z), 2.f * (x * z + w * y)},
+                      {2.f * (x * y + w * z), 1.f - 2.f * (x * x + z * z), 2.f * (y * z - w * x)},
+                      {2.f * (x * z - w * y), 2.f * (y * z + w * x), 1.f - 2.f * (x * x + y * y)}};
+    float Mm[3][3];  // M = R diag(s)
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) Mm[a][b] = Rm[a][b] * s[b];
+    float S3[3][3];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b)
+            S3[a][b] = Mm[a][0] * Mm[b][0] + Mm[a][1] * Mm[b][1] + Mm[a][2] * Mm[b][2];
+    const float sig = 1.0f / (1.0f + __expf(-logits[i]));
+
+    float gmean[3] = {0.f, 0.f, 0.f}, gS3[3][3] = {{0.f}}, glogit = 0.f;
+    for (int ci = 0; ci < cs.n; ++ci) {
+        const size_t r = (size_t)ci * N + i;
+        if (ntiles[r] == 0) continue;
+        const Cam& cam = cs.c[ci];
+        const float* gr = rec_grad + r * 6;
+        const float du = gr[0], dv = gr[1], dA = gr[2], dB = gr[3], dC = gr[4], dO = gr[5];
+        glogit += dO * sig * (1.0f - sig);
+        float W[3][3];
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) W[a][b] = cam.vm[4 * a + b];
+        const float cx = W[0][0] * m0 + W[0][1] * m1 + W[0][2] * m2 + cam.vm[3];
+        const float cy = W[1][0] * m0 + W[1][1] * m1 + W[1][2] * m2 + cam.vm[7];
+        const float cz = W[2][0] * m0 + W[2][1] * m1 + W[2][2] * m2 + cam.vm[11];
+        const float limx = (float)kFovClamp * (cam.w / (2.0f * cam.fx));
+        const float limy = (float)kFovClamp * (cam.h / (2.0f * cam.fy));
+        const float rx = cx / cz, ry = cy / cz;
+        const bool inx = rx >= -limx && rx <= limx, iny = ry >= -limy && ry <= limy;
+        const float tx = inx ? rx : (rx < 0.f ? -limx : limx);
+        const float ty = iny ? ry : (ry < 0.f ? -limy : limy);
+        const float iz = 1.0f / cz;
+        const float J[2][3] = {{cam.fx * iz, 0.f, -cam.fx * tx * iz}, {0.f, cam.fy * iz, -cam.fy * ty * iz}};
+        // camera covariance Sc = W S3 W^T
+        float WS[3][3], Sc[3][3];
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) WS[a][b] = W[a][0] * S3[0][b] + W[a][1] * S3[1][b] + W[a][2] * S3[2][b];
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) Sc[a][b] = WS[a][0] * W[b][0] + WS[a][1] * W[b][1] + WS[a][2] * W[b][2];
+        // screen covariance and its inverse (the conic)
+        float JS[2][3];
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 3; ++b) JS[a][b] = J[a][0] * Sc[0][b] + J[a][1] * Sc[1][b] + J[a][2] * Sc[2][b];
+        const float sa = JS[0][0] * J[0][0] + JS[0][1] * J[0][1] + JS[0][2] * J[0][2] + (float)kDilation;
+        const float sb = JS[0][0] * J[1][0] + JS[0][1] * J[1][1] + JS[0][2] * J[1][2];
+        const float sc = JS[1][0] * J[1][0] + JS[1][1] * J[1][1] + JS[1][2] * J[1][2] + (float)kDilation;
+        const float idet = 1.0f / (sa * sc - sb * sb);
+        const float Ci[2][2] = {{sc * idet, -sb * idet}, {-sb * idet, sa * idet}};
+        // gradient w.r.t. the conic matrix (off-diagonal shared), then -Ci G Ci
+        const float Gc[2][2] = {{dA, 0.5f * dB}, {0.5f * dB, dC}};
+        float T1[2][2], G2[2][2];
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b) T1[a][b] = Ci[a][0] * Gc[0][b] + Ci[a][1] * Gc[1][b];
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b) G2[a][b] = -(T1[a][0] * Ci[0][b] + T1[a][1] * Ci[1][b]);
+        // Sigma2 = J Sc J^T: G_Sc = J^T G2 J ; G_J = 2 G2 J Sc
+        float GJ[2][3];
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 3; ++b)
+                GJ[a][b] = 2.0f * (G2[a][0] * JS[0][b] + G2[a][1] * JS[1][b]);
+        float GSc[3][3];
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b)
+                GSc[a][b] = J[0][a] * (G2[0][0] * J[0][b] + G2[0][1] * J[1][b]) +
+                            J[1][a] * (G2[1][0] * J[0][b] + G2[1][1] * J[1][b]);
+        // Sc = W S3 W^T: G_S3 += W^T G_Sc W
+        float GW[3][3];
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) GW[a][b] = GSc[a][0] * W[0][b] + GSc[a][1] * W[1][b] + GSc[a][2] * W[2][b];
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) gS3[a][b] += W[0][a] * GW[0][b] + W[1][a] * GW[1][b] + W[2][a] * GW[2][b];
+        // camera-space centre through J and through (u, v)
+        float gx = du * cam.fx * iz, gy = dv * cam.fy * iz;
+        float gz = -(du * cam.fx * cx + dv * cam.fy * cy) * iz * iz;
+        gz += -(GJ[0][0] * cam.fx + GJ[1][1] * cam.fy) * iz * iz;
+        // J02 = -fx tx / z, tx = x / z when not clamped
+        gz += (GJ[0][2] * cam.fx * tx + GJ[1][2] * cam.fy * ty) * iz * iz;
+        if (inx) { gx += -GJ[0][2] * cam.fx * iz * iz; gz += GJ[0][2] * cam.fx * cx * iz * iz * iz; }
+        if (iny) { gy += -GJ[1][2] * cam.fy * iz * iz; gz += GJ[1][2] * cam.fy * cy * iz * iz * iz; }
+        for (int k = 0; k < 3; ++k) gmean[k] += W[0][k] * gx + W[1][k] * gy + W[2][k] * gz;
+    }
+    // S3 = M M^T: G_M = 2 G_S3 M ; M = R diag(s)
+    float GM[3][3];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) GM[a][b] = 2.0f * (gS3[a][0] * Mm[0][b] + gS3[a][1] * Mm[1][b] + gS3[a][2] * Mm[2][b]);
+    float GR[3][3];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) GR[a][b] = GM[a][b] * s[b];
+    for (int k = 0; k < 3; ++k)
+        d_log_scales[3 * i + k] = (GM[0][k] * Rm[0][k] + GM[1][k] * Rm[1][k] + GM[2][k] * Rm[2][k]) * s[k];
+    // rotation entries as functions of the unit quaternion, grouped per component
+    const float gw = 2.f * (-z * GR[0][1] + y * GR[0][2] + z * GR[1][0] - x * GR[1][2] - y * GR[2][0] + x * GR[2][1]);
+    const float gxq = 2.f * (y * GR[0][1] + z * GR[0][2] + y * GR[1][0] - 2.f * x * GR[1][1] - w * GR[1][2] +
+                             z * GR[2][0] + w * GR[2][1] - 2.f * x * GR[2][2]);
+    const float gyq = 2.f * (-2.f * y * GR[0][0] + x * GR[0][1] + w * GR[0][2] + x * GR[1][0] + z * GR[1][2] -
+                             w * GR[2][0] + z * GR[2][1] - 2.f * y * GR[2][2]);
+    const float gzq = 2.f * (-2.f * z * GR[0][0] - w * GR[0][1] + x * GR[0][2] + w * GR[1][0] - 2.f * z * GR[1][1] +
+                             y * GR[1][2] + x * GR[2][0] + y * GR[2][1]);
+    const float dot = gw * w + gxq * x + gyq * y + gzq * z;
+    d_quats[4 * i + 0] = (gw - w * dot) * iq;
+    d_quats[4 * i + 1] = (gxq - x * dot) * iq;
+    d_quats[4 * i + 2] = (gyq - y * dot) * iq;
+    d_quats[4 * i + 3] = (gzq - z * dot) * iq;
+    for (int k = 0; k < 3; ++k) d_means[3 * i + k] = gmean[k];
+    d_logits[i] = glogit;
+}
+
+// ------------------------------------------------------------- launchers
+
+hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t st)
+{
+    if (n == 0) return hipSuccess;
+    size_t blocks = (n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t render_forward_launch(const RenderArgs& A, const RenderLayout& L, hipStream_t st)
+{
+    const CamSet& cs = L.cams;
+    const uint32_t R = (uint32_t)L.records;
+    const uint32_t cap = (uint32_t)L.capacity;
+    hipError_t e;
+    if (A.n > 0) {
+        ProfScope ps("preprocess", st);
+        hipLaunchKernelGGL(k_preprocess, dim3((A.n + 255) / 256, cs.n), dim3(256), 0, st, cs, A.n,
+                           A.means, A.log_scales, A.quats, A.logits, L.rec0, L.rec1, L.foot,
+                           L.depth_key, L.ntiles);
+    }
+    bool in_b = false;
+    const uint32_t* tkeys;
+    const uint32_t* trecs;
+    {
+        ProfScope ps("render_sort", st);
+        e = launch_radix_sort(L.depth_key, L.depth_a, L.recs_a, L.depth_b, L.recs_b, true, nullptr,
+                              R, 32, L.sort_scratch, &in_b, st);
+        if (e != hipSuccess) return e;
+        const uint32_t* sorted_rec = in_b ? L.recs_b : L.recs_a;
+        e = launch_excl_scan(L.ntiles, sorted_rec, R, L.offsets, L.counters, L.sort_scratch, st);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_check_capacity, dim3(1), dim3(1), 0, st, L.counters, cap);
+        if (R > 0)
+            hipLaunchKernelGGL(k_emit, dim3((R + 255) / 256), dim3(256), 0, st, cs, A.n, R,
+                               sorted_rec, (const uint32_t*)L.offsets, (const uint32_t*)L.ntiles,
+                               (const uint2*)L.foot, cap, L.ikeys_a, L.ivals_a);
+        e = launch_radix_sort(nullptr, L.ikeys_a, L.ivals_a, L.ikeys_b, L.ivals_b, false,
+                              L.counters, cap, L.tile_bits, L.sort_scratch, &in_b, st);
+        if (e != hipSuccess) return e;
+        tkeys = in_b ? L.ikeys_b : L.ikeys_a;
+        trecs = in_b ? L.ivals_b : L.ivals_a;
+        e = launch_fill_u32(reinterpret_cast<uint32_t*>(L.ranges), 2 * (size_t)cs.total_tiles, 0u,
+                            st);
+        if (e != hipSuccess) return e;
+        if (cap > 0)
+            hipLaunchKernelGGL(k_ranges, dim3(std::min<uint32_t>((cap + 255) / 256, 8192u)),
+                               dim3(256), 0, st, tkeys, (const uint32_t*)L.counters, cap, L.ranges);
+    }
+    if (cs.total_tiles > 0) {
+        ProfScope ps("raster_fwd", st);
+        auto kern = A.d == 16 ? k_raster_fwd<16> : k_raster_fwd<32>;
+        hipLaunchKernelGGL(kern, dim3(cs.total_tiles), dim3(cs.tile_w * cs.tile_h), 0, st, cs, A.n,
+                           (const uint2*)L.ranges, trecs, (const float4*)L.rec0,
+                           (const float4*)L.rec1, (const uint2*)L.foot, A.queries, A.Q, A.T_final,
+                           L.t_final, L.n_contrib);
+    }
+    return hipGetLastError();
+}
+
+hipError_t render_backward_launch(const RenderArgs& A, const RenderLayout& L, hipStream_t st)
+{
+    const CamSet& cs = L.cams;
+    hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(L.rec_grad), (size_t)L.records * 6,
+                                   0u, st);
+    if (e != hipSuccess) return e;
+    e = launch_fill_u32(reinterpret_cast<uint32_t*>(A.d_queries), (size_t)A.n * A.d, 0u, st);
+    if (e != hipSuccess) return e;
+    const uint32_t* trecs = L.tile_in_b ? L.ivals_b : L.ivals_a;
+    if (cs.total_tiles > 0) {
+        ProfScope ps("raster_bwd", st);
+        auto kern = A.d == 16 ? k_raster_bwd<16> : k_raster_bwd<32>;
+        hipLaunchKernelGGL(kern, dim3(cs.total_tiles), dim3(cs.tile_w * cs.tile_h), 0, st, cs, A.n,
+                           (const uint2*)L.ranges, trecs, (const float4*)L.rec0,
+                           (const float4*)L.rec1, (const uint2*)L.foot, A.queries,
+                           (const float*)L.t_final, (const uint32_t*)L.n_contrib, A.dQ, L.rec_grad,
+                           A.d_queries);
+    }
+    if (A.n > 0) {
+        ProfScope ps("preprocess_bwd", st);
+        hipLaunchKernelGGL(k_preprocess_bwd, dim3((A.n + 255) / 256), dim3(256), 0, st, cs, A.n,
+                           A.means, A.log_scales, A.quats, A.logits, (const uint32_t*)L.ntiles,
+                           (const float*)L.rec_grad, A.d_means, A.d_log_scales, A.d_quats,
+                           A.d_logits);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace lam

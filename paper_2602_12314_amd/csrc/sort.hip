@@ -1,0 +1,266 @@
+// Device-wide exclusive scan and stable LSD radix sort (u32 keys, u32 values)
+// for gfx950.  Both operate on tiles of 4096 items per 256-thread workgroup.
+//
+// The radix sort ranks the 8-bit digits of a 64-item wave step with eight
+// ballots (lanes sharing a digit form a mask), so equal digits keep their
+// input order: wave w of a workgroup owns a contiguous 1024-item span, steps
+// through it 64 items at a time, and keeps per-digit running counts in LDS.
+// Workgroup-level and device-level digit offsets then come from a
+// digit-major histogram scan, which is what makes every pass stable.
+#include "common.h"
+#include "kernels.h"
+
+namespace lam {
+
+constexpr int kTileThreads = 256;
+constexpr int kTileItems = 16;
+constexpr int kTile = kTileThreads * kTileItems;  // 4096
+
+__device__ inline uint32_t load_count(const uint32_t* n_dev, uint32_t n_cap)
+{
+    if (!n_dev) return n_cap;
+    uint32_t n = *n_dev;
+    return n < n_cap ? n : n_cap;
+}
+
+// Inclusive wave scan (u32) with 64-lane shuffles.
+__device__ inline uint32_t wave_incl_scan(uint32_t v)
+{
+    unsigned lane = __lane_id();
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        uint32_t t = __shfl_up(v, o, kWave);
+        if (lane >= (unsigned)o) v += t;
+    }
+    return v;
+}
+
+// Exclusive scan of one value per thread across a 256-thread block; returns
+// the block total through *total.  ``sh`` holds 4 words.
+__device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t* total, uint32_t* sh)
+{
+    unsigned lane = __lane_id(), w = threadIdx.x / kWave;
+    uint32_t inc = wave_incl_scan(v);
+    if (lane == kWave - 1) sh[w] = inc;
+    __syncthreads();
+    uint32_t wo = 0, tot = 0;
+#pragma unroll
+    for (int k = 0; k < kTileThreads / kWave; ++k) {
+        uint32_t s = sh[k];
+        if (k < (int)w) wo += s;
+        tot += s;
+    }
+    __syncthreads();
+    *total = tot;
+    return wo + inc - v;
+}
+
+__device__ inline uint32_t scan_value(const uint32_t* in, const uint32_t* idx, uint32_t i)
+{
+    return idx ? in[idx[i]] : in[i];
+}
+
+__global__ __launch_bounds__(kTileThreads) void k_scan_reduce(const uint32_t* __restrict__ in,
+                                                              const uint32_t* __restrict__ idx,
+                                                              uint32_t n, uint32_t* block_sums)
+{
+    __shared__ uint32_t sh[4];
+    uint32_t base = blockIdx.x * (uint32_t)kTile, s = 0;
+    for (int k = 0; k < kTileItems; ++k) {
+        uint32_t i = base + k * kTileThreads + threadIdx.x;
+        if (i < n) s += scan_value(in, idx, i);
+    }
+    uint32_t tot;
+    block_excl_scan(s, &tot, sh);
+    if (threadIdx.x == 0) block_sums[blockIdx.x] = tot;
+}
+
+// Single workgroup: exclusive scan of the block sums in place; the grand total
+// goes to *total (may be NULL).
+__global__ __launch_bounds__(kTileThreads) void k_scan_top(uint32_t* sums, uint32_t nb, uint32_t* total)
+{
+    __shared__ uint32_t sh[4];
+    uint32_t carry = 0;
+    for (uint32_t base = 0; base < nb; base += kTile) {
+        uint32_t v[kTileItems];
+        uint32_t s = 0;
+        for (int k = 0; k < kTileItems; ++k) {
+            uint32_t i = base + threadIdx.x * kTileItems + k;
+            v[k] = i < nb ? sums[i] : 0u;
+            s += v[k];
+        }
+        uint32_t tot;
+        uint32_t off = block_excl_scan(s, &tot, sh) + carry;
+        for (int k = 0; k < kTileItems; ++k) {
+            uint32_t i = base + threadIdx.x * kTileItems + k;
+            if (i < nb) sums[i] = off;
+            off += v[k];
+        }
+        carry += tot;
+    }
+    if (total && threadIdx.x == 0) *total = carry;
+}
+
+__global__ __launch_bounds__(kTileThreads) void k_scan_down(const uint32_t* __restrict__ in,
+                                                            const uint32_t* __restrict__ idx,
+                                                            uint32_t n,
+                                                            const uint32_t* __restrict__ block_off,
+                                                            uint32_t* __restrict__ out)
+{
+    __shared__ uint32_t sh[4];
+    uint32_t base = blockIdx.x * (uint32_t)kTile + threadIdx.x * kTileItems;
+    uint32_t v[kTileItems], s = 0;
+    for (int k = 0; k < kTileItems; ++k) {
+        uint32_t i = base + k;
+        v[k] = i < n ? scan_value(in, idx, i) : 0u;
+        s += v[k];
+    }
+    uint32_t tot;
+    uint32_t off = block_excl_scan(s, &tot, sh) + block_off[blockIdx.x];
+    for (int k = 0; k < kTileItems; ++k) {
+        uint32_t i = base + k;
+        if (i < n) out[i] = off;
+        off += v[k];
+    }
+}
+
+size_t scan_scratch_words(uint32_t n) { return (n + kTile - 1) / kTile + 1; }
+
+hipError_t launch_excl_scan(const uint32_t* in, const uint32_t* idx, uint32_t n, uint32_t* out,
+                            uint32_t* total, uint32_t* scratch, hipStream_t st)
+{
+    uint32_t nb = (n + kTile - 1) / kTile;
+    if (nb == 0) {
+        // empty input: the total is zero
+        if (total) hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kTileThreads), 0, st, scratch, 0u, total);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kTileThreads), 0, st, in, idx, n, scratch);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kTileThreads), 0, st, scratch, nb, total);
+    hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(kTileThreads), 0, st, in, idx, n,
+                       (const uint32_t*)scratch, out);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ radix
+
+__global__ __launch_bounds__(kTileThreads) void k_radix_hist(const uint32_t* __restrict__ keys,
+                                                             const uint32_t* __restrict__ n_dev,
+                                                             uint32_t n_cap, int shift,
+                                                             uint32_t* __restrict__ hist,
+                                                             uint32_t nblocks)
+{
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    uint32_t n = load_count(n_dev, n_cap);
+    uint32_t base = blockIdx.x * (uint32_t)kTile;
+    for (int k = 0; k < kTileItems; ++k) {
+        uint32_t i = base + k * kTileThreads + threadIdx.x;
+        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    hist[threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+}
+
+__global__ __launch_bounds__(kTileThreads) void k_radix_scatter(
+    const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
+    uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
+    const uint32_t* __restrict__ n_dev, uint32_t n_cap, int shift,
+    const uint32_t* __restrict__ offsets, uint32_t nblocks)
+{
+    __shared__ uint32_t cnt[kTileThreads / kWave][256];
+    __shared__ uint32_t gbase[256];
+    const unsigned lane = __lane_id(), w = threadIdx.x / kWave;
+    for (int k = threadIdx.x; k < 4 * 256; k += kTileThreads) (&cnt[0][0])[k] = 0;
+    gbase[threadIdx.x] = offsets[threadIdx.x * nblocks + blockIdx.x];
+    __syncthreads();
+
+    const uint32_t n = load_count(n_dev, n_cap);
+    const uint32_t span = blockIdx.x * (uint32_t)kTile + w * (kWave * kTileItems);
+    const unsigned long long lt = (1ull << lane) - 1ull;
+    uint32_t key[kTileItems], val[kTileItems], rank[kTileItems];
+#pragma unroll
+    for (int s = 0; s < kTileItems; ++s) {
+        uint32_t i = span + s * kWave + lane;
+        bool ok = i < n;
+        key[s] = ok ? keys_in[i] : 0u;
+        val[s] = ok ? (vals_in ? vals_in[i] : i) : 0u;
+        uint32_t dg = (key[s] >> shift) & 255u;
+        unsigned long long peers = __ballot(ok);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            unsigned long long m = __ballot((dg >> b) & 1u);
+            peers &= ((dg >> b) & 1u) ? m : ~m;
+        }
+        uint32_t before = ok ? cnt[w][dg] : 0u;
+        rank[s] = before + (uint32_t)__popcll(peers & lt);
+        // the lowest lane of each digit group publishes the new running count
+        if (ok && (peers & lt) == 0ull) cnt[w][dg] = before + (uint32_t)__popcll(peers);
+        if (!ok) rank[s] = 0xFFFFFFFFu;
+    }
+    __syncthreads();
+    // exclusive prefix over waves per digit
+    {
+        uint32_t d = threadIdx.x, run = 0;
+#pragma unroll
+        for (int k = 0; k < kTileThreads / kWave; ++k) {
+            uint32_t c = cnt[k][d];
+            cnt[k][d] = run;
+            run += c;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < kTileItems; ++s) {
+        if (rank[s] == 0xFFFFFFFFu) continue;
+        uint32_t dg = (key[s] >> shift) & 255u;
+        uint32_t pos = gbase[dg] + cnt[w][dg] + rank[s];
+        keys_out[pos] = key[s];
+        vals_out[pos] = val[s];
+    }
+}
+
+size_t radix_scratch_words(uint32_t n_cap)
+{
+    uint32_t nb = (n_cap + kTile - 1) / kTile;
+    if (nb == 0) nb = 1;
+    size_t h = (size_t)256 * nb;
+    return h + scan_scratch_words((uint32_t)h) + 8;
+}
+
+// Sorts the ``bits`` low bits of the keys, 8 per pass, ping-ponging between
+// the A and B buffers; *in_b tells where the result ended.  keys_first, when
+// given, is the read-only input of the first pass (it is left intact).  With
+// iota_first the first pass takes value = input position instead of vals_a.
+hipError_t launch_radix_sort(const uint32_t* keys_first, uint32_t* keys_a, uint32_t* vals_a,
+                             uint32_t* keys_b, uint32_t* vals_b, bool iota_first,
+                             const uint32_t* n_dev, uint32_t n_cap, int bits, uint32_t* scratch,
+                             bool* in_b, hipStream_t st)
+{
+    uint32_t nb = (n_cap + kTile - 1) / kTile;
+    *in_b = false;
+    if (nb == 0) return hipSuccess;
+    uint32_t* hist = scratch;
+    uint32_t* sscr = scratch + (size_t)256 * nb;
+    uint32_t *ki = keys_a, *vi = vals_a, *ko = keys_b, *vo = vals_b;
+    int passes = (bits + 7) / 8;
+    if (passes < 1) passes = 1;
+    for (int p = 0; p < passes; ++p) {
+        int shift = 8 * p;
+        const uint32_t* kin = (p == 0 && keys_first) ? keys_first : ki;
+        hipLaunchKernelGGL(k_radix_hist, dim3(nb), dim3(kTileThreads), 0, st, kin, n_dev, n_cap,
+                           shift, hist, nb);
+        hipError_t e = launch_excl_scan(hist, nullptr, 256u * nb, hist, nullptr, sscr, st);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_radix_scatter, dim3(nb), dim3(kTileThreads), 0, st, kin,
+                           (p == 0 && iota_first) ? (const uint32_t*)nullptr : vi, ko, vo, n_dev,
+                           n_cap, shift, hist, nb);
+        uint32_t* t = ki; ki = ko; ko = t;
+        t = vi; vi = vo; vo = t;
+        *in_b = !*in_b;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace lam

@@ -1,0 +1,200 @@
+"""torch.autograd wrappers around the C ABI (memory, streams, autograd only).
+
+- ``Renderer`` owns the render workspace for one camera set and tile shape and
+  sizes its (Gaussian, tile) pair capacity from the library's own counters.
+- ``RenderQueries.apply(renderer, means, log_scales, quats, opacity_logits,
+  queries) -> (Q, T_final)``: Eq. 4, differentiable in the five inputs.
+- ``DecodeLoss.apply(Q, K, V, K0, target, lambda_tr, precision, decoder) -> loss``:
+  Eq. 5-6; the library computes the loss and its gradients in one call.
+- ``Decode.apply(Q, K, V, precision, decoder) -> F``: Eq. 5 alone.
+Every step runs in the HIP library; nothing here computes the method.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib
+
+
+@dataclass
+class Gaussians:
+    means: torch.Tensor           # [N,3]
+    log_scales: torch.Tensor      # [N,3]
+    quats: torch.Tensor           # [N,4] (w, x, y, z)
+    opacity_logits: torch.Tensor  # [N]
+    queries: torch.Tensor         # [N,d]
+
+    @classmethod
+    def from_numpy(cls, scene, device="cuda") -> "Gaussians":
+        f = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float32, device=device)
+        return cls(f(scene.means), f(scene.log_scales), f(scene.quats), f(scene.opacity_logits),
+                   f(scene.queries))
+
+    def zeros_like(self) -> "Gaussians":
+        return Gaussians(*[torch.zeros_like(t) for t in self.tensors()])
+
+    def tensors(self):
+        return (self.means, self.log_scales, self.quats, self.opacity_logits, self.queries)
+
+    @property
+    def n(self) -> int:
+        return self.means.shape[0]
+
+    @property
+    def d(self) -> int:
+        return self.queries.shape[1]
+
+
+def _contig(t):
+    t = t.detach()
+    assert t.dtype == torch.float32 and t.is_cuda, "expects float32 CUDA/HIP tensors"
+    return t.contiguous()
+
+
+class Renderer:
+    """Render workspace for a fixed camera set, Gaussian count and tile shape."""
+
+    def __init__(self, cams, n_gauss: int, d: int, tile=(16, 16), capacity: Optional[int] = None,
+                 device="cuda", headroom: float = 1.15):
+        self.cams = _lib._cams(cams)
+        self.n_gauss, self.d = int(n_gauss), int(d)
+        self.tile_w, self.tile_h = int(tile[0]), int(tile[1])
+        self.device = torch.device(device)
+        self.headroom = headroom
+        w = self.cams[:, 0].astype(np.int64)
+        h = self.cams[:, 1].astype(np.int64)
+        self.n_pixels = int((w * h).sum())
+        self.capacity = 0
+        self.ws = None
+        self._alloc(capacity if capacity is not None else 0)
+
+    def _alloc(self, capacity: int):
+        nbytes = _lib.render_workspace_size(self.n_gauss, self.d, self.cams, self.tile_w, self.tile_h,
+                                            capacity)
+        self.ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
+        self.capacity = int(capacity)
+
+    def counters(self):
+        """BLOCKING: (pairs needed, overflowed) of the last forward."""
+        return _lib.render_counters(self.ws)
+
+    def forward(self, g: Gaussians, Q=None, T_final=None, check: bool = True):
+        if Q is None:
+            Q = torch.empty((self.n_pixels, self.d), dtype=torch.float32, device=self.device)
+        if T_final is None:
+            T_final = torch.empty((self.n_pixels,), dtype=torch.float32, device=self.device)
+        gg = Gaussians(*[_contig(t) for t in g.tensors()])
+        for _ in range(3):
+            _lib.render_forward(gg, self.cams, self.tile_w, self.tile_h, Q, T_final, self.ws,
+                                self.capacity)
+            if not check:
+                break
+            need, over = self.counters()
+            if not over:
+                break
+            self._alloc(int(need * self.headroom) + 4096)
+        return Q, T_final
+
+    def backward(self, g: Gaussians, dQ: torch.Tensor, out: Optional[Gaussians] = None) -> Gaussians:
+        gg = Gaussians(*[_contig(t) for t in g.tensors()])
+        if out is None:
+            out = gg.zeros_like()
+        _lib.render_backward(gg, self.cams, self.tile_w, self.tile_h, _contig(dQ), out, self.ws,
+                             self.capacity)
+        return out
+
+    def debug_views(self):
+        return _lib.render_debug_views(self.ws, self.n_gauss, self.d, self.cams, self.tile_w,
+                                       self.tile_h, self.capacity)
+
+
+class RenderQueries(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, renderer: Renderer, means, log_scales, quats, opacity_logits, queries):
+        g = Gaussians(means, log_scales, quats, opacity_logits, queries)
+        Q, T = renderer.forward(g)
+        ctx.renderer = renderer
+        ctx.save_for_backward(means, log_scales, quats, opacity_logits, queries)
+        ctx.mark_non_differentiable(T)
+        return Q, T
+
+    @staticmethod
+    def backward(ctx, dQ, dT):
+        g = Gaussians(*ctx.saved_tensors)
+        gr = ctx.renderer.backward(g, dQ)
+        return (None,) + gr.tensors()
+
+
+class Decoder:
+    """Decode workspace for fixed (precision, n, d, M, D)."""
+
+    def __init__(self, precision: str, n: int, d: int, M: int, D: int, device="cuda"):
+        self.precision = precision
+        self.shape = (int(n), int(d), int(M), int(D))
+        nbytes = _lib.decode_workspace_size(precision, n, d, M, D)
+        self.ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+        self.device = torch.device(device)
+
+    def loss_and_grads(self, Q, K, V, target, K0, lambda_tr, want_dQ=True, row_cos=None):
+        n, d, M, D = self.shape
+        dev = self.device
+        loss = torch.empty(1, dtype=torch.float32, device=dev)
+        dQ = torch.empty((n, d), dtype=torch.float32, device=dev) if want_dQ else None
+        dK = torch.empty((M, d), dtype=torch.float32, device=dev)
+        dV = torch.empty((M, D), dtype=torch.float32, device=dev)
+        _lib.decode_loss(self.precision, _contig(Q), _contig(K), _contig(V), _contig(target),
+                         None if K0 is None else _contig(K0), lambda_tr, loss, dQ, dK, dV, row_cos,
+                         self.ws)
+        return loss, dQ, dK, dV
+
+    def forward(self, Q, K, V, F=None):
+        n, d, M, D = self.shape
+        if F is None:
+            F = torch.empty((n, D), dtype=torch.float32, device=self.device)
+        _lib.decode_forward(self.precision, _contig(Q), _contig(K), _contig(V), F, self.ws)
+        return F
+
+    def backward(self, Q, K, V, dF, want_dQ=True):
+        n, d, M, D = self.shape
+        dQ = torch.empty((n, d), dtype=torch.float32, device=self.device) if want_dQ else None
+        dK = torch.empty((M, d), dtype=torch.float32, device=self.device)
+        dV = torch.empty((M, D), dtype=torch.float32, device=self.device)
+        _lib.decode_backward(self.precision, _contig(Q), _contig(K), _contig(V), _contig(dF), dQ, dK,
+                             dV, self.ws)
+        return dQ, dK, dV
+
+
+class DecodeLoss(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, Q, K, V, K0, target, lambda_tr: float, decoder: Decoder):
+        loss, dQ, dK, dV = decoder.loss_and_grads(Q, K, V, target, K0, lambda_tr,
+                                                  want_dQ=Q.requires_grad)
+        ctx.save_for_backward(*(t for t in (dQ, dK, dV) if t is not None))
+        ctx.has_dQ = dQ is not None
+        return loss[0]
+
+    @staticmethod
+    def backward(ctx, gl):
+        saved = list(ctx.saved_tensors)
+        dQ = saved.pop(0) if ctx.has_dQ else None
+        dK, dV = saved
+        s = gl
+        return (None if dQ is None else dQ * s, dK * s, dV * s, None, None, None, None)
+
+
+class Decode(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, Q, K, V, decoder: Decoder):
+        ctx.save_for_backward(Q, K, V)
+        ctx.decoder = decoder
+        return decoder.forward(Q, K, V)
+
+    @staticmethod
+    def backward(ctx, dF):
+        Q, K, V = ctx.saved_tensors
+        dQ, dK, dV = ctx.decoder.backward(Q, K, V, dF)
+        return dQ, dK, dV, None

@@ -1,0 +1,100 @@
+"""The C-ABI library loads, exports every entry point include/latentam.h
+declares, and rejects invalid arguments on the host before any GPU work
+(these calls never reach the HIP runtime, so they run without a GPU)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2602_12314_amd import _lib, scenes
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "latentam.h")
+
+
+def declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lam_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("liblatentam.so not built")
+    return _lib.lib()
+
+
+def test_exports_every_declared_symbol(L):
+    names = declared()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_status_strings_and_version(L):
+    assert L.lam_version() == 1
+    for code in (0, -1, -2, -3, -4):
+        assert _lib.status_string(code)
+
+
+def _ws_size(n, d, cams, tw=16, th=16, cap=1000):
+    out = C.c_uint64()
+    cams = np.ascontiguousarray(cams, np.float32)
+    st = _lib.lib().lam_render_workspace_size(n, d, cams.ctypes.data_as(C.c_void_p), cams.shape[0],
+                                              tw, th, cap, C.byref(out))
+    return st, out.value
+
+
+def test_render_workspace_validation(L):
+    cams = np.stack([scenes.pinhole(640, 480, 525.0).packed()])
+    st, nbytes = _ws_size(1000, 16, cams)
+    assert st == 0 and nbytes > 1000 * 80
+    assert _ws_size(1000, 8, cams)[0] == _lib.LAM_ERR_UNSUPPORTED          # d
+    assert _ws_size(1000, 16, cams, 16, 32)[0] == _lib.LAM_ERR_UNSUPPORTED  # 512-pixel tiles
+    assert _ws_size(1000, 16, cams, 12, 12)[0] == _lib.LAM_ERR_UNSUPPORTED  # not powers of two
+    assert _ws_size(-1, 16, cams)[0] == _lib.LAM_ERR_INVALID_ARG
+    bad = cams.copy()
+    bad[0, 0] = 0
+    assert _ws_size(10, 16, bad)[0] == _lib.LAM_ERR_INVALID_ARG
+    bad = cams.copy()
+    bad[0, 2] = np.nan
+    assert _ws_size(10, 16, bad)[0] == _lib.LAM_ERR_INVALID_ARG
+    many = np.repeat(cams, 17, axis=0)
+    assert _ws_size(10, 16, many)[0] == _lib.LAM_ERR_UNSUPPORTED
+    # workspace grows with the capacity, 16 bytes per pair (two key/value buffers)
+    a, b = _ws_size(1000, 16, cams, cap=0)[1], _ws_size(1000, 16, cams, cap=1 << 20)[1]
+    assert b - a >= 16 * (1 << 20)
+
+
+def test_render_forward_rejects_null_inputs(L):
+    cams = np.ascontiguousarray(np.stack([scenes.pinhole(64, 48, 50.0).packed()]), np.float32)
+    st = L.lam_render_forward(None, None, None, None, None, 10, 16, cams.ctypes.data_as(C.c_void_p), 1,
+                              16, 16, None, None, None, 0, 0, None)
+    assert st == _lib.LAM_ERR_INVALID_ARG
+
+
+def test_decode_workspace_validation(L):
+    ok = C.c_uint64()
+    assert L.lam_decode_workspace_size(1, 1000, 16, 256, 512, C.byref(ok)) == 0 and ok.value > 0
+    assert L.lam_decode_workspace_size(0, 1000, 16, 256, 512, C.byref(ok)) == 0
+    for args in [(1, 1000, 8, 256, 512), (1, 1000, 16, 0, 512), (1, 1000, 16, 256, 100),
+                 (1, 1000, 16, 256, 2048), (1, 1000, 16, 4096, 512), (7, 10, 16, 64, 128)]:
+        assert L.lam_decode_workspace_size(*args, C.byref(ok)) == _lib.LAM_ERR_UNSUPPORTED, args
+    assert L.lam_decode_workspace_size(1, -1, 16, 64, 128, C.byref(ok)) == _lib.LAM_ERR_INVALID_ARG
+    assert L.lam_decode_workspace_size(1, 10, 16, 64, 128, None) == _lib.LAM_ERR_INVALID_ARG
+
+
+def test_decode_rejects_small_workspace(L):
+    st = L.lam_decode_loss(1, C.c_void_p(16), 10, 16, C.c_void_p(16), C.c_void_p(16), 64, 128,
+                           C.c_void_p(16), C.c_void_p(16), C.c_float(0.1), C.c_void_p(16), None,
+                           C.c_void_p(16), C.c_void_p(16), None, C.c_void_p(16), 8, None)
+    assert st == _lib.LAM_ERR_INVALID_ARG
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(_lib, "_lib", None)
+    with pytest.raises(RuntimeError, match="not built"):
+        _lib.lib()

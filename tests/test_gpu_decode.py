@@ -1,0 +1,163 @@
+"""GPU parity of the dictionary decode and feature loss (Eq. 5-6) against the
+FP64 oracle, through the C ABI.
+
+Bars: FP32 path within 1e-4 relative per output tensor (F, loss, dQ, dK, dV);
+BF16 path: minimum per-pixel cosine of F >= 0.999 and relative gradient error
+<= 1e-2 per tensor.  Shapes cover ragged pixel counts (not a multiple of the
+32-pixel block), atom counts that need padding, both query widths and the
+full 640x480 workload.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import decode_oracle as DO  # noqa: E402
+from tests.gpu_helpers import rel_err, say, to_np  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+BARS = {"fp32": dict(grad=1e-4, cos=None, F=1e-4), "bf16": dict(grad=1e-2, cos=0.999, F=None),
+        "fp8": dict(grad=1e-2, cos=0.999, F=None)}
+
+
+def _inputs(seed, n, d, M, D, qscale=1.0):
+    rng = np.random.default_rng(seed)
+    Q = (qscale * rng.standard_normal((n, d))).astype(np.float32)
+    K = rng.standard_normal((M, d)).astype(np.float32)
+    V = rng.standard_normal((M, D)).astype(np.float32)
+    T = rng.standard_normal((n, D))
+    T = (T / np.linalg.norm(T, axis=1, keepdims=True)).astype(np.float32)
+    K0 = (K + 0.01 * rng.standard_normal(K.shape)).astype(np.float32)
+    return Q, K, V, T, K0
+
+
+def _cuda(*arrs):
+    return [torch.as_tensor(a, device="cuda") for a in arrs]
+
+
+def _decoder(prec, n, d, M, D):
+    from paper_2602_12314_amd import ops
+    return ops.Decoder(prec, n, d, M, D)
+
+
+def _min_cos(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return float(((a * b).sum(1) / (np.linalg.norm(a, axis=1) * np.linalg.norm(b, axis=1))).min())
+
+
+SHAPES = [(1000, 16, 64, 128), (777, 32, 100, 256), (4096, 16, 256, 512), (333, 32, 512, 768),
+          (200, 16, 1, 128), (96, 32, 1024, 1024)]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8"])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_forward_F(prec, shape):
+    n, d, M, D = shape
+    say(f"[decode F] {prec} n={n} d={d} M={M} D={D}")
+    Q, K, V, _, _ = _inputs(1, n, d, M, D)
+    dec = _decoder(prec, n, d, M, D)
+    F = to_np(dec.forward(*_cuda(Q, K, V)))
+    ref = DO.decode_forward(Q, K, V)[0]
+    if BARS[prec]["F"]:
+        e = rel_err(F, ref)
+        say(f"  rel err {e:.3e}")
+        assert e < BARS[prec]["F"]
+    else:
+        c = _min_cos(F, ref)
+        say(f"  min cos {c:.6f}")
+        assert c >= BARS[prec]["cos"]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8"])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_loss_and_grads(prec, shape):
+    n, d, M, D = shape
+    say(f"[decode loss] {prec} n={n} d={d} M={M} D={D}")
+    Q, K, V, T, K0 = _inputs(2, n, d, M, D)
+    dec = _decoder(prec, n, d, M, D)
+    row_cos = torch.empty(n, device="cuda")
+    loss, dQ, dK, dV = dec.loss_and_grads(*_cuda(Q, K, V, T, K0), 0.1, row_cos=row_cos)
+    ref = DO.loss_and_grads(Q, K, V, T, K0, 0.1)
+    bar = BARS[prec]["grad"]
+    el = abs(float(loss) - ref["loss"]) / abs(ref["loss"])
+    say(f"  loss {float(loss):.7f} ref {ref['loss']:.7f} rel {el:.2e}")
+    assert el < bar
+    assert np.abs(to_np(row_cos) - ref["cos"]).max() < (1e-5 if prec == "fp32" else 5e-3)
+    for name, t in (("dQ", dQ), ("dK", dK), ("dV", dV)):
+        e = rel_err(to_np(t), ref[name])
+        say(f"  {name} rel err {e:.3e}")
+        assert e < bar, name
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_backward_given_dF(prec):
+    n, d, M, D = 1500, 32, 192, 384
+    say(f"[decode adjoint] {prec}")
+    Q, K, V, _, _ = _inputs(3, n, d, M, D)
+    dF = np.random.default_rng(4).standard_normal((n, D)).astype(np.float32)
+    dec = _decoder(prec, n, d, M, D)
+    dQ, dK, dV = dec.backward(*_cuda(Q, K, V, dF))
+    rQ, rK, rV = DO.decode_backward(Q, K, V, dF)
+    bar = BARS[prec]["grad"]
+    for name, t, r in (("dQ", dQ, rQ), ("dK", dK, rK), ("dV", dV, rV)):
+        e = rel_err(to_np(t), r)
+        say(f"  {name} rel err {e:.3e}")
+        assert e < bar, name
+
+
+def test_one_hot_row_returns_value_row():
+    rng = np.random.default_rng(5)
+    d, M, D = 16, 64, 128
+    basis, _ = np.linalg.qr(rng.standard_normal((d, d)))
+    K = np.zeros((M, d), np.float32)
+    K[:d] = 3.0 * basis
+    K[d:] = -3.0 * basis[0]
+    V = rng.standard_normal((M, D)).astype(np.float32)
+    js = np.arange(d)
+    Q = (40.0 * K[js]).astype(np.float32)  # logit gap 40*9/4 = 90: exp(-90) is below float32 resolution
+    say("[decode one-hot] fp32")
+    F = to_np(_decoder("fp32", d, d, M, D).forward(*_cuda(Q, K, V)))
+    np.testing.assert_allclose(F, V[js], rtol=0, atol=1e-6 * np.abs(V).max())
+
+
+def test_empty_pixels_gives_trust_region_only():
+    d, M, D = 16, 64, 128
+    _, K, V, _, K0 = _inputs(6, 1, d, M, D)
+    say("[decode n=0]")
+    dec = _decoder("bf16", 0, d, M, D)
+    Q = torch.zeros((0, d), device="cuda")
+    T = torch.zeros((0, D), device="cuda")
+    loss, dQ, dK, dV = dec.loss_and_grads(Q, *_cuda(K, V), T, *_cuda(K0), 0.1)
+    np.testing.assert_allclose(float(loss), 0.1 * ((K.astype(np.float64) - K0) ** 2).sum(), rtol=1e-5)
+    np.testing.assert_allclose(to_np(dK), 0.2 * (K - K0), rtol=1e-5, atol=1e-7)
+    assert np.all(to_np(dV) == 0)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_full_640x480_workload(prec):
+    # The 640x480 workload's decode sizes (n=307200, d=16, M=256, D=512), with a
+    # Voronoi target; the oracle runs at full size.
+    from paper_2602_12314_amd import scenes
+    sp = scenes.spec(1)
+    s = scenes.make_scene(sp, seed=11)
+    rng = np.random.default_rng(12)
+    Q = rng.standard_normal((sp.n_pixels, sp.d)).astype(np.float32)
+    say(f"[decode full 640x480] {prec}")
+    dec = _decoder(prec, sp.n_pixels, sp.d, sp.M, sp.D)
+    loss, dQ, dK, dV = dec.loss_and_grads(*_cuda(Q, s.K, s.V, s.target, s.K0), sp.lambda_tr)
+    ref = DO.loss_and_grads(Q, s.K, s.V, s.target, s.K0, sp.lambda_tr)
+    bar = BARS[prec]["grad"]
+    assert abs(float(loss) - ref["loss"]) / ref["loss"] < bar
+    for name, t in (("dQ", dQ), ("dK", dK), ("dV", dV)):
+        e = rel_err(to_np(t), ref[name])
+        say(f"  {name} rel err {e:.3e}")
+        assert e < bar, name
+    F = to_np(dec.forward(*_cuda(Q, s.K, s.V)))
+    if prec == "fp32":
+        assert rel_err(F, ref["F"]) < 1e-4
+    else:
+        c = _min_cos(F, ref["F"])
+        say(f"  min cos {c:.6f}")
+        assert c >= 0.999
