@@ -80,6 +80,12 @@ def run(args):
     K0 = torch.as_tensor(s.K0, device=dev)
     tgt = torch.as_tensor(s.target, device=dev)
     n = spec.n_pixels
+    tune = None
+    if args.autotune:
+        from paper_2602_12314_amd import autotune
+        (tw, th), tune = autotune.best_tile(g, s.cams)
+        args.tile = f"{tw}x{th}"
+        _log(f"[bench] autotuned tile {args.tile}: {tune}")
     r = ops.Renderer(s.cams, spec.n_gauss, spec.d, tile=(tw, th))
     Q = torch.empty((n, spec.d), device=dev)
     T = torch.empty((n,), device=dev)
@@ -123,14 +129,49 @@ def run(args):
             L.lam_profile_enable(0)
         return (t1 - t0) / steps, float(loss), prof, need
 
+    def graph_timed(dec, steps, warmup):
+        holder = {}
+        base = make_step(dec)
+
+        def step():
+            holder["loss"] = base()
+
+        r.forward(g, Q, T, check=True)
+        s_ = torch.cuda.Stream()
+        s_.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s_):
+            for _ in range(max(1, warmup)):
+                step()
+        torch.cuda.current_stream().wait_stream(s_)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            step()
+        graph.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            graph.replay()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        assert not r.counters()[1]
+        return (t1 - t0) / steps, float(holder["loss"])
+
     dec = ops.Decoder(prec, n, spec.d, spec.M, spec.D, device=dev)
     _log(f"[bench] timing {args.steps} steps ({prec} decode)")
     sec, loss, prof, pairs = timed(dec, args.steps, args.warmup, profile=True)
-    dec32 = ops.Decoder("fp32", n, spec.d, spec.M, spec.D, device=dev)
-    fp32_steps = max(3, args.steps // 4)
-    _log(f"[bench] timing {fp32_steps} steps (fp32 decode)")
-    sec32, loss32, prof32, _ = timed(dec32, fp32_steps, 2, profile=True)
-    del dec32
+    eager_sec = sec
+    if args.graph:
+        _log(f"[bench] timing {args.steps} HIP-graph replays ({prec} decode)")
+        sec, loss = graph_timed(dec, args.steps, args.warmup)
+    if args.no_fp32 or prec == "fp32":
+        sec32, prof32 = (sec, prof) if prec == "fp32" else (None, {})
+    else:
+        dec32 = ops.Decoder("fp32", n, spec.d, spec.M, spec.D, device=dev)
+        fp32_steps = max(3, args.steps // 4)
+        _log(f"[bench] timing {fp32_steps} steps (fp32 decode)")
+        sec32, loss32, prof32, _ = timed(dec32, fp32_steps, 2, profile=True)
+        del dec32
 
     out = {
         "metric": "feature-pixels/s fwd+bwd",
@@ -151,10 +192,14 @@ def run(args):
                    "pixels": n, "d": spec.d, "M": spec.M, "D": spec.D, "decode_precision": prec,
                    "tile": args.tile, "tile_pairs": pairs},
         "stage_ms": {k: round(v, 4) for k, v in prof.items()},
+        "launch": "hip_graph_replay" if args.graph else "eager",
+        "eager_ms_per_step": eager_sec * 1e3,
+        "autotune_ms": tune,
         "loss": loss,
-        "fp32_decode_path": {"value": n / sec32, "ms_per_step": sec32 * 1e3,
-                             "stage_ms": {k: round(v, 4) for k, v in prof32.items()},
-                             "speedup_of_reduced_precision": sec32 / sec},
+        "fp32_decode_path": None if sec32 is None else {
+            "value": n / sec32, "ms_per_step": sec32 * 1e3,
+            "stage_ms": {k: round(v, 4) for k, v in prof32.items()},
+            "speedup_of_reduced_precision": sec32 / sec},
     }
 
     # roofline of the dominant kernel, with algorithmic work from the oracle's pair counts
@@ -249,7 +294,21 @@ def main():
     ap.add_argument("--precision", default=None, help="decode precision: fp32 | bf16 (default: workload's)")
     ap.add_argument("--tile", default="16x16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--autotune", action="store_true", help="pick the render tile shape by timing")
+    ap.add_argument("--graph", action="store_true", help="time replays of the HIP-graph-captured step")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 decode comparison leg")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES (scales HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        a = torch.empty(args.copy_calibration // 4, dtype=torch.float32, device="cuda").uniform_()
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_launch": a.numel() * 4, "launches": 5}), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
               "(the multi-GPU design is described in DESIGN.md)", file=sys.stderr)

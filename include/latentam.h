@@ -16,7 +16,9 @@
  *   to the caller.  The library performs no device allocation on these paths:
  *   scratch and the state the backward pass needs live in a caller-owned
  *   workspace whose size the *_workspace_size functions report.
- * - All arrays are float32, C-contiguous (row-major).
+ * - All arrays are float32, C-contiguous (row-major).  The row arrays read or
+ *   written with 16-byte vector accesses (queries, Q, dQ, target, F, dF) must
+ *   be 16-byte aligned; misaligned pointers give LAM_ERR_INVALID_ARG.
  * - ``stream`` is a hipStream_t (NULL = the null stream).  Calls only enqueue
  *   work on it and return; there is no host synchronisation except in the
  *   functions documented as blocking.  Nothing is allocated or freed, and no

@@ -122,6 +122,9 @@ lam_status render_layout(int n_gauss, int d, const float* cams, int n_cams, int 
 
 bool ptr_ok(const void* p, uint64_t count) { return count == 0 || p != nullptr; }
 
+// Buffers accessed with 16-byte vector loads and stores.
+bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
 }  // namespace
 
 extern "C" {
@@ -176,6 +179,7 @@ lam_status lam_render_forward(const float* means, const float* log_scales, const
     if (s != LAM_OK) return s;
     if (!ws || ws_bytes < L.bytes) return LAM_ERR_INVALID_ARG;
     if (!ptr_ok(Q, L.pixels) || !ptr_ok(T_final, L.pixels)) return LAM_ERR_INVALID_ARG;
+    if (!aligned16(Q) || !aligned16(queries)) return LAM_ERR_INVALID_ARG;
     RenderArgs A{};
     A.n = n_gauss;
     A.d = d;
@@ -208,6 +212,7 @@ lam_status lam_render_backward(const float* means, const float* log_scales, cons
     if (s != LAM_OK) return s;
     if (!ws || ws_bytes < L.bytes) return LAM_ERR_INVALID_ARG;
     if (!ptr_ok(dQ, L.pixels)) return LAM_ERR_INVALID_ARG;
+    if (!aligned16(dQ) || !aligned16(queries)) return LAM_ERR_INVALID_ARG;
     RenderArgs A{};
     A.n = n_gauss;
     A.d = d;

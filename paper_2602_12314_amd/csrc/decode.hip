@@ -122,7 +122,7 @@ __global__ __launch_bounds__(256) void k_dec_prep(const float* __restrict__ K, c
         const int a = (int)(i / D), c = (int)(i % D);
         const float v = a < M ? V[(size_t)a * D + c] : 0.0f;
         Vb[i] = P::cvt(v);
-        Vt[(size_t)c * Mp + a] = P::cvt(v);
+        if (Vt) Vt[(size_t)c * Mp + a] = P::cvt(v);
     }
     for (size_t i = tid; i < (size_t)Mp * d; i += stride) {
         const int a = (int)(i / d);
@@ -135,50 +135,44 @@ __global__ __launch_bounds__(256) void k_dec_prep(const float* __restrict__ K, c
     }
 }
 
-// FP8 dictionary copies.  Per-atom scales s = amax(row) / 448 map each row of
-// K and V onto the E4M3 range; sc = [s^K (Mp) | s^V (Mp) | max_j s^V_j bits].
-__global__ __launch_bounds__(256) void k_dec_scales(const float* __restrict__ K, const float* __restrict__ V,
-                                                    int M, int Mp, int d, int D, float* __restrict__ sc)
+// FP8 forward contraction F = P V.  Per-atom scales s^V = amax(V_j) / 448 map
+// each row of V onto the E4M3 range; sc = [unused (Mp) | s^V (Mp) | max_j s^V_j bits].
+// The logits keep BF16 K and the backward keeps the BF16 copies of the FP32
+// dictionary: FP8 logits or an FP8 backward cost far more accuracy than the
+// few flops they would save.
+__global__ __launch_bounds__(256) void k_dec_scales(const float* __restrict__ V, int M, int Mp, int D,
+                                                    float* __restrict__ sc)
 {
-    __shared__ float sk[256], sv[256];
+    __shared__ float sv[256];
     const int row = blockIdx.x;
-    float ak = 0.f, av = 0.f;
-    if (row < M) {
-        for (int j = threadIdx.x; j < d; j += 256) ak = fmaxf(ak, fabsf(K[(size_t)row * d + j]));
+    float av = 0.f;
+    if (row < M)
         for (int j = threadIdx.x; j < D; j += 256) av = fmaxf(av, fabsf(V[(size_t)row * D + j]));
-    }
-    sk[threadIdx.x] = ak;
     sv[threadIdx.x] = av;
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o) {
-            sk[threadIdx.x] = fmaxf(sk[threadIdx.x], sk[threadIdx.x + o]);
-            sv[threadIdx.x] = fmaxf(sv[threadIdx.x], sv[threadIdx.x + o]);
-        }
+        if ((int)threadIdx.x < o) sv[threadIdx.x] = fmaxf(sv[threadIdx.x], sv[threadIdx.x + o]);
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        const float k = sk[0] > 0.f ? sk[0] / kFp8Max : 1.0f;
         const float v = sv[0] > 0.f ? sv[0] / kFp8Max : 0.0f;
-        sc[row] = k;
         sc[Mp + row] = v;
         atomicMax(reinterpret_cast<unsigned*>(sc + 2 * Mp), __float_as_uint(v));
     }
 }
 
+// E4M3 with round-to-nearest-even; the conversion does not saturate (values
+// beyond 448 become NaN), so inputs are clamped to the finite range first.
 __device__ inline uint8_t to_e4m3(float x)
 {
+    x = fminf(fmaxf(x, -kFp8Max), kFp8Max);
     return (uint8_t)(__builtin_amdgcn_cvt_pk_fp8_f32(x, 0.0f, 0, false) & 0xFF);
 }
 
-__device__ inline float from_e4m3(uint8_t q) { return __builtin_amdgcn_cvt_f32_fp8((int)q, 0); }
-
-// Kb, Ktp and Vb as bf16 of the FP8-rounded K and V (the backward works on the
-// same dictionary values the forward used); Vt8 = E4M3(V / s^V) transposed;
-// sv_fold = s^V * 448 / max s^V and unscale = max s^V / 448.
-__global__ __launch_bounds__(256) void k_dec_prep_fp8(const float* __restrict__ K, const float* __restrict__ V,
-                                                      int M, int Mp, int d, int D, const float* __restrict__ sc,
-                                                      __bf16* Kb, __bf16* Vb, uint8_t* Vt8, __bf16* Ktp,
+// Vt8 = E4M3(V / s^V) transposed [D, Mp]; sv_fold = s^V * 448 / max s^V and
+// unscale = max s^V / 448.  Kb, Vb, Ktp are filled by k_dec_prep<TBF16>.
+__global__ __launch_bounds__(256) void k_dec_prep_fp8(const float* __restrict__ V, int M, int Mp, int D,
+                                                      const float* __restrict__ sc, uint8_t* Vt8,
                                                       float* sv_fold, float* unscale)
 {
     const size_t tid = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
@@ -190,19 +184,6 @@ __global__ __launch_bounds__(256) void k_dec_prep_fp8(const float* __restrict__ 
         uint8_t q = 0;
         if (a < M && s > 0.f) q = to_e4m3(V[(size_t)a * D + c] / s);
         Vt8[(size_t)c * Mp + a] = q;
-        Vb[i] = (__bf16)(from_e4m3(q) * s);
-    }
-    for (size_t i = tid; i < (size_t)Mp * d; i += stride) {
-        const int a = (int)(i / d);
-        const float s = sc[a];
-        Kb[i] = (__bf16)(a < M ? from_e4m3(to_e4m3(K[i] / s)) * s : 0.0f);
-    }
-    for (size_t i = tid; i < (size_t)32 * Mp; i += stride) {
-        const int row = (int)(i / Mp), slot = (int)(i % Mp);
-        const int a = (slot & ~15) + perm16(slot & 15);
-        float v = 0.0f;
-        if (row < d && a < M) v = from_e4m3(to_e4m3(K[(size_t)a * d + row] / sc[a])) * sc[a];
-        Ktp[i] = (__bf16)v;
     }
     for (size_t i = tid; i < (size_t)Mp; i += stride)
         sv_fold[i] = vmax > 0.f ? sc[Mp + i] * (kFp8Max / vmax) : 0.0f;
@@ -679,7 +660,13 @@ static hipError_t launch_rows(const RowsArgs& ra, int nb, int D, int d, size_t l
 #define LAM_ROWS(NTV, DQV)                                                                           \
     if (NT == NTV && d == DQV) {                                                                     \
         auto kern = k_dec_rows<P, NTV, DQV, MODE, F8>;                                                   \
-        hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
+        static size_t lds_set = 0; /* raised only when needed, so captured replays make no call */    \
+        if (lds > lds_set) {                                                                         \
+            if (hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,   \
+                                    (int)lds) != hipSuccess)                                         \
+                return hipErrorInvalidValue;                                                         \
+            lds_set = lds;                                                                           \
+        }                                                                                            \
         hipLaunchKernelGGL(kern, dim3(nb), dim3(kRowsThreads), lds, st, ra);                        \
         return hipGetLastError();                                                                    \
     }
@@ -707,11 +694,12 @@ static hipError_t run_decode(const DecodeArgs& A, const DecodeLayout& L, int mod
             float* sc = reinterpret_cast<float*>(base + L.off_sc);
             hipError_t e0 = launch_fill_u32(reinterpret_cast<uint32_t*>(sc + 2 * Mp), 1, 0u, st);
             if (e0 != hipSuccess) return e0;
-            hipLaunchKernelGGL(k_dec_scales, dim3(Mp), dim3(256), 0, st, A.K, A.V, A.M, Mp, A.d, A.D, sc);
-            hipLaunchKernelGGL(k_dec_prep_fp8, dim3(grid), dim3(256), 0, st, A.K, A.V, A.M, Mp, A.d, A.D,
-                               (const float*)sc, reinterpret_cast<__bf16*>(Kb), reinterpret_cast<__bf16*>(Vb),
-                               reinterpret_cast<uint8_t*>(Vt), reinterpret_cast<__bf16*>(Ktp),
-                               sc + 2 * Mp + 64, sc + 2 * Mp + 8);
+            hipLaunchKernelGGL(k_dec_scales, dim3(Mp), dim3(256), 0, st, A.V, A.M, Mp, A.D, sc);
+            hipLaunchKernelGGL(k_dec_prep<P>, dim3(grid), dim3(256), 0, st, A.K, A.V, A.M, Mp, A.d, A.D,
+                               Kb, Vb, (T*)nullptr, Ktp);
+            hipLaunchKernelGGL(k_dec_prep_fp8, dim3(grid), dim3(256), 0, st, A.V, A.M, Mp, A.D,
+                               (const float*)sc, reinterpret_cast<uint8_t*>(Vt), sc + 2 * Mp + 64,
+                               sc + 2 * Mp + 8);
         } else {
             hipLaunchKernelGGL(k_dec_prep<P>, dim3(grid), dim3(256), 0, st, A.K, A.V, A.M, Mp, A.d, A.D,
                                Kb, Vb, Vt, Ktp);
@@ -803,9 +791,12 @@ hipError_t decode_backward_launch(const DecodeArgs& A, const DecodeLayout& L, hi
 
 using namespace lam;
 
+// Pixel-row arrays are read and written with 16-byte vector accesses.
+static bool a16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
 static bool dec_ptrs_ok(const float* Q, int n, const float* K, const float* V)
 {
-    return K && V && (n == 0 || Q);
+    return K && V && (n == 0 || Q) && a16(Q);
 }
 
 extern "C" {
@@ -839,6 +830,7 @@ lam_status lam_decode_loss(int precision, const float* Q, int n, int d, const fl
     lam_status s = dec_common(precision, n, d, M, D, ws, ws_bytes, &L);
     if (s != LAM_OK) return s;
     if (!dec_ptrs_ok(Q, n, K, V) || !loss || !dK || !dV || (n > 0 && !target)) return LAM_ERR_INVALID_ARG;
+    if (!a16(target) || !a16(dQ)) return LAM_ERR_INVALID_ARG;
     if (lambda_tr != 0.0f && !K0) return LAM_ERR_INVALID_ARG;
     DecodeArgs A{};
     A.prec = precision; A.n = n; A.d = d; A.M = M; A.D = D;
@@ -853,7 +845,7 @@ lam_status lam_decode_forward(int precision, const float* Q, int n, int d, const
     DecodeLayout L{};
     lam_status s = dec_common(precision, n, d, M, D, ws, ws_bytes, &L);
     if (s != LAM_OK) return s;
-    if (!dec_ptrs_ok(Q, n, K, V) || (n > 0 && !F)) return LAM_ERR_INVALID_ARG;
+    if (!dec_ptrs_ok(Q, n, K, V) || (n > 0 && !F) || !a16(F)) return LAM_ERR_INVALID_ARG;
     DecodeArgs A{};
     A.prec = precision; A.n = n; A.d = d; A.M = M; A.D = D;
     A.Q = Q; A.K = K; A.V = V; A.F = F;
@@ -867,7 +859,8 @@ lam_status lam_decode_backward(int precision, const float* Q, int n, int d, cons
     DecodeLayout L{};
     lam_status s = dec_common(precision, n, d, M, D, ws, ws_bytes, &L);
     if (s != LAM_OK) return s;
-    if (!dec_ptrs_ok(Q, n, K, V) || !dK || !dV || (n > 0 && !dF)) return LAM_ERR_INVALID_ARG;
+    if (!dec_ptrs_ok(Q, n, K, V) || !dK || !dV || (n > 0 && !dF) || !a16(dF) || !a16(dQ))
+        return LAM_ERR_INVALID_ARG;
     DecodeArgs A{};
     A.prec = precision; A.n = n; A.d = d; A.M = M; A.D = D;
     A.Q = Q; A.K = K; A.V = V; A.dF = dF; A.dQ = dQ; A.dK = dK; A.dV = dV;

@@ -250,12 +250,14 @@ __global__ __launch_bounds__(256) void k_raster_fwd(
     bool done = !inside;
     const float fpx = (float)px, fpy = (float)py;
 
-    for (uint32_t base = rg.x; base < rg.y; base += kChunk) {
+    // one list entry staged per thread: chunks are as long as the workgroup
+    const uint32_t chunk = blockDim.x;
+    for (uint32_t base = rg.x; base < rg.y; base += chunk) {
         if (__syncthreads_count(done) == (int)blockDim.x) break;
         stage_chunk<DQ>(st, (int)(base + threadIdx.x), rg.y, c, N, tile_recs, rec0, rec1, foot,
                         queries);
         __syncthreads();
-        const int cnt = min((uint32_t)kChunk, rg.y - base);
+        const int cnt = (int)min(chunk, rg.y - base);
         for (int j = 0; j < cnt && !done; ++j) {
             const uint2 f = st.fp[j];
             if (px < (int)(f.x & 0xFFFF) || px > (int)(f.x >> 16) || py < (int)(f.y & 0xFFFF) ||
@@ -344,8 +346,9 @@ __global__ __launch_bounds__(256) void k_raster_bwd(
     const uint32_t maxlast = s_max;
     const float fpx = (float)px, fpy = (float)py;
 
-    for (int end = (int)maxlast; end > 0; end -= kChunk) {
-        const int start = end > kChunk ? end - kChunk : 0;
+    const int chunk = (int)blockDim.x;  // one staged entry per thread
+    for (int end = (int)maxlast; end > 0; end -= chunk) {
+        const int start = end > chunk ? end - chunk : 0;
         __syncthreads();
         stage_chunk<DQ>(st, (int)(rg.x + start + threadIdx.x), rg.x + end, c, N, tile_recs, rec0,
                         rec1, foot, queries);
