@@ -352,6 +352,7 @@ __global__ __launch_bounds__(kRowsThreads) void k_dec_rows(RowsArgs a)
             }
         }
     } else {
+#pragma unroll 2
         for (int c = 0; c < a.Mp / 16; ++c) {
             const Frag bf = P::load(X + col * ldp + 16 * c + 8 * h);
 #pragma unroll
@@ -381,28 +382,30 @@ __global__ __launch_bounds__(kRowsThreads) void k_dec_rows(RowsArgs a)
         return;
     }
 
-    // ---- epilogue: cosine loss gradient (LOSS) or upstream dF (ADJ)
+    // ---- epilogue: cosine loss gradient (LOSS) or upstream dF (ADJ).  gsc first
+    // holds the target (or dF) and is overwritten in place by G = dL/dF / l.
     float gsc[NT][16];
     float delta = 0.0f;
+    const float* rowsrc = MODE == MODE_LOSS ? a.target : a.dF;
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int g4 = 0; g4 < 4; ++g4) {
+            const int dr = 32 * (w * NT + t) + 8 * g4 + 4 * h;
+            float4 x = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (valid) x = *reinterpret_cast<const float4*>(rowsrc + (size_t)px * a.D + dr);
+            gsc[t][4 * g4] = x.x; gsc[t][4 * g4 + 1] = x.y; gsc[t][4 * g4 + 2] = x.z; gsc[t][4 * g4 + 3] = x.w;
+        }
+    float ca = invl, cb = 0.0f;  // G = ca * row + cb * F
     if (MODE == MODE_LOSS) {
-        float tv[NT][16];
         float nf = 0.f, ft = 0.f, nt = 0.f;
-#pragma unroll
-        for (int t = 0; t < NT; ++t)
-#pragma unroll
-            for (int g4 = 0; g4 < 4; ++g4) {
-                const int dr = 32 * (w * NT + t) + 8 * g4 + 4 * h;
-                float4 x = make_float4(0.f, 0.f, 0.f, 0.f);
-                if (valid) x = *reinterpret_cast<const float4*>(a.target + (size_t)px * a.D + dr);
-                tv[t][4 * g4] = x.x; tv[t][4 * g4 + 1] = x.y; tv[t][4 * g4 + 2] = x.z; tv[t][4 * g4 + 3] = x.w;
-            }
 #pragma unroll
         for (int t = 0; t < NT; ++t)
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 nf += acc[t][r] * acc[t][r];
-                ft += acc[t][r] * tv[t][r];
-                nt += tv[t][r] * tv[t][r];
+                ft += acc[t][r] * gsc[t][r];
+                nt += gsc[t][r] * gsc[t][r];
             }
         nf += __shfl_xor(nf, 32, kWave);
         ft += __shfl_xor(ft, 32, kWave);
@@ -421,12 +424,8 @@ __global__ __launch_bounds__(kRowsThreads) void k_dec_rows(RowsArgs a)
         const float den = fmaxf(raw, 1e-8f);
         const float cs = ft / den;
         // dL/dF = -(1/n) (T / den - c F / |F|^2), then divided by l
-        const float ca = valid ? -a.inv_n / den : 0.0f;
-        const float cb = (valid && raw > 1e-8f && nf > 0.f) ? a.inv_n * cs / nf : 0.0f;
-#pragma unroll
-        for (int t = 0; t < NT; ++t)
-#pragma unroll
-            for (int r = 0; r < 16; ++r) gsc[t][r] = (ca * tv[t][r] + cb * acc[t][r]) * invl;
+        ca = valid ? -a.inv_n / den * invl : 0.0f;
+        cb = (valid && raw > 1e-8f && nf > 0.f) ? a.inv_n * cs / nf * invl : 0.0f;
         if (w == 0 && h == 0) {
             if (a.row_cos && valid) a.row_cos[px] = cs;
             // block sum of (1 - cos) over valid pixels
@@ -434,23 +433,16 @@ __global__ __launch_bounds__(kRowsThreads) void k_dec_rows(RowsArgs a)
             for (int o = 16; o >= 1; o >>= 1) lp += __shfl_xor(lp, o, kWave);
             if (col == 0) a.loss_part[blk] = lp;
         }
-    } else {
-#pragma unroll
-        for (int t = 0; t < NT; ++t)
-#pragma unroll
-            for (int g4 = 0; g4 < 4; ++g4) {
-                const int dr = 32 * (w * NT + t) + 8 * g4 + 4 * h;
-                float4 x = make_float4(0.f, 0.f, 0.f, 0.f);
-                if (valid) x = *reinterpret_cast<const float4*>(a.dF + (size_t)px * a.D + dr);
-                gsc[t][4 * g4] = x.x * invl; gsc[t][4 * g4 + 1] = x.y * invl;
-                gsc[t][4 * g4 + 2] = x.z * invl; gsc[t][4 * g4 + 3] = x.w * invl;
-            }
     }
-    // delta' = sum_D G F (zero for the pure cosine term up to rounding)
+    // G in place; delta' = sum_D G F (zero for the pure cosine term up to rounding)
 #pragma unroll
     for (int t = 0; t < NT; ++t)
 #pragma unroll
-        for (int r = 0; r < 16; ++r) delta += gsc[t][r] * acc[t][r];
+        for (int r = 0; r < 16; ++r) {
+            const float gv = ca * gsc[t][r] + cb * acc[t][r];
+            delta += gv * acc[t][r];
+            gsc[t][r] = gv;
+        }
     delta += __shfl_xor(delta, 32, kWave);
     __syncthreads();  // everyone is done reading P~ (region X) and red
     if (h == 0) red[12 * kPx + w * kPx + col] = delta;
@@ -471,13 +463,7 @@ __global__ __launch_bounds__(kRowsThreads) void k_dec_rows(RowsArgs a)
     // ---- per atom tile: dP = G V^T, dS = P~ (dP - delta) / sqrt(d), dQ^T += K^T dS^T
     f32x16 dq = {};
     T* St = reinterpret_cast<T*>(a.St) + (size_t)blk * a.Mp * kPx;
-    for (int tt = w; tt < ntiles; tt += 4) {
-        f32x16 dp = {};
-        for (int c = 0; c < a.D / 16; ++c) {
-            const Frag af = P::load(Vb + (size_t)(32 * tt + col) * a.D + 16 * c + 8 * h);
-            const Frag bf = P::load(X + col * ldg + 16 * c + 8 * h);
-            P::mma(dp, af, bf);
-        }
+    auto finish_tile = [&](int tt, const f32x16& dp) {
         const f32x16 s = s_tile(tt);
         float ds[16];
 #pragma unroll
@@ -494,6 +480,25 @@ __global__ __launch_bounds__(kRowsThreads) void k_dec_rows(RowsArgs a)
             const Frag bf = P::from_f32(ds + 8 * c);
             P::mma(dq, af, bf);
         }
+    };
+    // two atom tiles (tt and tt + 4) share each G fragment read from LDS
+    for (int tt = w; tt < ntiles; tt += 8) {
+        const bool two = tt + 4 < ntiles;
+        f32x16 dp0 = {}, dp1 = {};
+        const T* v0 = Vb + (size_t)(32 * tt + col) * a.D + 8 * h;
+        const T* v1 = Vb + (size_t)(32 * (tt + 4) + col) * a.D + 8 * h;
+#pragma unroll 4
+        for (int c = 0; c < a.D / 16; ++c) {
+            const Frag bf = P::load(X + col * ldg + 16 * c + 8 * h);
+            const Frag af0 = P::load(v0 + 16 * c);
+            P::mma(dp0, af0, bf);
+            if (two) {
+                const Frag af1 = P::load(v1 + 16 * c);
+                P::mma(dp1, af1, bf);
+            }
+        }
+        finish_tile(tt, dp0);
+        if (two) finish_tile(tt + 4, dp1);
     }
     if (!a.dQ) return;
     __syncthreads();  // region X (G) no longer read
@@ -514,19 +519,21 @@ __global__ __launch_bounds__(kRowsThreads) void k_dec_rows(RowsArgs a)
 
 // C_part[split][i][j] = sum over the split's pixel blocks of A^T[i][p] B^T[j][p]
 // with A^T, B^T in the pixel-blocked transposed layout X^T[blk][row][32].
-// Workgroup tile: 64 x 64 (wave tile 32 x 32); grid = tiles x splits, mapped so
-// that the tiles of one split share an XCD (and its L2).
-template <class P>
+// A wave owns WI x WJ result tiles of 32 x 32, the 4 waves are arranged
+// WVI x WVJ, so a workgroup covers (32 WI WVI) x (32 WJ WVJ).  Fragments of the
+// next pixel block are loaded before the MFMAs of the current one.  The grid
+// is tiles x splits, mapped so that the tiles of one split share an XCD.
+template <class P, int WI, int WJ, int WVI, int WVJ>
 __global__ __launch_bounds__(256) void k_dec_tn(const void* At_, int rowsA, const void* Bt_, int rowsB,
                                                 int nblocks, int splits, int tiles_i, int tiles_j,
                                                 float* __restrict__ part)
 {
+    static_assert(WVI * WVJ == 4, "four waves");
     using T = typename P::T;
     using Frag = typename P::Frag;
     const T* At = reinterpret_cast<const T*>(At_);
     const T* Bt = reinterpret_cast<const T*>(Bt_);
     const int ntiles = tiles_i * tiles_j;
-    // XCD-aware mapping: consecutive workgroup ids go to different XCDs
     const int b = blockIdx.x;
     const int xcd = b % 8, idx = b / 8;
     const int split = (idx / ntiles) * 8 + xcd;
@@ -535,26 +542,60 @@ __global__ __launch_bounds__(256) void k_dec_tn(const void* At_, int rowsA, cons
     const int ti = tile / tiles_j, tj = tile % tiles_j;
     const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int col = lane & 31, h = lane >> 5;
-    const int i0 = 64 * ti + 32 * (w >> 1), j0 = 64 * tj + 32 * (w & 1);
-    const bool ok = i0 < rowsA && j0 < rowsB;
+    const int i0 = (ti * WVI + w / WVJ) * WI * 32, j0 = (tj * WVJ + w % WVJ) * WJ * 32;
     const int per = (nblocks + splits - 1) / splits;
     const int b0 = split * per, b1 = min(nblocks, b0 + per);
-    f32x16 c = {};
-    if (ok) {
-        for (int blk = b0; blk < b1; ++blk) {
-            const T* ab = At + ((size_t)blk * rowsA + i0 + col) * kPx;
-            const T* bb = Bt + ((size_t)blk * rowsB + j0 + col) * kPx;
+    bool oka[WI], okb[WJ];
 #pragma unroll
-            for (int k = 0; k < 2; ++k) {
-                const Frag af = P::load(ab + 16 * k + 8 * h);
-                const Frag bf = P::load(bb + 16 * k + 8 * h);
-                P::mma(c, af, bf);
-            }
+    for (int a = 0; a < WI; ++a) oka[a] = i0 + 32 * a < rowsA;
+#pragma unroll
+    for (int q = 0; q < WJ; ++q) okb[q] = j0 + 32 * q < rowsB;
+    if (!oka[0] || !okb[0]) return;
+    f32x16 c[WI][WJ];
+#pragma unroll
+    for (int a = 0; a < WI; ++a)
+#pragma unroll
+        for (int q = 0; q < WJ; ++q) c[a][q] = f32x16{};
+    Frag af[2][WI], bf[2][WJ];
+    auto load = [&](int blk, Frag* fa, Frag* fb) {
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+#pragma unroll
+            for (int a = 0; a < WI; ++a)
+                fa[k * WI + a] = oka[a] ? P::load(At + ((size_t)blk * rowsA + i0 + 32 * a + col) * kPx + 16 * k + 8 * h)
+                                        : Frag{};
+#pragma unroll
+            for (int q = 0; q < WJ; ++q)
+                fb[k * WJ + q] = okb[q] ? P::load(Bt + ((size_t)blk * rowsB + j0 + 32 * q + col) * kPx + 16 * k + 8 * h)
+                                        : Frag{};
         }
-        float* out = part + (size_t)split * rowsA * rowsB;
+    };
+    Frag cur_a[2 * WI], cur_b[2 * WJ], nxt_a[2 * WI], nxt_b[2 * WJ];
+    if (b0 < b1) load(b0, cur_a, cur_b);
+    for (int blk = b0; blk < b1; ++blk) {
+        if (blk + 1 < b1) load(blk + 1, nxt_a, nxt_b);
 #pragma unroll
-        for (int r = 0; r < 16; ++r) out[(size_t)(i0 + crow(r, h)) * rowsB + j0 + col] = c[r];
+        for (int k = 0; k < 2; ++k)
+#pragma unroll
+            for (int a = 0; a < WI; ++a)
+#pragma unroll
+                for (int q = 0; q < WJ; ++q) P::mma(c[a][q], cur_a[k * WI + a], cur_b[k * WJ + q]);
+#pragma unroll
+        for (int k = 0; k < 2 * WI; ++k) cur_a[k] = nxt_a[k];
+#pragma unroll
+        for (int k = 0; k < 2 * WJ; ++k) cur_b[k] = nxt_b[k];
     }
+    (void)af; (void)bf;
+    float* out = part + (size_t)split * rowsA * rowsB;
+#pragma unroll
+    for (int a = 0; a < WI; ++a)
+#pragma unroll
+        for (int q = 0; q < WJ; ++q) {
+            if (!oka[a] || !okb[q]) continue;
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                out[(size_t)(i0 + 32 * a + crow(r, h)) * rowsB + j0 + 32 * q + col] = c[a][q][r];
+        }
 }
 
 // out[i][j] = scale * sum_split part[split][i][j] (+ 2 lambda (K - K0) for dK),
@@ -618,8 +659,8 @@ bool decode_layout(int prec, int n, int d, int M, int D, DecodeLayout* L)
     const int nb = (n + kPx - 1) / kPx;
     L->Mp = Mp;
     L->row_blocks = nb;
-    const int tiles_v = (Mp / 64) * (D / 64);
-    const int tiles_k = Mp / 64;
+    const int tiles_v = ((Mp + 127) / 128) * ((D + 127) / 128);
+    const int tiles_k = (Mp + 255) / 256;
     const int sv = pick_splits(std::max(nb, 1), tiles_v);
     const int sk = pick_splits(std::max(nb, 1), tiles_k);
     L->splits = sv;
@@ -733,10 +774,10 @@ static hipError_t run_decode(const DecodeArgs& A, const DecodeLayout& L, int mod
     float* part = reinterpret_cast<float*>(base + L.off_part);
     // dV = P~^T G over all pixels
     {
-        const int ti = Mp / 64, tj = A.D / 64;
+        const int ti = (Mp + 127) / 128, tj = (A.D + 127) / 128;
         if (nb > 0) {
             ProfScope ps("decode_tn", st);
-            hipLaunchKernelGGL(k_dec_tn<P>, dim3(L.splits * ti * tj), dim3(256), 0, st,
+            hipLaunchKernelGGL((k_dec_tn<P, 2, 2, 2, 2>), dim3(L.splits * ti * tj), dim3(256), 0, st,
                                (const void*)(base + L.off_p), Mp, (const void*)(base + L.off_gf), A.D, nb,
                                L.splits, ti, tj, part);
         }
@@ -746,9 +787,9 @@ static hipError_t run_decode(const DecodeArgs& A, const DecodeLayout& L, int mod
     }
     // dK = dS^T Q (1/sqrt(d) already in dS) + 2 lambda (K - K0)
     {
-        const int ti = Mp / 64, tj = 1;
+        const int ti = (Mp + 255) / 256, tj = 1;
         if (nb > 0) {
-            hipLaunchKernelGGL(k_dec_tn<P>, dim3(L.splits_k * ti * tj), dim3(256), 0, st,
+            hipLaunchKernelGGL((k_dec_tn<P, 2, 1, 4, 1>), dim3(L.splits_k * ti * tj), dim3(256), 0, st,
                                (const void*)(base + L.off_ds), Mp, (const void*)(base + L.off_qt), 32, nb,
                                L.splits_k, ti, tj, part);
         }

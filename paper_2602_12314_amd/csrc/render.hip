@@ -133,34 +133,43 @@ __global__ __launch_bounds__(256) void k_preprocess(
     ntiles[r] = (uint32_t)(nx * ny);
 }
 
-// One thread per depth-sorted record: write its (tile id, record) pairs.
+// One thread per emitted (tile id, record) pair, so Gaussians covering many
+// tiles do not serialise one thread: pair o belongs to the depth-sorted record
+// s with offsets[s] <= o < offsets[s + 1] (binary search; records emitting
+// nothing share their successor's offset and are never found), and is that
+// record's (o - offsets[s])-th tile of its footprint, rows outer.
 __global__ __launch_bounds__(256) void k_emit(CamSet cs, int N, uint32_t R,
                                              const uint32_t* __restrict__ sorted_rec,
                                              const uint32_t* __restrict__ offsets,
-                                             const uint32_t* __restrict__ ntiles,
-                                             const uint2* __restrict__ foot, uint32_t cap,
+                                             const uint2* __restrict__ foot,
+                                             const uint32_t* __restrict__ counters, uint32_t cap,
                                              uint32_t* __restrict__ keys,
                                              uint32_t* __restrict__ vals)
 {
-    const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= R) return;
-    const uint32_t r = sorted_rec[s];
-    const uint32_t cnt = ntiles[r];
-    if (cnt == 0) return;
-    const int c = (int)(r / (uint32_t)N);
-    int tbase = 0, tx_n = 1;
-    for (int k = 0; k < cs.n; ++k)
-        if (k == c) { tbase = cs.c[k].tile_base; tx_n = cs.c[k].tiles_x; }
-    const uint2 f = foot[r];
-    const int x0 = (f.x & 0xFFFF) >> cs.tile_shift_x, x1 = (f.x >> 16) >> cs.tile_shift_x;
-    const int y0 = (f.y & 0xFFFF) >> cs.tile_shift_y, y1 = (f.y >> 16) >> cs.tile_shift_y;
-    uint32_t off = offsets[s];
-    for (int ty = y0; ty <= y1; ++ty)
-        for (int tx = x0; tx <= x1; ++tx, ++off)
-            if (off < cap) {
-                keys[off] = (uint32_t)(tbase + ty * tx_n + tx);
-                vals[off] = r;
-            }
+    const uint32_t total = counters[0] < cap ? counters[0] : cap;
+    for (uint32_t o = blockIdx.x * blockDim.x + threadIdx.x; o < total;
+         o += gridDim.x * blockDim.x) {
+        uint32_t lo = 0, hi = R;  // first s with offsets[s] > o is in (lo, hi]
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (offsets[mid] <= o) lo = mid;
+            else hi = mid;
+        }
+        const uint32_t s = lo;
+        const uint32_t r = sorted_rec[s];
+        const int c = (int)(r / (uint32_t)N);
+        int tbase = 0, tx_n = 1;
+        for (int k = 0; k < cs.n; ++k)
+            if (k == c) { tbase = cs.c[k].tile_base; tx_n = cs.c[k].tiles_x; }
+        const uint2 f = foot[r];
+        const int x0 = (f.x & 0xFFFF) >> cs.tile_shift_x, x1 = (f.x >> 16) >> cs.tile_shift_x;
+        const int y0 = (f.y & 0xFFFF) >> cs.tile_shift_y;
+        const int nx = x1 - x0 + 1;
+        const int k = (int)(o - offsets[s]);
+        const int ty = y0 + k / nx, tx = x0 + k % nx;
+        keys[o] = (uint32_t)(tbase + ty * tx_n + tx);
+        vals[o] = r;
+    }
 }
 
 // counters[0] = pairs needed, counters[1] = 1 if they exceed the capacity.
@@ -298,6 +307,25 @@ __global__ __launch_bounds__(256) void k_raster_fwd(
 
 // ------------------------------------------------------------- raster bwd
 
+// Transposed wave reduction of N values: at the step with lane mask M a lane
+// keeps the upper half of its values if its M bit is set, the lower half
+// otherwise, and adds the partner's (lane ^ M) copy of the half it keeps.
+template <int N, int M>
+__device__ inline void halving_sum(float* v, unsigned lane)
+{
+    if constexpr (N > 1 && M >= 1) {
+        constexpr int H = N / 2;
+        const bool upper = (lane & M) != 0;
+#pragma unroll
+        for (int k = 0; k < H; ++k) {
+            const float send = upper ? v[k] : v[k + H];
+            const float keep = upper ? v[k + H] : v[k];
+            v[k] = keep + __shfl_xor(send, M, kWave);
+        }
+        halving_sum<H, M / 2>(v, lane);
+    }
+}
+
 // rec_grad[r] = (du, dv, dA, dB, dC, dopacity) accumulated over pixels.
 template <int DQ>
 __global__ __launch_bounds__(256) void k_raster_bwd(
@@ -394,24 +422,26 @@ __global__ __launch_bounds__(256) void k_raster_bwd(
                 }
             }
             if (__ballot(hit) == 0ull) continue;
-            const uint32_t r = st.rec[sj];
-            const float s0 = wave_sum_to_last(gu), s1 = wave_sum_to_last(gv);
-            const float s2 = wave_sum_to_last(gA), s3 = wave_sum_to_last(gB);
-            const float s4 = wave_sum_to_last(gC), s5 = wave_sum_to_last(gO);
-            float sq[DQ];
+            // 6 screen-space terms and DQ query terms, padded to NV, summed over the
+            // wave by halving: at each step a lane keeps half of its values and adds
+            // the partner's copy of that half, so after log2(64) steps lane l holds
+            // the total of value (l >> 1) (NV = 32) or l (NV = 64).
+            constexpr int NV = (6 + DQ <= 32) ? 32 : 64;
+            float v[NV];
+            v[0] = gu; v[1] = gv; v[2] = gA; v[3] = gB; v[4] = gC; v[5] = gO;
 #pragma unroll
-            for (int k = 0; k < DQ; ++k) sq[k] = wave_sum_to_last(wq * g[k]);
-            if (lane == kWave - 1) {
-                float* rgp = rec_grad + (size_t)r * 6;
-                unsafeAtomicAdd(rgp + 0, s0);
-                unsafeAtomicAdd(rgp + 1, s1);
-                unsafeAtomicAdd(rgp + 2, s2);
-                unsafeAtomicAdd(rgp + 3, s3);
-                unsafeAtomicAdd(rgp + 4, s4);
-                unsafeAtomicAdd(rgp + 5, s5);
-                float* dq = d_queries + (size_t)(r - (uint32_t)c * (uint32_t)N) * DQ;
+            for (int k = 0; k < DQ; ++k) v[6 + k] = wq * g[k];
 #pragma unroll
-                for (int k = 0; k < DQ; ++k) unsafeAtomicAdd(dq + k, sq[k]);
+            for (int k = 6 + DQ; k < NV; ++k) v[k] = 0.0f;
+            halving_sum<NV, 32>(v, lane);
+            if (NV == 32) v[0] += __shfl_xor(v[0], 1, kWave);
+            const int idx = NV == 32 ? (int)(lane >> 1) : (int)lane;
+            const bool owner = (NV == 64 || (lane & 1) == 0) && idx < 6 + DQ && v[0] != 0.0f;
+            if (owner) {
+                const uint32_t r = st.rec[sj];
+                float* dst = idx < 6 ? rec_grad + (size_t)r * 6 + idx
+                                     : d_queries + (size_t)(r - (uint32_t)c * (uint32_t)N) * DQ + (idx - 6);
+                unsafeAtomicAdd(dst, v[0]);
             }
         }
     }
@@ -580,10 +610,11 @@ hipError_t render_forward_launch(const RenderArgs& A, const RenderLayout& L, hip
         e = launch_excl_scan(L.ntiles, sorted_rec, R, L.offsets, L.counters, L.sort_scratch, st);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_check_capacity, dim3(1), dim3(1), 0, st, L.counters, cap);
-        if (R > 0)
-            hipLaunchKernelGGL(k_emit, dim3((R + 255) / 256), dim3(256), 0, st, cs, A.n, R,
-                               sorted_rec, (const uint32_t*)L.offsets, (const uint32_t*)L.ntiles,
-                               (const uint2*)L.foot, cap, L.ikeys_a, L.ivals_a);
+        if (R > 0 && cap > 0)
+            hipLaunchKernelGGL(k_emit, dim3(std::min<uint32_t>((cap + 255) / 256, 8192u)), dim3(256),
+                               0, st, cs, A.n, R, sorted_rec, (const uint32_t*)L.offsets,
+                               (const uint2*)L.foot, (const uint32_t*)L.counters, cap, L.ikeys_a,
+                               L.ivals_a);
         e = launch_radix_sort(nullptr, L.ikeys_a, L.ivals_a, L.ikeys_b, L.ivals_b, false,
                               L.counters, cap, L.tile_bits, L.sort_scratch, &in_b, st);
         if (e != hipSuccess) return e;

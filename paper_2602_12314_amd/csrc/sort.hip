@@ -124,15 +124,61 @@ __global__ __launch_bounds__(kTileThreads) void k_scan_down(const uint32_t* __re
     }
 }
 
+// One 1024-thread workgroup scans up to kSingleMax values in tiles of 16384:
+// each thread loads 16 consecutive values (16 loads in flight), the thread
+// sums are scanned across the workgroup, and a carry links the tiles.  One
+// launch instead of three for small inputs.
+constexpr int kSingleThreads = 1024;
+constexpr uint32_t kSingleTile = kSingleThreads * kTileItems;
+constexpr uint32_t kSingleMax = 4 * kSingleTile;
+
+__global__ __launch_bounds__(kSingleThreads) void k_scan_single(const uint32_t* __restrict__ in,
+                                                                const uint32_t* __restrict__ idx,
+                                                                uint32_t n, uint32_t* __restrict__ out,
+                                                                uint32_t* __restrict__ total)
+{
+    __shared__ uint32_t sh[kSingleThreads / kWave];
+    const unsigned lane = __lane_id(), w = threadIdx.x / kWave;
+    uint32_t carry = 0;
+    for (uint32_t base = 0; base < n; base += kSingleTile) {
+        uint32_t v[kTileItems], s = 0;
+#pragma unroll
+        for (int k = 0; k < kTileItems; ++k) {
+            const uint32_t i = base + threadIdx.x * kTileItems + k;
+            v[k] = i < n ? scan_value(in, idx, i) : 0u;
+            s += v[k];
+        }
+        const uint32_t inc = wave_incl_scan(s);
+        if (lane == kWave - 1) sh[w] = inc;
+        __syncthreads();
+        uint32_t wo = 0, tot = 0;
+        for (int k = 0; k < kSingleThreads / kWave; ++k) {
+            const uint32_t x = sh[k];
+            if (k < (int)w) wo += x;
+            tot += x;
+        }
+        __syncthreads();
+        uint32_t off = carry + wo + inc - s;
+#pragma unroll
+        for (int k = 0; k < kTileItems; ++k) {
+            const uint32_t i = base + threadIdx.x * kTileItems + k;
+            if (i < n) out[i] = off;
+            off += v[k];
+        }
+        carry += tot;
+    }
+    if (total && threadIdx.x == 0) *total = carry;
+}
+
 size_t scan_scratch_words(uint32_t n) { return (n + kTile - 1) / kTile + 1; }
 
 hipError_t launch_excl_scan(const uint32_t* in, const uint32_t* idx, uint32_t n, uint32_t* out,
                             uint32_t* total, uint32_t* scratch, hipStream_t st)
 {
     uint32_t nb = (n + kTile - 1) / kTile;
-    if (nb == 0) {
-        // empty input: the total is zero
-        if (total) hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kTileThreads), 0, st, scratch, 0u, total);
+    if (n <= kSingleMax) {
+        // includes n == 0, where only the total (zero) is written
+        hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(kSingleThreads), 0, st, in, idx, n, out, total);
         return hipGetLastError();
     }
     hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kTileThreads), 0, st, in, idx, n, scratch);
@@ -144,36 +190,42 @@ hipError_t launch_excl_scan(const uint32_t* in, const uint32_t* idx, uint32_t n,
 
 // ------------------------------------------------------------------ radix
 
+template <int DB>
 __global__ __launch_bounds__(kTileThreads) void k_radix_hist(const uint32_t* __restrict__ keys,
                                                              const uint32_t* __restrict__ n_dev,
                                                              uint32_t n_cap, int shift,
                                                              uint32_t* __restrict__ hist,
                                                              uint32_t nblocks)
 {
-    __shared__ uint32_t h[256];
-    h[threadIdx.x] = 0;
+    constexpr int BINS = 1 << DB;
+    __shared__ uint32_t h[BINS];
+    for (int k = threadIdx.x; k < BINS; k += kTileThreads) h[k] = 0;
     __syncthreads();
-    uint32_t n = load_count(n_dev, n_cap);
-    uint32_t base = blockIdx.x * (uint32_t)kTile;
+    const uint32_t n = load_count(n_dev, n_cap);
+    const uint32_t base = blockIdx.x * (uint32_t)kTile;
     for (int k = 0; k < kTileItems; ++k) {
-        uint32_t i = base + k * kTileThreads + threadIdx.x;
-        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+        const uint32_t i = base + k * kTileThreads + threadIdx.x;
+        if (i < n) atomicAdd(&h[(keys[i] >> shift) & (BINS - 1u)], 1u);
     }
     __syncthreads();
-    hist[threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+    for (int k = threadIdx.x; k < BINS; k += kTileThreads) hist[(size_t)k * nblocks + blockIdx.x] = h[k];
 }
 
+template <int DB>
 __global__ __launch_bounds__(kTileThreads) void k_radix_scatter(
     const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
     uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
     const uint32_t* __restrict__ n_dev, uint32_t n_cap, int shift,
     const uint32_t* __restrict__ offsets, uint32_t nblocks)
 {
-    __shared__ uint32_t cnt[kTileThreads / kWave][256];
-    __shared__ uint32_t gbase[256];
+    constexpr int BINS = 1 << DB;
+    constexpr int WAVES = kTileThreads / kWave;
+    __shared__ uint32_t cnt[WAVES][BINS];
+    __shared__ uint32_t gbase[BINS];
     const unsigned lane = __lane_id(), w = threadIdx.x / kWave;
-    for (int k = threadIdx.x; k < 4 * 256; k += kTileThreads) (&cnt[0][0])[k] = 0;
-    gbase[threadIdx.x] = offsets[threadIdx.x * nblocks + blockIdx.x];
+    for (int k = threadIdx.x; k < WAVES * BINS; k += kTileThreads) (&cnt[0][0])[k] = 0;
+    for (int k = threadIdx.x; k < BINS; k += kTileThreads)
+        gbase[k] = offsets[(size_t)k * nblocks + blockIdx.x];
     __syncthreads();
 
     const uint32_t n = load_count(n_dev, n_cap);
@@ -182,30 +234,30 @@ __global__ __launch_bounds__(kTileThreads) void k_radix_scatter(
     uint32_t key[kTileItems], val[kTileItems], rank[kTileItems];
 #pragma unroll
     for (int s = 0; s < kTileItems; ++s) {
-        uint32_t i = span + s * kWave + lane;
-        bool ok = i < n;
+        const uint32_t i = span + s * kWave + lane;
+        const bool ok = i < n;
         key[s] = ok ? keys_in[i] : 0u;
         val[s] = ok ? (vals_in ? vals_in[i] : i) : 0u;
-        uint32_t dg = (key[s] >> shift) & 255u;
+        const uint32_t dg = (key[s] >> shift) & (BINS - 1u);
+        // lanes holding the same digit: intersect the ballots of its bits
         unsigned long long peers = __ballot(ok);
 #pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            unsigned long long m = __ballot((dg >> b) & 1u);
+        for (int b = 0; b < DB; ++b) {
+            const unsigned long long m = __ballot((dg >> b) & 1u);
             peers &= ((dg >> b) & 1u) ? m : ~m;
         }
-        uint32_t before = ok ? cnt[w][dg] : 0u;
-        rank[s] = before + (uint32_t)__popcll(peers & lt);
+        const uint32_t before = ok ? cnt[w][dg] : 0u;
+        rank[s] = ok ? before + (uint32_t)__popcll(peers & lt) : 0xFFFFFFFFu;
         // the lowest lane of each digit group publishes the new running count
         if (ok && (peers & lt) == 0ull) cnt[w][dg] = before + (uint32_t)__popcll(peers);
-        if (!ok) rank[s] = 0xFFFFFFFFu;
     }
     __syncthreads();
-    // exclusive prefix over waves per digit
-    {
-        uint32_t d = threadIdx.x, run = 0;
+    // exclusive prefix over the waves, per digit
+    for (int d = threadIdx.x; d < BINS; d += kTileThreads) {
+        uint32_t run = 0;
 #pragma unroll
-        for (int k = 0; k < kTileThreads / kWave; ++k) {
-            uint32_t c = cnt[k][d];
+        for (int k = 0; k < WAVES; ++k) {
+            const uint32_t c = cnt[k][d];
             cnt[k][d] = run;
             run += c;
         }
@@ -214,53 +266,79 @@ __global__ __launch_bounds__(kTileThreads) void k_radix_scatter(
 #pragma unroll
     for (int s = 0; s < kTileItems; ++s) {
         if (rank[s] == 0xFFFFFFFFu) continue;
-        uint32_t dg = (key[s] >> shift) & 255u;
-        uint32_t pos = gbase[dg] + cnt[w][dg] + rank[s];
+        const uint32_t dg = (key[s] >> shift) & (BINS - 1u);
+        const uint32_t pos = gbase[dg] + cnt[w][dg] + rank[s];
         keys_out[pos] = key[s];
         vals_out[pos] = val[s];
     }
+}
+
+// Passes and digit width for ``bits`` key bits: at most 11 bits per pass.
+static void radix_plan(int bits, int* passes, int* width)
+{
+    if (bits < 1) bits = 1;
+    int p = (bits + 10) / 11;
+    int wdt = (bits + p - 1) / p;
+    *passes = p;
+    *width = wdt <= 8 ? 8 : 11;
 }
 
 size_t radix_scratch_words(uint32_t n_cap)
 {
     uint32_t nb = (n_cap + kTile - 1) / kTile;
     if (nb == 0) nb = 1;
-    size_t h = (size_t)256 * nb;
+    size_t h = (size_t)2048 * nb;
     return h + scan_scratch_words((uint32_t)h) + 8;
 }
 
-// Sorts the ``bits`` low bits of the keys, 8 per pass, ping-ponging between
-// the A and B buffers; *in_b tells where the result ended.  keys_first, when
-// given, is the read-only input of the first pass (it is left intact).  With
-// iota_first the first pass takes value = input position instead of vals_a.
+// Sorts the ``bits`` low bits of the keys, ping-ponging between the A and B
+// buffers; *in_b tells where the result ended.  keys_first, when given, is the
+// read-only input of the first pass (it is left intact).  With iota_first the
+// first pass takes value = input position instead of vals_a.
 hipError_t launch_radix_sort(const uint32_t* keys_first, uint32_t* keys_a, uint32_t* vals_a,
                              uint32_t* keys_b, uint32_t* vals_b, bool iota_first,
                              const uint32_t* n_dev, uint32_t n_cap, int bits, uint32_t* scratch,
                              bool* in_b, hipStream_t st)
 {
-    uint32_t nb = (n_cap + kTile - 1) / kTile;
+    const uint32_t nb = (n_cap + kTile - 1) / kTile;
     *in_b = false;
     if (nb == 0) return hipSuccess;
+    int passes, width;
+    radix_plan(bits, &passes, &width);
+    const uint32_t bins = 1u << width;
     uint32_t* hist = scratch;
-    uint32_t* sscr = scratch + (size_t)256 * nb;
+    uint32_t* sscr = scratch + (size_t)bins * nb;
     uint32_t *ki = keys_a, *vi = vals_a, *ko = keys_b, *vo = vals_b;
-    int passes = (bits + 7) / 8;
-    if (passes < 1) passes = 1;
     for (int p = 0; p < passes; ++p) {
-        int shift = 8 * p;
+        const int shift = width * p;
         const uint32_t* kin = (p == 0 && keys_first) ? keys_first : ki;
-        hipLaunchKernelGGL(k_radix_hist, dim3(nb), dim3(kTileThreads), 0, st, kin, n_dev, n_cap,
-                           shift, hist, nb);
-        hipError_t e = launch_excl_scan(hist, nullptr, 256u * nb, hist, nullptr, sscr, st);
+        const uint32_t* vin = (p == 0 && iota_first) ? (const uint32_t*)nullptr : vi;
+        if (width == 8)
+            hipLaunchKernelGGL(k_radix_hist<8>, dim3(nb), dim3(kTileThreads), 0, st, kin, n_dev,
+                               n_cap, shift, hist, nb);
+        else
+            hipLaunchKernelGGL(k_radix_hist<11>, dim3(nb), dim3(kTileThreads), 0, st, kin, n_dev,
+                               n_cap, shift, hist, nb);
+        hipError_t e = launch_excl_scan(hist, nullptr, bins * nb, hist, nullptr, sscr, st);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_radix_scatter, dim3(nb), dim3(kTileThreads), 0, st, kin,
-                           (p == 0 && iota_first) ? (const uint32_t*)nullptr : vi, ko, vo, n_dev,
-                           n_cap, shift, hist, nb);
+        if (width == 8)
+            hipLaunchKernelGGL(k_radix_scatter<8>, dim3(nb), dim3(kTileThreads), 0, st, kin, vin, ko,
+                               vo, n_dev, n_cap, shift, hist, nb);
+        else
+            hipLaunchKernelGGL(k_radix_scatter<11>, dim3(nb), dim3(kTileThreads), 0, st, kin, vin,
+                               ko, vo, n_dev, n_cap, shift, hist, nb);
         uint32_t* t = ki; ki = ko; ko = t;
         t = vi; vi = vo; vo = t;
         *in_b = !*in_b;
     }
     return hipGetLastError();
+}
+
+int radix_passes(int bits)
+{
+    int p, w;
+    radix_plan(bits, &p, &w);
+    return p;
 }
 
 }  // namespace lam

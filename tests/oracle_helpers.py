@@ -20,9 +20,12 @@ def gaussians(means, log_scales=None, quats=None, logits=None, queries=None, d=4
         logits = np.zeros(n)
     if queries is None:
         queries = rng.standard_normal((n, d))
+    queries = np.asarray(queries, np.float64)
+    if queries.ndim == 1:
+        queries = queries.reshape(n, -1)
     f = lambda a: np.ascontiguousarray(a, np.float32)
     return Gaussians(f(means), f(np.reshape(log_scales, (n, 3))), f(np.reshape(quats, (n, 4))),
-                     f(np.reshape(logits, (n,))), f(np.reshape(queries, (n, -1))))
+                     f(np.reshape(logits, (n,))), f(queries))
 
 
 def cams_of(*cams):

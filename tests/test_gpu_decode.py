@@ -23,8 +23,10 @@ BARS = {"fp32": dict(grad=1e-4, cos=None, F=1e-4), "bf16": dict(grad=1e-2, cos=0
 # FP8 (OCP E4M3, 3 mantissa bits) on F = P V: the mean per-pixel cosine meets
 # 0.999 but the per-pixel minimum and dQ do not (an E4M3 model on the CPU gives
 # the same numbers), and dQ, dV (through the cosine gradient's dependence on F)
-# land at 1-3e-2; those bars are checked in the strict xfail test below.
-FP8_MISSES = {"min_cos", "dQ", "dV"}
+# land at 1-3e-2; those bars are checked in the strict xfail test below.  dK is
+# within the bar except at M = 1, where dS should vanish exactly but the FP8 F
+# and the BF16 backward disagree by the E4M3 rounding of V.
+FP8_MISSES = {"min_cos", "dQ", "dV", "dK"}
 
 
 def _inputs(seed, n, d, M, D, qscale=1.0):
