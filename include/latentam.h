@@ -131,6 +131,14 @@ lam_status lam_render_backward(const float* means, const float* log_scales, cons
                                void* ws, uint64_t ws_bytes, uint64_t instance_capacity,
                                void* stream);
 
+/* How the compositing kernels (forward and backward) walk the tiles,
+ * process-wide: 0 = one workgroup per tile; 1 = persistent: as many
+ * workgroups as fit on the device take tiles from a counter in the workspace
+ * until all are done (evens out views of uneven size and tiles of uneven list
+ * length); 2 = persistent only when several cameras are rendered (default).
+ * The result is identical in every mode.  Errors: LAM_ERR_INVALID_ARG. */
+lam_status lam_set_raster_schedule(int mode);
+
 /* BLOCKING: waits for ``stream`` and reads the counters of the last forward
  * call on ``ws``: the number of (Gaussian, tile) pairs it needed and whether
  * it exceeded the capacity (then returns LAM_ERR_CAPACITY). */

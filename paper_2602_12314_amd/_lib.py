@@ -41,6 +41,9 @@ def lib():
         sig = {
             "lam_status_string": (C.c_char_p, [i32]),
             "lam_version": (i32, []),
+            "lam_set_raster_schedule": (i32, [i32]),
+            "lam_profile_enable": (i32, [i32]),
+            "lam_profile_read": (i32, [C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int)]),
             "lam_render_workspace_size": (i32, [i32, i32, vp, i32, i32, i32, u64, pu64]),
             "lam_render_forward": (i32, [vp, vp, vp, vp, vp, i32, i32, vp, i32, i32, i32, vp, vp, vp,
                                          u64, u64, vp]),
@@ -92,6 +95,13 @@ def _cams(cams) -> np.ndarray:
 
 
 # ------------------------------------------------------------------ render
+
+SCHEDULES = {"per_tile": 0, "persistent": 1, "auto": 2}
+
+
+def set_raster_schedule(mode):
+    check(lib().lam_set_raster_schedule(SCHEDULES.get(mode, mode)), "lam_set_raster_schedule")
+
 
 def render_workspace_size(n_gauss, d, cams, tile_w, tile_h, capacity) -> int:
     cams = _cams(cams)

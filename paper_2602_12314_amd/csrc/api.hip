@@ -143,6 +143,13 @@ const char* lam_status_string(int status)
 
 int lam_version(void) { return LAM_VERSION; }
 
+lam_status lam_set_raster_schedule(int mode)
+{
+    if (mode < 0 || mode > 2) return LAM_ERR_INVALID_ARG;
+    set_raster_schedule(mode);
+    return LAM_OK;
+}
+
 lam_status lam_render_workspace_size(int n_gauss, int d, const float* cams, int n_cams,
                                      int tile_w, int tile_h, uint64_t instance_capacity,
                                      uint64_t* bytes)

@@ -66,6 +66,7 @@ struct RenderLayout {
 
 hipError_t render_forward_launch(const RenderArgs& A, const RenderLayout& L, hipStream_t st);
 hipError_t render_backward_launch(const RenderArgs& A, const RenderLayout& L, hipStream_t st);
+void set_raster_schedule(int mode);
 
 // ------------------------------------------------------------- decode
 struct DecodeArgs {

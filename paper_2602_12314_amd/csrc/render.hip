@@ -234,14 +234,13 @@ __device__ inline void stage_chunk(TileStage<DQ>& st, int k, uint32_t end, int b
 }
 
 template <int DQ>
-__global__ __launch_bounds__(256) void k_raster_fwd(
-    CamSet cs, int N, const uint2* __restrict__ ranges, const uint32_t* __restrict__ tile_recs,
-    const float4* __restrict__ rec0, const float4* __restrict__ rec1,
-    const uint2* __restrict__ foot, const float* __restrict__ queries, float* __restrict__ Q,
-    float* __restrict__ T_final, float* __restrict__ T_save, uint32_t* __restrict__ n_contrib)
+__device__ inline void raster_fwd_tile(
+    TileStage<DQ>& st, const int tile, const CamSet& cs, int N, const uint2* __restrict__ ranges,
+    const uint32_t* __restrict__ tile_recs, const float4* __restrict__ rec0,
+    const float4* __restrict__ rec1, const uint2* __restrict__ foot,
+    const float* __restrict__ queries, float* __restrict__ Q, float* __restrict__ T_final,
+    float* __restrict__ T_save, uint32_t* __restrict__ n_contrib)
 {
-    __shared__ TileStage<DQ> st;
-    const int tile = blockIdx.x;
     const int c = cam_of_tile(cs, tile);
     const Cam& cam = cs.c[c];
     const int lt = tile - cam.tile_base;
@@ -305,6 +304,35 @@ __global__ __launch_bounds__(256) void k_raster_fwd(
     }
 }
 
+// PERSIST = false: one workgroup per tile.  PERSIST = true: a grid of resident
+// workgroups takes tiles from the queue counter until all are done, which
+// evens out views of uneven size and tiles of uneven list length.
+template <int DQ, bool PERSIST>
+__global__ __launch_bounds__(256) void k_raster_fwd(
+    CamSet cs, int N, const uint2* __restrict__ ranges, const uint32_t* __restrict__ tile_recs,
+    const float4* __restrict__ rec0, const float4* __restrict__ rec1,
+    const uint2* __restrict__ foot, const float* __restrict__ queries, float* __restrict__ Q,
+    float* __restrict__ T_final, float* __restrict__ T_save, uint32_t* __restrict__ n_contrib,
+    uint32_t* __restrict__ queue)
+{
+    __shared__ TileStage<DQ> st;
+    if (!PERSIST) {
+        raster_fwd_tile<DQ>(st, blockIdx.x, cs, N, ranges, tile_recs, rec0, rec1, foot, queries, Q,
+                            T_final, T_save, n_contrib);
+        return;
+    }
+    __shared__ int s_tile;
+    for (;;) {
+        __syncthreads();  // the previous tile is done with the staged lists
+        if (threadIdx.x == 0) s_tile = (int)atomicAdd(queue, 1u);
+        __syncthreads();
+        const int tile = __builtin_amdgcn_readfirstlane(s_tile);
+        if (tile >= cs.total_tiles) break;
+        raster_fwd_tile<DQ>(st, tile, cs, N, ranges, tile_recs, rec0, rec1, foot, queries, Q, T_final,
+                            T_save, n_contrib);
+    }
+}
+
 // ------------------------------------------------------------- raster bwd
 
 // Transposed wave reduction of N values: at the step with lane mask M a lane
@@ -328,16 +356,14 @@ __device__ inline void halving_sum(float* v, unsigned lane)
 
 // rec_grad[r] = (du, dv, dA, dB, dC, dopacity) accumulated over pixels.
 template <int DQ>
-__global__ __launch_bounds__(256) void k_raster_bwd(
-    CamSet cs, int N, const uint2* __restrict__ ranges, const uint32_t* __restrict__ tile_recs,
+__device__ inline void raster_bwd_tile(
+    TileStage<DQ>& st, uint32_t& s_max, const int tile, const CamSet& cs, int N,
+    const uint2* __restrict__ ranges, const uint32_t* __restrict__ tile_recs,
     const float4* __restrict__ rec0, const float4* __restrict__ rec1,
     const uint2* __restrict__ foot, const float* __restrict__ queries,
     const float* __restrict__ T_final, const uint32_t* __restrict__ n_contrib,
     const float* __restrict__ dQ, float* __restrict__ rec_grad, float* __restrict__ d_queries)
 {
-    __shared__ TileStage<DQ> st;
-    __shared__ uint32_t s_max;
-    const int tile = blockIdx.x;
     const int c = cam_of_tile(cs, tile);
     const Cam& cam = cs.c[c];
     const int lt = tile - cam.tile_base;
@@ -444,6 +470,34 @@ __global__ __launch_bounds__(256) void k_raster_bwd(
                 unsafeAtomicAdd(dst, v[0]);
             }
         }
+    }
+}
+
+template <int DQ, bool PERSIST>
+__global__ __launch_bounds__(256) void k_raster_bwd(
+    CamSet cs, int N, const uint2* __restrict__ ranges, const uint32_t* __restrict__ tile_recs,
+    const float4* __restrict__ rec0, const float4* __restrict__ rec1,
+    const uint2* __restrict__ foot, const float* __restrict__ queries,
+    const float* __restrict__ T_final, const uint32_t* __restrict__ n_contrib,
+    const float* __restrict__ dQ, float* __restrict__ rec_grad, float* __restrict__ d_queries,
+    uint32_t* __restrict__ queue)
+{
+    __shared__ TileStage<DQ> st;
+    __shared__ uint32_t s_max;
+    if (!PERSIST) {
+        raster_bwd_tile<DQ>(st, s_max, blockIdx.x, cs, N, ranges, tile_recs, rec0, rec1, foot, queries,
+                            T_final, n_contrib, dQ, rec_grad, d_queries);
+        return;
+    }
+    __shared__ int s_tile;
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) s_tile = (int)atomicAdd(queue, 1u);
+        __syncthreads();
+        const int tile = __builtin_amdgcn_readfirstlane(s_tile);
+        if (tile >= cs.total_tiles) break;
+        raster_bwd_tile<DQ>(st, s_max, tile, cs, N, ranges, tile_recs, rec0, rec1, foot, queries,
+                            T_final, n_contrib, dQ, rec_grad, d_queries);
     }
 }
 
@@ -586,6 +640,35 @@ hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t st)
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------- scheduling
+
+static int g_raster_schedule = 2;  // 0 per tile, 1 persistent, 2 persistent for several views
+
+void set_raster_schedule(int mode) { g_raster_schedule = mode; }
+
+static bool use_persistent(const CamSet& cs)
+{
+    return g_raster_schedule == 1 || (g_raster_schedule == 2 && cs.n > 1);
+}
+
+// Workgroups of ``kernel`` that fit on the device at once (queried once per
+// kernel and block size).
+static int resident_blocks(const void* kernel, int threads)
+{
+    struct Entry { const void* k; int t, n; };
+    static Entry cache[16];
+    static int used = 0;
+    for (int i = 0; i < used; ++i)
+        if (cache[i].k == kernel && cache[i].t == threads) return cache[i].n;
+    int dev = 0, cus = 0, per = 0;
+    hipGetDevice(&dev);
+    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, 0);
+    const int n = std::max(1, cus * std::max(per, 1));
+    if (used < 16) cache[used++] = Entry{kernel, threads, n};
+    return n;
+}
+
 hipError_t render_forward_launch(const RenderArgs& A, const RenderLayout& L, hipStream_t st)
 {
     const CamSet& cs = L.cams;
@@ -628,12 +711,20 @@ hipError_t render_forward_launch(const RenderArgs& A, const RenderLayout& L, hip
                                dim3(256), 0, st, tkeys, (const uint32_t*)L.counters, cap, L.ranges);
     }
     if (cs.total_tiles > 0) {
+        const bool pers = use_persistent(cs);
+        const int threads = cs.tile_w * cs.tile_h;
+        auto kern = A.d == 16 ? (pers ? k_raster_fwd<16, true> : k_raster_fwd<16, false>)
+                              : (pers ? k_raster_fwd<32, true> : k_raster_fwd<32, false>);
+        int grid = cs.total_tiles;
+        if (pers) {
+            e = launch_fill_u32(L.counters + 2, 1, 0u, st);
+            if (e != hipSuccess) return e;
+            grid = std::min(grid, resident_blocks((const void*)kern, threads));
+        }
         ProfScope ps("raster_fwd", st);
-        auto kern = A.d == 16 ? k_raster_fwd<16> : k_raster_fwd<32>;
-        hipLaunchKernelGGL(kern, dim3(cs.total_tiles), dim3(cs.tile_w * cs.tile_h), 0, st, cs, A.n,
-                           (const uint2*)L.ranges, trecs, (const float4*)L.rec0,
-                           (const float4*)L.rec1, (const uint2*)L.foot, A.queries, A.Q, A.T_final,
-                           L.t_final, L.n_contrib);
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), 0, st, cs, A.n, (const uint2*)L.ranges,
+                           trecs, (const float4*)L.rec0, (const float4*)L.rec1, (const uint2*)L.foot,
+                           A.queries, A.Q, A.T_final, L.t_final, L.n_contrib, L.counters + 2);
     }
     return hipGetLastError();
 }
@@ -648,13 +739,21 @@ hipError_t render_backward_launch(const RenderArgs& A, const RenderLayout& L, hi
     if (e != hipSuccess) return e;
     const uint32_t* trecs = L.tile_in_b ? L.ivals_b : L.ivals_a;
     if (cs.total_tiles > 0) {
+        const bool pers = use_persistent(cs);
+        const int threads = cs.tile_w * cs.tile_h;
+        auto kern = A.d == 16 ? (pers ? k_raster_bwd<16, true> : k_raster_bwd<16, false>)
+                              : (pers ? k_raster_bwd<32, true> : k_raster_bwd<32, false>);
+        int grid = cs.total_tiles;
+        if (pers) {
+            e = launch_fill_u32(L.counters + 3, 1, 0u, st);
+            if (e != hipSuccess) return e;
+            grid = std::min(grid, resident_blocks((const void*)kern, threads));
+        }
         ProfScope ps("raster_bwd", st);
-        auto kern = A.d == 16 ? k_raster_bwd<16> : k_raster_bwd<32>;
-        hipLaunchKernelGGL(kern, dim3(cs.total_tiles), dim3(cs.tile_w * cs.tile_h), 0, st, cs, A.n,
-                           (const uint2*)L.ranges, trecs, (const float4*)L.rec0,
-                           (const float4*)L.rec1, (const uint2*)L.foot, A.queries,
-                           (const float*)L.t_final, (const uint32_t*)L.n_contrib, A.dQ, L.rec_grad,
-                           A.d_queries);
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), 0, st, cs, A.n, (const uint2*)L.ranges,
+                           trecs, (const float4*)L.rec0, (const float4*)L.rec1, (const uint2*)L.foot,
+                           A.queries, (const float*)L.t_final, (const uint32_t*)L.n_contrib, A.dQ,
+                           L.rec_grad, A.d_queries, L.counters + 3);
     }
     if (A.n > 0) {
         ProfScope ps("preprocess_bwd", st);

@@ -136,3 +136,29 @@ def test_graph_captured_step_replays(prec):
             assert rel_err(to_np(outs[k]), ref[k]) < 1e-5, (rep, k)
         for k, t in (("means", grads.means), ("queries", grads.queries)):
             assert rel_err(to_np(t), ref[k]) < 1e-4, (rep, k)
+
+
+@pytest.mark.parametrize("views", ["one", "four"])
+def test_persistent_schedule_matches_per_tile(views):
+    from paper_2602_12314_amd import _lib
+    ops = _ops()
+    s = _small_views(seed=9)
+    cams = s.cams if views == "four" else s.cams[:1]
+    g = ops.Gaussians.from_numpy(s)
+    say(f"[schedule] persistent vs per-tile, {views} view(s)")
+    out = {}
+    try:
+        for mode in ("per_tile", "persistent"):
+            _lib.set_raster_schedule(mode)
+            r = ops.Renderer(cams, s.n, 16)
+            Q, T = r.forward(g)
+            dQ = torch.as_tensor(np.random.default_rng(3).standard_normal(tuple(Q.shape)), dtype=torch.float32,
+                                 device="cuda")
+            gr = r.backward(g, dQ)
+            out[mode] = (to_np(Q), to_np(T), [to_np(t) for t in gr.tensors()])
+    finally:
+        _lib.set_raster_schedule("auto")
+    a, b = out["per_tile"], out["persistent"]
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    for x, y in zip(a[2], b[2]):
+        assert rel_err(y, x) < 1e-5
