@@ -14,7 +14,6 @@ path for comparison, and the FP64 CPU oracle timed on the host.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -36,29 +35,55 @@ def _log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash() -> str:
-    h = hashlib.sha256()
-    for name in sorted(os.listdir(os.path.join(ROOT, "paper_2602_12314_amd", "csrc"))):
-        with open(os.path.join(ROOT, "paper_2602_12314_amd", "csrc", name), "rb") as fh:
-            h.update(name.encode() + fh.read())
-    return h.hexdigest()[:16]
+def algorithmic_work(spec, prec: str, pairs_eval: int, pairs_blend: int, tile_pairs: int):
+    """Algorithmic flops and HBM bytes per launch of each main kernel.
 
-
-def algorithmic_work(spec, pairs_eval: int, pairs_blend: int):
-    """Algorithmic flops / bytes per launch of each main kernel."""
+    Bytes count what the kernel must move to and from HBM once: its per-pixel
+    inputs and outputs, the per-pair records of the tile lists, and the
+    operands it hands to the next kernel.  The dictionary (K, V) is read from
+    the L2 cache and counted once per launch.
+    """
     n, d, M, D = spec.n_pixels, spec.d, spec.M, spec.D
+    N = spec.n_gauss * len(spec.cams)
+    tb = 4 if prec == "fp32" else 2  # bytes of the decode's compute type
+    dict_bytes = tb * (2 * M * D + 2 * M * d)
+    entry = 44 + 4 * d  # one tile-list entry: record id, rec0, rec1, footprint, query
     return {
-        # MFMA: S = Q K^T (2Md), F = P V (2MD), dP = G V^T (2MD), dQ = dS K (2Md) per pixel
-        "decode_rows": dict(flops=n * 4.0 * M * (d + D), bound="mfma"),
-        # MFMA: dV = P^T G, 2MD per pixel
-        "decode_tn": dict(flops=n * 2.0 * M * D, bound="mfma"),
+        # MFMA: S = Q K^T (2Md), F = P V (2MD), dP = G V^T (2MD), dQ = dS K (2Md) per pixel.
+        # Bytes: Q and the target in (FP32), P~^T, G^T, dS^T and Q^T out (compute type).
+        "decode_rows": dict(flops=n * 4.0 * M * (d + D), mfma=True,
+                            bytes=n * (4.0 * d + 4.0 * D + tb * (2 * M + D + 32)) + dict_bytes),
+        # MFMA: dV = P~^T G, 2MD per pixel; bytes: P~^T and G^T in, split partials out.
+        "decode_tn": dict(flops=n * 2.0 * M * D, mfma=True, bytes=n * tb * (M + D)),
         # VALU: per evaluated pair 20 flops (offset, conic form, exp, opacity, clamp,
-        # transmittance); per blended pair 2d more for the query accumulation
-        "raster_fwd": dict(flops=20.0 * pairs_eval + 2.0 * d * pairs_blend, bound="alu"),
+        # transmittance); per blended pair 2d more for the query accumulation.
+        # Bytes: the tile lists, and Q, T (twice) and the contributor count per pixel.
+        "raster_fwd": dict(flops=20.0 * pairs_eval + 2.0 * d * pairs_blend, mfma=False,
+                           bytes=tile_pairs * entry + n * (4.0 * d + 12)),
         # VALU: per blended pair 45 + 9d flops (alpha and transmittance rebuild,
-        # dq, dalpha, behind-sum update, conic/mean/opacity terms)
-        "raster_bwd": dict(flops=(45.0 + 9.0 * d) * pairs_blend, bound="alu"),
+        # dq, dalpha, behind-sum update, conic/mean/opacity terms).  Bytes: the tile
+        # lists, dQ, T and the count per pixel, and the per-record gradients.
+        "raster_bwd": dict(flops=(45.0 + 9.0 * d) * pairs_blend, mfma=False,
+                           bytes=tile_pairs * entry + n * (4.0 * d + 8) + N * (24.0 + 4 * d)),
     }
+
+
+def roofline(work: dict, ms: float, prec: str) -> dict:
+    """Which roof binds at the kernel's algorithmic intensity, and how close it is."""
+    if work["mfma"]:
+        fpeak = {"bf16": PEAKS["bf16_tflops"], "fp8": PEAKS["fp8_tflops"]}.get(prec, PEAKS["fp32_mfma_tflops"])
+    else:
+        fpeak = PEAKS["fp32_vector_tflops"]
+    t_flop = work["flops"] / (fpeak * 1e12)
+    t_hbm = work["bytes"] / (PEAKS["hbm_gbs"] * 1e9)
+    sec = ms * 1e-3
+    if t_hbm >= t_flop:
+        ach = work["bytes"] / sec / 1e9
+        return {"bound": "hbm", "achieved": ach, "peak": PEAKS["hbm_gbs"], "unit": "GB/s",
+                "frac": ach / PEAKS["hbm_gbs"]}
+    ach = work["flops"] / sec / 1e12
+    return {"bound": "mfma" if work["mfma"] else "alu", "achieved": ach, "peak": fpeak,
+            "unit": "TFLOP/s", "frac": ach / fpeak}
 
 
 def run(args):
@@ -209,19 +234,15 @@ def run(args):
         cpu, pairs_eval, pairs_blend = cpu_baseline(s, spec)
     else:
         pairs_eval, pairs_blend = oracle_pairs(s)
-    work = algorithmic_work(spec, pairs_eval, pairs_blend)
+    work = algorithmic_work(spec, prec, pairs_eval, pairs_blend, pairs)
     dom = max((k for k in prof if k in work), key=lambda k: prof[k])
     ms = prof[dom]
-    w = work[dom]
-    achieved = w["flops"] / (ms * 1e-3) / 1e12
-    if w["bound"] == "mfma":
-        peak = PEAKS["bf16_tflops"] if prec in ("bf16",) else (
-            PEAKS["fp8_tflops"] if prec == "fp8" else PEAKS["fp32_mfma_tflops"])
-    else:
-        peak = PEAKS["fp32_vector_tflops"]
-    out["roofline"] = {"kernel": dom, "bound": w["bound"], "achieved": achieved, "peak": peak,
-                       "unit": "TFLOP/s", "frac": achieved / peak, "kernel_ms": ms,
-                       "traffic": traffic_for(dom, spec.name)}
+    rl = roofline(work[dom], ms, prec)
+    out["roofline"] = dict(kernel=dom, **rl, kernel_ms=ms, algorithmic_bytes=work[dom]["bytes"],
+                           algorithmic_flops=work[dom]["flops"], traffic=traffic_for(dom, spec.name))
+    out["kernels"] = {k: dict(ms=round(prof[k], 4), **{kk: (round(vv, 4) if isinstance(vv, float) else vv)
+                                                        for kk, vv in roofline(work[k], prof[k], prec).items()})
+                      for k in work if k in prof}
     out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 
@@ -235,14 +256,17 @@ def _read_prof(L, name):
 
 def traffic_for(kernel, workload):
     """HBM bytes per launch from the committed rocprofv3 --pmc summary, if it
-    was taken on the current kernel sources; otherwise null."""
+    was taken on the current sources of that kernel; otherwise null."""
+    from paper_2602_12314_amd import profiling
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         rec = json.load(open(path))
     except (OSError, ValueError):
         return None
     ent = rec.get(workload, {}).get(kernel)
-    if not ent or ent.get("source_hash") != kernel_source_hash():
+    if not ent or kernel not in profiling.STAGES:
+        return None
+    if ent.get("source_hash") != profiling.source_hash(profiling.STAGES[kernel][1]):
         return None
     return ent.get("bytes_per_launch")
 
@@ -310,8 +334,9 @@ def main():
         print(json.dumps({"copy_bytes_per_launch": a.numel() * 4, "launches": 5}), flush=True)
         return
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
-              "(the multi-GPU design is described in DESIGN.md)", file=sys.stderr)
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(every stage is per view and per pixel block, so views would be split across GPUs "
+              "with one gradient all-reduce per step; that path is not built)", file=sys.stderr)
         sys.exit(2)
     run(args)
 

@@ -4,6 +4,9 @@ Flags:
   -munsafe-fp-atomics            hardware float atomics (global_atomic_add_f32)
   -Xclang -target-feature -Xclang -packed-fp32-ops
                                  no packed FP32 VALU instructions
+  -mllvm -amdgpu-mfma-vgpr-form  MFMA results in VGPRs rather than AGPRs, which
+                                 saves the AGPR<->VGPR copies around the VALU
+                                 epilogues of the decode kernels
 """
 from __future__ import annotations
 
@@ -31,6 +34,7 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     flags = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-munsafe-fp-atomics",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+             "-mllvm", "-amdgpu-mfma-vgpr-form",
              "-Wno-unused-result", "-Wno-unknown-pragmas"]
     objs = []
     procs = []

@@ -96,6 +96,11 @@ struct TBF16 {
     }
 };
 
+// 2^x for the softmax weights, whose arguments (logit minus the row max) are
+// never positive: the hardware exp2 without the range fix-ups of exp2f (a
+// result below the FP32 normal range becomes zero, which the sums ignore).
+__device__ inline float exp2_weight(float x) { return __builtin_amdgcn_exp2f(x); }
+
 // Row of the 32x32 MFMA result held in register r of lane l (column = l % 32).
 __device__ inline int crow(int r, int h) { return 8 * (r >> 2) + 4 * h + (r & 3); }
 
@@ -104,12 +109,50 @@ __device__ inline int crow(int r, int h) { return 8 * (r >> 2) + 4 * h + (r & 3)
 // 8c + t, i.e. atom 8 (t / 4) + 4 h + t % 4.
 __host__ __device__ inline int perm16(int k) { return 8 * ((k & 7) >> 2) + 4 * (k >> 3) + (k & 3); }
 
+// Fragment-major operand layout.  An operand X[R][C] (R a multiple of 32, C of
+// 16) used with its row as the MFMA row/column and C as the K dimension is
+// stored block by block: block (row / 32, k / 16) holds 64 lanes x 8 elements,
+// element (row, k) at lane 32 (k / 8 % 2) + row % 32, slot k % 8.  A wave's
+// fragment load is then one contiguous run instead of 32 strided rows.  The
+// E4M3 operand uses K chunks of 64: 64 lanes x 32 bytes, lane 32 (k / 32 % 2) +
+// row % 32, byte k % 32.
+// Fragment (row block rb, K chunk c) of a fragment-major operand with nc chunks.
+template <class P>
+__device__ inline typename P::Frag load_frag(const typename P::T* X, int rb, int c, int nc, int lane)
+{
+    return P::load(X + ((((size_t)rb * nc + c) << 6) + lane) * 8);
+}
+
+// Row stride (elements) of a wave's dS scratch tile [32 pixels][32 atoms + pad].
+constexpr int kScLd = 40;
+
+// Rows [0, nrows) of the transpose of an LDS tile S[pixel][row] (32 pixels,
+// leading dimension ld) written to Dst[row][32 pixels] in HBM, one chunk of 8
+// pixels (16 bytes in BF16) per store: chunk q = q0, q0 + dq, ... covers row
+// q / 4, pixels 8 (q % 4) .. + 7.  This turns the one-pixel-per-lane MFMA
+// result layout into whole-chunk stores of the pixel-blocked transposes.
+template <class P>
+__device__ inline void store_transposed(const typename P::T* S, int ld, int nrows, typename P::T* Dst,
+                                        int q0, int dq)
+{
+    for (int q = q0; q < nrows * 4; q += dq) {
+        const int row = q >> 2, pg = (q & 3) * 8;
+        typename P::Frag f;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) f[j] = S[(pg + j) * ld + row];
+        *reinterpret_cast<typename P::Frag*>(Dst + (size_t)row * kPx + pg) = f;
+    }
+}
+
 // ------------------------------------------------------------ prep
 
-// Kb [Mp, d]   K in the compute type, rows >= M zero
-// Vb [Mp, D]   V in the compute type
-// Vt [D, Mp]   V transposed
-// Ktp [32, Mp] K transposed, rows >= d zero, atoms permuted by perm16 in each 16-chunk
+// All four in the fragment-major layout (frag_index), converted to the compute type:
+// Kb  = K   [Mp][d]   rows >= M zero
+// Vb  = V   [Mp][D]
+// Vt  = V^T [D][Mp]
+// Ktp = K^T [32][Mp]  rows >= d zero, atoms permuted by perm16 in each 16-chunk
+// Each thread writes consecutive destination elements (reads of K and V are
+// scattered; both are small and cached).
 template <class P>
 __global__ __launch_bounds__(256) void k_dec_prep(const float* __restrict__ K, const float* __restrict__ V,
                                                   int M, int Mp, int d, int D, typename P::T* Kb,
@@ -118,19 +161,30 @@ __global__ __launch_bounds__(256) void k_dec_prep(const float* __restrict__ K, c
 {
     const size_t tid = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
     const size_t stride = (size_t)gridDim.x * blockDim.x;
+    // inverse of frag_index for an operand with C columns
+    auto rowk = [](size_t i, int C, int& row, int& k) {
+        const int e = (int)(i & 7), lane = (int)((i >> 3) & 63);
+        const size_t blk = i >> 9;
+        const int nc = C >> 4;
+        row = (int)(blk / nc) * 32 + (lane & 31);
+        k = (int)(blk % nc) * 16 + (lane >> 5) * 8 + e;
+    };
+    int row, k;
     for (size_t i = tid; i < (size_t)Mp * D; i += stride) {
-        const int a = (int)(i / D), c = (int)(i % D);
-        const float v = a < M ? V[(size_t)a * D + c] : 0.0f;
-        Vb[i] = P::cvt(v);
-        if (Vt) Vt[(size_t)c * Mp + a] = P::cvt(v);
+        rowk(i, D, row, k);  // row = atom, k = feature
+        Vb[i] = P::cvt(row < M ? V[(size_t)row * D + k] : 0.0f);
+        if (Vt) {
+            rowk(i, Mp, row, k);  // row = feature, k = atom
+            Vt[i] = P::cvt(k < M ? V[(size_t)k * D + row] : 0.0f);
+        }
     }
     for (size_t i = tid; i < (size_t)Mp * d; i += stride) {
-        const int a = (int)(i / d);
-        Kb[i] = P::cvt(a < M ? K[i] : 0.0f);
+        rowk(i, d, row, k);
+        Kb[i] = P::cvt(row < M ? K[(size_t)row * d + k] : 0.0f);
     }
     for (size_t i = tid; i < (size_t)32 * Mp; i += stride) {
-        const int row = (int)(i / Mp), slot = (int)(i % Mp);
-        const int a = (slot & ~15) + perm16(slot & 15);
+        rowk(i, Mp, row, k);
+        const int a = (k & ~15) + perm16(k & 15);
         Ktp[i] = P::cvt((row < d && a < M) ? K[(size_t)a * d + row] : 0.0f);
     }
 }
@@ -169,8 +223,9 @@ __device__ inline uint8_t to_e4m3(float x)
     return (uint8_t)(__builtin_amdgcn_cvt_pk_fp8_f32(x, 0.0f, 0, false) & 0xFF);
 }
 
-// Vt8 = E4M3(V / s^V) transposed [D, Mp]; sv_fold = s^V * 448 / max s^V and
-// unscale = max s^V / 448.  Kb, Vb, Ktp are filled by k_dec_prep<TBF16>.
+// Vt8 = E4M3(V / s^V) transposed [D][Mp] in the E4M3 fragment-major layout
+// (frag8_index); sv_fold = s^V * 448 / max s^V and unscale = max s^V / 448.
+// Kb, Vb, Ktp are filled by k_dec_prep<TBF16>.
 __global__ __launch_bounds__(256) void k_dec_prep_fp8(const float* __restrict__ V, int M, int Mp, int D,
                                                       const float* __restrict__ sc, uint8_t* Vt8,
                                                       float* sv_fold, float* unscale)
@@ -178,12 +233,16 @@ __global__ __launch_bounds__(256) void k_dec_prep_fp8(const float* __restrict__ 
     const size_t tid = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     const float vmax = __uint_as_float(reinterpret_cast<const unsigned*>(sc)[2 * Mp]);
+    const int nc = Mp >> 6;
     for (size_t i = tid; i < (size_t)Mp * D; i += stride) {
-        const int a = (int)(i / D), c = (int)(i % D);
+        const int e = (int)(i & 31), lane = (int)((i >> 5) & 63);
+        const size_t blk = i >> 11;
+        const int c = (int)(blk / nc) * 32 + (lane & 31);       // feature
+        const int a = (int)(blk % nc) * 64 + (lane >> 5) * 32 + e;  // atom
         const float s = sc[Mp + a];
         uint8_t q = 0;
         if (a < M && s > 0.f) q = to_e4m3(V[(size_t)a * D + c] / s);
-        Vt8[(size_t)c * Mp + a] = q;
+        Vt8[i] = q;
     }
     for (size_t i = tid; i < (size_t)Mp; i += stride)
         sv_fold[i] = vmax > 0.f ? sc[Mp + i] * (kFp8Max / vmax) : 0.0f;
@@ -219,15 +278,28 @@ struct RowsArgs {
     void* Qt;   // [blocks, 32, 32]  Q^T (rows >= d zero)
 };
 
+// Chunks of fragments kept in flight by the contraction loops (a ring of
+// registers).  Two suffice once two or more waves share a SIMD, and keep the
+// register count within the budget of two waves per SIMD; callers rely on the
+// depth dividing 4 (the chunk counts are multiples of 4).
+template <class P, int TILES>
+constexpr int pipe_depth()
+{
+    return 2;
+}
+
 template <class P, int NT, int DQ, int MODE, bool F8>
 __global__ __launch_bounds__(kRowsThreads) void k_dec_rows(RowsArgs a)
 {
     using T = typename P::T;
     using Frag = typename P::Frag;
+    constexpr int NQ = DQ / 16;  // K chunks of the logits contraction
     extern __shared__ __align__(16) char smem[];
-    // LDS: red [4][32] x 4 floats, then region X (P~ [32][Mp+8], later G [32][D+8], later dQ red)
+    // LDS: red [16][32] floats, the waves' dS scratch tiles [4][32][kScLd], then
+    // region X (P~ [32][Mp+8], later G [32][D+8], later the dQ reduction)
     float* red = reinterpret_cast<float*>(smem);
-    T* X = reinterpret_cast<T*>(smem + 4 * 4 * kPx * sizeof(float));
+    T* Wsc = reinterpret_cast<T*>(smem + 4 * 4 * kPx * sizeof(float)) + (threadIdx.x / kWave) * kPx * kScLd;
+    T* X = reinterpret_cast<T*>(smem + 4 * 4 * kPx * sizeof(float) + 4 * kPx * kScLd * sizeof(T));
     const int ldp = a.Mp + 8, ldg = a.D + 8;
 
     const int w = threadIdx.x / kWave;
@@ -237,6 +309,8 @@ __global__ __launch_bounds__(kRowsThreads) void k_dec_rows(RowsArgs a)
     const int px = blk * kPx + col;
     const bool valid = px < a.n;
     const int ntiles = a.Mp / 32;
+    const int nca = a.Mp / 16;  // 16-wide K chunks over the atoms (a multiple of 4)
+    const int ncd = a.D / 16;   // 16-wide K chunks over the features (a multiple of 8)
 
     const T* Kb = reinterpret_cast<const T*>(a.Kb);
     const T* Vb = reinterpret_cast<const T*>(a.Vb);
@@ -244,9 +318,9 @@ __global__ __launch_bounds__(kRowsThreads) void k_dec_rows(RowsArgs a)
     const T* Ktp = reinterpret_cast<const T*>(a.Ktp);
 
     // query fragments (B operand of S^T = K Q^T): Q[px][16 c + 8 h + t]
-    Frag qf[DQ / 16];
+    Frag qf[NQ];
 #pragma unroll
-    for (int c = 0; c < DQ / 16; ++c) {
+    for (int c = 0; c < NQ; ++c) {
         float v[8];
         if (valid) {
             const float4* qp = reinterpret_cast<const float4*>(a.Q + (size_t)px * DQ + 16 * c + 8 * h);
@@ -271,24 +345,41 @@ __global__ __launch_bounds__(kRowsThreads) void k_dec_rows(RowsArgs a)
         for (int t = 0; t < 8; ++t) qt[(16 + 8 * h + t) * kPx + col] = P::cvt(0.0f);
     }
 
-    auto s_tile = [&](int tt) {
+    auto kload = [&](int tt, Frag* kf) {
+#pragma unroll
+        for (int c = 0; c < NQ; ++c) kf[c] = load_frag<P>(Kb, tt, c, NQ, lane);
+    };
+    auto s_of = [&](const Frag* kf) {
         f32x16 s = {};
 #pragma unroll
-        for (int c = 0; c < DQ / 16; ++c) {
-            const Frag kf = P::load(Kb + (size_t)(32 * tt + col) * DQ + 16 * c + 8 * h);
-            P::mma(s, kf, qf[c]);
-        }
+        for (int c = 0; c < NQ; ++c) P::mma(s, kf[c], qf[c]);
         return s;
+    };
+    // Visit the wave's atom tiles w, w + 4, ... with S^T of each; the K
+    // fragments of the next tile are in flight while one is processed.
+    auto for_tiles = [&](auto&& body) {
+        Frag ka[NQ], kb[NQ];
+        if (w < ntiles) kload(w, ka);
+        for (int tt = w; tt < ntiles; tt += 8) {
+            if (tt + 4 < ntiles) kload(tt + 4, kb);
+            body(tt, s_of(ka));
+            if (tt + 8 < ntiles) kload(tt + 8, ka);
+            if (tt + 4 < ntiles) body(tt + 4, s_of(kb));
+        }
     };
 
     // ---- pass 1: row max of the logits (in log2 units)
     float mx = -INFINITY;
-    for (int tt = w; tt < ntiles; tt += 4) {
-        const f32x16 s = s_tile(tt);
+    for_tiles([&](int tt, const f32x16& s) {
+        if (32 * tt + 32 <= a.M) {  // every atom of the tile exists
 #pragma unroll
-        for (int r = 0; r < 16; ++r)
-            if (32 * tt + crow(r, h) < a.M) mx = fmaxf(mx, s[r]);
-    }
+            for (int r = 0; r < 16; ++r) mx = fmaxf(mx, s[r]);
+        } else {
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                if (32 * tt + crow(r, h) < a.M) mx = fmaxf(mx, s[r]);
+        }
+    });
     mx = fmaxf(mx, __shfl_xor(mx, 32, kWave));
     if (h == 0) red[w * kPx + col] = mx;
     __syncthreads();
@@ -299,15 +390,17 @@ __global__ __launch_bounds__(kRowsThreads) void k_dec_rows(RowsArgs a)
     // ---- pass 2: P~ = exp2(S scale - m) into LDS [px][atom] and HBM (P~^T blocked)
     float lsum = 0.0f;
     T* Pt = reinterpret_cast<T*>(a.Pt) + (size_t)blk * a.Mp * kPx;
-    for (int tt = w; tt < ntiles; tt += 4) {
-        const f32x16 s = s_tile(tt);
+    for_tiles([&](int tt, const f32x16& s) {
         float p[16];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int atom = 32 * tt + crow(r, h);
-            p[r] = atom < a.M ? exp2f(s[r] * a.scale_log2 - m2) : 0.0f;
-            lsum += p[r];
+        for (int r = 0; r < 16; ++r) p[r] = exp2_weight(s[r] * a.scale_log2 - m2);
+        if (32 * tt + 32 > a.M) {  // padded atoms get no weight
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                if (32 * tt + crow(r, h) >= a.M) p[r] = 0.0f;
         }
+#pragma unroll
+        for (int r = 0; r < 16; ++r) lsum += p[r];
 #pragma unroll
         for (int g4 = 0; g4 < 4; ++g4) {
             const int atom0 = 32 * tt + 8 * g4 + 4 * h;
@@ -321,46 +414,89 @@ __global__ __launch_bounds__(kRowsThreads) void k_dec_rows(RowsArgs a)
             } else {
                 P::store4(X + col * ldp + atom0, p[4 * g4], p[4 * g4 + 1], p[4 * g4 + 2], p[4 * g4 + 3]);
             }
-            if (MODE != MODE_INFER) {
+            if (F8 && MODE != MODE_INFER) {  // LDS holds E4M3 weights here: store from registers
 #pragma unroll
                 for (int k = 0; k < 4; ++k) Pt[(size_t)(atom0 + k) * kPx + col] = P::cvt(p[4 * g4 + k]);
             }
         }
-    }
+    });
     lsum += __shfl_xor(lsum, 32, kWave);
     if (h == 0) red[kPx * 4 + w * kPx + col] = lsum;
     __syncthreads();
     const float l = red[4 * kPx + col] + red[5 * kPx + col] + red[6 * kPx + col] + red[7 * kPx + col];
     const float invl = 1.0f / l;
+    // P~^T of the block from the LDS copy, in whole chunks
+    if (!F8 && MODE != MODE_INFER) store_transposed<P>(X, ldp, a.Mp, Pt, threadIdx.x, kRowsThreads);
 
     // ---- F^T = V^T P~^T: wave w owns D tiles [w NT, w NT + NT)
     f32x16 acc[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[t] = f32x16{};
     if (F8) {
-        // K = 64 atoms per E4M3 MFMA; lane half h holds atoms 32 h + 0..31
+        // K = 64 atoms per E4M3 MFMA; lane half h holds atoms 32 h + 0..31.
+        // Two chunks in flight; the chunk count Mp / 64 may be odd.
+        const int nc8 = a.Mp / 64;
         const uint8_t* X8 = reinterpret_cast<const uint8_t*>(X) + col * (a.Mp + 16);
-        for (int c = 0; c < a.Mp / 64; ++c) {
+        auto bload = [&](int c) {
             const i32x4 b0 = *reinterpret_cast<const i32x4*>(X8 + 64 * c + 32 * h);
             const i32x4 b1 = *reinterpret_cast<const i32x4*>(X8 + 64 * c + 32 * h + 16);
             const i32x8 bf = {b0[0], b0[1], b0[2], b0[3], b1[0], b1[1], b1[2], b1[3]};
+            return bf;
+        };
+        // at most four D tiles per sweep over the atoms keeps the ring at 64 registers
+        constexpr int NH = NT < 4 ? NT : 4;
 #pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                const i32x8 af = *reinterpret_cast<const i32x8*>(
-                    a.Vt8 + (size_t)(32 * (w * NT + t) + col) * a.Mp + 64 * c + 32 * h);
-                acc[t] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(af, bf, acc[t], 0, 0, 0, 127, 0, 127);
+        for (int t0 = 0; t0 < NT; t0 += NH) {
+            i32x8 ra[NH], rb[NH], ba, bb;
+            auto vload = [&](int c, i32x8* af) {
+#pragma unroll
+                for (int t = 0; t < NH; ++t)
+                    af[t] = *reinterpret_cast<const i32x8*>(
+                        a.Vt8 + ((((size_t)(w * NT + t0 + t) * nc8 + c) << 6) + lane) * 32);
+            };
+            vload(0, ra);
+            ba = bload(0);
+            for (int c = 0; c < nc8; c += 2) {
+                if (c + 1 < nc8) { vload(c + 1, rb); bb = bload(c + 1); }
+#pragma unroll
+                for (int t = 0; t < NH; ++t)
+                    acc[t0 + t] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(ra[t], ba, acc[t0 + t], 0, 0,
+                                                                                   0, 127, 0, 127);
+                if (c + 2 < nc8) { vload(c + 2, ra); ba = bload(c + 2); }
+                if (c + 1 < nc8) {
+#pragma unroll
+                    for (int t = 0; t < NH; ++t)
+                        acc[t0 + t] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(rb[t], bb, acc[t0 + t], 0,
+                                                                                       0, 0, 127, 0, 127);
+                }
             }
         }
     } else {
-#pragma unroll 2
-        for (int c = 0; c < a.Mp / 16; ++c) {
-            const Frag bf = P::load(X + col * ldp + 16 * c + 8 * h);
+        // ring of PD chunks: chunk c + PD - 1 is loaded while chunk c is multiplied.
+        // The loads are unconditional (the last PD chunks are peeled) so that
+        // each MFMA waits only for its own fragments.
+        constexpr int PD = pipe_depth<P, NT>();
+        Frag ring[PD][NT], bring[PD];
+        auto fetch = [&](int slot_c, Frag* r, Frag& b) {
 #pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                const Frag af = P::load(Vt + (size_t)(32 * (w * NT + t) + col) * a.Mp + 16 * c + 8 * h);
-                P::mma(acc[t], af, bf);
+            for (int t = 0; t < NT; ++t) r[t] = load_frag<P>(Vt, w * NT + t, slot_c, nca, lane);
+            b = P::load(X + col * ldp + 16 * slot_c + 8 * h);
+        };
+#pragma unroll
+        for (int s = 0; s < PD - 1; ++s) fetch(s, ring[s], bring[s]);
+        for (int c0 = 0; c0 < nca - PD; c0 += PD) {
+#pragma unroll
+            for (int s = 0; s < PD; ++s) {
+                fetch(c0 + s + PD - 1, ring[(s + PD - 1) % PD], bring[(s + PD - 1) % PD]);
+#pragma unroll
+                for (int t = 0; t < NT; ++t) P::mma(acc[t], ring[s][t], bring[s]);
             }
         }
+        fetch(nca - 1, ring[PD - 1], bring[PD - 1]);
+#pragma unroll
+        for (int s = 0; s < PD; ++s)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) P::mma(acc[t], ring[s][t], bring[s]);
     }
     const float fscale = F8 ? invl * a.fp8_unscale[0] : invl;
 #pragma unroll
@@ -383,20 +519,24 @@ __global__ __launch_bounds__(kRowsThreads) void k_dec_rows(RowsArgs a)
     }
 
     // ---- epilogue: cosine loss gradient (LOSS) or upstream dF (ADJ).  gsc first
-    // holds the target (or dF) and is overwritten in place by G = dL/dF / l.
+    // holds the target (or dF) rows and is overwritten in place by G = dL/dF / l.
+    // (Requesting these rows before the F contraction is slower: loads retire in
+    // order, so every fragment wait of the contraction would wait for them.)
+    // A pixel past n reads row n - 1, unused since its G is zeroed through ca, cb.
     float gsc[NT][16];
+    {
+        const float* rowsrc = MODE == MODE_LOSS ? a.target : a.dF;
+        const float* prow = rowsrc + (size_t)(valid ? px : a.n - 1) * a.D;
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int g4 = 0; g4 < 4; ++g4) {
+                const float4 x = *reinterpret_cast<const float4*>(prow + 32 * (w * NT + t) + 8 * g4 + 4 * h);
+                gsc[t][4 * g4] = x.x; gsc[t][4 * g4 + 1] = x.y; gsc[t][4 * g4 + 2] = x.z; gsc[t][4 * g4 + 3] = x.w;
+            }
+    }
     float delta = 0.0f;
-    const float* rowsrc = MODE == MODE_LOSS ? a.target : a.dF;
-#pragma unroll
-    for (int t = 0; t < NT; ++t)
-#pragma unroll
-        for (int g4 = 0; g4 < 4; ++g4) {
-            const int dr = 32 * (w * NT + t) + 8 * g4 + 4 * h;
-            float4 x = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (valid) x = *reinterpret_cast<const float4*>(rowsrc + (size_t)px * a.D + dr);
-            gsc[t][4 * g4] = x.x; gsc[t][4 * g4 + 1] = x.y; gsc[t][4 * g4 + 2] = x.z; gsc[t][4 * g4 + 3] = x.w;
-        }
-    float ca = invl, cb = 0.0f;  // G = ca * row + cb * F
+    float ca = valid ? invl : 0.0f, cb = 0.0f;  // G = ca * row + cb * F (zero past n)
     if (MODE == MODE_LOSS) {
         float nf = 0.f, ft = 0.f, nt = 0.f;
 #pragma unroll
@@ -446,59 +586,92 @@ __global__ __launch_bounds__(kRowsThreads) void k_dec_rows(RowsArgs a)
     delta += __shfl_xor(delta, 32, kWave);
     __syncthreads();  // everyone is done reading P~ (region X) and red
     if (h == 0) red[12 * kPx + w * kPx + col] = delta;
-    // stage G into LDS [px][D] and write G^T blocked to HBM
-    T* Gt = reinterpret_cast<T*>(a.Gt) + (size_t)blk * a.D * kPx;
+    // stage G into LDS [px][D]
 #pragma unroll
     for (int t = 0; t < NT; ++t)
 #pragma unroll
         for (int g4 = 0; g4 < 4; ++g4) {
             const int dr = 32 * (w * NT + t) + 8 * g4 + 4 * h;
             P::store4(X + col * ldg + dr, gsc[t][4 * g4], gsc[t][4 * g4 + 1], gsc[t][4 * g4 + 2], gsc[t][4 * g4 + 3]);
-#pragma unroll
-            for (int k = 0; k < 4; ++k) Gt[(size_t)(dr + k) * kPx + col] = P::cvt(gsc[t][4 * g4 + k]);
         }
     __syncthreads();
     delta = red[12 * kPx + col] + red[13 * kPx + col] + red[14 * kPx + col] + red[15 * kPx + col];
+    // G^T of this wave's D rows from the LDS copy, in whole chunks
+    {
+        T* Gt = reinterpret_cast<T*>(a.Gt) + ((size_t)blk * a.D + 32 * w * NT) * kPx;
+        store_transposed<P>(X + 32 * w * NT, ldg, 32 * NT, Gt, lane, kWave);
+    }
 
     // ---- per atom tile: dP = G V^T, dS = P~ (dP - delta) / sqrt(d), dQ^T += K^T dS^T
     f32x16 dq = {};
     T* St = reinterpret_cast<T*>(a.St) + (size_t)blk * a.Mp * kPx;
-    auto finish_tile = [&](int tt, const f32x16& dp) {
-        const f32x16 s = s_tile(tt);
+    auto finish_tile = [&](int tt, const f32x16& dp, const Frag* kf, const Frag* kt) {
+        const f32x16 s = s_of(kf);
+        // A pixel past n has G = 0, hence dP = 0 and delta = 0, so its dS is
+        // zero without a mask; padded atoms are masked.
         float ds[16];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int atom = 32 * tt + crow(r, h);
-            const float pt = atom < a.M ? exp2f(s[r] * a.scale_log2 - m2) : 0.0f;
-            ds[r] = valid ? pt * (dp[r] - delta) * a.inv_sqrt_d : 0.0f;
-        }
+        for (int r = 0; r < 16; ++r)
+            ds[r] = exp2_weight(s[r] * a.scale_log2 - m2) * (dp[r] - delta) * a.inv_sqrt_d;
+        if (32 * tt + 32 > a.M) {
 #pragma unroll
-        for (int r = 0; r < 16; ++r) St[(size_t)(32 * tt + crow(r, h)) * kPx + col] = P::cvt(ds[r]);
-#pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            const Frag af = P::load(Ktp + (size_t)col * a.Mp + 32 * tt + 16 * c + 8 * h);
-            const Frag bf = P::from_f32(ds + 8 * c);
-            P::mma(dq, af, bf);
+            for (int r = 0; r < 16; ++r)
+                if (32 * tt + crow(r, h) >= a.M) ds[r] = 0.0f;
         }
+        // dS^T of the tile through the wave's scratch [px][atom], in whole chunks
+#pragma unroll
+        for (int g4 = 0; g4 < 4; ++g4)
+            P::store4(Wsc + col * kScLd + 8 * g4 + 4 * h, ds[4 * g4], ds[4 * g4 + 1], ds[4 * g4 + 2], ds[4 * g4 + 3]);
+        __builtin_amdgcn_wave_barrier();
+        store_transposed<P>(Wsc, kScLd, 32, St + (size_t)32 * tt * kPx, lane, kWave);
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int c = 0; c < 2; ++c) P::mma(dq, kt[c], P::from_f32(ds + 8 * c));
     };
-    // two atom tiles (tt and tt + 4) share each G fragment read from LDS
+    // Two atom tiles (tt and tt + 4) share each G fragment read from LDS; their
+    // V fragments run PG chunks ahead of the MFMAs, and the K fragments of the
+    // dS step are requested before the contraction that hides their latency.
+    constexpr int PG = pipe_depth<P, 2>();
     for (int tt = w; tt < ntiles; tt += 8) {
         const bool two = tt + 4 < ntiles;
+        Frag kf0[NQ], kf1[NQ], kt0[2], kt1[2];
+        kload(tt, kf0);
+#pragma unroll
+        for (int c = 0; c < 2; ++c) kt0[c] = load_frag<P>(Ktp, 0, 2 * tt + c, nca, lane);
+        if (two) {
+            kload(tt + 4, kf1);
+#pragma unroll
+            for (int c = 0; c < 2; ++c) kt1[c] = load_frag<P>(Ktp, 0, 2 * (tt + 4) + c, nca, lane);
+        }
         f32x16 dp0 = {}, dp1 = {};
-        const T* v0 = Vb + (size_t)(32 * tt + col) * a.D + 8 * h;
-        const T* v1 = Vb + (size_t)(32 * (tt + 4) + col) * a.D + 8 * h;
-#pragma unroll 4
-        for (int c = 0; c < a.D / 16; ++c) {
-            const Frag bf = P::load(X + col * ldg + 16 * c + 8 * h);
-            const Frag af0 = P::load(v0 + 16 * c);
-            P::mma(dp0, af0, bf);
-            if (two) {
-                const Frag af1 = P::load(v1 + 16 * c);
-                P::mma(dp1, af1, bf);
+        // a wave with an odd tile count multiplies its last tile twice and
+        // keeps one result, which keeps the loop free of branches
+        const int tt1 = two ? tt + 4 : tt;
+        Frag ra[PG], rb[PG], gb[PG];
+        auto fetch = [&](int c, Frag& x, Frag& y, Frag& g) {
+            x = load_frag<P>(Vb, tt, c, ncd, lane);
+            y = load_frag<P>(Vb, tt1, c, ncd, lane);
+            g = P::load(X + col * ldg + 16 * c + 8 * h);
+        };
+#pragma unroll
+        for (int s = 0; s < PG - 1; ++s) fetch(s, ra[s], rb[s], gb[s]);
+        for (int c0 = 0; c0 < ncd - PG; c0 += PG) {
+#pragma unroll
+            for (int s = 0; s < PG; ++s) {
+                const int sl = (s + PG - 1) % PG;
+                fetch(c0 + s + PG - 1, ra[sl], rb[sl], gb[sl]);
+                P::mma(dp0, ra[s], gb[s]);
+                P::mma(dp1, rb[s], gb[s]);
             }
         }
-        finish_tile(tt, dp0);
-        if (two) finish_tile(tt + 4, dp1);
+        fetch(ncd - 1, ra[PG - 1], rb[PG - 1], gb[PG - 1]);
+#pragma unroll
+        for (int s = 0; s < PG; ++s) {
+            P::mma(dp0, ra[s], gb[s]);
+            P::mma(dp1, rb[s], gb[s]);
+        }
+        finish_tile(tt, dp0, kf0, kt0);
+        if (two) finish_tile(tt + 4, dp1, kf1, kt1);
     }
     if (!a.dQ) return;
     __syncthreads();  // region X (G) no longer read
@@ -520,9 +693,11 @@ __global__ __launch_bounds__(kRowsThreads) void k_dec_rows(RowsArgs a)
 // C_part[split][i][j] = sum over the split's pixel blocks of A^T[i][p] B^T[j][p]
 // with A^T, B^T in the pixel-blocked transposed layout X^T[blk][row][32].
 // A wave owns WI x WJ result tiles of 32 x 32, the 4 waves are arranged
-// WVI x WVJ, so a workgroup covers (32 WI WVI) x (32 WJ WVJ).  Fragments of the
-// next pixel block are loaded before the MFMAs of the current one.  The grid
-// is tiles x splits, mapped so that the tiles of one split share an XCD.
+// WVI x WVJ, so a workgroup covers (32 WI WVI) x (32 WJ WVJ); rowsA must be a
+// multiple of 32 WI and rowsB of 32 WJ.  The fragments of RB pixel blocks are in
+// flight at once (a ring of registers, loads never skipped so that each MFMA
+// waits only for its own block).  The grid is tiles x splits, mapped so that
+// the tiles of one split share an XCD.
 template <class P, int WI, int WJ, int WVI, int WVJ>
 __global__ __launch_bounds__(256) void k_dec_tn(const void* At_, int rowsA, const void* Bt_, int rowsB,
                                                 int nblocks, int splits, int tiles_i, int tiles_j,
@@ -531,6 +706,8 @@ __global__ __launch_bounds__(256) void k_dec_tn(const void* At_, int rowsA, cons
     static_assert(WVI * WVJ == 4, "four waves");
     using T = typename P::T;
     using Frag = typename P::Frag;
+    constexpr int kFragRegs = (int)(sizeof(Frag) / 4);
+    constexpr int RB = 2 * (WI + WJ) * kFragRegs * 4 <= 128 ? 4 : 2;
     const T* At = reinterpret_cast<const T*>(At_);
     const T* Bt = reinterpret_cast<const T*>(Bt_);
     const int ntiles = tiles_i * tiles_j;
@@ -543,75 +720,122 @@ __global__ __launch_bounds__(256) void k_dec_tn(const void* At_, int rowsA, cons
     const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int col = lane & 31, h = lane >> 5;
     const int i0 = (ti * WVI + w / WVJ) * WI * 32, j0 = (tj * WVJ + w % WVJ) * WJ * 32;
+    if (i0 >= rowsA || j0 >= rowsB) return;
     const int per = (nblocks + splits - 1) / splits;
     const int b0 = split * per, b1 = min(nblocks, b0 + per);
-    bool oka[WI], okb[WJ];
-#pragma unroll
-    for (int a = 0; a < WI; ++a) oka[a] = i0 + 32 * a < rowsA;
-#pragma unroll
-    for (int q = 0; q < WJ; ++q) okb[q] = j0 + 32 * q < rowsB;
-    if (!oka[0] || !okb[0]) return;
     f32x16 c[WI][WJ];
 #pragma unroll
     for (int a = 0; a < WI; ++a)
 #pragma unroll
         for (int q = 0; q < WJ; ++q) c[a][q] = f32x16{};
-    Frag af[2][WI], bf[2][WJ];
-    auto load = [&](int blk, Frag* fa, Frag* fb) {
+    Frag fa[RB][2 * WI], fb[RB][2 * WJ];
+    auto load = [&](int blk, Frag* xa, Frag* xb) {
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
 #pragma unroll
             for (int a = 0; a < WI; ++a)
-                fa[k * WI + a] = oka[a] ? P::load(At + ((size_t)blk * rowsA + i0 + 32 * a + col) * kPx + 16 * k + 8 * h)
-                                        : Frag{};
+                xa[k * WI + a] = P::load(At + ((size_t)blk * rowsA + i0 + 32 * a + col) * kPx + 16 * k + 8 * h);
 #pragma unroll
             for (int q = 0; q < WJ; ++q)
-                fb[k * WJ + q] = okb[q] ? P::load(Bt + ((size_t)blk * rowsB + j0 + 32 * q + col) * kPx + 16 * k + 8 * h)
-                                        : Frag{};
+                xb[k * WJ + q] = P::load(Bt + ((size_t)blk * rowsB + j0 + 32 * q + col) * kPx + 16 * k + 8 * h);
         }
     };
-    Frag cur_a[2 * WI], cur_b[2 * WJ], nxt_a[2 * WI], nxt_b[2 * WJ];
-    if (b0 < b1) load(b0, cur_a, cur_b);
-    for (int blk = b0; blk < b1; ++blk) {
-        if (blk + 1 < b1) load(blk + 1, nxt_a, nxt_b);
+    auto mma = [&](const Frag* xa, const Frag* xb) {
 #pragma unroll
         for (int k = 0; k < 2; ++k)
 #pragma unroll
             for (int a = 0; a < WI; ++a)
 #pragma unroll
-                for (int q = 0; q < WJ; ++q) P::mma(c[a][q], cur_a[k * WI + a], cur_b[k * WJ + q]);
+                for (int q = 0; q < WJ; ++q) P::mma(c[a][q], xa[k * WI + a], xb[k * WJ + q]);
+    };
+    // whole groups of RB blocks through the ring, the rest one at a time
+    const int nfull = b1 > b0 ? (b1 - b0) / RB * RB : 0;
+    if (nfull > 0) {
 #pragma unroll
-        for (int k = 0; k < 2 * WI; ++k) cur_a[k] = nxt_a[k];
+        for (int s = 0; s < RB - 1; ++s) load(b0 + s, fa[s], fb[s]);
+        for (int base = b0; base < b0 + nfull - RB; base += RB) {
 #pragma unroll
-        for (int k = 0; k < 2 * WJ; ++k) cur_b[k] = nxt_b[k];
+            for (int s = 0; s < RB; ++s) {
+                const int sl = (s + RB - 1) % RB;
+                load(base + s + RB - 1, fa[sl], fb[sl]);
+                mma(fa[s], fb[s]);
+            }
+        }
+        load(b0 + nfull - 1, fa[RB - 1], fb[RB - 1]);
+#pragma unroll
+        for (int s = 0; s < RB; ++s) mma(fa[s], fb[s]);
     }
-    (void)af; (void)bf;
+    for (int blk = b0 + nfull; blk < b1; ++blk) {
+        load(blk, fa[0], fb[0]);
+        mma(fa[0], fb[0]);
+    }
     float* out = part + (size_t)split * rowsA * rowsB;
 #pragma unroll
     for (int a = 0; a < WI; ++a)
 #pragma unroll
-        for (int q = 0; q < WJ; ++q) {
-            if (!oka[a] || !okb[q]) continue;
+        for (int q = 0; q < WJ; ++q)
 #pragma unroll
             for (int r = 0; r < 16; ++r)
                 out[(size_t)(i0 + 32 * a + crow(r, h)) * rowsB + j0 + 32 * q + col] = c[a][q][r];
-        }
 }
 
-// out[i][j] = scale * sum_split part[split][i][j] (+ 2 lambda (K - K0) for dK),
-// for i < rows_out, j < cols_out; part has ld = ldp columns.
+// out[i][j] = sum_split part[split][i][j] (+ 2 lambda (K - K0)[i][j] for dK)
+// for i < rows_out, j < cols_out (a multiple of 4); part has ld = ldp columns
+// and rows_p rows per split.  A workgroup covers 64 groups of 4 consecutive
+// outputs; wave w sums the splits w, w + 4, ... with four 16-byte loads in
+// flight, and the four wave sums are added in LDS in a fixed order.
 __global__ __launch_bounds__(256) void k_dec_reduce(const float* __restrict__ part, int splits,
                                                     int rows_p, int ldp, int rows_out, int cols_out,
                                                     float* __restrict__ out, const float* __restrict__ K,
                                                     const float* __restrict__ K0, float two_lambda)
 {
-    const size_t n = (size_t)rows_out * cols_out;
-    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
-        const int i = (int)(e / cols_out), j = (int)(e % cols_out);
-        float s = 0.f;
-        for (int k = 0; k < splits; ++k) s += part[((size_t)k * rows_p + i) * ldp + j];
-        if (K0) s += two_lambda * (K[e] - K0[e]);
-        out[e] = s;
+    __shared__ float4 sh[4][64];
+    const int c4 = cols_out >> 2;
+    const size_t n4 = (size_t)rows_out * c4;
+    const int g = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const size_t e4 = (size_t)blockIdx.x * 64 + g;
+    int i = 0, j = 0;
+    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (e4 < n4) {
+        i = (int)(e4 / c4);
+        j = (int)(e4 % c4) * 4;
+        const float* p = part + (size_t)i * ldp + j;
+        const size_t ss = (size_t)rows_p * ldp;
+        float4 a[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) a[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+        int k = wv;
+        for (; k + 12 < splits; k += 16) {
+            float4 x[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) x[u] = *reinterpret_cast<const float4*>(p + (size_t)(k + 4 * u) * ss);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                a[u].x += x[u].x; a[u].y += x[u].y; a[u].z += x[u].z; a[u].w += x[u].w;
+            }
+        }
+        for (; k < splits; k += 4) {
+            const float4 x = *reinterpret_cast<const float4*>(p + (size_t)k * ss);
+            a[0].x += x.x; a[0].y += x.y; a[0].z += x.z; a[0].w += x.w;
+        }
+        acc.x = (a[0].x + a[1].x) + (a[2].x + a[3].x);
+        acc.y = (a[0].y + a[1].y) + (a[2].y + a[3].y);
+        acc.z = (a[0].z + a[1].z) + (a[2].z + a[3].z);
+        acc.w = (a[0].w + a[1].w) + (a[2].w + a[3].w);
+    }
+    sh[wv][g] = acc;
+    __syncthreads();
+    if (wv == 0 && e4 < n4) {
+        const float4 s0 = sh[0][g], s1 = sh[1][g], s2 = sh[2][g], s3 = sh[3][g];
+        const float r[4] = {(s0.x + s1.x) + (s2.x + s3.x), (s0.y + s1.y) + (s2.y + s3.y),
+                            (s0.z + s1.z) + (s2.z + s3.z), (s0.w + s1.w) + (s2.w + s3.w)};
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const size_t o = (size_t)i * cols_out + j + t;
+            float v = r[t];
+            if (K0) v += two_lambda * (K[o] - K0[o]);
+            out[o] = v;
+        }
     }
 }
 
@@ -691,7 +915,7 @@ static size_t rows_lds(int prec, int Mp, int D)
     const size_t tb = prec == LAM_FP32 ? 4 : 2;
     size_t x = std::max((size_t)kPx * (Mp + 8) * tb, (size_t)kPx * (D + 8) * tb);
     x = std::max(x, (size_t)4 * 32 * kPx * 4);  // dQ reduction
-    return 16 * kPx * 4 + x;
+    return 16 * kPx * 4 + (size_t)4 * kPx * kScLd * tb + x;
 }
 
 template <class P, int MODE, bool F8>
@@ -781,7 +1005,7 @@ static hipError_t run_decode(const DecodeArgs& A, const DecodeLayout& L, int mod
                                (const void*)(base + L.off_p), Mp, (const void*)(base + L.off_gf), A.D, nb,
                                L.splits, ti, tj, part);
         }
-        hipLaunchKernelGGL(k_dec_reduce, dim3(std::min(2048, (A.M * A.D + 255) / 256)), dim3(256), 0, st,
+        hipLaunchKernelGGL(k_dec_reduce, dim3((A.M * A.D / 4 + 63) / 64), dim3(256), 0, st,
                            (const float*)part, nb > 0 ? L.splits : 0, Mp, A.D, A.M, A.D, A.dV,
                            (const float*)nullptr, (const float*)nullptr, 0.0f);
     }
@@ -794,7 +1018,7 @@ static hipError_t run_decode(const DecodeArgs& A, const DecodeLayout& L, int mod
                                L.splits_k, ti, tj, part);
         }
         const bool tr = mode == MODE_LOSS && A.K0 && A.lambda_tr != 0.0f;
-        hipLaunchKernelGGL(k_dec_reduce, dim3(std::min(2048, (A.M * A.d + 255) / 256)), dim3(256), 0, st,
+        hipLaunchKernelGGL(k_dec_reduce, dim3((A.M * A.d / 4 + 63) / 64), dim3(256), 0, st,
                            (const float*)part, nb > 0 ? L.splits_k : 0, Mp, 32, A.M, A.d, A.dK,
                            tr ? A.K : (const float*)nullptr, tr ? A.K0 : (const float*)nullptr,
                            tr ? 2.0f * A.lambda_tr : 0.0f);

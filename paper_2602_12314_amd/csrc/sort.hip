@@ -23,15 +23,24 @@ __device__ inline uint32_t load_count(const uint32_t* n_dev, uint32_t n_cap)
     return n < n_cap ? n : n_cap;
 }
 
-// Inclusive wave scan (u32) with 64-lane shuffles.
+// v from lane (lane - shift) in a DPP row pattern; lanes without a source read 0.
+template <int CTRL, int ROW_MASK>
+__device__ inline uint32_t dpp_u(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROW_MASK, 0xF, true);
+}
+
+// Inclusive wave scan (u32): Hillis-Steele steps inside each 16-lane row
+// (row_shr 1, 2, 4, 8), then the row totals carried with row_bcast:15 into rows
+// 1 and 3 and row_bcast:31 into rows 2 and 3.
 __device__ inline uint32_t wave_incl_scan(uint32_t v)
 {
-    unsigned lane = __lane_id();
-#pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-        uint32_t t = __shfl_up(v, o, kWave);
-        if (lane >= (unsigned)o) v += t;
-    }
+    v += dpp_u<0x111, 0xF>(v);  // row_shr:1
+    v += dpp_u<0x112, 0xF>(v);  // row_shr:2
+    v += dpp_u<0x114, 0xF>(v);  // row_shr:4
+    v += dpp_u<0x118, 0xF>(v);  // row_shr:8
+    v += dpp_u<0x142, 0xA>(v);  // row_bcast:15
+    v += dpp_u<0x143, 0xC>(v);  // row_bcast:31
     return v;
 }
 
@@ -55,9 +64,45 @@ __device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t* total, uint32_t
     return wo + inc - v;
 }
 
-__device__ inline uint32_t scan_value(const uint32_t* in, const uint32_t* idx, uint32_t i)
+// Loads the scan inputs i0 + k * stride (k < kTileItems), zero past n; with
+// idx the input is in[idx[i]].  Every load is issued (indices clamped into
+// range, n >= 1) before any is used, so the 16 (or 2 x 16) loads are in flight
+// together instead of one round trip each.
+__device__ inline void load_scan_values(const uint32_t* in, const uint32_t* idx, uint32_t i0,
+                                        uint32_t stride, uint32_t n, uint32_t* v)
 {
-    return idx ? in[idx[i]] : in[i];
+    uint32_t j[kTileItems];
+#pragma unroll
+    for (int k = 0; k < kTileItems; ++k) {
+        const uint32_t i = i0 + k * stride;
+        j[k] = i < n ? i : n - 1;
+    }
+    if (idx) {
+#pragma unroll
+        for (int k = 0; k < kTileItems; ++k) j[k] = idx[j[k]];
+    }
+#pragma unroll
+    for (int k = 0; k < kTileItems; ++k) v[k] = in[j[k]];
+#pragma unroll
+    for (int k = 0; k < kTileItems; ++k)
+        if (i0 + k * stride >= n) v[k] = 0u;
+}
+
+// Exclusive scan of the 1024 values of a wave stripe held as v[k] = value
+// k * 64 + lane (coalesced loads): 16 chained wave scans.  Returns the stripe
+// total; ex[k] receives the exclusive prefix of value k * 64 + lane.
+constexpr uint32_t kStripe = kWave * kTileItems;  // 1024 values per wave stripe
+
+__device__ inline uint32_t stripe_excl_scan(const uint32_t* v, uint32_t* ex)
+{
+    uint32_t run = 0;
+#pragma unroll
+    for (int k = 0; k < kTileItems; ++k) {
+        const uint32_t inc = wave_incl_scan(v[k]);
+        ex[k] = run + inc - v[k];
+        run += (uint32_t)__builtin_amdgcn_readlane((int)inc, kWave - 1);
+    }
+    return run;
 }
 
 __global__ __launch_bounds__(kTileThreads) void k_scan_reduce(const uint32_t* __restrict__ in,
@@ -65,11 +110,10 @@ __global__ __launch_bounds__(kTileThreads) void k_scan_reduce(const uint32_t* __
                                                               uint32_t n, uint32_t* block_sums)
 {
     __shared__ uint32_t sh[4];
-    uint32_t base = blockIdx.x * (uint32_t)kTile, s = 0;
-    for (int k = 0; k < kTileItems; ++k) {
-        uint32_t i = base + k * kTileThreads + threadIdx.x;
-        if (i < n) s += scan_value(in, idx, i);
-    }
+    uint32_t v[kTileItems], s = 0;
+    load_scan_values(in, idx, blockIdx.x * (uint32_t)kTile + threadIdx.x, kTileThreads, n, v);
+#pragma unroll
+    for (int k = 0; k < kTileItems; ++k) s += v[k];
     uint32_t tot;
     block_excl_scan(s, &tot, sh);
     if (threadIdx.x == 0) block_sums[blockIdx.x] = tot;
@@ -82,13 +126,10 @@ __global__ __launch_bounds__(kTileThreads) void k_scan_top(uint32_t* sums, uint3
     __shared__ uint32_t sh[4];
     uint32_t carry = 0;
     for (uint32_t base = 0; base < nb; base += kTile) {
-        uint32_t v[kTileItems];
-        uint32_t s = 0;
-        for (int k = 0; k < kTileItems; ++k) {
-            uint32_t i = base + threadIdx.x * kTileItems + k;
-            v[k] = i < nb ? sums[i] : 0u;
-            s += v[k];
-        }
+        uint32_t v[kTileItems], s = 0;
+        load_scan_values(sums, nullptr, base + threadIdx.x * kTileItems, 1, nb, v);
+#pragma unroll
+        for (int k = 0; k < kTileItems; ++k) s += v[k];
         uint32_t tot;
         uint32_t off = block_excl_scan(s, &tot, sh) + carry;
         for (int k = 0; k < kTileItems; ++k) {
@@ -101,33 +142,35 @@ __global__ __launch_bounds__(kTileThreads) void k_scan_top(uint32_t* sums, uint3
     if (total && threadIdx.x == 0) *total = carry;
 }
 
+// Block b's 4096 values as four wave stripes (coalesced), offset by the block's
+// scanned sum and the stripes before it.
 __global__ __launch_bounds__(kTileThreads) void k_scan_down(const uint32_t* __restrict__ in,
                                                             const uint32_t* __restrict__ idx,
                                                             uint32_t n,
                                                             const uint32_t* __restrict__ block_off,
                                                             uint32_t* __restrict__ out)
 {
-    __shared__ uint32_t sh[4];
-    uint32_t base = blockIdx.x * (uint32_t)kTile + threadIdx.x * kTileItems;
-    uint32_t v[kTileItems], s = 0;
+    __shared__ uint32_t sh[kTileThreads / kWave];
+    const unsigned lane = __lane_id(), w = threadIdx.x / kWave;
+    const uint32_t sbase = blockIdx.x * (uint32_t)kTile + w * kStripe;
+    uint32_t v[kTileItems], ex[kTileItems];
+    load_scan_values(in, idx, sbase + lane, kWave, n, v);
+    const uint32_t st = stripe_excl_scan(v, ex);
+    if (lane == 0) sh[w] = st;
+    __syncthreads();
+    uint32_t off = block_off[blockIdx.x];
+    for (int k = 0; k < (int)w; ++k) off += sh[k];
+#pragma unroll
     for (int k = 0; k < kTileItems; ++k) {
-        uint32_t i = base + k;
-        v[k] = i < n ? scan_value(in, idx, i) : 0u;
-        s += v[k];
-    }
-    uint32_t tot;
-    uint32_t off = block_excl_scan(s, &tot, sh) + block_off[blockIdx.x];
-    for (int k = 0; k < kTileItems; ++k) {
-        uint32_t i = base + k;
-        if (i < n) out[i] = off;
-        off += v[k];
+        const uint32_t i = sbase + k * kWave + lane;
+        if (i < n) out[i] = off + ex[k];
     }
 }
 
 // One 1024-thread workgroup scans up to kSingleMax values in tiles of 16384:
-// each thread loads 16 consecutive values (16 loads in flight), the thread
-// sums are scanned across the workgroup, and a carry links the tiles.  One
-// launch instead of three for small inputs.
+// wave w takes the stripe of 1024 values at w * 1024 with coalesced loads (all
+// 16 in flight), scans it, and the 16 stripe totals are combined in LDS; a
+// carry links the tiles.  One launch instead of three for small inputs.
 constexpr int kSingleThreads = 1024;
 constexpr uint32_t kSingleTile = kSingleThreads * kTileItems;
 constexpr uint32_t kSingleMax = 4 * kSingleTile;
@@ -141,15 +184,11 @@ __global__ __launch_bounds__(kSingleThreads) void k_scan_single(const uint32_t* 
     const unsigned lane = __lane_id(), w = threadIdx.x / kWave;
     uint32_t carry = 0;
     for (uint32_t base = 0; base < n; base += kSingleTile) {
-        uint32_t v[kTileItems], s = 0;
-#pragma unroll
-        for (int k = 0; k < kTileItems; ++k) {
-            const uint32_t i = base + threadIdx.x * kTileItems + k;
-            v[k] = i < n ? scan_value(in, idx, i) : 0u;
-            s += v[k];
-        }
-        const uint32_t inc = wave_incl_scan(s);
-        if (lane == kWave - 1) sh[w] = inc;
+        const uint32_t sbase = base + w * kStripe;
+        uint32_t v[kTileItems], ex[kTileItems];
+        load_scan_values(in, idx, sbase + lane, kWave, n, v);
+        const uint32_t st = stripe_excl_scan(v, ex);
+        if (lane == 0) sh[w] = st;
         __syncthreads();
         uint32_t wo = 0, tot = 0;
         for (int k = 0; k < kSingleThreads / kWave; ++k) {
@@ -158,12 +197,10 @@ __global__ __launch_bounds__(kSingleThreads) void k_scan_single(const uint32_t* 
             tot += x;
         }
         __syncthreads();
-        uint32_t off = carry + wo + inc - s;
 #pragma unroll
         for (int k = 0; k < kTileItems; ++k) {
-            const uint32_t i = base + threadIdx.x * kTileItems + k;
-            if (i < n) out[i] = off;
-            off += v[k];
+            const uint32_t i = sbase + k * kWave + lane;
+            if (i < n) out[i] = carry + wo + ex[k];
         }
         carry += tot;
     }
@@ -203,9 +240,16 @@ __global__ __launch_bounds__(kTileThreads) void k_radix_hist(const uint32_t* __r
     __syncthreads();
     const uint32_t n = load_count(n_dev, n_cap);
     const uint32_t base = blockIdx.x * (uint32_t)kTile;
-    for (int k = 0; k < kTileItems; ++k) {
-        const uint32_t i = base + k * kTileThreads + threadIdx.x;
-        if (i < n) atomicAdd(&h[(keys[i] >> shift) & (BINS - 1u)], 1u);
+    if (base < n) {  // keys loaded together (clamped), then counted
+        uint32_t key[kTileItems];
+#pragma unroll
+        for (int k = 0; k < kTileItems; ++k) {
+            const uint32_t i = base + k * kTileThreads + threadIdx.x;
+            key[k] = keys[i < n ? i : n - 1];
+        }
+#pragma unroll
+        for (int k = 0; k < kTileItems; ++k)
+            if (base + k * kTileThreads + threadIdx.x < n) atomicAdd(&h[(key[k] >> shift) & (BINS - 1u)], 1u);
     }
     __syncthreads();
     for (int k = threadIdx.x; k < BINS; k += kTileThreads) hist[(size_t)k * nblocks + blockIdx.x] = h[k];
@@ -232,12 +276,28 @@ __global__ __launch_bounds__(kTileThreads) void k_radix_scatter(
     const uint32_t span = blockIdx.x * (uint32_t)kTile + w * (kWave * kTileItems);
     const unsigned long long lt = (1ull << lane) - 1ull;
     uint32_t key[kTileItems], val[kTileItems], rank[kTileItems];
+    // all keys and values of the wave's span are requested before the ranking
+    // (indices clamped into range; entries past n are never written)
+    const uint32_t nl = n > 0 ? n - 1 : 0;
+#pragma unroll
+    for (int s = 0; s < kTileItems; ++s) {
+        const uint32_t i = span + s * kWave + lane;
+        key[s] = keys_in[i < n ? i : nl];
+    }
+    if (vals_in) {
+#pragma unroll
+        for (int s = 0; s < kTileItems; ++s) {
+            const uint32_t i = span + s * kWave + lane;
+            val[s] = vals_in[i < n ? i : nl];
+        }
+    } else {
+#pragma unroll
+        for (int s = 0; s < kTileItems; ++s) val[s] = span + s * kWave + lane;
+    }
 #pragma unroll
     for (int s = 0; s < kTileItems; ++s) {
         const uint32_t i = span + s * kWave + lane;
         const bool ok = i < n;
-        key[s] = ok ? keys_in[i] : 0u;
-        val[s] = ok ? (vals_in ? vals_in[i] : i) : 0u;
         const uint32_t dg = (key[s] >> shift) & (BINS - 1u);
         // lanes holding the same digit: intersect the ballots of its bits
         unsigned long long peers = __ballot(ok);
@@ -268,8 +328,10 @@ __global__ __launch_bounds__(kTileThreads) void k_radix_scatter(
         if (rank[s] == 0xFFFFFFFFu) continue;
         const uint32_t dg = (key[s] >> shift) & (BINS - 1u);
         const uint32_t pos = gbase[dg] + cnt[w][dg] + rank[s];
-        keys_out[pos] = key[s];
-        vals_out[pos] = val[s];
+        if (pos < n) {  // always true for a consistent histogram; keeps a bad one in bounds
+            keys_out[pos] = key[s];
+            vals_out[pos] = val[s];
+        }
     }
 }
 

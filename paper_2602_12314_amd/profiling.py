@@ -1,0 +1,155 @@
+"""Summaries of rocprofv3 CSV output for the library's kernels.
+
+    python -m paper_2602_12314_amd.profiling stats DIR
+        per-kernel calls, total and average duration from a
+        ``rocprofv3 --kernel-trace --stats --output-format csv -d DIR`` run
+        (markdown table).
+
+    python -m paper_2602_12314_amd.profiling counters DIR [KERNEL_PREFIX]
+        mean value per dispatch of every counter of a ``--pmc`` run, by kernel.
+
+    python -m paper_2602_12314_amd.profiling traffic --workload NAME \\
+            --fetch DIR --write DIR --copy-fetch DIR --copy-write DIR --copy-bytes N
+        HBM bytes per launch of each kernel from two ``--pmc FETCH_SIZE`` /
+        ``--pmc WRITE_SIZE`` runs, each counter scaled by what it reads for a
+        plain device copy of N bytes (``bench.py --copy-calibration N`` under the
+        same counter).  Prints a markdown table and, with ``--json FILE``, merges
+        the figures into FILE keyed by workload and the bench's stage names,
+        together with the hash of the kernel sources they were taken on.
+
+Counter values are KiB per dispatch (rocprofv3's derived FETCH_SIZE and
+WRITE_SIZE).
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import hashlib
+import json
+import os
+import sys
+from collections import defaultdict
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+
+# bench stage name -> (kernel name prefix in the trace, source files it is built from)
+STAGES = {
+    "decode_rows": ("k_dec_rows", ["decode.hip", "common.h", "kernels.h"]),
+    "decode_tn": ("k_dec_tn<TBF16, 2, 2, 2, 2>", ["decode.hip", "common.h", "kernels.h"]),
+    "raster_fwd": ("k_raster_fwd", ["render.hip", "common.h", "kernels.h"]),
+    "raster_bwd": ("k_raster_bwd", ["render.hip", "common.h", "kernels.h"]),
+}
+
+
+def source_hash(files) -> str:
+    """Hash of the named files under csrc/ (what a counter figure was taken on)."""
+    h = hashlib.sha256()
+    for name in sorted(files):
+        with open(os.path.join(CSRC, name), "rb") as fh:
+            h.update(name.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def short(name: str) -> str:
+    name = name.replace("lam::", "").replace("void ", "")
+    i = name.find("(")
+    return name[:i] if i > 0 else name
+
+
+def _one(d, pattern):
+    f = glob.glob(os.path.join(d, "**", pattern), recursive=True)
+    if not f:
+        raise FileNotFoundError(f"no {pattern} under {d}")
+    return f[0]
+
+
+def kernel_stats(d):
+    rows = list(csv.DictReader(open(_one(d, "*kernel_stats.csv"))))
+    return [(short(r["Name"]), int(r["Calls"]), float(r["TotalDurationNs"]) / 1e3,
+             float(r["AverageNs"]) / 1e3, float(r["Percentage"])) for r in rows]
+
+
+def counter_means(d, counter):
+    """Mean counter value per dispatch, by kernel."""
+    acc = defaultdict(list)
+    for r in csv.DictReader(open(_one(d, "*counter_collection.csv"))):
+        if r.get("Counter_Name") == counter:
+            acc[short(r["Kernel_Name"])].append(float(r["Counter_Value"]))
+    return {k: sum(v) / len(v) for k, v in acc.items()}
+
+
+def copy_factor(d, counter, copy_bytes):
+    """Bytes per KiB of counter for the plain copy kernel (true bytes / counted)."""
+    m = counter_means(d, counter)
+    ks = [k for k in m if "copyBuffer" in k]
+    if not ks:
+        raise RuntimeError(f"no copy kernel in {d}")
+    return copy_bytes / (m[ks[0]] * 1024.0)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("dir")
+    c = sub.add_parser("counters")
+    c.add_argument("dir")
+    c.add_argument("prefix", nargs="?", default="")
+    t = sub.add_parser("traffic")
+    t.add_argument("--workload", required=True)
+    for k in ("fetch", "write", "copy-fetch", "copy-write"):
+        t.add_argument("--" + k, required=True)
+    t.add_argument("--copy-bytes", type=int, required=True)
+    t.add_argument("--json", default=None)
+    a = ap.parse_args(argv)
+    if a.cmd == "stats":
+        print("| kernel | calls | total us | avg us | % |")
+        print("|---|---|---|---|---|")
+        for k, calls, tot, avg, pct in kernel_stats(a.dir):
+            print(f"| {k} | {calls} | {tot:.1f} | {avg:.2f} | {pct:.1f} |")
+        return 0
+    if a.cmd == "counters":
+        acc = defaultdict(lambda: defaultdict(list))
+        for r in csv.DictReader(open(_one(a.dir, "*counter_collection.csv"))):
+            k = short(r["Kernel_Name"])
+            if k.startswith(a.prefix):
+                acc[k][r["Counter_Name"]].append(float(r["Counter_Value"]))
+        for k in sorted(acc):
+            print(f"{k}: " + ", ".join(f"{c}={sum(v) / len(v):.6g}" for c, v in sorted(acc[k].items())))
+        return 0
+    ff = copy_factor(a.copy_fetch, "FETCH_SIZE", a.copy_bytes)
+    fw = copy_factor(a.copy_write, "WRITE_SIZE", a.copy_bytes)
+    fetch = counter_means(a.fetch, "FETCH_SIZE")
+    write = counter_means(a.write, "WRITE_SIZE")
+    print(f"copy calibration: FETCH_SIZE x {ff:.3f}, WRITE_SIZE x {fw:.3f} "
+          f"({a.copy_bytes} bytes copied per launch)")
+    print("| kernel | FETCH_SIZE KiB | WRITE_SIZE KiB | HBM bytes per launch (scaled) |")
+    print("|---|---|---|---|")
+    for k in sorted(set(fetch) | set(write)):
+        b = fetch.get(k, 0.0) * 1024 * ff + write.get(k, 0.0) * 1024 * fw
+        print(f"| {k} | {fetch.get(k, 0.0):.1f} | {write.get(k, 0.0):.1f} | {b:.4g} |")
+    if a.json:
+        try:
+            rec = json.load(open(a.json))
+        except (OSError, ValueError):
+            rec = {}
+        ent = rec.setdefault(a.workload, {})
+        for stage, (prefix, files) in STAGES.items():
+            ks = [k for k in set(fetch) & set(write) if k.startswith(prefix)]
+            if len(ks) != 1:
+                continue
+            k = ks[0]
+            ent[stage] = {"kernel": k, "fetch_kib": fetch[k], "write_kib": write[k],
+                          "fetch_factor": ff, "write_factor": fw,
+                          "bytes_per_launch": fetch[k] * 1024 * ff + write[k] * 1024 * fw,
+                          "source_hash": source_hash(files)}
+        with open(a.json, "w") as fh:
+            json.dump(rec, fh, indent=1, sort_keys=True)
+            fh.write("\n")
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

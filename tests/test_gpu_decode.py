@@ -59,8 +59,11 @@ def _min_cos(a, b):
     return float(_cos(a, b).min())
 
 
+# (n, d, M, D).  M = 150 pads to 192 atoms: six 32-atom tiles (two waves hold
+# an odd number), three 64-atom E4M3 chunks, and D = 384 gives three D tiles
+# per wave.
 SHAPES = [(1000, 16, 64, 128), (777, 32, 100, 256), (4096, 16, 256, 512), (333, 32, 512, 768),
-          (200, 16, 1, 128), (96, 32, 1024, 1024)]
+          (200, 16, 1, 128), (96, 32, 1024, 1024), (515, 16, 150, 384)]
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8"])
