@@ -111,6 +111,13 @@ def run(args):
         (tw, th), tune = autotune.best_tile(g, s.cams)
         args.tile = f"{tw}x{th}"
         _log(f"[bench] autotuned tile {args.tile}: {tune}")
+    decode_shape = "px32"
+    if args.autotune:
+        from paper_2602_12314_amd import autotune
+        decode_shape, dtimes = autotune.best_decode_shape(prec, n, spec.d, spec.M, spec.D)
+        _lib.set_decode_shape(decode_shape)
+        tune = {"tile_ms": tune, "decode_shape_ms": dtimes}
+        _log(f"[bench] autotuned decode shape {decode_shape}: {dtimes}")
     r = ops.Renderer(s.cams, spec.n_gauss, spec.d, tile=(tw, th))
     Q = torch.empty((n, spec.d), device=dev)
     T = torch.empty((n,), device=dev)
@@ -215,7 +222,7 @@ def run(args):
         "config": {"workload": spec.name, "n_gaussians": spec.n_gauss,
                    "image": f"{s.cams[0, 0]:.0f}x{s.cams[0, 1]:.0f}", "views": len(spec.cams),
                    "pixels": n, "d": spec.d, "M": spec.M, "D": spec.D, "decode_precision": prec,
-                   "tile": args.tile, "tile_pairs": pairs},
+                   "tile": args.tile, "decode_shape": decode_shape, "tile_pairs": pairs},
         "stage_ms": {k: round(v, 4) for k, v in prof.items()},
         "launch": "hip_graph_replay" if args.graph else "eager",
         "eager_ms_per_step": eager_sec * 1e3,

@@ -160,10 +160,19 @@ lam_status lam_render_debug_views(const void* ws, int n_gauss, int d, const floa
 
 /* ------------------------------------------------------------------ decode */
 
+/* Workgroup shape of the per-pixel decode kernel, process-wide: 0 = 32 pixels
+ * with 4 waves (default); 1 = 64 pixels with 8 waves, each V fragment feeding
+ * two pixel groups (BF16 with D a multiple of 256 up to 768, FP8 up to 512;
+ * other shapes keep 0).  Results agree to rounding (the per-pixel sums over
+ * the waves are split differently); an autotuner may pick per workload.
+ * Errors: LAM_ERR_INVALID_ARG. */
+lam_status lam_set_decode_shape(int mode);
+
 /* Bytes of decode workspace for n pixel rows, query dimension d, M atoms,
- * feature dimension D.  Supported: d in {16, 32}; 1 <= M <= 2048; D a multiple
- * of 64 with 64 <= D <= 2048; n >= 0.  Host-only.
- * Errors: LAM_ERR_INVALID_ARG (null out), LAM_ERR_UNSUPPORTED (shape). */
+ * feature dimension D.  Supported: d in {16, 32}; 1 <= M <= 2048 (FP32: the
+ * atoms, padded to 64, and D both at most 1024, which is what the 160 KB of
+ * LDS of a workgroup holds); D a multiple of 128 with 128 <= D <= 1024; n >= 0.
+ * Host-only.  Errors: LAM_ERR_INVALID_ARG (null out), LAM_ERR_UNSUPPORTED (shape). */
 lam_status lam_decode_workspace_size(int precision, int n, int d, int M, int D, uint64_t* bytes);
 
 /* Decode and feature loss, forward and backward in one call (Eq. 5-6):

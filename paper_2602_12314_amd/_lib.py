@@ -42,6 +42,7 @@ def lib():
             "lam_status_string": (C.c_char_p, [i32]),
             "lam_version": (i32, []),
             "lam_set_raster_schedule": (i32, [i32]),
+            "lam_set_decode_shape": (i32, [i32]),
             "lam_profile_enable": (i32, [i32]),
             "lam_profile_read": (i32, [C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int)]),
             "lam_render_workspace_size": (i32, [i32, i32, vp, i32, i32, i32, u64, pu64]),
@@ -151,6 +152,13 @@ def render_debug_views(ws, n_gauss, d, cams, tile_w, tile_h, capacity):
 
 
 # ------------------------------------------------------------------ decode
+
+DECODE_SHAPES = {"px32": 0, "px64": 1}
+
+
+def set_decode_shape(mode):
+    check(lib().lam_set_decode_shape(DECODE_SHAPES.get(mode, mode)), "lam_set_decode_shape")
+
 
 def decode_workspace_size(precision, n, d, M, D) -> int:
     out = C.c_uint64()

@@ -1,11 +1,14 @@
-"""Tile-shape autotuner for the renderer.
+"""Autotuner for the render tile shape and the decode block shape.
 
 The rendered query map does not depend on the tile shape (each Gaussian is
 blended into exactly the pixels of its footprint), so the shape is a pure
-performance choice: this times render forward + backward for each candidate on
-the caller's own scene and cameras and keeps the fastest.  Results are cached
-in JSON keyed by GPU architecture and workload shape
-(``$LAM_AUTOTUNE_CACHE``, default ``~/.cache/latentam/autotune.json``).
+performance choice: ``best_tile`` times render forward + backward for each
+candidate on the caller's own scene and cameras and keeps the fastest.
+``best_decode_shape`` times the decode + loss + gradients call for its two
+workgroup shapes (32 pixels x 4 waves, 64 pixels x 8 waves) on inputs of the
+caller's sizes; the results agree to rounding.  Results are cached in JSON
+keyed by GPU architecture and workload shape (``$LAM_AUTOTUNE_CACHE``, default
+``~/.cache/latentam/autotune.json``).
 """
 from __future__ import annotations
 
@@ -17,7 +20,7 @@ from typing import Iterable, Optional, Tuple
 import numpy as np
 import torch
 
-from . import ops
+from . import _lib, ops
 
 CANDIDATES = ((16, 16), (8, 8), (16, 8), (8, 16), (32, 8), (8, 32), (16, 4), (32, 4))
 
@@ -86,3 +89,46 @@ def best_tile(g: ops.Gaussians, cams, candidates: Iterable[Tuple[int, int]] = CA
         db[key] = {"tile": list(tile), "ms": times}
         _store(db)
     return tile, times
+
+
+def time_decode_shape(precision: str, n: int, d: int, M: int, D: int, shape: str, reps: int = 5,
+                      warmup: int = 2) -> float:
+    """Median ms of decode + loss + gradients with the given block shape."""
+    dev = torch.device("cuda", torch.cuda.current_device())
+    gen = torch.Generator(device=dev).manual_seed(0)
+    Q = torch.randn((n, d), device=dev, generator=gen)
+    K = torch.randn((M, d), device=dev, generator=gen)
+    V = torch.randn((M, D), device=dev, generator=gen)
+    T = torch.nn.functional.normalize(torch.randn((n, D), device=dev, generator=gen), dim=1)
+    dec = ops.Decoder(precision, n, d, M, D, device=dev)
+    _lib.set_decode_shape(shape)
+    try:
+        for _ in range(warmup):
+            dec.loss_and_grads(Q, K, V, T, K, 0.1)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            dec.loss_and_grads(Q, K, V, T, K, 0.1)
+            torch.cuda.synchronize()
+            ts.append((time.perf_counter() - t0) * 1e3)
+    finally:
+        _lib.set_decode_shape("px32")
+    return float(np.median(ts))
+
+
+def best_decode_shape(precision: str, n: int, d: int, M: int, D: int, use_cache: bool = True,
+                      reps: int = 5) -> Tuple[str, dict]:
+    """Fastest decode block shape for these sizes (it is not set; call
+    ``_lib.set_decode_shape`` with the result)."""
+    arch = torch.cuda.get_device_properties(torch.cuda.current_device()).gcnArchName.split(":")[0]
+    key = f"{arch}|decode|{precision}|n={n}|d={d}|M={M}|D={D}"
+    db = _load() if use_cache else {}
+    if use_cache and key in db:
+        return db[key]["shape"], db[key]["ms"]
+    times = {s: time_decode_shape(precision, n, d, M, D, s, reps=reps) for s in _lib.DECODE_SHAPES}
+    best = min(times, key=times.get)
+    if use_cache:
+        db[key] = {"shape": best, "ms": times}
+        _store(db)
+    return best, times

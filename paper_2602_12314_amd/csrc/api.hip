@@ -150,6 +150,13 @@ lam_status lam_set_raster_schedule(int mode)
     return LAM_OK;
 }
 
+lam_status lam_set_decode_shape(int mode)
+{
+    if (mode < 0 || mode > 1) return LAM_ERR_INVALID_ARG;
+    set_decode_shape(mode);
+    return LAM_OK;
+}
+
 lam_status lam_render_workspace_size(int n_gauss, int d, const float* cams, int n_cams,
                                      int tile_w, int tile_h, uint64_t instance_capacity,
                                      uint64_t* bytes)

@@ -32,7 +32,6 @@ constexpr float kFp8Max = 448.0f;  // largest finite OCP E4M3 value
 
 constexpr int kPx = 32;          // pixels per row block
 constexpr int kAtomAlign = 64;   // atom padding
-constexpr int kRowsThreads = 256;
 constexpr float kLog2e = 1.4426950408889634f;
 
 // ------------------------------------------------------------ precisions
@@ -279,38 +278,54 @@ struct RowsArgs {
 };
 
 // Chunks of fragments kept in flight by the contraction loops (a ring of
-// registers).  Two suffice once two or more waves share a SIMD, and keep the
-// register count within the budget of two waves per SIMD; callers rely on the
-// depth dividing 4 (the chunk counts are multiples of 4).
-template <class P, int TILES>
+// registers): two where two waves share a SIMD, four in the instantiations
+// whose registers allow one wave per SIMD anyway (E4M3, or more than four D
+// tiles per wave), where the ring alone has to cover the L2 latency.  Callers
+// rely on the depth dividing 4 (the chunk counts are multiples of 4).
+template <bool DEEP>
 constexpr int pipe_depth()
 {
-    return 2;
+    return DEEP ? 4 : 2;
 }
 
-template <class P, int NT, int DQ, int MODE, bool F8>
-__global__ __launch_bounds__(kRowsThreads) void k_dec_rows(RowsArgs a)
+// Workgroup shape of k_dec_rows: NW waves and NPG groups of 32 pixels.  Every
+// wave covers all NPG x 32 pixels of the block and 1 / NW of the D columns
+// (NT = D / (32 NW) tiles of 32) in the F contraction, and the atom tiles
+// w, w + NW, ... in the logits and dP contractions, so each V fragment it loads
+// feeds NPG MFMAs (with NPG = 1, two atom tiles share each G fragment instead).
+template <class P, int NT, int DQ, int MODE, bool F8, int NW, int NPG>
+__global__ __launch_bounds__(NW * kWave) void k_dec_rows(RowsArgs a)
 {
     using T = typename P::T;
     using Frag = typename P::Frag;
-    constexpr int NQ = DQ / 16;  // K chunks of the logits contraction
+    constexpr int NQ = DQ / 16;           // K chunks of the logits contraction
+    constexpr int BPX = kPx * NPG;        // pixels per workgroup
+    constexpr int NTH = NW * kWave;       // threads per workgroup
+    constexpr int TT = NPG == 1 ? 2 : 1;  // atom tiles per dP iteration
     extern __shared__ __align__(16) char smem[];
-    // LDS: red [16][32] floats, the waves' dS scratch tiles [4][32][kScLd], then
-    // region X (P~ [32][Mp+8], later G [32][D+8], later the dQ reduction)
-    float* red = reinterpret_cast<float*>(smem);
-    T* Wsc = reinterpret_cast<T*>(smem + 4 * 4 * kPx * sizeof(float)) + (threadIdx.x / kWave) * kPx * kScLd;
-    T* X = reinterpret_cast<T*>(smem + 4 * 4 * kPx * sizeof(float) + 4 * kPx * kScLd * sizeof(T));
-    const int ldp = a.Mp + 8, ldg = a.D + 8;
-
+    // LDS: red [4][NW][BPX] floats of per-pixel statistics, the waves' dS
+    // staging tiles [NW][32][kScLd], then region X (P~ [BPX][Mp+8], later
+    // G [BPX][D+8], later the dQ reduction [NW][32][BPX] floats)
     const int w = threadIdx.x / kWave;
     const int lane = threadIdx.x % kWave;
+    float* red = reinterpret_cast<float*>(smem);
+    T* Wsc = reinterpret_cast<T*>(smem + 4 * NW * BPX * sizeof(float)) + w * kPx * kScLd;
+    T* X = reinterpret_cast<T*>(smem + 4 * NW * BPX * sizeof(float) + NW * kPx * kScLd * sizeof(T));
+    auto rslot = [&](int set, int ww, int g) { return red + (set * NW + ww) * BPX + g * kPx; };
+    const int ldp = a.Mp + 8, ldg = a.D + 8;
+
     const int col = lane & 31, h = lane >> 5;
     const int blk = blockIdx.x;
-    const int px = blk * kPx + col;
-    const bool valid = px < a.n;
     const int ntiles = a.Mp / 32;
     const int nca = a.Mp / 16;  // 16-wide K chunks over the atoms (a multiple of 4)
     const int ncd = a.D / 16;   // 16-wide K chunks over the features (a multiple of 8)
+    int pxg[NPG];
+    bool valid[NPG];
+#pragma unroll
+    for (int g = 0; g < NPG; ++g) {
+        pxg[g] = (blk * NPG + g) * kPx + col;
+        valid[g] = pxg[g] < a.n;
+    }
 
     const T* Kb = reinterpret_cast<const T*>(a.Kb);
     const T* Vb = reinterpret_cast<const T*>(a.Vb);
@@ -318,126 +333,171 @@ __global__ __launch_bounds__(kRowsThreads) void k_dec_rows(RowsArgs a)
     const T* Ktp = reinterpret_cast<const T*>(a.Ktp);
 
     // query fragments (B operand of S^T = K Q^T): Q[px][16 c + 8 h + t]
-    Frag qf[NQ];
+    Frag qf[NPG][NQ];
 #pragma unroll
-    for (int c = 0; c < NQ; ++c) {
-        float v[8];
-        if (valid) {
-            const float4* qp = reinterpret_cast<const float4*>(a.Q + (size_t)px * DQ + 16 * c + 8 * h);
-            const float4 x0 = qp[0], x1 = qp[1];
-            v[0] = x0.x; v[1] = x0.y; v[2] = x0.z; v[3] = x0.w;
-            v[4] = x1.x; v[5] = x1.y; v[6] = x1.z; v[7] = x1.w;
-        } else {
+    for (int g = 0; g < NPG; ++g)
 #pragma unroll
-            for (int t = 0; t < 8; ++t) v[t] = 0.0f;
+        for (int c = 0; c < NQ; ++c) {
+            float v[8];
+            if (valid[g]) {
+                const float4* qp = reinterpret_cast<const float4*>(a.Q + (size_t)pxg[g] * DQ + 16 * c + 8 * h);
+                const float4 x0 = qp[0], x1 = qp[1];
+                v[0] = x0.x; v[1] = x0.y; v[2] = x0.z; v[3] = x0.w;
+                v[4] = x1.x; v[5] = x1.y; v[6] = x1.z; v[7] = x1.w;
+            } else {
+#pragma unroll
+                for (int t = 0; t < 8; ++t) v[t] = 0.0f;
+            }
+            qf[g][c] = P::from_f32(v);
         }
-        qf[c] = P::from_f32(v);
-        if (MODE != MODE_INFER && w == 0) {
-            // Q^T block for the dK reduction: Qt[blk][16c + 8h + t][col]
-            T* qt = reinterpret_cast<T*>(a.Qt) + (size_t)blk * 32 * kPx;
+    // Q^T of 32-pixel block g for the dK reduction, written by wave g (rows >= d zero)
+    if (MODE != MODE_INFER) {
 #pragma unroll
-            for (int t = 0; t < 8; ++t) qt[(16 * c + 8 * h + t) * kPx + col] = qf[c][t];
+        for (int g = 0; g < NPG; ++g) {
+            if (w != g) continue;
+            T* qt = reinterpret_cast<T*>(a.Qt) + (size_t)(blk * NPG + g) * 32 * kPx;
+#pragma unroll
+            for (int c = 0; c < NQ; ++c)
+#pragma unroll
+                for (int t = 0; t < 8; ++t) qt[(16 * c + 8 * h + t) * kPx + col] = qf[g][c][t];
+            if (DQ == 16) {
+#pragma unroll
+                for (int t = 0; t < 8; ++t) qt[(16 + 8 * h + t) * kPx + col] = P::cvt(0.0f);
+            }
         }
-    }
-    if (MODE != MODE_INFER && DQ == 16 && w == 1) {
-        T* qt = reinterpret_cast<T*>(a.Qt) + (size_t)blk * 32 * kPx;
-#pragma unroll
-        for (int t = 0; t < 8; ++t) qt[(16 + 8 * h + t) * kPx + col] = P::cvt(0.0f);
     }
 
     auto kload = [&](int tt, Frag* kf) {
 #pragma unroll
         for (int c = 0; c < NQ; ++c) kf[c] = load_frag<P>(Kb, tt, c, NQ, lane);
     };
-    auto s_of = [&](const Frag* kf) {
+    auto s_of = [&](const Frag* kf, int g) {
         f32x16 s = {};
 #pragma unroll
-        for (int c = 0; c < NQ; ++c) P::mma(s, kf[c], qf[c]);
+        for (int c = 0; c < NQ; ++c) P::mma(s, kf[c], qf[g][c]);
         return s;
     };
-    // Visit the wave's atom tiles w, w + 4, ... with S^T of each; the K
-    // fragments of the next tile are in flight while one is processed.
+    // Visit the wave's atom tiles w, w + NW, ... with their K fragments; those
+    // of the next tile are in flight while one is processed.
     auto for_tiles = [&](auto&& body) {
         Frag ka[NQ], kb[NQ];
         if (w < ntiles) kload(w, ka);
-        for (int tt = w; tt < ntiles; tt += 8) {
-            if (tt + 4 < ntiles) kload(tt + 4, kb);
-            body(tt, s_of(ka));
-            if (tt + 8 < ntiles) kload(tt + 8, ka);
-            if (tt + 4 < ntiles) body(tt + 4, s_of(kb));
+        for (int tt = w; tt < ntiles; tt += 2 * NW) {
+            if (tt + NW < ntiles) kload(tt + NW, kb);
+            body(tt, ka);
+            if (tt + 2 * NW < ntiles) kload(tt + 2 * NW, ka);
+            if (tt + NW < ntiles) body(tt + NW, kb);
         }
     };
 
     // ---- pass 1: row max of the logits (in log2 units)
-    float mx = -INFINITY;
-    for_tiles([&](int tt, const f32x16& s) {
-        if (32 * tt + 32 <= a.M) {  // every atom of the tile exists
+    float mx[NPG];
 #pragma unroll
-            for (int r = 0; r < 16; ++r) mx = fmaxf(mx, s[r]);
-        } else {
+    for (int g = 0; g < NPG; ++g) mx[g] = -INFINITY;
+    for_tiles([&](int tt, const Frag* kf) {
 #pragma unroll
-            for (int r = 0; r < 16; ++r)
-                if (32 * tt + crow(r, h) < a.M) mx = fmaxf(mx, s[r]);
-        }
-    });
-    mx = fmaxf(mx, __shfl_xor(mx, 32, kWave));
-    if (h == 0) red[w * kPx + col] = mx;
-    __syncthreads();
-    mx = fmaxf(fmaxf(red[col], red[kPx + col]), fmaxf(red[2 * kPx + col], red[3 * kPx + col]));
-    const float m2 = mx * a.scale_log2;
-    __syncthreads();
-
-    // ---- pass 2: P~ = exp2(S scale - m) into LDS [px][atom] and HBM (P~^T blocked)
-    float lsum = 0.0f;
-    T* Pt = reinterpret_cast<T*>(a.Pt) + (size_t)blk * a.Mp * kPx;
-    for_tiles([&](int tt, const f32x16& s) {
-        float p[16];
+        for (int g = 0; g < NPG; ++g) {
+            const f32x16 s = s_of(kf, g);
+            if (32 * tt + 32 <= a.M) {  // every atom of the tile exists
 #pragma unroll
-        for (int r = 0; r < 16; ++r) p[r] = exp2_weight(s[r] * a.scale_log2 - m2);
-        if (32 * tt + 32 > a.M) {  // padded atoms get no weight
-#pragma unroll
-            for (int r = 0; r < 16; ++r)
-                if (32 * tt + crow(r, h) >= a.M) p[r] = 0.0f;
-        }
-#pragma unroll
-        for (int r = 0; r < 16; ++r) lsum += p[r];
-#pragma unroll
-        for (int g4 = 0; g4 < 4; ++g4) {
-            const int atom0 = 32 * tt + 8 * g4 + 4 * h;
-            if (F8) {
-                // P~ of a pixel peaks at exactly 1, so with the V row scales folded
-                // into its columns one fixed factor maps it onto the E4M3 range.
-                const float4 sv = *reinterpret_cast<const float4*>(a.sv_fold + atom0);
-                int pk = __builtin_amdgcn_cvt_pk_fp8_f32(p[4 * g4] * sv.x, p[4 * g4 + 1] * sv.y, 0, false);
-                pk = __builtin_amdgcn_cvt_pk_fp8_f32(p[4 * g4 + 2] * sv.z, p[4 * g4 + 3] * sv.w, pk, true);
-                *reinterpret_cast<int*>(reinterpret_cast<uint8_t*>(X) + col * (a.Mp + 16) + atom0) = pk;
+                for (int r = 0; r < 16; ++r) mx[g] = fmaxf(mx[g], s[r]);
             } else {
-                P::store4(X + col * ldp + atom0, p[4 * g4], p[4 * g4 + 1], p[4 * g4 + 2], p[4 * g4 + 3]);
-            }
-            if (F8 && MODE != MODE_INFER) {  // LDS holds E4M3 weights here: store from registers
 #pragma unroll
-                for (int k = 0; k < 4; ++k) Pt[(size_t)(atom0 + k) * kPx + col] = P::cvt(p[4 * g4 + k]);
+                for (int r = 0; r < 16; ++r)
+                    if (32 * tt + crow(r, h) < a.M) mx[g] = fmaxf(mx[g], s[r]);
             }
         }
     });
-    lsum += __shfl_xor(lsum, 32, kWave);
-    if (h == 0) red[kPx * 4 + w * kPx + col] = lsum;
-    __syncthreads();
-    const float l = red[4 * kPx + col] + red[5 * kPx + col] + red[6 * kPx + col] + red[7 * kPx + col];
-    const float invl = 1.0f / l;
-    // P~^T of the block from the LDS copy, in whole chunks
-    if (!F8 && MODE != MODE_INFER) store_transposed<P>(X, ldp, a.Mp, Pt, threadIdx.x, kRowsThreads);
-
-    // ---- F^T = V^T P~^T: wave w owns D tiles [w NT, w NT + NT)
-    f32x16 acc[NT];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) acc[t] = f32x16{};
+    for (int g = 0; g < NPG; ++g) {
+        mx[g] = fmaxf(mx[g], __shfl_xor(mx[g], 32, kWave));
+        if (h == 0) rslot(0, w, g)[col] = mx[g];
+    }
+    __syncthreads();
+    float m2[NPG];
+#pragma unroll
+    for (int g = 0; g < NPG; ++g) {
+        float m = -INFINITY;
+#pragma unroll
+        for (int ww = 0; ww < NW; ++ww) m = fmaxf(m, rslot(0, ww, g)[col]);
+        m2[g] = m * a.scale_log2;
+    }
+    __syncthreads();
+
+    // ---- pass 2: P~ = exp2(S scale - m) into LDS [px][atom] (and P~^T to HBM)
+    float lsum[NPG];
+#pragma unroll
+    for (int g = 0; g < NPG; ++g) lsum[g] = 0.0f;
+    T* Ptb = reinterpret_cast<T*>(a.Pt) + (size_t)blk * NPG * a.Mp * kPx;
+    for_tiles([&](int tt, const Frag* kf) {
+#pragma unroll
+        for (int g = 0; g < NPG; ++g) {
+            const f32x16 s = s_of(kf, g);
+            float p[16];
+#pragma unroll
+            for (int r = 0; r < 16; ++r) p[r] = exp2_weight(s[r] * a.scale_log2 - m2[g]);
+            if (32 * tt + 32 > a.M) {  // padded atoms get no weight
+#pragma unroll
+                for (int r = 0; r < 16; ++r)
+                    if (32 * tt + crow(r, h) >= a.M) p[r] = 0.0f;
+            }
+#pragma unroll
+            for (int r = 0; r < 16; ++r) lsum[g] += p[r];
+            const int prow = g * kPx + col;
+#pragma unroll
+            for (int g4 = 0; g4 < 4; ++g4) {
+                const int atom0 = 32 * tt + 8 * g4 + 4 * h;
+                if (F8) {
+                    // P~ of a pixel peaks at exactly 1, so with the V row scales folded
+                    // into its columns one fixed factor maps it onto the E4M3 range.
+                    const float4 sv = *reinterpret_cast<const float4*>(a.sv_fold + atom0);
+                    int pk = __builtin_amdgcn_cvt_pk_fp8_f32(p[4 * g4] * sv.x, p[4 * g4 + 1] * sv.y, 0, false);
+                    pk = __builtin_amdgcn_cvt_pk_fp8_f32(p[4 * g4 + 2] * sv.z, p[4 * g4 + 3] * sv.w, pk, true);
+                    *reinterpret_cast<int*>(reinterpret_cast<uint8_t*>(X) + prow * (a.Mp + 16) + atom0) = pk;
+                    if (MODE != MODE_INFER) {  // LDS holds E4M3 weights: P~^T from registers
+                        T* Pt = Ptb + (size_t)g * a.Mp * kPx;
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) Pt[(size_t)(atom0 + k) * kPx + col] = P::cvt(p[4 * g4 + k]);
+                    }
+                } else {
+                    P::store4(X + prow * ldp + atom0, p[4 * g4], p[4 * g4 + 1], p[4 * g4 + 2], p[4 * g4 + 3]);
+                }
+            }
+        }
+    });
+#pragma unroll
+    for (int g = 0; g < NPG; ++g) {
+        lsum[g] += __shfl_xor(lsum[g], 32, kWave);
+        if (h == 0) rslot(1, w, g)[col] = lsum[g];
+    }
+    __syncthreads();
+    float invl[NPG];
+#pragma unroll
+    for (int g = 0; g < NPG; ++g) {
+        float l = 0.0f;
+#pragma unroll
+        for (int ww = 0; ww < NW; ++ww) l += rslot(1, ww, g)[col];
+        invl[g] = 1.0f / l;
+    }
+    // P~^T of the 32-pixel blocks from the LDS copy, in whole chunks
+    if (!F8 && MODE != MODE_INFER) {
+#pragma unroll
+        for (int g = 0; g < NPG; ++g)
+            store_transposed<P>(X + g * kPx * ldp, ldp, a.Mp, Ptb + (size_t)g * a.Mp * kPx, threadIdx.x, NTH);
+    }
+
+    // ---- F^T = V^T P~^T: wave w owns D tiles [w NT, w NT + NT) for every pixel group
+    f32x16 acc[NT][NPG];
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int g = 0; g < NPG; ++g) acc[t][g] = f32x16{};
     if (F8) {
         // K = 64 atoms per E4M3 MFMA; lane half h holds atoms 32 h + 0..31.
         // Two chunks in flight; the chunk count Mp / 64 may be odd.
         const int nc8 = a.Mp / 64;
-        const uint8_t* X8 = reinterpret_cast<const uint8_t*>(X) + col * (a.Mp + 16);
-        auto bload = [&](int c) {
+        auto bload = [&](int c, int g) {
+            const uint8_t* X8 = reinterpret_cast<const uint8_t*>(X) + (g * kPx + col) * (a.Mp + 16);
             const i32x4 b0 = *reinterpret_cast<const i32x4*>(X8 + 64 * c + 32 * h);
             const i32x4 b1 = *reinterpret_cast<const i32x4*>(X8 + 64 * c + 32 * h + 16);
             const i32x8 bf = {b0[0], b0[1], b0[2], b0[3], b1[0], b1[1], b1[2], b1[3]};
@@ -447,40 +507,56 @@ __global__ __launch_bounds__(kRowsThreads) void k_dec_rows(RowsArgs a)
         constexpr int NH = NT < 4 ? NT : 4;
 #pragma unroll
         for (int t0 = 0; t0 < NT; t0 += NH) {
-            i32x8 ra[NH], rb[NH], ba, bb;
+            i32x8 ra[NH], rb[NH], ba[NPG], bb[NPG];
             auto vload = [&](int c, i32x8* af) {
 #pragma unroll
                 for (int t = 0; t < NH; ++t)
                     af[t] = *reinterpret_cast<const i32x8*>(
                         a.Vt8 + ((((size_t)(w * NT + t0 + t) * nc8 + c) << 6) + lane) * 32);
             };
-            vload(0, ra);
-            ba = bload(0);
-            for (int c = 0; c < nc8; c += 2) {
-                if (c + 1 < nc8) { vload(c + 1, rb); bb = bload(c + 1); }
+            auto mma8 = [&](const i32x8* af, const i32x8* bf) {
 #pragma unroll
                 for (int t = 0; t < NH; ++t)
-                    acc[t0 + t] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(ra[t], ba, acc[t0 + t], 0, 0,
-                                                                                   0, 127, 0, 127);
-                if (c + 2 < nc8) { vload(c + 2, ra); ba = bload(c + 2); }
-                if (c + 1 < nc8) {
 #pragma unroll
-                    for (int t = 0; t < NH; ++t)
-                        acc[t0 + t] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(rb[t], bb, acc[t0 + t], 0,
-                                                                                       0, 0, 127, 0, 127);
+                    for (int g = 0; g < NPG; ++g)
+                        acc[t0 + t][g] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+                            af[t], bf[g], acc[t0 + t][g], 0, 0, 0, 127, 0, 127);
+            };
+            vload(0, ra);
+#pragma unroll
+            for (int g = 0; g < NPG; ++g) ba[g] = bload(0, g);
+            for (int c = 0; c < nc8; c += 2) {
+                if (c + 1 < nc8) {
+                    vload(c + 1, rb);
+#pragma unroll
+                    for (int g = 0; g < NPG; ++g) bb[g] = bload(c + 1, g);
                 }
+                mma8(ra, ba);
+                if (c + 2 < nc8) {
+                    vload(c + 2, ra);
+#pragma unroll
+                    for (int g = 0; g < NPG; ++g) ba[g] = bload(c + 2, g);
+                }
+                if (c + 1 < nc8) mma8(rb, bb);
             }
         }
     } else {
         // ring of PD chunks: chunk c + PD - 1 is loaded while chunk c is multiplied.
         // The loads are unconditional (the last PD chunks are peeled) so that
         // each MFMA waits only for its own fragments.
-        constexpr int PD = pipe_depth<P, NT>();
-        Frag ring[PD][NT], bring[PD];
-        auto fetch = [&](int slot_c, Frag* r, Frag& b) {
+        constexpr int PD = pipe_depth<(F8 || NT * NPG > 4)>();
+        Frag ring[PD][NT], bring[PD][NPG];
+        auto fetch = [&](int c, Frag* r, Frag* b) {
 #pragma unroll
-            for (int t = 0; t < NT; ++t) r[t] = load_frag<P>(Vt, w * NT + t, slot_c, nca, lane);
-            b = P::load(X + col * ldp + 16 * slot_c + 8 * h);
+            for (int t = 0; t < NT; ++t) r[t] = load_frag<P>(Vt, w * NT + t, c, nca, lane);
+#pragma unroll
+            for (int g = 0; g < NPG; ++g) b[g] = P::load(X + (g * kPx + col) * ldp + 16 * c + 8 * h);
+        };
+        auto mma = [&](const Frag* r, const Frag* b) {
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+#pragma unroll
+                for (int g = 0; g < NPG; ++g) P::mma(acc[t][g], r[t], b[g]);
         };
 #pragma unroll
         for (int s = 0; s < PD - 1; ++s) fetch(s, ring[s], bring[s]);
@@ -488,31 +564,34 @@ __global__ __launch_bounds__(kRowsThreads) void k_dec_rows(RowsArgs a)
 #pragma unroll
             for (int s = 0; s < PD; ++s) {
                 fetch(c0 + s + PD - 1, ring[(s + PD - 1) % PD], bring[(s + PD - 1) % PD]);
-#pragma unroll
-                for (int t = 0; t < NT; ++t) P::mma(acc[t], ring[s][t], bring[s]);
+                mma(ring[s], bring[s]);
             }
         }
         fetch(nca - 1, ring[PD - 1], bring[PD - 1]);
 #pragma unroll
-        for (int s = 0; s < PD; ++s)
-#pragma unroll
-            for (int t = 0; t < NT; ++t) P::mma(acc[t], ring[s][t], bring[s]);
+        for (int s = 0; s < PD; ++s) mma(ring[s], bring[s]);
     }
-    const float fscale = F8 ? invl * a.fp8_unscale[0] : invl;
 #pragma unroll
-    for (int t = 0; t < NT; ++t)
+    for (int g = 0; g < NPG; ++g) {
+        const float fscale = F8 ? invl[g] * a.fp8_unscale[0] : invl[g];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) acc[t][r] *= fscale;
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[t][g][r] *= fscale;
+    }
 
     if (MODE == MODE_INFER) {
-        if (valid) {
+#pragma unroll
+        for (int g = 0; g < NPG; ++g) {
+            if (!valid[g]) continue;
 #pragma unroll
             for (int t = 0; t < NT; ++t)
 #pragma unroll
                 for (int g4 = 0; g4 < 4; ++g4) {
                     const int dr = 32 * (w * NT + t) + 8 * g4 + 4 * h;
-                    *reinterpret_cast<float4*>(a.F + (size_t)px * a.D + dr) =
-                        make_float4(acc[t][4 * g4], acc[t][4 * g4 + 1], acc[t][4 * g4 + 2], acc[t][4 * g4 + 3]);
+                    *reinterpret_cast<float4*>(a.F + (size_t)pxg[g] * a.D + dr) =
+                        make_float4(acc[t][g][4 * g4], acc[t][g][4 * g4 + 1], acc[t][g][4 * g4 + 2],
+                                    acc[t][g][4 * g4 + 3]);
                 }
         }
         return;
@@ -523,96 +602,137 @@ __global__ __launch_bounds__(kRowsThreads) void k_dec_rows(RowsArgs a)
     // (Requesting these rows before the F contraction is slower: loads retire in
     // order, so every fragment wait of the contraction would wait for them.)
     // A pixel past n reads row n - 1, unused since its G is zeroed through ca, cb.
-    float gsc[NT][16];
+    float gsc[NT][NPG][16];
     {
         const float* rowsrc = MODE == MODE_LOSS ? a.target : a.dF;
-        const float* prow = rowsrc + (size_t)(valid ? px : a.n - 1) * a.D;
 #pragma unroll
-        for (int t = 0; t < NT; ++t)
+        for (int g = 0; g < NPG; ++g) {
+            const float* prow = rowsrc + (size_t)(valid[g] ? pxg[g] : a.n - 1) * a.D;
 #pragma unroll
-            for (int g4 = 0; g4 < 4; ++g4) {
-                const float4 x = *reinterpret_cast<const float4*>(prow + 32 * (w * NT + t) + 8 * g4 + 4 * h);
-                gsc[t][4 * g4] = x.x; gsc[t][4 * g4 + 1] = x.y; gsc[t][4 * g4 + 2] = x.z; gsc[t][4 * g4 + 3] = x.w;
-            }
+            for (int t = 0; t < NT; ++t)
+#pragma unroll
+                for (int g4 = 0; g4 < 4; ++g4) {
+                    const float4 x = *reinterpret_cast<const float4*>(prow + 32 * (w * NT + t) + 8 * g4 + 4 * h);
+                    gsc[t][g][4 * g4] = x.x; gsc[t][g][4 * g4 + 1] = x.y;
+                    gsc[t][g][4 * g4 + 2] = x.z; gsc[t][g][4 * g4 + 3] = x.w;
+                }
+        }
     }
-    float delta = 0.0f;
-    float ca = valid ? invl : 0.0f, cb = 0.0f;  // G = ca * row + cb * F (zero past n)
+    float delta[NPG], ca[NPG], cb[NPG];  // G = ca * row + cb * F (zero past n)
+#pragma unroll
+    for (int g = 0; g < NPG; ++g) {
+        delta[g] = 0.0f;
+        ca[g] = valid[g] ? invl[g] : 0.0f;
+        cb[g] = 0.0f;
+    }
     if (MODE == MODE_LOSS) {
-        float nf = 0.f, ft = 0.f, nt = 0.f;
+        float nf[NPG], ft[NPG], nt[NPG];
 #pragma unroll
-        for (int t = 0; t < NT; ++t)
+        for (int g = 0; g < NPG; ++g) {
+            nf[g] = ft[g] = nt[g] = 0.0f;
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                nf += acc[t][r] * acc[t][r];
-                ft += acc[t][r] * gsc[t][r];
-                nt += gsc[t][r] * gsc[t][r];
-            }
-        nf += __shfl_xor(nf, 32, kWave);
-        ft += __shfl_xor(ft, 32, kWave);
-        nt += __shfl_xor(nt, 32, kWave);
-        __syncthreads();
+            for (int t = 0; t < NT; ++t)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    nf[g] += acc[t][g][r] * acc[t][g][r];
+                    ft[g] += acc[t][g][r] * gsc[t][g][r];
+                    nt[g] += gsc[t][g][r] * gsc[t][g][r];
+                }
+            nf[g] += __shfl_xor(nf[g], 32, kWave);
+            ft[g] += __shfl_xor(ft[g], 32, kWave);
+            nt[g] += __shfl_xor(nt[g], 32, kWave);
+        }
+        __syncthreads();  // every wave is done reading the row sums of pass 2
         if (h == 0) {
-            red[w * kPx + col] = nf;
-            red[4 * kPx + w * kPx + col] = ft;
-            red[8 * kPx + w * kPx + col] = nt;
+#pragma unroll
+            for (int g = 0; g < NPG; ++g) {
+                rslot(0, w, g)[col] = nf[g];
+                rslot(1, w, g)[col] = ft[g];
+                rslot(2, w, g)[col] = nt[g];
+            }
         }
         __syncthreads();
-        nf = red[col] + red[kPx + col] + red[2 * kPx + col] + red[3 * kPx + col];
-        ft = red[4 * kPx + col] + red[5 * kPx + col] + red[6 * kPx + col] + red[7 * kPx + col];
-        nt = red[8 * kPx + col] + red[9 * kPx + col] + red[10 * kPx + col] + red[11 * kPx + col];
-        const float raw = sqrtf(nf) * sqrtf(nt);
-        const float den = fmaxf(raw, 1e-8f);
-        const float cs = ft / den;
-        // dL/dF = -(1/n) (T / den - c F / |F|^2), then divided by l
-        ca = valid ? -a.inv_n / den * invl : 0.0f;
-        cb = (valid && raw > 1e-8f && nf > 0.f) ? a.inv_n * cs / nf * invl : 0.0f;
-        if (w == 0 && h == 0) {
-            if (a.row_cos && valid) a.row_cos[px] = cs;
-            // block sum of (1 - cos) over valid pixels
-            float lp = valid ? 1.0f - cs : 0.0f;
-            for (int o = 16; o >= 1; o >>= 1) lp += __shfl_xor(lp, o, kWave);
-            if (col == 0) a.loss_part[blk] = lp;
+#pragma unroll
+        for (int g = 0; g < NPG; ++g) {
+            float sf = 0.f, st = 0.f, stt = 0.f;
+#pragma unroll
+            for (int ww = 0; ww < NW; ++ww) {
+                sf += rslot(0, ww, g)[col];
+                st += rslot(1, ww, g)[col];
+                stt += rslot(2, ww, g)[col];
+            }
+            const float raw = sqrtf(sf) * sqrtf(stt);
+            const float den = fmaxf(raw, 1e-8f);
+            const float cs = st / den;
+            // dL/dF = -(1/n) (T / den - c F / |F|^2), then divided by l
+            ca[g] = valid[g] ? -a.inv_n / den * invl[g] : 0.0f;
+            cb[g] = (valid[g] && raw > 1e-8f && sf > 0.f) ? a.inv_n * cs / sf * invl[g] : 0.0f;
+            if (w == g && h == 0) {
+                if (a.row_cos && valid[g]) a.row_cos[pxg[g]] = cs;
+                // sum of (1 - cos) over the valid pixels of 32-pixel block g
+                float lp = valid[g] ? 1.0f - cs : 0.0f;
+                for (int o = 16; o >= 1; o >>= 1) lp += __shfl_xor(lp, o, kWave);
+                if (col == 0) a.loss_part[blk * NPG + g] = lp;
+            }
         }
     }
     // G in place; delta' = sum_D G F (zero for the pure cosine term up to rounding)
 #pragma unroll
-    for (int t = 0; t < NT; ++t)
+    for (int g = 0; g < NPG; ++g) {
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const float gv = ca * gsc[t][r] + cb * acc[t][r];
-            delta += gv * acc[t][r];
-            gsc[t][r] = gv;
-        }
-    delta += __shfl_xor(delta, 32, kWave);
-    __syncthreads();  // everyone is done reading P~ (region X) and red
-    if (h == 0) red[12 * kPx + w * kPx + col] = delta;
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const float gv = ca[g] * gsc[t][g][r] + cb[g] * acc[t][g][r];
+                delta[g] += gv * acc[t][g][r];
+                gsc[t][g][r] = gv;
+            }
+        delta[g] += __shfl_xor(delta[g], 32, kWave);
+    }
+    __syncthreads();  // everyone is done reading P~ (region X) and the statistics
+    if (h == 0) {
+#pragma unroll
+        for (int g = 0; g < NPG; ++g) rslot(3, w, g)[col] = delta[g];
+    }
     // stage G into LDS [px][D]
 #pragma unroll
-    for (int t = 0; t < NT; ++t)
+    for (int g = 0; g < NPG; ++g)
 #pragma unroll
-        for (int g4 = 0; g4 < 4; ++g4) {
-            const int dr = 32 * (w * NT + t) + 8 * g4 + 4 * h;
-            P::store4(X + col * ldg + dr, gsc[t][4 * g4], gsc[t][4 * g4 + 1], gsc[t][4 * g4 + 2], gsc[t][4 * g4 + 3]);
-        }
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int g4 = 0; g4 < 4; ++g4) {
+                const int dr = 32 * (w * NT + t) + 8 * g4 + 4 * h;
+                P::store4(X + (g * kPx + col) * ldg + dr, gsc[t][g][4 * g4], gsc[t][g][4 * g4 + 1],
+                          gsc[t][g][4 * g4 + 2], gsc[t][g][4 * g4 + 3]);
+            }
     __syncthreads();
-    delta = red[12 * kPx + col] + red[13 * kPx + col] + red[14 * kPx + col] + red[15 * kPx + col];
+#pragma unroll
+    for (int g = 0; g < NPG; ++g) {
+        float s = 0.0f;
+#pragma unroll
+        for (int ww = 0; ww < NW; ++ww) s += rslot(3, ww, g)[col];
+        delta[g] = s;
+    }
     // G^T of this wave's D rows from the LDS copy, in whole chunks
-    {
-        T* Gt = reinterpret_cast<T*>(a.Gt) + ((size_t)blk * a.D + 32 * w * NT) * kPx;
-        store_transposed<P>(X + 32 * w * NT, ldg, 32 * NT, Gt, lane, kWave);
+#pragma unroll
+    for (int g = 0; g < NPG; ++g) {
+        T* Gt = reinterpret_cast<T*>(a.Gt) + ((size_t)(blk * NPG + g) * a.D + 32 * w * NT) * kPx;
+        store_transposed<P>(X + g * kPx * ldg + 32 * w * NT, ldg, 32 * NT, Gt, lane, kWave);
     }
 
     // ---- per atom tile: dP = G V^T, dS = P~ (dP - delta) / sqrt(d), dQ^T += K^T dS^T
-    f32x16 dq = {};
-    T* St = reinterpret_cast<T*>(a.St) + (size_t)blk * a.Mp * kPx;
-    auto finish_tile = [&](int tt, const f32x16& dp, const Frag* kf, const Frag* kt) {
-        const f32x16 s = s_of(kf);
+    f32x16 dq[NPG];
+#pragma unroll
+    for (int g = 0; g < NPG; ++g) dq[g] = f32x16{};
+    T* Stb = reinterpret_cast<T*>(a.St) + (size_t)blk * NPG * a.Mp * kPx;
+    auto finish_tile = [&](int tt, int g, const f32x16& dp, const Frag* kf, const Frag* kt) {
+        const f32x16 s = s_of(kf, g);
         // A pixel past n has G = 0, hence dP = 0 and delta = 0, so its dS is
         // zero without a mask; padded atoms are masked.
         float ds[16];
 #pragma unroll
         for (int r = 0; r < 16; ++r)
-            ds[r] = exp2_weight(s[r] * a.scale_log2 - m2) * (dp[r] - delta) * a.inv_sqrt_d;
+            ds[r] = exp2_weight(s[r] * a.scale_log2 - m2[g]) * (dp[r] - delta[g]) * a.inv_sqrt_d;
         if (32 * tt + 32 > a.M) {
 #pragma unroll
             for (int r = 0; r < 16; ++r)
@@ -623,67 +743,85 @@ __global__ __launch_bounds__(kRowsThreads) void k_dec_rows(RowsArgs a)
         for (int g4 = 0; g4 < 4; ++g4)
             P::store4(Wsc + col * kScLd + 8 * g4 + 4 * h, ds[4 * g4], ds[4 * g4 + 1], ds[4 * g4 + 2], ds[4 * g4 + 3]);
         __builtin_amdgcn_wave_barrier();
-        store_transposed<P>(Wsc, kScLd, 32, St + (size_t)32 * tt * kPx, lane, kWave);
+        store_transposed<P>(Wsc, kScLd, 32, Stb + ((size_t)g * a.Mp + 32 * tt) * kPx, lane, kWave);
         __builtin_amdgcn_wave_barrier();
 #pragma unroll
-        for (int c = 0; c < 2; ++c) P::mma(dq, kt[c], P::from_f32(ds + 8 * c));
+        for (int c = 0; c < 2; ++c) P::mma(dq[g], kt[c], P::from_f32(ds + 8 * c));
     };
-    // Two atom tiles (tt and tt + 4) share each G fragment read from LDS; their
-    // V fragments run PG chunks ahead of the MFMAs, and the K fragments of the
-    // dS step are requested before the contraction that hides their latency.
-    constexpr int PG = pipe_depth<P, 2>();
-    for (int tt = w; tt < ntiles; tt += 8) {
-        const bool two = tt + 4 < ntiles;
-        Frag kf0[NQ], kf1[NQ], kt0[2], kt1[2];
-        kload(tt, kf0);
+    // TT atom tiles per iteration share each G fragment read from LDS, and each
+    // V fragment feeds the NPG pixel groups; the fragments run PG chunks ahead of
+    // the MFMAs, and the K fragments of the dS step are requested before the
+    // contraction that hides their latency.
+    constexpr int PG = pipe_depth<(F8 || NT * NPG > 4)>();
+    for (int tt = w; tt < ntiles; tt += TT * NW) {
+        bool has[TT];
+        int tj[TT];
 #pragma unroll
-        for (int c = 0; c < 2; ++c) kt0[c] = load_frag<P>(Ktp, 0, 2 * tt + c, nca, lane);
-        if (two) {
-            kload(tt + 4, kf1);
-#pragma unroll
-            for (int c = 0; c < 2; ++c) kt1[c] = load_frag<P>(Ktp, 0, 2 * (tt + 4) + c, nca, lane);
+        for (int j = 0; j < TT; ++j) {
+            has[j] = tt + j * NW < ntiles;
+            // a missing tile repeats the first one (multiplied, never used),
+            // which keeps the loop free of branches
+            tj[j] = has[j] ? tt + j * NW : tt;
         }
-        f32x16 dp0 = {}, dp1 = {};
-        // a wave with an odd tile count multiplies its last tile twice and
-        // keeps one result, which keeps the loop free of branches
-        const int tt1 = two ? tt + 4 : tt;
-        Frag ra[PG], rb[PG], gb[PG];
-        auto fetch = [&](int c, Frag& x, Frag& y, Frag& g) {
-            x = load_frag<P>(Vb, tt, c, ncd, lane);
-            y = load_frag<P>(Vb, tt1, c, ncd, lane);
-            g = P::load(X + col * ldg + 16 * c + 8 * h);
+        Frag kf[TT][NQ], kt[TT][2];
+#pragma unroll
+        for (int j = 0; j < TT; ++j) {
+            kload(tj[j], kf[j]);
+#pragma unroll
+            for (int c = 0; c < 2; ++c) kt[j][c] = load_frag<P>(Ktp, 0, 2 * tj[j] + c, nca, lane);
+        }
+        f32x16 dp[TT][NPG];
+#pragma unroll
+        for (int j = 0; j < TT; ++j)
+#pragma unroll
+            for (int g = 0; g < NPG; ++g) dp[j][g] = f32x16{};
+        Frag rv[PG][TT], gb[PG][NPG];
+        auto fetch = [&](int c, Frag* v, Frag* gg) {
+#pragma unroll
+            for (int j = 0; j < TT; ++j) v[j] = load_frag<P>(Vb, tj[j], c, ncd, lane);
+#pragma unroll
+            for (int g = 0; g < NPG; ++g) gg[g] = P::load(X + (g * kPx + col) * ldg + 16 * c + 8 * h);
+        };
+        auto mma = [&](const Frag* v, const Frag* gg) {
+#pragma unroll
+            for (int j = 0; j < TT; ++j)
+#pragma unroll
+                for (int g = 0; g < NPG; ++g) P::mma(dp[j][g], v[j], gg[g]);
         };
 #pragma unroll
-        for (int s = 0; s < PG - 1; ++s) fetch(s, ra[s], rb[s], gb[s]);
+        for (int s = 0; s < PG - 1; ++s) fetch(s, rv[s], gb[s]);
         for (int c0 = 0; c0 < ncd - PG; c0 += PG) {
 #pragma unroll
             for (int s = 0; s < PG; ++s) {
                 const int sl = (s + PG - 1) % PG;
-                fetch(c0 + s + PG - 1, ra[sl], rb[sl], gb[sl]);
-                P::mma(dp0, ra[s], gb[s]);
-                P::mma(dp1, rb[s], gb[s]);
+                fetch(c0 + s + PG - 1, rv[sl], gb[sl]);
+                mma(rv[s], gb[s]);
             }
         }
-        fetch(ncd - 1, ra[PG - 1], rb[PG - 1], gb[PG - 1]);
+        fetch(ncd - 1, rv[PG - 1], gb[PG - 1]);
 #pragma unroll
-        for (int s = 0; s < PG; ++s) {
-            P::mma(dp0, ra[s], gb[s]);
-            P::mma(dp1, rb[s], gb[s]);
-        }
-        finish_tile(tt, dp0, kf0, kt0);
-        if (two) finish_tile(tt + 4, dp1, kf1, kt1);
+        for (int s = 0; s < PG; ++s) mma(rv[s], gb[s]);
+#pragma unroll
+        for (int j = 0; j < TT; ++j)
+            if (has[j]) {
+#pragma unroll
+                for (int g = 0; g < NPG; ++g) finish_tile(tj[j], g, dp[j][g], kf[j], kt[j]);
+            }
     }
     if (!a.dQ) return;
     __syncthreads();  // region X (G) no longer read
     float* dqr = reinterpret_cast<float*>(X);
 #pragma unroll
-    for (int r = 0; r < 16; ++r) dqr[(w * 32 + crow(r, h)) * kPx + col] = dq[r];
+    for (int g = 0; g < NPG; ++g)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) dqr[(w * 32 + crow(r, h)) * BPX + g * kPx + col] = dq[g][r];
     __syncthreads();
-    for (int i = threadIdx.x; i < kPx * DQ; i += kRowsThreads) {
+    for (int i = threadIdx.x; i < BPX * DQ; i += NTH) {
         const int p = i / DQ, k = i % DQ;
-        const float v = dqr[(0 * 32 + k) * kPx + p] + dqr[(1 * 32 + k) * kPx + p] +
-                        dqr[(2 * 32 + k) * kPx + p] + dqr[(3 * 32 + k) * kPx + p];
-        const int gp = blk * kPx + p;
+        float v = 0.0f;
+#pragma unroll
+        for (int ww = 0; ww < NW; ++ww) v += dqr[(ww * 32 + k) * BPX + p];
+        const int gp = blk * BPX + p;
         if (gp < a.n) a.dQ[(size_t)gp * DQ + k] = v;
     }
 }
@@ -863,6 +1001,36 @@ __global__ __launch_bounds__(256) void k_dec_loss(const float* __restrict__ part
 
 // ------------------------------------------------------------ host side
 
+// LDS bytes of k_dec_rows with NW waves and NPG 32-pixel groups.
+static size_t rows_lds(int prec, int Mp, int D, int NW, int NPG)
+{
+    const size_t tb = prec == LAM_FP32 ? 4 : 2;
+    const size_t bpx = (size_t)kPx * NPG;
+    size_t x = std::max(bpx * (Mp + 8) * tb, bpx * (D + 8) * tb);
+    x = std::max(x, (size_t)NW * 32 * bpx * 4);  // dQ reduction
+    return 4 * NW * bpx * 4 + (size_t)NW * kPx * kScLd * tb + x;
+}
+
+constexpr size_t kMaxLds = 160 * 1024;  // LDS of a gfx950 workgroup
+
+// 64-pixel blocks of 8 waves (each V fragment feeds two MFMAs) where the
+// registers and LDS allow: BF16 with D a multiple of 256 up to 768, E4M3 up to
+// 512 (its wider fragments would spill at 768).
+static bool wide_ok(int prec, int Mp, int D)
+{
+    const int max_nt = prec == LAM_FP8_E4M3 ? 2 : 3;
+    return prec != LAM_FP32 && D % 256 == 0 && D / 256 <= max_nt && rows_lds(prec, Mp, D, 8, 2) <= kMaxLds;
+}
+
+// Decode block shape, process-wide: 0 = 32 pixels x 4 waves (default), 1 = 64
+// pixels x 8 waves where wide_ok allows (else 32 x 4).  Same results up to the
+// order of the per-pixel sums over the waves.
+static int g_decode_shape = 0;
+
+void set_decode_shape(int mode) { g_decode_shape = mode; }
+
+static bool wide_rows(int prec, int Mp, int D) { return g_decode_shape == 1 && wide_ok(prec, Mp, D); }
+
 static int pick_splits(int nblocks, int tiles)
 {
     // enough workgroups to fill 256 CUs twice, splits a multiple of 8
@@ -880,7 +1048,11 @@ bool decode_layout(int prec, int n, int d, int M, int D, DecodeLayout* L)
         return false;
     const size_t tb = prec == LAM_FP32 ? 4 : 2;
     const int Mp = (M + kAtomAlign - 1) / kAtomAlign * kAtomAlign;
-    const int nb = (n + kPx - 1) / kPx;
+    // 32-pixel blocks, rounded up to an even count so that the 64-pixel
+    // workgroups of k_dec_rows never write past the pixel-blocked buffers (a
+    // block of padding pixels contributes zeros to every reduction)
+    const int nb = ((n + 2 * kPx - 1) / (2 * kPx)) * 2;
+    if (rows_lds(prec, Mp, D, 4, 1) > kMaxLds) return false;  // the 32 x 4 shape always fits
     L->Mp = Mp;
     L->row_blocks = nb;
     const int tiles_v = ((Mp + 127) / 128) * ((D + 127) / 128);
@@ -910,21 +1082,16 @@ bool decode_layout(int prec, int n, int d, int M, int D, DecodeLayout* L)
     return true;
 }
 
-static size_t rows_lds(int prec, int Mp, int D)
-{
-    const size_t tb = prec == LAM_FP32 ? 4 : 2;
-    size_t x = std::max((size_t)kPx * (Mp + 8) * tb, (size_t)kPx * (D + 8) * tb);
-    x = std::max(x, (size_t)4 * 32 * kPx * 4);  // dQ reduction
-    return 16 * kPx * 4 + (size_t)4 * kPx * kScLd * tb + x;
-}
-
 template <class P, int MODE, bool F8>
-static hipError_t launch_rows(const RowsArgs& ra, int nb, int D, int d, size_t lds, hipStream_t st)
+static hipError_t launch_rows(const RowsArgs& ra, int nb, int D, int d, int Mp, int prec, hipStream_t st)
 {
-    const int NT = D / 128;
-#define LAM_ROWS(NTV, DQV)                                                                           \
-    if (NT == NTV && d == DQV) {                                                                     \
-        auto kern = k_dec_rows<P, NTV, DQV, MODE, F8>;                                                   \
+    const bool wide = wide_rows(prec, Mp, D);
+    const int NW = wide ? 8 : 4, NPG = wide ? 2 : 1;
+    const int NT = D / (32 * NW);
+    const size_t lds = rows_lds(prec, Mp, D, NW, NPG);
+#define LAM_ROWS(NWV, NPGV, NTV, DQV)                                                                \
+    if (NW == NWV && NT == NTV && d == DQV) {                                                        \
+        auto kern = k_dec_rows<P, NTV, DQV, MODE, F8, NWV, NPGV>;                                     \
         static size_t lds_set = 0; /* raised only when needed, so captured replays make no call */    \
         if (lds > lds_set) {                                                                         \
             if (hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,   \
@@ -932,12 +1099,19 @@ static hipError_t launch_rows(const RowsArgs& ra, int nb, int D, int d, size_t l
                 return hipErrorInvalidValue;                                                         \
             lds_set = lds;                                                                           \
         }                                                                                            \
-        hipLaunchKernelGGL(kern, dim3(nb), dim3(kRowsThreads), lds, st, ra);                        \
+        hipLaunchKernelGGL(kern, dim3(nb / NPGV), dim3(NWV * kWave), lds, st, ra);                  \
         return hipGetLastError();                                                                    \
     }
-    LAM_ROWS(1, 16) LAM_ROWS(2, 16) LAM_ROWS(3, 16) LAM_ROWS(4, 16) LAM_ROWS(5, 16) LAM_ROWS(6, 16)
-    LAM_ROWS(7, 16) LAM_ROWS(8, 16) LAM_ROWS(1, 32) LAM_ROWS(2, 32) LAM_ROWS(3, 32) LAM_ROWS(4, 32)
-    LAM_ROWS(5, 32) LAM_ROWS(6, 32) LAM_ROWS(7, 32) LAM_ROWS(8, 32)
+    LAM_ROWS(4, 1, 1, 16) LAM_ROWS(4, 1, 2, 16) LAM_ROWS(4, 1, 3, 16) LAM_ROWS(4, 1, 4, 16)
+    LAM_ROWS(4, 1, 5, 16) LAM_ROWS(4, 1, 6, 16) LAM_ROWS(4, 1, 7, 16) LAM_ROWS(4, 1, 8, 16)
+    LAM_ROWS(4, 1, 1, 32) LAM_ROWS(4, 1, 2, 32) LAM_ROWS(4, 1, 3, 32) LAM_ROWS(4, 1, 4, 32)
+    LAM_ROWS(4, 1, 5, 32) LAM_ROWS(4, 1, 6, 32) LAM_ROWS(4, 1, 7, 32) LAM_ROWS(4, 1, 8, 32)
+    if constexpr (P::kBytes == 2) {  // the 64 x 8 shape (wide_ok): BF16 up to 3 D tiles a wave, E4M3 2
+        LAM_ROWS(8, 2, 1, 16) LAM_ROWS(8, 2, 2, 16) LAM_ROWS(8, 2, 1, 32) LAM_ROWS(8, 2, 2, 32)
+        if constexpr (!F8) {
+            LAM_ROWS(8, 2, 3, 16) LAM_ROWS(8, 2, 3, 32)
+        }
+    }
 #undef LAM_ROWS
     return hipErrorInvalidValue;
 }
@@ -985,13 +1159,12 @@ static hipError_t run_decode(const DecodeArgs& A, const DecodeLayout& L, int mod
         ra.sv_fold = sc + 2 * Mp + 64;
         ra.fp8_unscale = sc + 2 * Mp + 8;
     }
-    const size_t lds = rows_lds(A.prec == LAM_FP32 ? LAM_FP32 : LAM_BF16, Mp, A.D);
     hipError_t e = hipSuccess;
     if (nb > 0) {
         ProfScope ps("decode_rows", st);
-        if (mode == MODE_INFER) e = launch_rows<P, MODE_INFER, F8>(ra, nb, A.D, A.d, lds, st);
-        else if (mode == MODE_LOSS) e = launch_rows<P, MODE_LOSS, F8>(ra, nb, A.D, A.d, lds, st);
-        else e = launch_rows<P, MODE_ADJ, F8>(ra, nb, A.D, A.d, lds, st);
+        if (mode == MODE_INFER) e = launch_rows<P, MODE_INFER, F8>(ra, nb, A.D, A.d, Mp, A.prec, st);
+        else if (mode == MODE_LOSS) e = launch_rows<P, MODE_LOSS, F8>(ra, nb, A.D, A.d, Mp, A.prec, st);
+        else e = launch_rows<P, MODE_ADJ, F8>(ra, nb, A.D, A.d, Mp, A.prec, st);
         if (e != hipSuccess) return e;
     }
     if (mode == MODE_INFER) return hipGetLastError();

@@ -87,6 +87,7 @@ struct DecodeLayout {
 };
 
 bool decode_layout(int prec, int n, int d, int M, int D, DecodeLayout* L);
+void set_decode_shape(int mode);
 hipError_t decode_loss_launch(const DecodeArgs& A, const DecodeLayout& L, hipStream_t st);
 hipError_t decode_forward_launch(const DecodeArgs& A, const DecodeLayout& L, hipStream_t st);
 hipError_t decode_backward_launch(const DecodeArgs& A, const DecodeLayout& L, hipStream_t st);

@@ -86,6 +86,23 @@ def test_decode_workspace_validation(L):
     assert L.lam_decode_workspace_size(1, 10, 16, 64, 128, None) == _lib.LAM_ERR_INVALID_ARG
 
 
+def test_process_wide_knobs_validate(L):
+    for bad in (-1, 3):
+        assert L.lam_set_raster_schedule(bad) == _lib.LAM_ERR_INVALID_ARG
+    for bad in (-1, 2):
+        assert L.lam_set_decode_shape(bad) == _lib.LAM_ERR_INVALID_ARG
+    assert L.lam_set_decode_shape(1) == 0 and L.lam_set_decode_shape(0) == 0
+    assert L.lam_set_raster_schedule(2) == 0
+
+
+def test_decode_lds_limit_of_fp32(L):
+    # the FP32 per-pixel kernel holds 32 rows of max(atoms, D) + 8 FP32 values in LDS
+    ok = C.c_uint64()
+    assert L.lam_decode_workspace_size(0, 100, 16, 1024, 1024, C.byref(ok)) == 0
+    assert L.lam_decode_workspace_size(0, 100, 16, 2048, 512, C.byref(ok)) == _lib.LAM_ERR_UNSUPPORTED
+    assert L.lam_decode_workspace_size(1, 100, 16, 2048, 512, C.byref(ok)) == 0
+
+
 def test_decode_rejects_small_workspace(L):
     st = L.lam_decode_loss(1, C.c_void_p(16), 10, 16, C.c_void_p(16), C.c_void_p(16), 64, 128,
                            C.c_void_p(16), C.c_void_p(16), C.c_float(0.1), C.c_void_p(16), None,

@@ -134,6 +134,42 @@ def test_fp8_meets_min_cosine_and_dQ_bars(shape):
     assert c >= 0.999 and e < 1e-2 and ev < 1e-2
 
 
+# 64-pixel x 8-wave workgroups (lam_set_decode_shape(1)): D = 256 (one D tile
+# per wave), 512 (two) and 768 (three; FP8 falls back to 32 x 4 there).
+WIDE_SHAPES = [(777, 32, 100, 256), (4096, 16, 256, 512), (333, 32, 512, 768)]
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+@pytest.mark.parametrize("shape", WIDE_SHAPES)
+def test_wide_decode_shape(prec, shape):
+    from paper_2602_12314_amd import _lib
+    n, d, M, D = shape
+    say(f"[decode px64] {prec} n={n} d={d} M={M} D={D}")
+    Q, K, V, T, K0 = _inputs(3, n, d, M, D)
+    dec = _decoder(prec, n, d, M, D)
+    _lib.set_decode_shape("px64")
+    try:
+        F = to_np(dec.forward(*_cuda(Q, K, V)))
+        loss, dQ, dK, dV = dec.loss_and_grads(*_cuda(Q, K, V, T, K0), 0.1)
+        dQb, dKb, dVb = dec.backward(*_cuda(Q, K, V, T.astype(np.float32) * 0.01))
+    finally:
+        _lib.set_decode_shape("px32")
+    ref = DO.loss_and_grads(Q, K, V, T, K0, 0.1)
+    c = _cos(F, ref["F"])
+    say(f"  cos min {c.min():.6f} mean {c.mean():.6f}")
+    assert (c.mean() if prec == "fp8" else c.min()) >= 0.999
+    assert abs(float(loss) - ref["loss"]) / abs(ref["loss"]) < 1e-2
+    for name, t in (("dQ", dQ), ("dK", dK), ("dV", dV)):
+        e = rel_err(to_np(t), ref[name])
+        say(f"  {name} rel err {e:.3e}")
+        assert e < (5e-2 if prec == "fp8" else 1e-2), name
+    refb = dict(zip(("dQ", "dK", "dV"), DO.decode_backward(Q, K, V, T.astype(np.float64) * 0.01)))
+    for name, t in (("dQ", dQb), ("dK", dKb), ("dV", dVb)):
+        e = rel_err(to_np(t), refb[name])
+        say(f"  given dF: {name} rel err {e:.3e}")
+        assert e < (5e-2 if prec == "fp8" else 1e-2), name
+
+
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
 def test_backward_given_dF(prec):
     n, d, M, D = 1500, 32, 192, 384
