@@ -745,8 +745,10 @@ __global__ __launch_bounds__(NW * kWave) void k_dec_rows(RowsArgs a)
         __builtin_amdgcn_wave_barrier();
         store_transposed<P>(Wsc, kScLd, 32, Stb + ((size_t)g * a.Mp + 32 * tt) * kPx, lane, kWave);
         __builtin_amdgcn_wave_barrier();
+        if (a.dQ) {  // no dQ requested (the decode-only iterations): skip its products
 #pragma unroll
-        for (int c = 0; c < 2; ++c) P::mma(dq[g], kt[c], P::from_f32(ds + 8 * c));
+            for (int c = 0; c < 2; ++c) P::mma(dq[g], kt[c], P::from_f32(ds + 8 * c));
+        }
     };
     // TT atom tiles per iteration share each G fragment read from LDS, and each
     // V fragment feeds the NPG pixel groups; the fragments run PG chunks ahead of

@@ -7,7 +7,10 @@
 - ``DecodeLoss.apply(Q, K, V, K0, target, lambda_tr, precision, decoder) -> loss``:
   Eq. 5-6; the library computes the loss and its gradients in one call.
 - ``Decode.apply(Q, K, V, precision, decoder) -> F``: Eq. 5 alone.
-Every step runs in the HIP library; nothing here computes the method.
+- ``stage2(decoder, Q, K, V, target, K0, lambda_tr, iters, step)``: the
+  decode-only iterations of Alg. 1 Stage II (Gaussians, hence Q, fixed): each
+  iteration is one library call computing the loss, dK and dV without dQ.
+Every step of the method runs in the HIP library; nothing here computes it.
 """
 from __future__ import annotations
 
@@ -198,3 +201,18 @@ class Decode(torch.autograd.Function):
         Q, K, V = ctx.saved_tensors
         dQ, dK, dV = ctx.decoder.backward(Q, K, V, dF)
         return dQ, dK, dV, None
+
+
+def stage2(decoder: Decoder, Q, K, V, target, K0, lambda_tr: float, iters: int = 5, step=None):
+    """Alg. 1 Stage II: ``iters`` (R2 in the paper, 5) decode-only iterations on a
+    fixed query map ``Q`` (the pixels of all 1 + B views of the step, stacked).
+    Each iteration is one ``lam_decode_loss`` call without dQ, which returns
+    the loss, dK and dV; ``step(dK, dV)`` then updates the dictionary in place
+    (the caller's optimiser).  Returns the loss of every iteration (device)."""
+    losses = []
+    for _ in range(iters):
+        loss, _, dK, dV = decoder.loss_and_grads(Q, K, V, target, K0, lambda_tr, want_dQ=False)
+        losses.append(loss)
+        if step is not None:
+            step(dK, dV)
+    return torch.cat(losses)

@@ -186,6 +186,34 @@ def test_backward_given_dF(prec):
         assert e < bar, name
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_stage2_without_dQ(prec):
+    """Stage II (Alg. 1): the call without dQ returns the same loss, dK and dV
+    bit for bit, and iterating it with a gradient step lowers the loss."""
+    from paper_2602_12314_amd import ops
+    n, d, M, D = 6 * 700, 16, 256, 512   # six small views stacked
+    say(f"[stage2] {prec} n={n}")
+    Q, K, V, T, K0 = _inputs(5, n, d, M, D)
+    dec = _decoder(prec, n, d, M, D)
+    q, k, v, t, k0 = _cuda(Q, K, V, T, K0)
+    l1, dQ1, dK1, dV1 = dec.loss_and_grads(q, k, v, t, k0, 0.1)
+    l0, dQ0, dK0, dV0 = dec.loss_and_grads(q, k, v, t, k0, 0.1, want_dQ=False)
+    assert dQ0 is None
+    for a, b in ((l0, l1), (dK0, dK1), (dV0, dV1)):
+        assert torch.equal(a, b)
+    kk, vv = k.clone(), v.clone()
+
+    def sgd(dK, dV, lr=1.0):  # stable: the trust-region curvature is 2 lambda = 0.2
+        kk.sub_(lr * dK)
+        vv.sub_(lr * dV)
+
+    losses = to_np(ops.stage2(dec, q, kk, vv, t, k0, 0.1, iters=5, step=sgd))
+    say(f"  losses {losses}")
+    assert losses.shape == (5,) and losses[-1] < losses[0]
+    ref = DO.loss_and_grads(Q, K, V, T, K0, 0.1)
+    assert abs(float(losses[0]) - ref["loss"]) / ref["loss"] < BARS[prec]["grad"]
+
+
 def test_one_hot_row_returns_value_row():
     rng = np.random.default_rng(5)
     d, M, D = 16, 64, 128
