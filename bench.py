@@ -45,16 +45,21 @@ def algorithmic_work(spec, prec: str, pairs_eval: int, pairs_blend: int, tile_pa
     """
     n, d, M, D = spec.n_pixels, spec.d, spec.M, spec.D
     N = spec.n_gauss * len(spec.cams)
+    Mp = (M + 63) // 64 * 64
+    splits = dv_splits(n, Mp, D)
     tb = 4 if prec == "fp32" else 2  # bytes of the decode's compute type
     dict_bytes = tb * (2 * M * D + 2 * M * d)
     entry = 44 + 4 * d  # one tile-list entry: record id, rec0, rec1, footprint, query
     return {
         # MFMA: S = Q K^T (2Md), F = P V (2MD), dP = G V^T (2MD), dQ = dS K (2Md) per pixel.
-        # Bytes: Q and the target in (FP32), P~^T, G^T, dS^T and Q^T out (compute type).
+        # Bytes: Q and the target in (FP32); G^T, dS^T, Q^T (compute type) and the
+        # row max (FP32) out.
         "decode_rows": dict(flops=n * 4.0 * M * (d + D), mfma=True,
-                            bytes=n * (4.0 * d + 4.0 * D + tb * (2 * M + D + 32)) + dict_bytes),
-        # MFMA: dV = P~^T G, 2MD per pixel; bytes: P~^T and G^T in, split partials out.
-        "decode_tn": dict(flops=n * 2.0 * M * D, mfma=True, bytes=n * tb * (M + D)),
+                            bytes=n * (4.0 * d + 4.0 * D + tb * (M + D + 32) + 4) + dict_bytes),
+        # MFMA: dV = P~^T G with P~ rebuilt from S = Q K^T, 2M (D + d) per pixel;
+        # bytes: G^T, Q and the row max in, the split partials out.
+        "decode_tn": dict(flops=n * 2.0 * M * (D + d), mfma=True,
+                          bytes=n * (tb * D + 4.0 * d + 4) + splits * Mp * D * 4.0),
         # VALU: per evaluated pair 20 flops (offset, conic form, exp, opacity, clamp,
         # transmittance); per blended pair 2d more for the query accumulation.
         # Bytes: the tile lists, and Q, T (twice) and the contributor count per pixel.
@@ -66,6 +71,18 @@ def algorithmic_work(spec, prec: str, pairs_eval: int, pairs_blend: int, tile_pa
         "raster_bwd": dict(flops=(45.0 + 9.0 * d) * pairs_blend, mfma=False,
                            bytes=tile_pairs * entry + n * (4.0 * d + 8) + N * (24.0 + 4 * d)),
     }
+
+
+def dv_splits(n: int, Mp: int, D: int) -> int:
+    """Split-K count of the dV reduction (decode_layout's rule): enough
+    workgroups to fill 256 CUs twice, a multiple of 8, at most the block count."""
+    nb = max(((n + 63) // 64) * 2, 1)
+    tiles = ((Mp + 127) // 128) * ((D + 127) // 128)
+    s = (512 + tiles - 1) // tiles
+    s = (s + 7) // 8 * 8
+    if s > nb:
+        s = (nb + 7) // 8 * 8
+    return max(s, 8)
 
 
 def roofline(work: dict, ms: float, prec: str) -> dict:

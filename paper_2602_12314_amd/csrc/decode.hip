@@ -3,19 +3,21 @@
 //   S = Q K^T / sqrt(d),  P = softmax_atoms(S),  F = P V
 //   L = mean_p (1 - cos(F_p, T_p)) + lambda ||K - K0||^2
 //
-// k_dec_rows handles 32 pixels per 256-thread workgroup (4 waves):
+// k_dec_rows handles 32 pixels per 256-thread workgroup (4 waves; or 64 pixels
+// per 8 waves, each V fragment then feeding two pixel groups):
 //   S^T tiles (32 atoms x 32 pixels) come from MFMA with the pixel as the
 //   column, so the softmax statistics of a pixel stay inside one lane pair;
 //   pass 1 takes the row max, pass 2 writes the unnormalised weights
-//   P~ = exp(S - m) to LDS, F^T = V^T P~^T runs with each wave owning a quarter
+//   P~ = exp(S - m) to LDS, F^T = V^T P~^T runs with each wave owning a share
 //   of the D rows, and the epilogue forms 1 - cos and the cosine gradient
 //   G = dL/dF / l (the softmax normaliser l folded in).  Then, per atom tile,
 //   dP = G V^T (G staged in LDS), dS = P~ (dP - delta) and dQ^T += K^T dS^T with
 //   dS^T fed from registers (K^T pre-permuted to match the MFMA lane layout).
-// The pixel reductions dV = P~^T G and dK = dS^T Q are split-K MFMA GEMMs
-// (k_dec_tn) over "pixel-blocked transposed" copies that k_dec_rows writes:
-// X^T_blk[block][row][32 pixels], so every MFMA fragment is one 16-byte load.
-// The softmax is recomputed in the backward part instead of being stored.
+// The pixel reductions are split-K MFMA GEMMs over "pixel-blocked transposed"
+// copies that k_dec_rows writes, X^T_blk[block][row][32 pixels], so every MFMA
+// fragment is one 16-byte load: dK = dS^T Q (k_dec_tn) and dV = P~^T G
+// (k_dec_dv), which rebuilds P~ from Q, K and the saved row max rather than
+// reading it.  The softmax is recomputed in the backward part, never stored.
 #include "common.h"
 #include "kernels.h"
 
@@ -130,7 +132,10 @@ constexpr int kScLd = 40;
 // pixels (16 bytes in BF16) per store: chunk q = q0, q0 + dq, ... covers row
 // q / 4, pixels 8 (q % 4) .. + 7.  This turns the one-pixel-per-lane MFMA
 // result layout into whole-chunk stores of the pixel-blocked transposes.
-template <class P>
+// With PERM the pixels of each 16-pixel half are stored in perm16 order
+// (position p holds pixel perm16(p)), the order in which k_dec_dv's recomputed
+// P~ fragments hold them.
+template <class P, bool PERM = false>
 __device__ inline void store_transposed(const typename P::T* S, int ld, int nrows, typename P::T* Dst,
                                         int q0, int dq)
 {
@@ -138,7 +143,10 @@ __device__ inline void store_transposed(const typename P::T* S, int ld, int nrow
         const int row = q >> 2, pg = (q & 3) * 8;
         typename P::Frag f;
 #pragma unroll
-        for (int j = 0; j < 8; ++j) f[j] = S[(pg + j) * ld + row];
+        for (int j = 0; j < 8; ++j) {
+            const int pix = PERM ? (pg & 16) + perm16((pg & 15) + j) : pg + j;
+            f[j] = S[pix * ld + row];
+        }
         *reinterpret_cast<typename P::Frag*>(Dst + (size_t)row * kPx + pg) = f;
     }
 }
@@ -271,7 +279,7 @@ struct RowsArgs {
     const uint8_t* Vt8;     // FP8 forward: V^T / s^V as E4M3 [D, Mp]
     const float* sv_fold;   // FP8 forward: s^V_j * 448 / max_j s^V_j   [Mp]
     const float* fp8_unscale;  // FP8 forward: max_j s^V_j / 448         [1]
-    void* Pt;   // [blocks, Mp, 32]  P~^T
+    float* M2;  // [blocks, 32]      row max of the logits in log2 units, per pixel
     void* Gt;   // [blocks, D, 32]   G^T
     void* St;   // [blocks, Mp, 32]  dS^T
     void* Qt;   // [blocks, 32, 32]  Q^T (rows >= d zero)
@@ -424,11 +432,10 @@ __global__ __launch_bounds__(NW * kWave) void k_dec_rows(RowsArgs a)
     }
     __syncthreads();
 
-    // ---- pass 2: P~ = exp2(S scale - m) into LDS [px][atom] (and P~^T to HBM)
+    // ---- pass 2: P~ = exp2(S scale - m) into LDS [px][atom]
     float lsum[NPG];
 #pragma unroll
     for (int g = 0; g < NPG; ++g) lsum[g] = 0.0f;
-    T* Ptb = reinterpret_cast<T*>(a.Pt) + (size_t)blk * NPG * a.Mp * kPx;
     for_tiles([&](int tt, const Frag* kf) {
 #pragma unroll
         for (int g = 0; g < NPG; ++g) {
@@ -454,11 +461,6 @@ __global__ __launch_bounds__(NW * kWave) void k_dec_rows(RowsArgs a)
                     int pk = __builtin_amdgcn_cvt_pk_fp8_f32(p[4 * g4] * sv.x, p[4 * g4 + 1] * sv.y, 0, false);
                     pk = __builtin_amdgcn_cvt_pk_fp8_f32(p[4 * g4 + 2] * sv.z, p[4 * g4 + 3] * sv.w, pk, true);
                     *reinterpret_cast<int*>(reinterpret_cast<uint8_t*>(X) + prow * (a.Mp + 16) + atom0) = pk;
-                    if (MODE != MODE_INFER) {  // LDS holds E4M3 weights: P~^T from registers
-                        T* Pt = Ptb + (size_t)g * a.Mp * kPx;
-#pragma unroll
-                        for (int k = 0; k < 4; ++k) Pt[(size_t)(atom0 + k) * kPx + col] = P::cvt(p[4 * g4 + k]);
-                    }
                 } else {
                     P::store4(X + prow * ldp + atom0, p[4 * g4], p[4 * g4 + 1], p[4 * g4 + 2], p[4 * g4 + 3]);
                 }
@@ -479,11 +481,10 @@ __global__ __launch_bounds__(NW * kWave) void k_dec_rows(RowsArgs a)
         for (int ww = 0; ww < NW; ++ww) l += rslot(1, ww, g)[col];
         invl[g] = 1.0f / l;
     }
-    // P~^T of the 32-pixel blocks from the LDS copy, in whole chunks
-    if (!F8 && MODE != MODE_INFER) {
+    // the row max of every pixel (past n too) for k_dec_dv, which rebuilds P~
+    if (MODE != MODE_INFER && w == 0 && h == 0) {
 #pragma unroll
-        for (int g = 0; g < NPG; ++g)
-            store_transposed<P>(X + g * kPx * ldp, ldp, a.Mp, Ptb + (size_t)g * a.Mp * kPx, threadIdx.x, NTH);
+        for (int g = 0; g < NPG; ++g) a.M2[(blk * NPG + g) * kPx + col] = m2[g];
     }
 
     // ---- F^T = V^T P~^T: wave w owns D tiles [w NT, w NT + NT) for every pixel group
@@ -713,11 +714,12 @@ __global__ __launch_bounds__(NW * kWave) void k_dec_rows(RowsArgs a)
         for (int ww = 0; ww < NW; ++ww) s += rslot(3, ww, g)[col];
         delta[g] = s;
     }
-    // G^T of this wave's D rows from the LDS copy, in whole chunks
+    // G^T of this wave's D rows from the LDS copy, in whole chunks, pixels in the
+    // perm16 order of k_dec_dv's P~ fragments
 #pragma unroll
     for (int g = 0; g < NPG; ++g) {
         T* Gt = reinterpret_cast<T*>(a.Gt) + ((size_t)(blk * NPG + g) * a.D + 32 * w * NT) * kPx;
-        store_transposed<P>(X + g * kPx * ldg + 32 * w * NT, ldg, 32 * NT, Gt, lane, kWave);
+        store_transposed<P, true>(X + g * kPx * ldg + 32 * w * NT, ldg, 32 * NT, Gt, lane, kWave);
     }
 
     // ---- per atom tile: dP = G V^T, dS = P~ (dP - delta) / sqrt(d), dQ^T += K^T dS^T
@@ -919,6 +921,129 @@ __global__ __launch_bounds__(256) void k_dec_tn(const void* At_, int rowsA, cons
                 out[(size_t)(i0 + 32 * a + crow(r, h)) * rowsB + j0 + 32 * q + col] = c[a][q][r];
 }
 
+// dV partials with P~ rebuilt instead of read: C_part[split][i][j] = sum over
+// the split's 32-pixel blocks of P~[px][i] G[px][j].  Per block the wave's two
+// atom tiles of S = Q K^T come from MFMA with the pixel as the row, so a lane
+// holds one atom and 16 pixels (rows crow(r, h)); P~ = exp2(S log2(e)/sqrt(d)
+// - m2[px]) with the row max k_dec_rows saved, and result registers 8k..8k+7
+// are directly the A fragment of pixel chunk k in perm16 order, the order in
+// which k_dec_rows stores G^T.  Waves 2 x 2, each 64 atoms x 64 features; two
+// blocks of Q, m2 and G^T fragments in flight; splits mapped as in k_dec_tn.
+template <class P, int DQ>
+__global__ __launch_bounds__(256) void k_dec_dv(const float* __restrict__ Q, int n, const void* Kb_, int M,
+                                                const float* __restrict__ m2, float scale_log2, const void* Gt_,
+                                                int Mp, int D, int nblocks, int splits, int tiles_i, int tiles_j,
+                                                float* __restrict__ part)
+{
+    using T = typename P::T;
+    using Frag = typename P::Frag;
+    constexpr int NQ = DQ / 16;
+    const T* Kb = reinterpret_cast<const T*>(Kb_);
+    const T* Gt = reinterpret_cast<const T*>(Gt_);
+    const int ntiles = tiles_i * tiles_j;
+    const int b = blockIdx.x;
+    const int xcd = b % 8, idx = b / 8;
+    const int split = (idx / ntiles) * 8 + xcd;
+    const int tile = idx % ntiles;
+    if (split >= splits) return;
+    const int ti = tile / tiles_j, tj = tile % tiles_j;
+    const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int col = lane & 31, h = lane >> 5;
+    const int i0 = (ti * 2 + w / 2) * 64, j0 = (tj * 2 + w % 2) * 64;
+    if (i0 >= Mp || j0 >= D) return;
+    const int per = (nblocks + splits - 1) / splits;
+    const int b0 = split * per, b1 = min(nblocks, b0 + per);
+
+    Frag kf[2][NQ];
+    bool atom_ok[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        atom_ok[t] = i0 + 32 * t + col < M;
+#pragma unroll
+        for (int c = 0; c < NQ; ++c) kf[t][c] = load_frag<P>(Kb, i0 / 32 + t, c, NQ, lane);
+    }
+    f32x16 acc[2][2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) acc[t][q] = f32x16{};
+
+    // one block's operands: Q rows of pixel col (zero past n), the row max of
+    // the lane's 16 pixels, and the G^T fragments of its two feature tiles
+    struct Blk {
+        float4 q[NQ][2];
+        float4 m[4];
+        Frag g[2][2];
+    };
+    auto load = [&](int blk, Blk& B) {
+        const int px = blk * kPx + col;
+        const float* qrow = Q + (size_t)(px < n ? px : n - 1) * DQ;
+#pragma unroll
+        for (int c = 0; c < NQ; ++c) {
+            B.q[c][0] = *reinterpret_cast<const float4*>(qrow + 16 * c + 8 * h);
+            B.q[c][1] = *reinterpret_cast<const float4*>(qrow + 16 * c + 8 * h + 4);
+        }
+#pragma unroll
+        for (int g4 = 0; g4 < 4; ++g4)
+            B.m[g4] = *reinterpret_cast<const float4*>(m2 + (size_t)blk * kPx + 8 * g4 + 4 * h);
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int k = 0; k < 2; ++k)
+                B.g[q][k] = P::load(Gt + ((size_t)blk * D + j0 + 32 * q + col) * kPx + 16 * k + 8 * h);
+    };
+    auto compute = [&](int blk, const Blk& B) {
+        const bool valid = blk * kPx + col < n;
+        Frag qf[NQ];
+#pragma unroll
+        for (int c = 0; c < NQ; ++c) {
+            const float v[8] = {B.q[c][0].x, B.q[c][0].y, B.q[c][0].z, B.q[c][0].w,
+                                B.q[c][1].x, B.q[c][1].y, B.q[c][1].z, B.q[c][1].w};
+            float z[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) z[e] = valid ? v[e] : 0.0f;
+            qf[c] = P::from_f32(z);
+        }
+        const float mr[16] = {B.m[0].x, B.m[0].y, B.m[0].z, B.m[0].w, B.m[1].x, B.m[1].y, B.m[1].z, B.m[1].w,
+                              B.m[2].x, B.m[2].y, B.m[2].z, B.m[2].w, B.m[3].x, B.m[3].y, B.m[3].z, B.m[3].w};
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            f32x16 s = {};
+#pragma unroll
+            for (int c = 0; c < NQ; ++c) P::mma(s, qf[c], kf[t][c]);
+            float p[16];
+#pragma unroll
+            for (int r = 0; r < 16; ++r) p[r] = atom_ok[t] ? exp2_weight(s[r] * scale_log2 - mr[r]) : 0.0f;
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                const Frag af = P::from_f32(p + 8 * k);
+#pragma unroll
+                for (int q = 0; q < 2; ++q) P::mma(acc[t][q], af, B.g[q][k]);
+            }
+        }
+    };
+    if (b0 < b1) {
+        Blk ring[2];
+        load(b0, ring[0]);
+        int blk = b0;
+        for (; blk + 2 <= b1; blk += 2) {
+            load(min(blk + 1, b1 - 1), ring[1]);
+            compute(blk, ring[0]);
+            load(min(blk + 2, b1 - 1), ring[0]);
+            compute(blk + 1, ring[1]);
+        }
+        if (blk < b1) compute(blk, ring[0]);
+    }
+    float* out = part + (size_t)split * Mp * D;
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                out[(size_t)(i0 + 32 * t + crow(r, h)) * D + j0 + 32 * q + col] = acc[t][q][r];
+}
+
 // out[i][j] = sum_split part[split][i][j] (+ 2 lambda (K - K0)[i][j] for dK)
 // for i < rows_out, j < cols_out (a multiple of 4); part has ld = ldp columns
 // and rows_p rows per split.  A workgroup covers 64 groups of 4 consecutive
@@ -1073,7 +1198,7 @@ bool decode_layout(int prec, int n, int d, int M, int D, DecodeLayout* L)
     L->off_vb = take((size_t)Mp * D * tb);
     L->off_vt = take((size_t)Mp * D * tb);
     L->off_kt = take((size_t)32 * Mp * tb);
-    L->off_p = take((size_t)nb * Mp * kPx * tb);
+    L->off_m2 = take((size_t)nb * kPx * 4);
     L->off_gf = take((size_t)nb * D * kPx * tb);
     L->off_ds = take((size_t)nb * Mp * kPx * tb);
     L->off_qt = take((size_t)nb * 32 * kPx * tb);
@@ -1154,7 +1279,8 @@ static hipError_t run_decode(const DecodeArgs& A, const DecodeLayout& L, int mod
     ra.Q = A.Q; ra.target = A.target; ra.dF = A.dF; ra.F = A.F; ra.dQ = A.dQ; ra.row_cos = A.row_cos;
     ra.loss_part = reinterpret_cast<float*>(base + L.off_loss);
     ra.Kb = Kb; ra.Vb = Vb; ra.Vt = Vt; ra.Ktp = Ktp;
-    ra.Pt = base + L.off_p; ra.Gt = base + L.off_gf; ra.St = base + L.off_ds; ra.Qt = base + L.off_qt;
+    ra.M2 = reinterpret_cast<float*>(base + L.off_m2);
+    ra.Gt = base + L.off_gf; ra.St = base + L.off_ds; ra.Qt = base + L.off_qt;
     if (F8) {
         float* sc = reinterpret_cast<float*>(base + L.off_sc);
         ra.Vt8 = reinterpret_cast<const uint8_t*>(Vt);
@@ -1171,14 +1297,15 @@ static hipError_t run_decode(const DecodeArgs& A, const DecodeLayout& L, int mod
     }
     if (mode == MODE_INFER) return hipGetLastError();
     float* part = reinterpret_cast<float*>(base + L.off_part);
-    // dV = P~^T G over all pixels
+    // dV = P~^T G over all pixels, P~ rebuilt from Q, K and the saved row max
     {
         const int ti = (Mp + 127) / 128, tj = (A.D + 127) / 128;
         if (nb > 0) {
             ProfScope ps("decode_tn", st);
-            hipLaunchKernelGGL((k_dec_tn<P, 2, 2, 2, 2>), dim3(L.splits * ti * tj), dim3(256), 0, st,
-                               (const void*)(base + L.off_p), Mp, (const void*)(base + L.off_gf), A.D, nb,
-                               L.splits, ti, tj, part);
+            auto kern = A.d == 16 ? k_dec_dv<P, 16> : k_dec_dv<P, 32>;
+            hipLaunchKernelGGL(kern, dim3(L.splits * ti * tj), dim3(256), 0, st, A.Q, A.n,
+                               (const void*)Kb, A.M, (const float*)ra.M2, ra.scale_log2,
+                               (const void*)(base + L.off_gf), Mp, A.D, nb, L.splits, ti, tj, part);
         }
         hipLaunchKernelGGL(k_dec_reduce, dim3((A.M * A.D / 4 + 63) / 64), dim3(256), 0, st,
                            (const float*)part, nb > 0 ? L.splits : 0, Mp, A.D, A.M, A.D, A.dV,

@@ -82,7 +82,7 @@ struct DecodeLayout {
     uint64_t bytes;
     void* base;
     // byte offsets inside the workspace, filled by decode_layout()
-    size_t off_kb, off_vb, off_vt, off_kt, off_gf, off_p, off_ds, off_qt, off_part, off_loss, off_sc;
+    size_t off_kb, off_vb, off_vt, off_kt, off_gf, off_m2, off_ds, off_qt, off_part, off_loss, off_sc;
     int splits, splits_k;
 };
 

@@ -37,7 +37,7 @@ CSRC = os.path.join(HERE, "csrc")
 # bench stage name -> (kernel name prefix in the trace, source files it is built from)
 STAGES = {
     "decode_rows": ("k_dec_rows", ["decode.hip", "common.h", "kernels.h"]),
-    "decode_tn": ("k_dec_tn<TBF16, 2, 2, 2, 2>", ["decode.hip", "common.h", "kernels.h"]),
+    "decode_tn": ("k_dec_dv", ["decode.hip", "common.h", "kernels.h"]),
     "raster_fwd": ("k_raster_fwd", ["render.hip", "common.h", "kernels.h"]),
     "raster_bwd": ("k_raster_bwd", ["render.hip", "common.h", "kernels.h"]),
 }
