@@ -84,7 +84,7 @@ lam_status render_layout(int n_gauss, int d, const float* cams, int n_cams, int 
     L->pixels = pixels;
     const int tb = log2i(std::max(L->cams.total_tiles, 2));
     L->tile_bits = tb;
-    L->tile_in_b = radix_passes(tb) % 2 == 1;
+    L->tile_in_b = radix_passes(tb, (uint32_t)capacity) % 2 == 1;
     if (capacity == 0) L->tile_in_b = false;
     size_t scratch_words = std::max(radix_scratch_words((uint32_t)R),
                                     radix_scratch_words((uint32_t)capacity));

@@ -1104,22 +1104,46 @@ __global__ __launch_bounds__(256) void k_dec_reduce(const float* __restrict__ pa
     }
 }
 
-// loss = (1/n) sum_blocks part + lambda ||K - K0||^2  (single workgroup, fixed order)
-__global__ __launch_bounds__(256) void k_dec_loss(const float* __restrict__ part, int nblocks, float inv_n,
-                                                  const float* __restrict__ K, const float* __restrict__ K0,
-                                                  int nk, float lambda, float* __restrict__ loss)
+// loss = (1/n) sum_blocks part + lambda ||K - K0||^2: one 1024-thread
+// workgroup, each thread with eight independent loads in flight per round,
+// then a fixed-order tree in LDS (deterministic).
+__global__ __launch_bounds__(1024) void k_dec_loss(const float* __restrict__ part, int nblocks, float inv_n,
+                                                   const float* __restrict__ K, const float* __restrict__ K0,
+                                                   int nk, float lambda, float* __restrict__ loss)
 {
-    __shared__ float sh[256];
-    float s = 0.f, tr = 0.f;
-    for (int i = threadIdx.x; i < nblocks; i += 256) s += part[i];
-    if (K0 && lambda != 0.f)
-        for (int i = threadIdx.x; i < nk; i += 256) {
-            const float dlt = K[i] - K0[i];
-            tr += dlt * dlt;
+    __shared__ float sh[1024];
+    constexpr int U = 8;
+    float s[U], tr[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) s[u] = tr[u] = 0.0f;
+    for (int i0 = 0; i0 < nblocks; i0 += 1024 * U) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + u * 1024 + (int)threadIdx.x;
+            const float x = part[i < nblocks ? i : nblocks - 1];  // every load issued, then masked
+            s[u] += i < nblocks ? x : 0.0f;
         }
-    sh[threadIdx.x] = s * inv_n + lambda * tr;
+    }
+    if (K0 && lambda != 0.f) {
+        for (int i0 = 0; i0 < nk; i0 += 1024 * U) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int i = i0 + u * 1024 + (int)threadIdx.x;
+                const int ic = i < nk ? i : nk - 1;
+                const float dlt = K[ic] - K0[ic];
+                tr[u] += i < nk ? dlt * dlt : 0.0f;
+            }
+        }
+    }
+    float ss = 0.0f, tt = 0.0f;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        ss += s[u];
+        tt += tr[u];
+    }
+    sh[threadIdx.x] = ss * inv_n + lambda * tt;
     __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
+    for (int o = 512; o > 0; o >>= 1) {
         if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
         __syncthreads();
     }
@@ -1326,7 +1350,7 @@ static hipError_t run_decode(const DecodeArgs& A, const DecodeLayout& L, int mod
                            tr ? 2.0f * A.lambda_tr : 0.0f);
     }
     if (mode == MODE_LOSS)
-        hipLaunchKernelGGL(k_dec_loss, dim3(1), dim3(256), 0, st, (const float*)ra.loss_part, nb,
+        hipLaunchKernelGGL(k_dec_loss, dim3(1), dim3(1024), 0, st, (const float*)ra.loss_part, nb,
                            ra.inv_n, A.K, A.K0, A.M * A.d, A.K0 ? A.lambda_tr : 0.0f, A.loss);
     return hipGetLastError();
 }

@@ -12,7 +12,7 @@ namespace lam {
 // ------------------------------------------------------------- sort / scan
 size_t scan_scratch_words(uint32_t n);
 size_t radix_scratch_words(uint32_t n_cap);
-int radix_passes(int bits);  // passes launch_radix_sort makes for ``bits`` key bits
+int radix_passes(int bits, uint32_t n_cap);  // passes launch_radix_sort makes for ``bits`` key bits
 hipError_t launch_excl_scan(const uint32_t* in, const uint32_t* idx, uint32_t n, uint32_t* out,
                             uint32_t* total, uint32_t* scratch, hipStream_t st);
 hipError_t launch_radix_sort(const uint32_t* keys_first, uint32_t* keys_a, uint32_t* vals_a,

@@ -227,7 +227,7 @@ hipError_t launch_excl_scan(const uint32_t* in, const uint32_t* idx, uint32_t n,
 
 // ------------------------------------------------------------------ radix
 
-template <int DB>
+template <int DB, int ITEMS>
 __global__ __launch_bounds__(kTileThreads) void k_radix_hist(const uint32_t* __restrict__ keys,
                                                              const uint32_t* __restrict__ n_dev,
                                                              uint32_t n_cap, int shift,
@@ -239,23 +239,23 @@ __global__ __launch_bounds__(kTileThreads) void k_radix_hist(const uint32_t* __r
     for (int k = threadIdx.x; k < BINS; k += kTileThreads) h[k] = 0;
     __syncthreads();
     const uint32_t n = load_count(n_dev, n_cap);
-    const uint32_t base = blockIdx.x * (uint32_t)kTile;
+    const uint32_t base = blockIdx.x * (uint32_t)(kTileThreads * ITEMS);
     if (base < n) {  // keys loaded together (clamped), then counted
-        uint32_t key[kTileItems];
+        uint32_t key[ITEMS];
 #pragma unroll
-        for (int k = 0; k < kTileItems; ++k) {
+        for (int k = 0; k < ITEMS; ++k) {
             const uint32_t i = base + k * kTileThreads + threadIdx.x;
             key[k] = keys[i < n ? i : n - 1];
         }
 #pragma unroll
-        for (int k = 0; k < kTileItems; ++k)
+        for (int k = 0; k < ITEMS; ++k)
             if (base + k * kTileThreads + threadIdx.x < n) atomicAdd(&h[(key[k] >> shift) & (BINS - 1u)], 1u);
     }
     __syncthreads();
     for (int k = threadIdx.x; k < BINS; k += kTileThreads) hist[(size_t)k * nblocks + blockIdx.x] = h[k];
 }
 
-template <int DB>
+template <int DB, int ITEMS>
 __global__ __launch_bounds__(kTileThreads) void k_radix_scatter(
     const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
     uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
@@ -273,29 +273,29 @@ __global__ __launch_bounds__(kTileThreads) void k_radix_scatter(
     __syncthreads();
 
     const uint32_t n = load_count(n_dev, n_cap);
-    const uint32_t span = blockIdx.x * (uint32_t)kTile + w * (kWave * kTileItems);
+    const uint32_t span = blockIdx.x * (uint32_t)(kTileThreads * ITEMS) + w * (kWave * ITEMS);
     const unsigned long long lt = (1ull << lane) - 1ull;
-    uint32_t key[kTileItems], val[kTileItems], rank[kTileItems];
+    uint32_t key[ITEMS], val[ITEMS], rank[ITEMS];
     // all keys and values of the wave's span are requested before the ranking
     // (indices clamped into range; entries past n are never written)
     const uint32_t nl = n > 0 ? n - 1 : 0;
 #pragma unroll
-    for (int s = 0; s < kTileItems; ++s) {
+    for (int s = 0; s < ITEMS; ++s) {
         const uint32_t i = span + s * kWave + lane;
         key[s] = keys_in[i < n ? i : nl];
     }
     if (vals_in) {
 #pragma unroll
-        for (int s = 0; s < kTileItems; ++s) {
+        for (int s = 0; s < ITEMS; ++s) {
             const uint32_t i = span + s * kWave + lane;
             val[s] = vals_in[i < n ? i : nl];
         }
     } else {
 #pragma unroll
-        for (int s = 0; s < kTileItems; ++s) val[s] = span + s * kWave + lane;
+        for (int s = 0; s < ITEMS; ++s) val[s] = span + s * kWave + lane;
     }
 #pragma unroll
-    for (int s = 0; s < kTileItems; ++s) {
+    for (int s = 0; s < ITEMS; ++s) {
         const uint32_t i = span + s * kWave + lane;
         const bool ok = i < n;
         const uint32_t dg = (key[s] >> shift) & (BINS - 1u);
@@ -324,7 +324,7 @@ __global__ __launch_bounds__(kTileThreads) void k_radix_scatter(
     }
     __syncthreads();
 #pragma unroll
-    for (int s = 0; s < kTileItems; ++s) {
+    for (int s = 0; s < ITEMS; ++s) {
         if (rank[s] == 0xFFFFFFFFu) continue;
         const uint32_t dg = (key[s] >> shift) & (BINS - 1u);
         const uint32_t pos = gbase[dg] + cnt[w][dg] + rank[s];
@@ -335,21 +335,30 @@ __global__ __launch_bounds__(kTileThreads) void k_radix_scatter(
     }
 }
 
-// Passes and digit width for ``bits`` key bits: at most 11 bits per pass.
-static void radix_plan(int bits, int* passes, int* width)
+// Plan of a sort of ``bits`` key bits over at most n_cap keys.  Wide keys over
+// a modest count (the depth keys of up to 2^20 records) take 8-bit digits over
+// tiles of 1024 keys: four times the workgroups of 4096-key tiles and a
+// histogram (bins x tiles) eight times smaller to scan, for one pass more.
+// Otherwise at most 11 bits per pass over 4096-key tiles.
+struct RadixPlan {
+    int passes, width, items;
+};
+
+static RadixPlan radix_plan(int bits, uint32_t n_cap)
 {
     if (bits < 1) bits = 1;
-    int p = (bits + 10) / 11;
-    int wdt = (bits + p - 1) / p;
-    *passes = p;
-    *width = wdt <= 8 ? 8 : 11;
+    if (bits > 16 && n_cap <= (1u << 20)) return RadixPlan{(bits + 7) / 8, 8, 4};
+    const int p = (bits + 10) / 11;
+    const int wdt = (bits + p - 1) / p;
+    return RadixPlan{p, wdt <= 8 ? 8 : 11, kTileItems};
 }
 
 size_t radix_scratch_words(uint32_t n_cap)
 {
-    uint32_t nb = (n_cap + kTile - 1) / kTile;
-    if (nb == 0) nb = 1;
-    size_t h = (size_t)2048 * nb;
+    // the larger histogram of the two plans
+    const uint32_t nb4k = std::max((n_cap + kTile - 1) / kTile, 1u);
+    const uint32_t nb1k = std::max((n_cap + kTileThreads * 4 - 1) / (kTileThreads * 4), 1u);
+    const size_t h = std::max((size_t)2048 * nb4k, (size_t)256 * nb1k);
     return h + scan_scratch_words((uint32_t)h) + 8;
 }
 
@@ -362,32 +371,39 @@ hipError_t launch_radix_sort(const uint32_t* keys_first, uint32_t* keys_a, uint3
                              const uint32_t* n_dev, uint32_t n_cap, int bits, uint32_t* scratch,
                              bool* in_b, hipStream_t st)
 {
-    const uint32_t nb = (n_cap + kTile - 1) / kTile;
+    const RadixPlan plan = radix_plan(bits, n_cap);
+    const uint32_t tile = (uint32_t)(kTileThreads * plan.items);
+    const uint32_t nb = (n_cap + tile - 1) / tile;
     *in_b = false;
     if (nb == 0) return hipSuccess;
-    int passes, width;
-    radix_plan(bits, &passes, &width);
+    const int width = plan.width;
     const uint32_t bins = 1u << width;
     uint32_t* hist = scratch;
     uint32_t* sscr = scratch + (size_t)bins * nb;
     uint32_t *ki = keys_a, *vi = vals_a, *ko = keys_b, *vo = vals_b;
-    for (int p = 0; p < passes; ++p) {
+    for (int p = 0; p < plan.passes; ++p) {
         const int shift = width * p;
         const uint32_t* kin = (p == 0 && keys_first) ? keys_first : ki;
         const uint32_t* vin = (p == 0 && iota_first) ? (const uint32_t*)nullptr : vi;
-        if (width == 8)
-            hipLaunchKernelGGL(k_radix_hist<8>, dim3(nb), dim3(kTileThreads), 0, st, kin, n_dev,
+        if (plan.items == 4)
+            hipLaunchKernelGGL((k_radix_hist<8, 4>), dim3(nb), dim3(kTileThreads), 0, st, kin, n_dev, n_cap,
+                               shift, hist, nb);
+        else if (width == 8)
+            hipLaunchKernelGGL((k_radix_hist<8, kTileItems>), dim3(nb), dim3(kTileThreads), 0, st, kin, n_dev,
                                n_cap, shift, hist, nb);
         else
-            hipLaunchKernelGGL(k_radix_hist<11>, dim3(nb), dim3(kTileThreads), 0, st, kin, n_dev,
+            hipLaunchKernelGGL((k_radix_hist<11, kTileItems>), dim3(nb), dim3(kTileThreads), 0, st, kin, n_dev,
                                n_cap, shift, hist, nb);
         hipError_t e = launch_excl_scan(hist, nullptr, bins * nb, hist, nullptr, sscr, st);
         if (e != hipSuccess) return e;
-        if (width == 8)
-            hipLaunchKernelGGL(k_radix_scatter<8>, dim3(nb), dim3(kTileThreads), 0, st, kin, vin, ko,
-                               vo, n_dev, n_cap, shift, hist, nb);
+        if (plan.items == 4)
+            hipLaunchKernelGGL((k_radix_scatter<8, 4>), dim3(nb), dim3(kTileThreads), 0, st, kin, vin, ko, vo,
+                               n_dev, n_cap, shift, hist, nb);
+        else if (width == 8)
+            hipLaunchKernelGGL((k_radix_scatter<8, kTileItems>), dim3(nb), dim3(kTileThreads), 0, st, kin, vin,
+                               ko, vo, n_dev, n_cap, shift, hist, nb);
         else
-            hipLaunchKernelGGL(k_radix_scatter<11>, dim3(nb), dim3(kTileThreads), 0, st, kin, vin,
+            hipLaunchKernelGGL((k_radix_scatter<11, kTileItems>), dim3(nb), dim3(kTileThreads), 0, st, kin, vin,
                                ko, vo, n_dev, n_cap, shift, hist, nb);
         uint32_t* t = ki; ki = ko; ko = t;
         t = vi; vi = vo; vo = t;
@@ -396,11 +412,6 @@ hipError_t launch_radix_sort(const uint32_t* keys_first, uint32_t* keys_a, uint3
     return hipGetLastError();
 }
 
-int radix_passes(int bits)
-{
-    int p, w;
-    radix_plan(bits, &p, &w);
-    return p;
-}
+int radix_passes(int bits, uint32_t n_cap) { return radix_plan(bits, n_cap).passes; }
 
 }  // namespace lam
