@@ -225,6 +225,9 @@ def run(args):
     stage2 = None
     if not args.no_stage2:
         stage2 = stage2_leg(ops, dec, prec, spec, Q, K, V, tgt, K0, dev)
+    tied = None
+    if not args.no_tied:
+        tied = tied_leg(ops, prec, spec, Q, V, tgt, dev)
 
     out = {
         "metric": "feature-pixels/s fwd+bwd",
@@ -254,6 +257,7 @@ def run(args):
             "stage_ms": {k: round(v, 4) for k, v in prof32.items()},
             "speedup_of_reduced_precision": sec32 / sec},
         "stage2": stage2,
+        "tied_decode": tied,
     }
 
     # roofline of the dominant kernel, with algorithmic work from the oracle's pair counts
@@ -307,6 +311,29 @@ def stage2_leg(ops, dec1, prec, spec, Q, K, V, tgt, K0, dev, views=6, iters=5, r
     return {"views": views, "iters": iters, "pixels_per_iter": n, "ms": sec * 1e3,
             "value": n * iters / sec, "unit": "feature-pixels/s (decode + loss + dK, dV; Adam on K, V)",
             "loss_first_last": [float(losses[0]), float(losses[-1])]}
+
+
+def tied_leg(ops, prec, spec, Q, V, tgt, dev, reps=10):
+    """The paper's tied decode (Eq. 5 with cosine logits at temperature 0.1,
+    V = D) and full loss (cosine + L2 + hinge trust region, the paper's weights)
+    with gradients to Q, W and D, on this workload's query map and shapes; W is
+    a random d x D projection and D0 the dictionary before one perturbation."""
+    import torch
+    n, d, M, Dd = spec.n_pixels, spec.d, spec.M, spec.D
+    g = torch.Generator(device=dev).manual_seed(3)
+    W = torch.randn((d, Dd), device=dev, generator=g) / d ** 0.5
+    D0 = V.clone()
+    Dm = D0 + 0.05 * torch.randn(D0.shape, device=dev, generator=g)
+    dec = ops.TiedDecoder(prec, n, d, M, Dd, device=dev)
+    dec.loss_and_grads(Q, W, Dm, tgt, D0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        loss, _, _, _ = dec.loss_and_grads(Q, W, Dm, tgt, D0)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / reps
+    return {"ms": sec * 1e3, "value": n / sec, "unit": "feature-pixels/s (decode + loss + dQ, dW, dD)",
+            "params": dict(ops.PAPER_TIED_PARAMS), "loss": float(loss)}
 
 
 def _read_prof(L, name):
@@ -384,6 +411,7 @@ def main():
     ap.add_argument("--graph", action="store_true", help="time replays of the HIP-graph-captured step")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 decode comparison leg")
     ap.add_argument("--no-stage2", action="store_true", help="skip the Stage-II decode-only leg")
+    ap.add_argument("--no-tied", action="store_true", help="skip the tied-decode leg")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (scales HBM byte counters)")
     args = ap.parse_args()

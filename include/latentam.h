@@ -205,11 +205,52 @@ lam_status lam_decode_backward(int precision, const float* Q, int n, int d, cons
                                const float* V, int M, int D, const float* dF, float* dQ,
                                float* dK, float* dV, void* ws, uint64_t ws_bytes, void* stream);
 
+/* ------------------------------------------------------ tied decode (paper) */
+
+/* The decode and loss as the paper states them (Sec. III-C, Eq. 5-6):
+ *   F^ = Softmax(Q W D^T) D with the softmax taken over the cosine similarity
+ *        of the rows of Q W and the atoms D_j, divided by a temperature tau,
+ *   L  = lambda_cos mean_p (1 - cos(F^_p, F_p)) + lambda_2 mean_p |F^_p - F_p|^2
+ *        + lambda_D sum_j ReLU(|D0_j - D_j| - delta).
+ * Norms are guarded as max(|.|, 1e-12), the cosine denominator as
+ * max(|F^||F|, 1e-8).  The paper's values: lambda_cos = lambda_2 = 0.5,
+ * lambda_D = 0.2, delta = 0.1; it gives no temperature. */
+typedef struct {
+    float tau;        /* > 0 */
+    float lambda_cos; /* >= 0 */
+    float lambda_2;   /* >= 0 */
+    float lambda_D;   /* >= 0 */
+    float delta;      /* >= 0 */
+} lam_tied_params;
+
+/* Workspace bytes for lam_decode_tied_loss: n pixel rows, query dimension ds
+ * (16 or 32), M atoms, feature dimension df (the decode's D; same limits as
+ * lam_decode_workspace_size).  Host-only.
+ * Errors: LAM_ERR_INVALID_ARG (null out, n < 0), LAM_ERR_UNSUPPORTED (shape). */
+lam_status lam_decode_tied_workspace_size(int precision, int n, int ds, int M, int df, uint64_t* bytes);
+
+/* Loss and gradients of the tied decode.  Device inputs (FP32, row-major):
+ * Q [n, ds], W [ds, df], D [M, df], target F [n, df], D0 [M, df] (the initial
+ * dictionary); params on the host.  Device outputs (overwritten): loss [1],
+ * dQ [n, ds] (nullable: the decode-only iterations skip it), dW [ds, df],
+ * dD [M, df].  precision selects the attention arithmetic as in
+ * lam_decode_loss; the normalisations and the gradient chain run in FP32.
+ * Q, target and dQ rows are read and written 16 bytes at a time (16-byte
+ * aligned).  Stream-ordered, no host synchronisation.
+ * Errors: LAM_ERR_INVALID_ARG (null or misaligned pointers, workspace too
+ * small, tau <= 0 or a negative weight), LAM_ERR_UNSUPPORTED (shape),
+ * LAM_ERR_HIP. */
+lam_status lam_decode_tied_loss(int precision, const float* Q, int n, int ds, const float* W, const float* D,
+                                int M, int df, const float* target, const float* D0,
+                                const lam_tied_params* params, float* loss, float* dQ, float* dW, float* dD,
+                                void* ws, uint64_t ws_bytes, void* stream);
+
 /* --------------------------------------------------------------- profiling */
 
 /* Turns per-kernel timing on or off (process-wide, off by default).  While on,
  * the main kernels (names: "raster_fwd", "raster_bwd", "decode_rows",
- * "decode_tn", "render_sort", "preprocess", "preprocess_bwd") are bracketed by
+ * "decode_tn", "render_sort", "preprocess", "preprocess_bwd", "tied_prep",
+ * "tied_grads") are bracketed by
  * HIP events recorded on their launch stream.  Not for use under graph capture. */
 lam_status lam_profile_enable(int on);
 

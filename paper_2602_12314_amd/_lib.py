@@ -23,6 +23,12 @@ CAM_FLOATS = 22
 _lib = None
 
 
+class TiedParams(C.Structure):
+    """lam_tied_params: temperature and loss weights of the tied decode."""
+    _fields_ = [("tau", C.c_float), ("lambda_cos", C.c_float), ("lambda_2", C.c_float),
+                ("lambda_D", C.c_float), ("delta", C.c_float)]
+
+
 class LamError(RuntimeError):
     def __init__(self, status: int, where: str):
         super().__init__(f"{where}: {status_string(status)} ({status})")
@@ -58,6 +64,9 @@ def lib():
             "lam_decode_forward": (i32, [i32, vp, i32, i32, vp, vp, i32, i32, vp, vp, u64, vp]),
             "lam_decode_backward": (i32, [i32, vp, i32, i32, vp, vp, i32, i32, vp, vp, vp, vp, vp, u64,
                                           vp]),
+            "lam_decode_tied_workspace_size": (i32, [i32, i32, i32, i32, i32, pu64]),
+            "lam_decode_tied_loss": (i32, [i32, vp, i32, i32, vp, vp, i32, i32, vp, vp, C.POINTER(TiedParams),
+                                           vp, vp, vp, vp, vp, u64, vp]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -191,3 +200,20 @@ def decode_backward(precision, Q, K, V, dF, dQ, dK, dV, ws, stream=None):
                                     D, _p(dF), _p(dQ), _p(dK), _p(dV), _p(ws),
                                     ws.numel() * ws.element_size(), _stream(stream)),
           "lam_decode_backward")
+
+
+def decode_tied_workspace_size(precision, n, ds, M, df) -> int:
+    out = C.c_uint64()
+    check(lib().lam_decode_tied_workspace_size(PRECISIONS.get(precision, precision), n, ds, M, df,
+                                               C.byref(out)), "lam_decode_tied_workspace_size")
+    return int(out.value)
+
+
+def decode_tied_loss(precision, Q, W, D, target, D0, params, loss, dQ, dW, dD, ws, stream=None):
+    n, ds = Q.shape
+    M, df = D.shape
+    p = TiedParams(*[float(params[k]) for k in ("tau", "lambda_cos", "lambda_2", "lambda_D", "delta")])
+    check(lib().lam_decode_tied_loss(PRECISIONS.get(precision, precision), _p(Q), n, ds, _p(W), _p(D), M, df,
+                                     _p(target), _p(D0), C.byref(p), _p(loss), _p(dQ), _p(dW), _p(dD), _p(ws),
+                                     ws.numel() * ws.element_size(), _stream(stream)),
+          "lam_decode_tied_loss")

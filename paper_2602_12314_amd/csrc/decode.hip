@@ -265,6 +265,7 @@ struct RowsArgs {
     float scale_log2;   // log2(e) / sqrt(d)
     float inv_sqrt_d;
     float inv_n;
+    float lam_cos, lam_l2;  // loss weights of 1 - cos and of |F - T|^2 (LOSS mode)
     const float* Q;
     const float* target;  // MODE_LOSS
     const float* dF;      // MODE_ADJ
@@ -665,13 +666,16 @@ __global__ __launch_bounds__(NW * kWave) void k_dec_rows(RowsArgs a)
             const float raw = sqrtf(sf) * sqrtf(stt);
             const float den = fmaxf(raw, 1e-8f);
             const float cs = st / den;
-            // dL/dF = -(1/n) (T / den - c F / |F|^2), then divided by l
-            ca[g] = valid[g] ? -a.inv_n / den * invl[g] : 0.0f;
-            cb[g] = (valid[g] && raw > 1e-8f && sf > 0.f) ? a.inv_n * cs / sf * invl[g] : 0.0f;
+            // dL/dF = lam_cos (-(1/n) (T / den - c F / |F|^2)) + lam_l2 (2/n) (F - T),
+            // then divided by l
+            const float l2 = 2.0f * a.lam_l2 * a.inv_n;
+            ca[g] = valid[g] ? (-a.lam_cos * a.inv_n / den - l2) * invl[g] : 0.0f;
+            cb[g] = valid[g] ? (((raw > 1e-8f && sf > 0.f) ? a.lam_cos * a.inv_n * cs / sf : 0.0f) + l2) * invl[g]
+                             : 0.0f;
             if (w == g && h == 0) {
                 if (a.row_cos && valid[g]) a.row_cos[pxg[g]] = cs;
-                // sum of (1 - cos) over the valid pixels of 32-pixel block g
-                float lp = valid[g] ? 1.0f - cs : 0.0f;
+                // sum of the pixel losses over the valid pixels of 32-pixel block g
+                float lp = valid[g] ? a.lam_cos * (1.0f - cs) + a.lam_l2 * (sf - 2.0f * st + stt) : 0.0f;
                 for (int o = 16; o >= 1; o >>= 1) lp += __shfl_xor(lp, o, kWave);
                 if (col == 0) a.loss_part[blk * NPG + g] = lp;
             }
@@ -1297,8 +1301,12 @@ static hipError_t run_decode(const DecodeArgs& A, const DecodeLayout& L, int mod
     }
     RowsArgs ra{};
     ra.n = A.n; ra.d = A.d; ra.M = A.M; ra.Mp = Mp; ra.D = A.D;
-    ra.scale_log2 = kLog2e / sqrtf((float)A.d);
-    ra.inv_sqrt_d = 1.0f / sqrtf((float)A.d);
+    // logits Q K^T / sqrt(d), or Q K^T * logit_scale when the caller sets it
+    const float lscale = A.logit_scale > 0.0f ? A.logit_scale : 1.0f / sqrtf((float)A.d);
+    ra.scale_log2 = kLog2e * lscale;
+    ra.inv_sqrt_d = lscale;
+    ra.lam_cos = A.lam_cos;
+    ra.lam_l2 = A.lam_l2;
     ra.inv_n = A.n > 0 ? 1.0f / (float)A.n : 0.0f;
     ra.Q = A.Q; ra.target = A.target; ra.dF = A.dF; ra.F = A.F; ra.dQ = A.dQ; ra.row_cos = A.row_cos;
     ra.loss_part = reinterpret_cast<float*>(base + L.off_loss);

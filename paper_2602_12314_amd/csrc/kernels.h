@@ -74,6 +74,8 @@ struct DecodeArgs {
     const float *Q, *K, *V, *target, *K0, *dF;
     float lambda_tr;
     float *loss, *dQ, *dK, *dV, *row_cos, *F;
+    float lam_cos = 1.0f, lam_l2 = 0.0f;  // loss weights (1 - cos, |F - T|^2)
+    float logit_scale = 0.0f;             // logits Q K^T * logit_scale; 0: 1 / sqrt(d)
 };
 
 struct DecodeLayout {
@@ -91,5 +93,23 @@ void set_decode_shape(int mode);
 hipError_t decode_loss_launch(const DecodeArgs& A, const DecodeLayout& L, hipStream_t st);
 hipError_t decode_forward_launch(const DecodeArgs& A, const DecodeLayout& L, hipStream_t st);
 hipError_t decode_backward_launch(const DecodeArgs& A, const DecodeLayout& L, hipStream_t st);
+
+// ------------------------------------------------------------- tied decode
+struct TiedArgs {
+    int prec, n, ds, M, df;
+    const float *Q, *W, *D, *target, *D0;
+    float tau, lam_cos, lam_2, lam_D, delta;
+    float *loss, *dQ, *dW, *dD;
+};
+
+struct TiedLayout {
+    DecodeLayout dec;  // the decode call's workspace, at offset 0
+    uint64_t bytes;
+    size_t off_qs, off_gq, off_cq, off_dqs, off_k, off_gd, off_g, off_dk, off_dv, off_apart, off_a, off_pen,
+        off_loss;
+};
+
+bool tied_layout(int prec, int n, int ds, int M, int df, TiedLayout* L);
+hipError_t tied_loss_launch(const TiedArgs& T, const TiedLayout& L, void* base, hipStream_t st);
 
 }  // namespace lam

@@ -1,0 +1,404 @@
+// The paper's tied dictionary decode and full feature loss (Eq. 5-6):
+//
+//   C[p][j] = < x_p / |x_p|, D_j / |D_j| >,  x_p = Q_p W     (cosine logits)
+//   F^ = softmax_j(C / tau) D
+//   L = lambda_cos mean_p (1 - cos(F^_p, F_p)) + lambda_2 mean_p |F^_p - F_p|^2
+//       + lambda_D sum_j ReLU(|D0_j - D_j| - delta)
+//
+// mapped onto the attention kernels of decode.hip: with Q'_p = Q_p / (tau |Q_p W|)
+// and K = normalize_rows(D) W^T the logits are Q' K^T (logit scale 1) and the
+// values are V = D, so one decode call gives the loss terms, dQ', dK and dV.
+// The kernels here form Q' and K before it and chain the gradients after it:
+//   dQ_p = dQ'_p / (tau |x_p|) - (dQ'_p . Q_p) (G Q_p) / (tau |x_p|^3),  G = W W^T
+//   dW   = dK^T normalize_rows(D) + (sum_p c_p Q_p^T Q_p) W,  c_p = -(dQ'_p . Q_p) / (tau |x_p|^3)
+//   dD   = dV + (dB - B <B, dB>) / |D_j| + lambda_D (D - D0) / |D - D0| outside delta,
+//          with B = normalize_rows(D), dB = dK W
+// |x_p|^2 = Q_p G Q_p^T uses the d x d Gram matrix instead of the D-wide x_p.
+// Norms are guarded as max(|.|, 1e-12) (a zero row normalises to zero, and its
+// derivative is 1 / 1e-12 there).  Everything outside the decode call is FP32
+// VALU work of O(n d^2 + M d D).
+#include "common.h"
+#include "kernels.h"
+
+namespace lam {
+
+constexpr float kNormEps = 1e-12f;
+constexpr int kASplits = 256;  // pixel ranges of the sum_p c_p Q_p^T Q_p reduction
+
+// Workgroup r < M: K[r][a] = <D_r, W_a> / max(|D_r|, eps) for a < DS and
+// gD[r] = max(|D_r|, eps); workgroup M + a: G[a][b] = <W_a, W_b>.  The 256
+// threads stride over the features and their partial sums meet in LDS.
+template <int DS>
+__global__ __launch_bounds__(256) void k_tied_dict(const float* __restrict__ W, const float* __restrict__ D, int M,
+                                                   int df, float* __restrict__ K, float* __restrict__ gD,
+                                                   float* __restrict__ G)
+{
+    __shared__ float red[DS + 1][256];
+    const int r = blockIdx.x;
+    const bool atom = r < M;
+    const float* x = atom ? D + (size_t)r * df : W + (size_t)(r - M) * df;
+    float acc[DS + 1];
+#pragma unroll
+    for (int a = 0; a <= DS; ++a) acc[a] = 0.f;
+    for (int f = threadIdx.x; f < df; f += 256) {
+        const float v = x[f];
+        acc[DS] += v * v;
+#pragma unroll
+        for (int a = 0; a < DS; ++a) acc[a] += v * W[(size_t)a * df + f];
+    }
+#pragma unroll
+    for (int a = 0; a <= DS; ++a) red[a][threadIdx.x] = acc[a];
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+#pragma unroll
+            for (int a = 0; a <= DS; ++a) red[a][threadIdx.x] += red[a][threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (atom) {
+        const float g = fmaxf(sqrtf(red[DS][0]), kNormEps);
+        if ((int)threadIdx.x < DS) K[(size_t)r * DS + threadIdx.x] = red[threadIdx.x][0] / g;
+        if (threadIdx.x == 0) gD[r] = g;
+    } else if ((int)threadIdx.x < DS) {
+        G[(size_t)(r - M) * DS + threadIdx.x] = red[threadIdx.x][0];
+    }
+}
+
+// Q'_p = Q_p / (tau max(|x_p|, eps)) with |x_p|^2 = Q_p G Q_p^T; gq[p] = max(|x_p|, eps).
+template <int DS>
+__global__ __launch_bounds__(256) void k_tied_queries(const float* __restrict__ Q, int n, const float* __restrict__ G,
+                                                      float tau, float* __restrict__ Qs, float* __restrict__ gq)
+{
+    __shared__ float sG[DS * DS];
+    for (int e = threadIdx.x; e < DS * DS; e += 256) sG[e] = G[e];
+    __syncthreads();
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= n) return;
+    float q[DS];
+#pragma unroll
+    for (int a = 0; a < DS; a += 4) {
+        const float4 v = *reinterpret_cast<const float4*>(Q + (size_t)p * DS + a);
+        q[a] = v.x; q[a + 1] = v.y; q[a + 2] = v.z; q[a + 3] = v.w;
+    }
+    float x2 = 0.f;
+#pragma unroll
+    for (int a = 0; a < DS; ++a) {
+        float r = 0.f;
+#pragma unroll
+        for (int b = 0; b < DS; ++b) r += sG[a * DS + b] * q[b];
+        x2 += q[a] * r;
+    }
+    const float g = fmaxf(sqrtf(fmaxf(x2, 0.f)), kNormEps);
+    gq[p] = g;
+    const float s = 1.0f / (tau * g);
+#pragma unroll
+    for (int a = 0; a < DS; a += 4)
+        *reinterpret_cast<float4*>(Qs + (size_t)p * DS + a) = make_float4(q[a] * s, q[a + 1] * s, q[a + 2] * s, q[a + 3] * s);
+}
+
+// dQ_p from dQ'_p (through Q' = Q / (tau g)) and c_p for the W-gradient of the
+// query norm; dQ may be NULL.
+template <int DS>
+__global__ __launch_bounds__(256) void k_tied_dq(const float* __restrict__ Q, const float* __restrict__ dQs, int n,
+                                                 const float* __restrict__ G, const float* __restrict__ gq,
+                                                 float tau, float* __restrict__ dQ, float* __restrict__ cq)
+{
+    __shared__ float sG[DS * DS];
+    for (int e = threadIdx.x; e < DS * DS; e += 256) sG[e] = G[e];
+    __syncthreads();
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= n) return;
+    float q[DS], dq[DS];
+#pragma unroll
+    for (int a = 0; a < DS; a += 4) {
+        const float4 v = *reinterpret_cast<const float4*>(Q + (size_t)p * DS + a);
+        const float4 u = *reinterpret_cast<const float4*>(dQs + (size_t)p * DS + a);
+        q[a] = v.x; q[a + 1] = v.y; q[a + 2] = v.z; q[a + 3] = v.w;
+        dq[a] = u.x; dq[a + 1] = u.y; dq[a + 2] = u.z; dq[a + 3] = u.w;
+    }
+    const float g = gq[p];
+    const bool active = g > kNormEps;
+    float t = 0.f;
+#pragma unroll
+    for (int a = 0; a < DS; ++a) t += dq[a] * q[a];
+    const float inv = 1.0f / (tau * g);
+    const float c = active ? -t * inv / (g * g) : 0.0f;
+    cq[p] = c;
+    if (!dQ) return;
+#pragma unroll
+    for (int a = 0; a < DS; ++a) {
+        float gqa = 0.f;
+#pragma unroll
+        for (int b = 0; b < DS; ++b) gqa += sG[a * DS + b] * q[b];
+        dQ[(size_t)p * DS + a] = dq[a] * inv + c * gqa;
+    }
+}
+
+// part[s][a][b] = sum over pixel range s of c_p Q_p[a] Q_p[b]; thread t of the
+// workgroup owns pairs t, t + 256, ... (ds^2 <= 1024); pixels are staged in LDS.
+template <int DS>
+__global__ __launch_bounds__(256) void k_tied_gram_q(const float* __restrict__ Q, const float* __restrict__ cq, int n,
+                                                     int splits, float* __restrict__ part)
+{
+    constexpr int PAIRS = DS * DS, PER = (PAIRS + 255) / 256, CH = 256;
+    __shared__ float sq[CH][DS + 1];
+    __shared__ float sc[CH];
+    const int per = (n + splits - 1) / splits;
+    const int p0 = blockIdx.x * per, p1 = min(n, p0 + per);
+    float acc[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) acc[k] = 0.f;
+    for (int base = p0; base < p1; base += CH) {
+        __syncthreads();
+        const int p = base + (int)threadIdx.x;
+        if (p < p1) {
+#pragma unroll
+            for (int a = 0; a < DS; ++a) sq[threadIdx.x][a] = Q[(size_t)p * DS + a];
+            sc[threadIdx.x] = cq[p];
+        } else {
+#pragma unroll
+            for (int a = 0; a < DS; ++a) sq[threadIdx.x][a] = 0.f;
+            sc[threadIdx.x] = 0.f;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int e = (int)threadIdx.x + 256 * k;
+            if (e >= PAIRS) break;
+            const int a = e / DS, b = e % DS;
+            float s = 0.f;
+            for (int i = 0; i < CH; ++i) s += sc[i] * sq[i][a] * sq[i][b];
+            acc[k] += s;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int e = (int)threadIdx.x + 256 * k;
+        if (e < PAIRS) part[(size_t)blockIdx.x * PAIRS + e] = acc[k];
+    }
+}
+
+// A[a][b] = sum over the splits of part[s][a][b] (fixed order).
+__global__ __launch_bounds__(256) void k_tied_areduce(const float* __restrict__ part, int splits, int pairs,
+                                                      float* __restrict__ A)
+{
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= pairs) return;
+    float s = 0.f;
+    for (int k = 0; k < splits; ++k) s += part[(size_t)k * pairs + e];
+    A[e] = s;
+}
+
+// dW[a][f] = sum_j dK[j][a] D[j][f] / gD[j] + sum_b A[a][b] W[b][f].
+__global__ __launch_bounds__(256) void k_tied_dw(const float* __restrict__ dK, const float* __restrict__ D,
+                                                 const float* __restrict__ gD, const float* __restrict__ A,
+                                                 const float* __restrict__ W, int ds, int M, int df,
+                                                 float* __restrict__ dW)
+{
+    const int idx = blockIdx.x * 256 + threadIdx.x;
+    if (idx >= ds * df) return;
+    const int a = idx / df, f = idx % df;
+    float s = 0.f;
+#pragma unroll 8
+    for (int j = 0; j < M; ++j) s += dK[(size_t)j * ds + a] * (D[(size_t)j * df + f] / gD[j]);
+#pragma unroll 8
+    for (int b = 0; b < ds; ++b) s += A[a * ds + b] * W[(size_t)b * df + f];
+    dW[idx] = s;
+}
+
+// One workgroup per atom j: dB = dK_j W, B = D_j / gD_j,
+// dD_j = dV_j + (dB - B <B, dB>) / gD_j (+ the hinge term), pen[j] = its penalty.
+__global__ __launch_bounds__(256) void k_tied_dd(const float* __restrict__ dK, const float* __restrict__ dV,
+                                                 const float* __restrict__ D, const float* __restrict__ D0,
+                                                 const float* __restrict__ gD, const float* __restrict__ W,
+                                                 int ds, int df, float lam_D, float delta, float* __restrict__ dD,
+                                                 float* __restrict__ pen)
+{
+    extern __shared__ float sh[];  // dB [df], then two reduction slots [256] each
+    float* sdb = sh;
+    float* r0 = sh + df;
+    float* r1 = r0 + 256;
+    const int j = blockIdx.x;
+    const float g = gD[j];
+    const float* dj = D + (size_t)j * df;
+    const float* d0 = D0 + (size_t)j * df;
+    float dot = 0.f, dev2 = 0.f;
+    for (int f = threadIdx.x; f < df; f += 256) {
+        float b = 0.f;
+        for (int a = 0; a < ds; ++a) b += dK[(size_t)j * ds + a] * W[(size_t)a * df + f];
+        sdb[f] = b;
+        dot += (dj[f] / g) * b;
+        const float e = dj[f] - d0[f];
+        dev2 += e * e;
+    }
+    r0[threadIdx.x] = dot;
+    r1[threadIdx.x] = dev2;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            r0[threadIdx.x] += r0[threadIdx.x + o];
+            r1[threadIdx.x] += r1[threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    const float proj = g > kNormEps ? r0[0] : 0.0f;
+    const float dev = sqrtf(r1[0]);
+    const float th = dev > delta ? lam_D / dev : 0.0f;
+    for (int f = threadIdx.x; f < df; f += 256)
+        dD[(size_t)j * df + f] = dV[(size_t)j * df + f] + (sdb[f] - (dj[f] / g) * proj) / g + th * (dj[f] - d0[f]);
+    if (threadIdx.x == 0) pen[j] = lam_D * fmaxf(dev - delta, 0.0f);
+}
+
+// loss = decode loss + sum_j pen[j] (fixed order).
+__global__ __launch_bounds__(256) void k_tied_loss(const float* __restrict__ dec_loss, const float* __restrict__ pen,
+                                                   int M, float* __restrict__ loss)
+{
+    __shared__ float sh[256];
+    float s = 0.f;
+    for (int j = threadIdx.x; j < M; j += 256) s += pen[j];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) loss[0] = dec_loss[0] + sh[0];
+}
+
+bool tied_layout(int prec, int n, int ds, int M, int df, TiedLayout* L)
+{
+    if (!decode_layout(prec, n, ds, M, df, &L->dec)) return false;
+    size_t off = (L->dec.bytes + 255) / 256 * 256;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += (bytes + 255) / 256 * 256;
+        return o;
+    };
+    L->off_qs = take((size_t)n * ds * 4);
+    L->off_gq = take((size_t)n * 4);
+    L->off_cq = take((size_t)n * 4);
+    L->off_dqs = take((size_t)n * ds * 4);
+    L->off_k = take((size_t)M * ds * 4);
+    L->off_gd = take((size_t)M * 4);
+    L->off_g = take((size_t)ds * ds * 4);
+    L->off_dk = take((size_t)M * ds * 4);
+    L->off_dv = take((size_t)M * df * 4);
+    L->off_apart = take((size_t)kASplits * ds * ds * 4);
+    L->off_a = take((size_t)ds * ds * 4);
+    L->off_pen = take((size_t)M * 4);
+    L->off_loss = take(4);
+    L->bytes = off;
+    return true;
+}
+
+hipError_t tied_loss_launch(const TiedArgs& T, const TiedLayout& L, void* base_, hipStream_t st)
+{
+    char* base = reinterpret_cast<char*>(base_);
+    float* Qs = reinterpret_cast<float*>(base + L.off_qs);
+    float* gq = reinterpret_cast<float*>(base + L.off_gq);
+    float* cq = reinterpret_cast<float*>(base + L.off_cq);
+    float* dQs = reinterpret_cast<float*>(base + L.off_dqs);
+    float* K = reinterpret_cast<float*>(base + L.off_k);
+    float* gD = reinterpret_cast<float*>(base + L.off_gd);
+    float* G = reinterpret_cast<float*>(base + L.off_g);
+    float* dK = reinterpret_cast<float*>(base + L.off_dk);
+    float* dV = reinterpret_cast<float*>(base + L.off_dv);
+    float* apart = reinterpret_cast<float*>(base + L.off_apart);
+    float* Am = reinterpret_cast<float*>(base + L.off_a);
+    float* pen = reinterpret_cast<float*>(base + L.off_pen);
+    float* dloss = reinterpret_cast<float*>(base + L.off_loss);
+    const int n = T.n, ds = T.ds, M = T.M, df = T.df;
+    const int pblocks = (n + 255) / 256;
+    {
+        ProfScope ps("tied_prep", st);
+        if (ds == 16)
+            hipLaunchKernelGGL(k_tied_dict<16>, dim3(M + ds), dim3(256), 0, st, T.W, T.D, M, df, K, gD, G);
+        else
+            hipLaunchKernelGGL(k_tied_dict<32>, dim3(M + ds), dim3(256), 0, st, T.W, T.D, M, df, K, gD, G);
+        if (n > 0) {
+            if (ds == 16)
+                hipLaunchKernelGGL(k_tied_queries<16>, dim3(pblocks), dim3(256), 0, st, T.Q, n, (const float*)G,
+                                   T.tau, Qs, gq);
+            else
+                hipLaunchKernelGGL(k_tied_queries<32>, dim3(pblocks), dim3(256), 0, st, T.Q, n, (const float*)G,
+                                   T.tau, Qs, gq);
+        }
+    }
+    DecodeArgs A{};
+    A.prec = T.prec; A.n = n; A.d = ds; A.M = M; A.D = df;
+    A.Q = Qs; A.K = K; A.V = T.D; A.target = T.target; A.K0 = nullptr; A.lambda_tr = 0.0f;
+    A.loss = dloss; A.dQ = dQs; A.dK = dK; A.dV = dV; A.row_cos = nullptr;
+    A.lam_cos = T.lam_cos; A.lam_l2 = T.lam_2; A.logit_scale = 1.0f;
+    DecodeLayout DL = L.dec;
+    DL.base = base_;
+    hipError_t e = decode_loss_launch(A, DL, st);
+    if (e != hipSuccess) return e;
+    ProfScope ps("tied_grads", st);
+    const int splits = n > 0 ? std::min(kASplits, pblocks) : 0;
+    if (n > 0) {
+        if (ds == 16) {
+            hipLaunchKernelGGL(k_tied_dq<16>, dim3(pblocks), dim3(256), 0, st, T.Q, (const float*)dQs, n,
+                               (const float*)G, (const float*)gq, T.tau, T.dQ, cq);
+            hipLaunchKernelGGL(k_tied_gram_q<16>, dim3(splits), dim3(256), 0, st, T.Q, (const float*)cq, n, splits,
+                               apart);
+        } else {
+            hipLaunchKernelGGL(k_tied_dq<32>, dim3(pblocks), dim3(256), 0, st, T.Q, (const float*)dQs, n,
+                               (const float*)G, (const float*)gq, T.tau, T.dQ, cq);
+            hipLaunchKernelGGL(k_tied_gram_q<32>, dim3(splits), dim3(256), 0, st, T.Q, (const float*)cq, n, splits,
+                               apart);
+        }
+    }
+    hipLaunchKernelGGL(k_tied_areduce, dim3((ds * ds + 255) / 256), dim3(256), 0, st, (const float*)apart, splits,
+                       ds * ds, Am);
+    hipLaunchKernelGGL(k_tied_dw, dim3((ds * df + 255) / 256), dim3(256), 0, st, (const float*)dK, T.D,
+                       (const float*)gD, (const float*)Am, T.W, ds, M, df, T.dW);
+    hipLaunchKernelGGL(k_tied_dd, dim3(M), dim3(256), (size_t)(df + 512) * 4, st, (const float*)dK,
+                       (const float*)dV, T.D, T.D0, (const float*)gD, T.W, ds, df, T.lam_D, T.delta, T.dD, pen);
+    hipLaunchKernelGGL(k_tied_loss, dim3(1), dim3(256), 0, st, (const float*)dloss, (const float*)pen, M, T.loss);
+    return hipGetLastError();
+}
+
+}  // namespace lam
+
+// ------------------------------------------------------------ C ABI
+
+using namespace lam;
+
+static bool tied_aligned(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
+extern "C" {
+
+lam_status lam_decode_tied_workspace_size(int precision, int n, int ds, int M, int df, uint64_t* bytes)
+{
+    if (!bytes || n < 0) return LAM_ERR_INVALID_ARG;
+    TiedLayout L{};
+    if (!tied_layout(precision, n, ds, M, df, &L)) return LAM_ERR_UNSUPPORTED;
+    *bytes = L.bytes;
+    return LAM_OK;
+}
+
+lam_status lam_decode_tied_loss(int precision, const float* Q, int n, int ds, const float* W, const float* D,
+                                int M, int df, const float* target, const float* D0,
+                                const lam_tied_params* params, float* loss, float* dQ, float* dW, float* dD,
+                                void* ws, uint64_t ws_bytes, void* stream)
+{
+    if (n < 0 || !params) return LAM_ERR_INVALID_ARG;
+    TiedLayout L{};
+    if (!tied_layout(precision, n, ds, M, df, &L)) return LAM_ERR_UNSUPPORTED;
+    if (!ws || ws_bytes < L.bytes) return LAM_ERR_INVALID_ARG;
+    if (!W || !D || !D0 || !loss || !dW || !dD || (n > 0 && (!Q || !target))) return LAM_ERR_INVALID_ARG;
+    if (!tied_aligned(Q) || !tied_aligned(target) || !tied_aligned(dQ)) return LAM_ERR_INVALID_ARG;
+    const lam_tied_params& p = *params;
+    if (!(p.tau > 0.0f) || !(p.delta >= 0.0f) || !(p.lambda_cos >= 0.0f) || !(p.lambda_2 >= 0.0f) ||
+        !(p.lambda_D >= 0.0f))
+        return LAM_ERR_INVALID_ARG;
+    TiedArgs T{};
+    T.prec = precision; T.n = n; T.ds = ds; T.M = M; T.df = df;
+    T.Q = Q; T.W = W; T.D = D; T.target = target; T.D0 = D0;
+    T.tau = p.tau; T.lam_cos = p.lambda_cos; T.lam_2 = p.lambda_2; T.lam_D = p.lambda_D; T.delta = p.delta;
+    T.loss = loss; T.dQ = dQ; T.dW = dW; T.dD = dD;
+    return tied_loss_launch(T, L, ws, (hipStream_t)stream) == hipSuccess ? LAM_OK : LAM_ERR_HIP;
+}
+
+}  // extern "C"

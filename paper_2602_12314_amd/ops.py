@@ -7,6 +7,9 @@
 - ``DecodeLoss.apply(Q, K, V, K0, target, lambda_tr, precision, decoder) -> loss``:
   Eq. 5-6; the library computes the loss and its gradients in one call.
 - ``Decode.apply(Q, K, V, precision, decoder) -> F``: Eq. 5 alone.
+- ``TiedDecoder``: the paper's tied decode and full feature loss (Eq. 5-6:
+  cosine logits of Q W against the atoms D at temperature tau, V = D, and the
+  cosine, L2 and hinge trust-region terms) with gradients to Q, W and D.
 - ``stage2(decoder, Q, K, V, target, K0, lambda_tr, iters, step)``: the
   decode-only iterations of Alg. 1 Stage II (Gaussians, hence Q, fixed): each
   iteration is one library call computing the loss, dK and dV without dQ.
@@ -216,3 +219,31 @@ def stage2(decoder: Decoder, Q, K, V, target, K0, lambda_tr: float, iters: int =
         if step is not None:
             step(dK, dV)
     return torch.cat(losses)
+
+
+# the paper's weights (Sec. IV); it gives no temperature, 0.1 is this library's reading
+PAPER_TIED_PARAMS = dict(tau=0.1, lambda_cos=0.5, lambda_2=0.5, lambda_D=0.2, delta=0.1)
+
+
+class TiedDecoder:
+    """Workspace for the tied decode of n pixel rows (query dimension ds, M atoms,
+    feature dimension df)."""
+
+    def __init__(self, precision: str, n: int, ds: int, M: int, df: int, device="cuda"):
+        self.precision = precision
+        self.shape = (int(n), int(ds), int(M), int(df))
+        nbytes = _lib.decode_tied_workspace_size(precision, n, ds, M, df)
+        self.ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+        self.device = torch.device(device)
+
+    def loss_and_grads(self, Q, W, D, target, D0, params=None, want_dQ=True):
+        n, ds, M, df = self.shape
+        dev = self.device
+        params = dict(PAPER_TIED_PARAMS, **(params or {}))
+        loss = torch.empty(1, dtype=torch.float32, device=dev)
+        dQ = torch.empty((n, ds), dtype=torch.float32, device=dev) if want_dQ else None
+        dW = torch.empty((ds, df), dtype=torch.float32, device=dev)
+        dD = torch.empty((M, df), dtype=torch.float32, device=dev)
+        _lib.decode_tied_loss(self.precision, _contig(Q), _contig(W), _contig(D), _contig(target), _contig(D0),
+                              params, loss, dQ, dW, dD, self.ws)
+        return loss, dQ, dW, dD

@@ -115,3 +115,19 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(_lib, "_lib", None)
     with pytest.raises(RuntimeError, match="not built"):
         _lib.lib()
+
+
+def test_tied_decode_validation(L):
+    ok = C.c_uint64()
+    assert L.lam_decode_tied_workspace_size(1, 1000, 16, 256, 512, C.byref(ok)) == 0 and ok.value > 0
+    base = ok.value
+    assert L.lam_decode_workspace_size(1, 1000, 16, 256, 512, C.byref(ok)) == 0 and ok.value < base
+    assert L.lam_decode_tied_workspace_size(1, 1000, 8, 256, 512, C.byref(ok)) == _lib.LAM_ERR_UNSUPPORTED
+    assert L.lam_decode_tied_workspace_size(1, -1, 16, 256, 512, C.byref(ok)) == _lib.LAM_ERR_INVALID_ARG
+    bad = _lib.TiedParams(0.0, 0.5, 0.5, 0.2, 0.1)  # tau must be positive
+    p = C.c_void_p(16)
+    st = L.lam_decode_tied_loss(1, p, 10, 16, p, p, 64, 128, p, p, C.byref(bad), p, None, p, p, p,
+                                C.c_uint64(1 << 30), None)
+    assert st == _lib.LAM_ERR_INVALID_ARG
+    assert L.lam_decode_tied_loss(1, p, 10, 16, p, p, 64, 128, p, p, None, p, None, p, p, p,
+                                  C.c_uint64(1 << 30), None) == _lib.LAM_ERR_INVALID_ARG

@@ -1,0 +1,73 @@
+"""GPU parity of the paper's tied decode and full feature loss (Eq. 5-6: cosine
+logits of Q W against the atoms at temperature tau, V = D, cosine + L2 + hinge
+trust-region terms) against the FP64 oracle, through the C ABI.
+
+Bars: FP32 within 1e-4 relative per output (loss, dQ, dW, dD); BF16 within
+1e-2.  Shapes: padded atom counts, one atom, d = 16 and 32, D = 128 ... 512;
+the dictionary has atoms inside and outside the trust-region radius.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import tied_decode_oracle as TD  # noqa: E402
+from tests.gpu_helpers import rel_err, say, to_np  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+PARAMS = dict(tau=0.1, lambda_cos=0.5, lambda_2=0.5, lambda_D=0.2, delta=0.1)
+BAR = {"fp32": 1e-4, "bf16": 1e-2}
+SHAPES = [(1000, 16, 64, 512), (777, 32, 100, 256), (4096, 16, 256, 512), (200, 16, 1, 128),
+          (515, 32, 150, 384)]
+
+
+def _inputs(seed, n, ds, M, df):
+    rng = np.random.default_rng(seed)
+    Q = rng.standard_normal((n, ds)).astype(np.float32)
+    W = (rng.standard_normal((ds, df)) / np.sqrt(ds)).astype(np.float32)
+    D0 = rng.standard_normal((M, df)).astype(np.float32)
+    # every other atom moved by 0.02 (inside delta), the rest by about 0.5 (outside)
+    step = rng.standard_normal((M, df))
+    step /= np.linalg.norm(step, axis=1, keepdims=True)
+    radius = np.where(np.arange(M) % 2 == 0, 0.02, 0.5)[:, None]
+    D = (D0 + radius * step).astype(np.float32)
+    T = rng.standard_normal((n, df))
+    T = (T / np.linalg.norm(T, axis=1, keepdims=True)).astype(np.float32)
+    return Q, W, D, T, D0
+
+
+def _run(prec, Q, W, D, T, D0, want_dQ=True):
+    from paper_2602_12314_amd import ops
+    n, ds = Q.shape
+    M, df = D.shape
+    dec = ops.TiedDecoder(prec, n, ds, M, df)
+    c = [torch.as_tensor(a, device="cuda") for a in (Q, W, D, T, D0)]
+    return dec.loss_and_grads(*c, params=PARAMS, want_dQ=want_dQ)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_tied_loss_and_grads(prec, shape):
+    n, ds, M, df = shape
+    say(f"[tied] {prec} n={n} ds={ds} M={M} df={df}")
+    Q, W, D, T, D0 = _inputs(11, *shape)
+    loss, dQ, dW, dD = _run(prec, Q, W, D, T, D0)
+    ref = TD.tied_loss_and_grads(Q, W, D, T, D0, PARAMS["tau"], PARAMS["lambda_cos"], PARAMS["lambda_2"],
+                                 PARAMS["lambda_D"], PARAMS["delta"])
+    el = abs(float(loss) - ref["loss"]) / abs(ref["loss"])
+    say(f"  loss {float(loss):.7f} ref {ref['loss']:.7f} rel {el:.2e}")
+    assert el < BAR[prec]
+    for name, t in (("dQ", dQ), ("dW", dW), ("dD", dD)):
+        e = rel_err(to_np(t), ref[name])
+        say(f"  {name} rel err {e:.3e}")
+        assert e < BAR[prec], name
+
+
+def test_tied_without_dQ_is_identical():
+    Q, W, D, T, D0 = _inputs(12, 700, 16, 96, 256)
+    l1, dQ1, dW1, dD1 = _run("bf16", Q, W, D, T, D0)
+    l0, dQ0, dW0, dD0 = _run("bf16", Q, W, D, T, D0, want_dQ=False)
+    assert dQ0 is None
+    for a, b in ((l0, l1), (dW0, dW1), (dD0, dD1)):
+        assert torch.equal(a, b)
