@@ -8,6 +8,8 @@
  *                    and dL/dQ, dL/dK, dL/dV                    Sec. III-B, Eq. 5 and Eq. 6
  *   decode_forward   F alone (inference form of Eq. 5)
  *   decode_backward  the adjoint of decode_forward for a given dL/dF
+ *   decode_tied_loss the tied decode and full feature loss as printed   Eq. 5-6
+ *   stream_kmeans    dictionary initialisation by streaming K-means     Sec. III-D, Eq. 10
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -245,12 +247,78 @@ lam_status lam_decode_tied_loss(int precision, const float* Q, int n, int ds, co
                                 const lam_tied_params* params, float* loss, float* dQ, float* dW, float* dD,
                                 void* ws, uint64_t ws_bytes, void* stream);
 
+/* -------------------------------------------- streaming K-means (Eq. 10) */
+
+/* The dictionary initialisation of Sec. III-D, D_t0 = StreamKMeans(F_t,
+ * D_{t-1}, K), read as the streaming K-means the paper cites: the keyframe's
+ * embeddings are summarised into m weighted micro-centres by Lloyd's
+ * iteration, merged with the current weighted global centres, and the merged
+ * set is re-clustered into K centres.
+ *
+ * One Lloyd iteration assigns every point to its nearest centre in squared
+ * Euclidean distance (ties to the lowest index) and moves every centre to the
+ * weighted mean of its points; a centre without points (or with zero total
+ * weight) stays where it is.  Iteration counts are fixed (no convergence
+ * test), so the calls are stream-ordered and never synchronise.
+ *
+ * precision selects the distance products: LAM_FP32 (float32 MFMA) or
+ * LAM_BF16 (bfloat16 operands, float32 accumulation; an assignment can differ
+ * from the float32 one only where two centres are within the bfloat16
+ * rounding of the products).  Norms, means and weights are float32; the sums
+ * of an update are taken in point-index order per centre, so results do not
+ * depend on the launch schedule.
+ *
+ * Shapes: D a multiple of 32 in [32, 2048] (FP32: up to 1024), 1 <= k <=
+ * 65536.  Row arrays (points, centres) are float32 row-major and 16-byte
+ * aligned.  Otherwise LAM_ERR_UNSUPPORTED (shape) or LAM_ERR_INVALID_ARG. */
+
+/* Workspace bytes for lam_kmeans_assign / lam_kmeans_lloyd with up to n
+ * points of dimension D and k centres.  Host-only. */
+lam_status lam_kmeans_workspace_size(int precision, int n, int D, int k, uint64_t* bytes);
+
+/* Nearest centre of every point.  Device: X [n, D], C [k, D]; outputs
+ * assign [n] (int32, overwritten) and d2 [n] (nullable: the squared distance
+ * to that centre, float32, clamped at zero).  Stream-ordered. */
+lam_status lam_kmeans_assign(int precision, const float* X, int n, int D, const float* C, int k, int32_t* assign,
+                             float* d2, void* ws, uint64_t ws_bytes, void* stream);
+
+/* iters >= 1 Lloyd iterations from C0.  Device: X [n, D], weights [n]
+ * (nullable: all 1), C0 [k, D]; outputs C [k, D] (may be C0), W [k]
+ * (nullable: total weight per centre under the last assignment) and
+ * assign [n] (nullable: the last assignment, from which C was computed).
+ * Stream-ordered. */
+lam_status lam_kmeans_lloyd(int precision, const float* X, const float* weights, int n, int D, const float* C0,
+                            int k, int iters, float* C, float* W, int32_t* assign, void* ws, uint64_t ws_bytes,
+                            void* stream);
+
+/* Workspace bytes for lam_stream_kmeans.  Requires 0 <= m <= n, 0 <= Kp <= K
+ * and m >= K - Kp.  Host-only. */
+lam_status lam_stream_kmeans_workspace_size(int precision, int n, int D, int Kp, int K, int m, uint64_t* bytes);
+
+/* One streaming step.  Device: F [n, D] the new embeddings (weight 1 each),
+ * D_prev [Kp, D] and w_prev [Kp] the global centres and their weights (Kp = 0
+ * on the first keyframe: both may be NULL).  Host: seeds [m], distinct
+ * indices into F (the random draw), read before the call returns; the
+ * micro-centres start at F[seeds].  Steps: iters_local Lloyd iterations of F
+ * into the m micro-centres (each weighted by its point count); the merged set
+ * [D_prev; micro-centres] with weights [w_prev; counts] then takes
+ * iters_global >= 1 weighted Lloyd iterations from [D_prev; the first K - Kp
+ * micro-centres].  Outputs D_out [K, D] and W_out [K] (total weight per
+ * centre).  Stream-ordered.
+ * Errors: LAM_ERR_INVALID_ARG (sizes, null or misaligned pointers, a seed
+ * outside [0, n), workspace too small), LAM_ERR_UNSUPPORTED (shape),
+ * LAM_ERR_HIP. */
+lam_status lam_stream_kmeans(int precision, const float* F, int n, int D, const float* D_prev,
+                             const float* w_prev, int Kp, int K, const int32_t* seeds, int m, int iters_local,
+                             int iters_global, float* D_out, float* W_out, void* ws, uint64_t ws_bytes,
+                             void* stream);
+
 /* --------------------------------------------------------------- profiling */
 
 /* Turns per-kernel timing on or off (process-wide, off by default).  While on,
  * the main kernels (names: "raster_fwd", "raster_bwd", "decode_rows",
  * "decode_tn", "render_sort", "preprocess", "preprocess_bwd", "tied_prep",
- * "tied_grads") are bracketed by
+ * "tied_grads", "kmeans") are bracketed by
  * HIP events recorded on their launch stream.  Not for use under graph capture. */
 lam_status lam_profile_enable(int on);
 

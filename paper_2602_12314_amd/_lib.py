@@ -67,6 +67,12 @@ def lib():
             "lam_decode_tied_workspace_size": (i32, [i32, i32, i32, i32, i32, pu64]),
             "lam_decode_tied_loss": (i32, [i32, vp, i32, i32, vp, vp, i32, i32, vp, vp, C.POINTER(TiedParams),
                                            vp, vp, vp, vp, vp, u64, vp]),
+            "lam_kmeans_workspace_size": (i32, [i32, i32, i32, i32, pu64]),
+            "lam_kmeans_assign": (i32, [i32, vp, i32, i32, vp, i32, vp, vp, vp, u64, vp]),
+            "lam_kmeans_lloyd": (i32, [i32, vp, vp, i32, i32, vp, i32, i32, vp, vp, vp, vp, u64, vp]),
+            "lam_stream_kmeans_workspace_size": (i32, [i32, i32, i32, i32, i32, i32, pu64]),
+            "lam_stream_kmeans": (i32, [i32, vp, i32, i32, vp, vp, i32, i32, vp, i32, i32, i32, vp, vp, vp,
+                                        u64, vp]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -217,3 +223,50 @@ def decode_tied_loss(precision, Q, W, D, target, D0, params, loss, dQ, dW, dD, w
                                      _p(target), _p(D0), C.byref(p), _p(loss), _p(dQ), _p(dW), _p(dD), _p(ws),
                                      ws.numel() * ws.element_size(), _stream(stream)),
           "lam_decode_tied_loss")
+
+
+# ------------------------------------------------------------ streaming K-means
+
+KMEANS_PRECISIONS = ("fp32", "bf16")
+
+
+def kmeans_workspace_size(precision, n, D, k) -> int:
+    out = C.c_uint64()
+    check(lib().lam_kmeans_workspace_size(PRECISIONS.get(precision, precision), n, D, k, C.byref(out)),
+          "lam_kmeans_workspace_size")
+    return int(out.value)
+
+
+def kmeans_assign(precision, X, C_, assign, d2, ws, stream=None):
+    n, D = X.shape
+    check(lib().lam_kmeans_assign(PRECISIONS.get(precision, precision), _p(X), n, D, _p(C_), C_.shape[0],
+                                  _p(assign), _p(d2), _p(ws), ws.numel() * ws.element_size(), _stream(stream)),
+          "lam_kmeans_assign")
+
+
+def kmeans_lloyd(precision, X, weights, C0, iters, C_out, W, assign, ws, stream=None):
+    n, D = X.shape
+    check(lib().lam_kmeans_lloyd(PRECISIONS.get(precision, precision), _p(X), _p(weights), n, D, _p(C0),
+                                 C0.shape[0], int(iters), _p(C_out), _p(W), _p(assign), _p(ws),
+                                 ws.numel() * ws.element_size(), _stream(stream)),
+          "lam_kmeans_lloyd")
+
+
+def stream_kmeans_workspace_size(precision, n, D, Kp, K, m) -> int:
+    out = C.c_uint64()
+    check(lib().lam_stream_kmeans_workspace_size(PRECISIONS.get(precision, precision), n, D, Kp, K, m,
+                                                 C.byref(out)), "lam_stream_kmeans_workspace_size")
+    return int(out.value)
+
+
+def stream_kmeans(precision, F, D_prev, w_prev, K, seeds, iters_local, iters_global, D_out, W_out, ws,
+                  stream=None):
+    """seeds: host int32 array (numpy), read before the call returns."""
+    n, D = F.shape
+    Kp = 0 if D_prev is None else D_prev.shape[0]
+    sd = np.ascontiguousarray(np.asarray(seeds, dtype=np.int32).reshape(-1))
+    check(lib().lam_stream_kmeans(PRECISIONS.get(precision, precision), _p(F), n, D, _p(D_prev), _p(w_prev), Kp,
+                                  int(K), sd.ctypes.data_as(C.c_void_p), sd.shape[0], int(iters_local),
+                                  int(iters_global), _p(D_out), _p(W_out), _p(ws), ws.numel() * ws.element_size(),
+                                  _stream(stream)),
+          "lam_stream_kmeans")

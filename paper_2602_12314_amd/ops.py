@@ -10,6 +10,9 @@
 - ``TiedDecoder``: the paper's tied decode and full feature loss (Eq. 5-6:
   cosine logits of Q W against the atoms D at temperature tau, V = D, and the
   cosine, L2 and hinge trust-region terms) with gradients to Q, W and D.
+- ``StreamKMeans``: the dictionary initialisation of Eq. 10 (weighted
+  micro-centres of the keyframe's embeddings, merged with the weighted global
+  centres and re-clustered to K), plus plain ``assign`` / ``lloyd`` calls.
 - ``stage2(decoder, Q, K, V, target, K0, lambda_tr, iters, step)``: the
   decode-only iterations of Alg. 1 Stage II (Gaussians, hence Q, fixed): each
   iteration is one library call computing the loss, dK and dV without dQ.
@@ -247,3 +250,72 @@ class TiedDecoder:
         _lib.decode_tied_loss(self.precision, _contig(Q), _contig(W), _contig(D), _contig(target), _contig(D0),
                               params, loss, dQ, dW, dD, self.ws)
         return loss, dQ, dW, dD
+
+
+MICRO_FACTOR = 5  # micro-centres per global centre (the paper's "5 by default")
+
+
+class StreamKMeans:
+    """Streaming K-means state: global centres D [Kp, D] and weights W [Kp]
+    (empty until the first keyframe), K the dictionary size.
+
+    ``step(F, seeds=None, m=None)`` summarises the keyframe's embeddings F [n, D]
+    into m micro-centres (default min(n, MICRO_FACTOR K)) started at F[seeds]
+    (default: a seeded random draw of m distinct rows), merges them with the
+    global centres and re-clusters to K; returns the new (D, W)."""
+
+    def __init__(self, precision: str, K: int, dim: int, iters_local: int = 10, iters_global: int = 10,
+                 seed: int = 0, device="cuda"):
+        self.precision = precision
+        self.K, self.dim = int(K), int(dim)
+        self.iters_local, self.iters_global = int(iters_local), int(iters_global)
+        self.device = torch.device(device)
+        self.rng = np.random.default_rng(seed)
+        self.D = torch.zeros((0, dim), dtype=torch.float32, device=self.device)
+        self.W = torch.zeros(0, dtype=torch.float32, device=self.device)
+        self._ws = None
+
+    def _workspace(self, nbytes):
+        if self._ws is None or self._ws.numel() < nbytes:
+            self._ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
+        return self._ws
+
+    def step(self, F, seeds=None, m: Optional[int] = None):
+        F = _contig(F)
+        n = F.shape[0]
+        Kp = self.D.shape[0]
+        if m is None:
+            m = min(n, MICRO_FACTOR * self.K)
+        if seeds is None:
+            seeds = self.rng.choice(n, size=m, replace=False) if m > 0 else np.zeros(0, np.int64)
+        seeds = np.asarray(seeds, dtype=np.int32)
+        ws = self._workspace(_lib.stream_kmeans_workspace_size(self.precision, n, self.dim, Kp, self.K, len(seeds)))
+        D_out = torch.empty((self.K, self.dim), dtype=torch.float32, device=self.device)
+        W_out = torch.empty(self.K, dtype=torch.float32, device=self.device)
+        _lib.stream_kmeans(self.precision, F, self.D if Kp else None, self.W if Kp else None, self.K, seeds,
+                           self.iters_local, self.iters_global, D_out, W_out, ws)
+        self.D, self.W = D_out, W_out
+        return D_out, W_out
+
+
+def kmeans_assign(precision: str, X, C):
+    """Nearest centre (int32) and squared distance of every row of X."""
+    X, C = _contig(X), _contig(C)
+    ws = torch.empty(max(_lib.kmeans_workspace_size(precision, X.shape[0], X.shape[1], C.shape[0]), 256),
+                     dtype=torch.uint8, device=X.device)
+    a = torch.empty(X.shape[0], dtype=torch.int32, device=X.device)
+    d2 = torch.empty(X.shape[0], dtype=torch.float32, device=X.device)
+    _lib.kmeans_assign(precision, X, C, a, d2, ws)
+    return a, d2
+
+
+def kmeans_lloyd(precision: str, X, C0, iters: int, weights=None):
+    """``iters`` Lloyd iterations from C0: (C, W, last assignment)."""
+    X, C0 = _contig(X), _contig(C0)
+    ws = torch.empty(max(_lib.kmeans_workspace_size(precision, X.shape[0], X.shape[1], C0.shape[0]), 256),
+                     dtype=torch.uint8, device=X.device)
+    C = torch.empty_like(C0)
+    W = torch.empty(C0.shape[0], dtype=torch.float32, device=X.device)
+    a = torch.empty(X.shape[0], dtype=torch.int32, device=X.device)
+    _lib.kmeans_lloyd(precision, X, None if weights is None else _contig(weights), C0, iters, C, W, a, ws)
+    return C, W, a

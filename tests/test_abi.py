@@ -131,3 +131,33 @@ def test_tied_decode_validation(L):
     assert st == _lib.LAM_ERR_INVALID_ARG
     assert L.lam_decode_tied_loss(1, p, 10, 16, p, p, 64, 128, p, p, None, p, None, p, p, p,
                                   C.c_uint64(1 << 30), None) == _lib.LAM_ERR_INVALID_ARG
+
+
+def test_kmeans_validation(L):
+    ok = C.c_uint64()
+    assert L.lam_kmeans_workspace_size(1, 307200, 512, 1280, C.byref(ok)) == 0 and ok.value > 0
+    assert L.lam_kmeans_workspace_size(0, 100, 1024, 10, C.byref(ok)) == 0       # FP32 up to D = 1024
+    assert L.lam_kmeans_workspace_size(0, 100, 2048, 10, C.byref(ok)) == _lib.LAM_ERR_UNSUPPORTED
+    assert L.lam_kmeans_workspace_size(1, 100, 2048, 10, C.byref(ok)) == 0       # BF16 up to 2048
+    assert L.lam_kmeans_workspace_size(1, 100, 48, 10, C.byref(ok)) == _lib.LAM_ERR_UNSUPPORTED
+    assert L.lam_kmeans_workspace_size(2, 100, 512, 10, C.byref(ok)) == _lib.LAM_ERR_UNSUPPORTED  # no FP8
+    assert L.lam_kmeans_workspace_size(1, 100, 512, 0, C.byref(ok)) == _lib.LAM_ERR_UNSUPPORTED
+    assert L.lam_kmeans_workspace_size(1, -1, 512, 10, C.byref(ok)) == _lib.LAM_ERR_INVALID_ARG
+    p = C.c_void_p(256)
+    big = C.c_uint64(1 << 40)
+    # iters must be >= 1; misaligned rows are rejected
+    assert L.lam_kmeans_lloyd(1, p, None, 10, 64, p, 4, 0, p, None, None, p, big, None) == _lib.LAM_ERR_INVALID_ARG
+    assert L.lam_kmeans_assign(1, C.c_void_p(260), 10, 64, p, 4, p, None, p, big, None) == _lib.LAM_ERR_INVALID_ARG
+    assert L.lam_kmeans_assign(1, p, 10, 64, p, 4, p, None, p, C.c_uint64(16), None) == _lib.LAM_ERR_INVALID_ARG
+    # stream: m <= n, Kp <= K, m >= K - Kp, seeds inside [0, n)
+    for n, Kp, K, m in ((10, 0, 4, 11), (10, 5, 4, 3), (10, 0, 4, 3)):
+        assert L.lam_stream_kmeans_workspace_size(1, n, 64, Kp, K, m, C.byref(ok)) == _lib.LAM_ERR_INVALID_ARG
+    assert L.lam_stream_kmeans_workspace_size(1, 10, 64, 2, 4, 3, C.byref(ok)) == 0
+    seeds = np.array([0, 3, 10], dtype=np.int32)  # 10 is out of range for n = 10
+    st = L.lam_stream_kmeans(1, p, 10, 64, None, None, 0, 3, seeds.ctypes.data_as(C.c_void_p), 3, 2, 2, p, p, p,
+                             big, None)
+    assert st == _lib.LAM_ERR_INVALID_ARG
+    seeds[2] = -1
+    st = L.lam_stream_kmeans(1, p, 10, 64, None, None, 0, 3, seeds.ctypes.data_as(C.c_void_p), 3, 2, 2, p, p, p,
+                             big, None)
+    assert st == _lib.LAM_ERR_INVALID_ARG
