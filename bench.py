@@ -228,6 +228,9 @@ def run(args):
     tied = None
     if not args.no_tied:
         tied = tied_leg(ops, prec, spec, Q, V, tgt, dev)
+    kmeans = None
+    if not args.no_kmeans:
+        kmeans = kmeans_leg(ops, prec, spec, tgt, dev)
 
     out = {
         "metric": "feature-pixels/s fwd+bwd",
@@ -258,6 +261,7 @@ def run(args):
             "speedup_of_reduced_precision": sec32 / sec},
         "stage2": stage2,
         "tied_decode": tied,
+        "stream_kmeans": kmeans,
     }
 
     # roofline of the dominant kernel, with algorithmic work from the oracle's pair counts
@@ -336,6 +340,56 @@ def tied_leg(ops, prec, spec, Q, V, tgt, dev, reps=10):
             "params": dict(ops.PAPER_TIED_PARAMS), "loss": float(loss)}
 
 
+def kmeans_leg(ops, prec, spec, tgt, dev, reps=3, iters=10):
+    """The streaming K-means dictionary initialisation (Eq. 10) on this
+    workload's embedding map: m = 5 K micro-centres from seeded random rows,
+    merged into K = M global centres (the previous dictionary: K rows of an
+    earlier draw, weight 100 each), ``iters`` Lloyd iterations in each stage.
+    Also the nearest-centre kernel alone (n x m x D distance GEMM) against the
+    MFMA roof of its precision."""
+    import numpy as np
+    import torch
+    from paper_2602_12314_amd import _lib
+    kprec = "fp32" if prec == "fp32" else "bf16"
+    n, Dd, K = tgt.shape[0], tgt.shape[1], spec.M
+    m = min(n, ops.MICRO_FACTOR * K)
+    rng = np.random.default_rng(5)
+    prev = tgt[torch.as_tensor(rng.choice(n, K, replace=False), device=dev)].contiguous()
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ms = []
+    for r in range(reps + 1):
+        sk = ops.StreamKMeans(kprec, K, Dd, iters_local=iters, iters_global=iters, seed=r, device=dev)
+        sk.D, sk.W = prev, torch.full((K,), 100.0, device=dev)
+        seeds = sk.rng.choice(n, size=m, replace=False)
+        torch.cuda.synchronize()
+        e0.record(st)
+        sk.step(tgt, seeds=seeds)
+        e1.record(st)
+        torch.cuda.synchronize()
+        if r > 0:
+            ms.append(e0.elapsed_time(e1))
+    step_ms = float(np.median(ms))
+    C = tgt[torch.as_tensor(rng.choice(n, m, replace=False), device=dev)].contiguous()
+    ws = torch.empty(_lib.kmeans_workspace_size(kprec, n, Dd, m), dtype=torch.uint8, device=dev)
+    a = torch.empty(n, dtype=torch.int32, device=dev)
+    _lib.kmeans_assign(kprec, tgt, C, a, None, ws)
+    torch.cuda.synchronize()
+    e0.record(st)
+    for _ in range(10):
+        _lib.kmeans_assign(kprec, tgt, C, a, None, ws)
+    e1.record(st)
+    torch.cuda.synchronize()
+    amsec = e0.elapsed_time(e1) / 10
+    flops = 2.0 * n * m * Dd
+    peak = PEAKS["fp32_mfma_tflops" if kprec == "fp32" else "bf16_tflops"]
+    ach = flops / (amsec * 1e-3) / 1e12
+    return {"ms": step_ms, "value": n / (step_ms * 1e-3), "unit": "embeddings/s (Eq. 10 streaming step)",
+            "precision": kprec, "n": n, "D": Dd, "K": K, "micro": m, "iters_local": iters, "iters_global": iters,
+            "assign": {"ms": amsec, "bound": "mfma", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
+                       "frac": ach / peak, "flops": flops}}
+
+
 def _read_prof(L, name):
     import ctypes as C
     tot, cnt = C.c_double(), C.c_int()
@@ -412,6 +466,7 @@ def main():
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 decode comparison leg")
     ap.add_argument("--no-stage2", action="store_true", help="skip the Stage-II decode-only leg")
     ap.add_argument("--no-tied", action="store_true", help="skip the tied-decode leg")
+    ap.add_argument("--no-kmeans", action="store_true", help="skip the streaming K-means leg")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (scales HBM byte counters)")
     args = ap.parse_args()

@@ -10,7 +10,7 @@ namespace km {
 // Byte offsets of one Lloyd run's scratch inside a workspace, for up to npts
 // points, k centres and dimension D.
 struct KmLayout {
-    size_t off_cf, off_cn, off_a, off_ka, off_va, off_kb, off_vb, off_sort, off_start, off_end, off_head, off_tail,
+    size_t off_cf, off_cn, off_a, off_bv, off_ka, off_va, off_kb, off_vb, off_sort, off_start, off_end, off_head, off_tail,
         off_headw, off_tailw, off_c0, off_c1, off_w, off_n;
     size_t bytes;
     int npts, k, D;

@@ -31,6 +31,7 @@ namespace km {
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef float f32x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int kChunk = 256;     // sorted points per update chunk
@@ -38,7 +39,8 @@ constexpr int kNcw = 2;         // 32-centre row blocks per wave step
 constexpr int kCentreAlign = 32 * kNcw;
 constexpr int kPipe = 4;        // centre fragments in flight per wave
 constexpr int kAssignThreads = 256;
-constexpr size_t kMaxTileLds = 128 * 1024;
+constexpr size_t kMaxTileLds = 64 * 1024;  // two workgroups per CU
+constexpr int kSlice = 2048;    // centres per assign launch (their norms sit in LDS)
 
 // Products in float32 (the 32x32x2 f32 MFMA, eight steps per 16-wide K chunk).
 struct PF32 {
@@ -138,12 +140,21 @@ __global__ __launch_bounds__(256) void k_km_norms(const float* __restrict__ C, i
     if (lane == 0) cn[row] = row < k ? s : __builtin_huge_valf();
 }
 
-// Nearest centre of 32 NP points per workgroup.  LDS: the points' tile in the
-// product type, fragment-major [NP][D/16][64][8], then the per-wave results.
-template <class P, int NP>
+// Nearest centre of 32 NP points per workgroup (NP <= 2: with the tile at most
+// 64 KB, two workgroups share a CU and one stages its points while the other
+// computes) among one slice of at most
+// kSlice centres (global indices kbase ..): the slice's norms are staged in
+// LDS next to the points' tile (product type, fragment-major [NP][D/16][64][8]),
+// so the epilogue reads only LDS and every global load is a centre fragment of
+// the branch-free ring, whose waits the compiler can count exactly.  With
+// merge, the result is compared with the best of the earlier slices (lower
+// indices, so ties keep it).
+template <class P, int NP, int PIPE>
 __global__ __launch_bounds__(kAssignThreads, 1) void k_km_assign(const float* __restrict__ X, int n, int D,
                                                                  const typename P::T* __restrict__ Cf,
-                                                                 const float* __restrict__ cn, int kp, int k,
+                                                                 const float* __restrict__ cn, int kcp,
+                                                                 int kbase, int k, int merge,
+                                                                 float* __restrict__ best_v,
                                                                  uint32_t* __restrict__ a_out,
                                                                  float* __restrict__ d2_out)
 {
@@ -154,14 +165,16 @@ __global__ __launch_bounds__(kAssignThreads, 1) void k_km_assign(const float* __
     extern __shared__ __align__(16) unsigned char smem[];
     T* xs = reinterpret_cast<T*>(smem);
     const int nc = D / 16, g8 = D / 8;
-    float* red_v = reinterpret_cast<float*>(smem + (size_t)BP * D * P::kBytes);
+    float* cn_s = reinterpret_cast<float*>(smem + (size_t)BP * D * P::kBytes);
+    float* red_v = cn_s + kcp;
     int* red_j = reinterpret_cast<int*>(red_v + NW * BP);
     const int p0 = blockIdx.x * BP;
 
-    // stage the point tile: 8 consecutive floats of one row per item, the
-    // threads walking along the rows (coalesced), U items in flight
+    // stage the slice's norms and the point tile: 8 consecutive floats of one
+    // row per item, the threads walking along the rows (coalesced)
+    for (int t = threadIdx.x; t < kcp; t += kAssignThreads) cn_s[t] = cn[t];
     {
-        constexpr int U = 4;
+        constexpr int U = 8;
         const int items = BP * g8;
         for (int base = threadIdx.x; base < items; base += U * kAssignThreads) {
             float4 va[U], vb[U];
@@ -172,9 +185,11 @@ __global__ __launch_bounds__(kAssignThreads, 1) void k_km_assign(const float* __
                 va[u] = make_float4(0.f, 0.f, 0.f, 0.f);
                 vb[u] = va[u];
                 if (g < items && p0 + row < n) {
-                    const float4* src = reinterpret_cast<const float4*>(X + (size_t)(p0 + row) * D + j * 8);
-                    va[u] = src[0];
-                    vb[u] = src[1];
+                    // read once: streamed past the L2 that holds the centres
+                    const f32x4* src = reinterpret_cast<const f32x4*>(X + (size_t)(p0 + row) * D + j * 8);
+                    const f32x4 t0 = __builtin_nontemporal_load(src), t1 = __builtin_nontemporal_load(src + 1);
+                    va[u] = make_float4(t0.x, t0.y, t0.z, t0.w);
+                    vb[u] = make_float4(t1.x, t1.y, t1.z, t1.w);
                 }
             }
 #pragma unroll
@@ -191,9 +206,8 @@ __global__ __launch_bounds__(kAssignThreads, 1) void k_km_assign(const float* __
     __syncthreads();
 
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave, h = lane >> 5;
-    const int ngroups = kp / kCentreAlign;
+    const int ngroups = kcp / kCentreAlign;
     const int mine = ngroups > w ? (ngroups - w + NW - 1) / NW : 0;
-    const int S = mine * nc;  // steps: (group, K chunk)
     float bv[NP];
     int bj[NP];
 #pragma unroll
@@ -201,7 +215,7 @@ __global__ __launch_bounds__(kAssignThreads, 1) void k_km_assign(const float* __
         bv[p] = __builtin_huge_valf();
         bj[p] = 0x7fffffff;
     }
-    if (S > 0) {
+    if (mine > 0) {
         f32x16 acc[kNcw][NP];
 #pragma unroll
         for (int i = 0; i < kNcw; ++i)
@@ -209,57 +223,68 @@ __global__ __launch_bounds__(kAssignThreads, 1) void k_km_assign(const float* __
             for (int p = 0; p < NP; ++p)
 #pragma unroll
                 for (int r = 0; r < 16; ++r) acc[i][p][r] = 0.0f;
-        Frag ring[kPipe][kNcw];
-        auto fetch = [&](Frag* slot, int s) {
-            const int q = s / nc, c = s - q * nc;
+        auto cfrag = [&](int rb, int c) { return P::load(Cf + ((((size_t)rb * nc + c) << 6) + lane) * 8); };
+        auto xfrag = [&](int p, int c) { return P::load(xs + ((((size_t)p * nc + c) << 6) + lane) * 8); };
+        Frag ring[PIPE][kNcw];
+        Frag bcur[NP];
+#pragma unroll
+        for (int u = 0; u < PIPE; ++u)
+#pragma unroll
+            for (int i = 0; i < kNcw; ++i) ring[u][i] = cfrag(w * kNcw + i, u);
+#pragma unroll
+        for (int p = 0; p < NP; ++p) bcur[p] = xfrag(p, 0);
+        const int nblk = nc / PIPE;
+        for (int q = 0; q < mine; ++q) {
             const int rb0 = (w + NW * q) * kNcw;
+            const int rbn = q + 1 < mine ? rb0 + NW * kNcw : rb0;  // the last group refetches its own rows
+            for (int cb = 0; cb < nblk; ++cb) {
+                const bool lastblk = cb == nblk - 1;
+                const int rbp = lastblk ? rbn : rb0;
 #pragma unroll
-            for (int i = 0; i < kNcw; ++i)
-                slot[i] = P::load(Cf + ((((size_t)(rb0 + i) * nc + c) << 6) + lane) * 8);
-        };
+                for (int u = 0; u < PIPE; ++u) {
+                    const int c = cb * PIPE + u;
+                    Frag bnext[NP];
+                    const int cx = c + 1 == nc ? 0 : c + 1;
 #pragma unroll
-        for (int u = 0; u < kPipe; ++u) fetch(ring[u], u < S ? u : S - 1);
-        for (int s0 = 0; s0 < S; s0 += kPipe) {
-#pragma unroll
-            for (int u = 0; u < kPipe; ++u) {
-                const int s = s0 + u;
-                if (s < S) {
-                    const int q = s / nc, c = s - q * nc;
-                    Frag b[NP];
-#pragma unroll
-                    for (int p = 0; p < NP; ++p) b[p] = P::load(xs + ((((size_t)p * nc + c) << 6) + lane) * 8);
+                    for (int p = 0; p < NP; ++p) bnext[p] = xfrag(p, cx);
+                    __builtin_amdgcn_sched_barrier(0);  // the next step's LDS reads go out first
 #pragma unroll
                     for (int i = 0; i < kNcw; ++i)
 #pragma unroll
-                        for (int p = 0; p < NP; ++p) P::mma(acc[i][p], ring[u][i], b[p]);
-                    fetch(ring[u], s + kPipe < S ? s + kPipe : S - 1);
-                    if (c == nc - 1) {
-                        // epilogue of centre group q: rows are centres, columns points
-                        const int rb0 = (w + NW * q) * kNcw;
+                        for (int p = 0; p < NP; ++p) P::mma(acc[i][p], ring[u][i], bcur[p]);
+                    // chunk c + PIPE of this group, or chunk u of the next one
+                    const int cp = lastblk ? u : c + PIPE;
 #pragma unroll
-                        for (int i = 0; i < kNcw; ++i) {
-                            const int j0 = 32 * (rb0 + i);
-                            float cv[16];
+                    for (int i = 0; i < kNcw; ++i) ring[u][i] = cfrag(rbp + i, cp);
 #pragma unroll
-                            for (int q4 = 0; q4 < 4; ++q4) {
-                                const float4 t = *reinterpret_cast<const float4*>(cn + j0 + 8 * q4 + 4 * h);
-                                cv[4 * q4] = t.x; cv[4 * q4 + 1] = t.y; cv[4 * q4 + 2] = t.z; cv[4 * q4 + 3] = t.w;
-                            }
-#pragma unroll
-                            for (int p = 0; p < NP; ++p)
-#pragma unroll
-                                for (int r = 0; r < 16; ++r) {
-                                    // rows visited in increasing order: strict < keeps the lowest index
-                                    const float v = cv[r] - 2.0f * acc[i][p][r];
-                                    if (v < bv[p]) {
-                                        bv[p] = v;
-                                        bj[p] = j0 + crow(r, h);
-                                    }
-                                    acc[i][p][r] = 0.0f;
-                                }
-                        }
-                    }
+                    for (int p = 0; p < NP; ++p) bcur[p] = bnext[p];
+                    // keep the refill in this step: sunk to the end of the
+                    // block it would leave the first slots no time in flight
+                    __builtin_amdgcn_sched_barrier(0);
                 }
+            }
+            // epilogue of group q: rows are centres, columns points; rows are
+            // visited in increasing order, so strict < keeps the lowest index
+#pragma unroll
+            for (int i = 0; i < kNcw; ++i) {
+                const int jl = 32 * (rb0 + i);
+                float cv[16];
+#pragma unroll
+                for (int q4 = 0; q4 < 4; ++q4) {
+                    const float4 t = *reinterpret_cast<const float4*>(cn_s + jl + 8 * q4 + 4 * h);
+                    cv[4 * q4] = t.x; cv[4 * q4 + 1] = t.y; cv[4 * q4 + 2] = t.z; cv[4 * q4 + 3] = t.w;
+                }
+#pragma unroll
+                for (int p = 0; p < NP; ++p)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        const float v = cv[r] - 2.0f * acc[i][p][r];
+                        if (v < bv[p]) {
+                            bv[p] = v;
+                            bj[p] = kbase + jl + crow(r, h);
+                        }
+                        acc[i][p][r] = 0.0f;
+                    }
             }
         }
     }
@@ -289,8 +314,17 @@ __global__ __launch_bounds__(kAssignThreads, 1) void k_km_assign(const float* __
             }
         const int pt = p0 + t;
         if (pt < n) {
+            if (merge) {
+                const float ov = best_v[pt];
+                if (!(v < ov)) {
+                    v = ov;
+                    j = (int)a_out[pt];
+                }
+            }
             // a non-finite distance (non-finite input) leaves no winner: centre 0
-            a_out[pt] = (j >= 0 && j < k) ? (uint32_t)j : 0u;
+            if (!(j >= 0 && j < k)) j = 0;
+            a_out[pt] = (uint32_t)j;
+            if (best_v) best_v[pt] = v;
             if (d2_out) {
                 const float4* row = reinterpret_cast<const float4*>(X + (size_t)pt * D);
                 float s = 0.0f;
@@ -468,12 +502,14 @@ __global__ __launch_bounds__(128) void k_km_gather(const float* __restrict__ X, 
 
 // ------------------------------------------------------------ host side
 
+// Points per assign workgroup: tiles of at most 64 KB (two workgroups per CU),
+// else 32 points in up to 128 KB (one per CU) for the widest rows.
 static int tile_points(int prec, int D)
 {
     const size_t bytes = prec == LAM_BF16 ? 2 : 4;
-    for (int bp : {128, 64, 32})
+    for (int bp : {64, 32})
         if ((size_t)bp * D * bytes <= kMaxTileLds) return bp;
-    return 0;
+    return (size_t)32 * D * bytes <= 2 * kMaxTileLds ? 32 : 0;
 }
 
 static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
@@ -500,6 +536,7 @@ KmLayout kmeans_layout(int prec, int npts, int D, int k)
     L.off_cf = take(kp * D * (prec == LAM_BF16 ? 2 : 4));
     L.off_cn = take(kp * 4);
     L.off_a = take(np * 4);
+    L.off_bv = take(np * 4);
     L.off_ka = take(np * 4);
     L.off_va = take(np * 4);
     L.off_kb = take(np * 4);
@@ -522,23 +559,39 @@ KmLayout kmeans_layout(int prec, int npts, int D, int k)
     return L;
 }
 
-template <class P, int NP>
-static hipError_t launch_assign_np(const float* X, int n, int D, const void* Cf, const float* cn, int kp, int k,
-                                   uint32_t* a, float* d2, hipStream_t st)
+template <class P, int NP, int PIPE>
+static hipError_t launch_assign_np(const float* X, int n, int D, const typename P::T* Cf, const float* cn, int kp,
+                                   int k, float* best_v, uint32_t* a, float* d2, hipStream_t st)
 {
-    const size_t lds = (size_t)32 * NP * D * P::kBytes + (size_t)2 * 4 * 32 * NP * 4;
-    auto kern = k_km_assign<P, NP>;
+    auto kern = k_km_assign<P, NP, PIPE>;
+    const size_t lds_max = (size_t)32 * NP * D * P::kBytes + (size_t)kSlice * 4 + (size_t)2 * 4 * 32 * NP * 4;
     static size_t lds_set = 0;  // raised only when needed, so captured replays make no call
-    if (lds > lds_set) {
-        if (hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
+    if (lds_max > lds_set) {
+        if (hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_max) !=
             hipSuccess)
             return hipErrorInvalidValue;
-        lds_set = lds;
+        lds_set = lds_max;
     }
     const int blocks = (n + 32 * NP - 1) / (32 * NP);
-    hipLaunchKernelGGL(kern, dim3(blocks), dim3(kAssignThreads), lds, st, X, n, D,
-                       reinterpret_cast<const typename P::T*>(Cf), cn, kp, k, a, d2);
+    const int nc = D / 16;
+    const int slices = (kp + kSlice - 1) / kSlice;
+    for (int s = 0; s < slices; ++s) {
+        const int kbase = s * kSlice, kcp = std::min(kSlice, kp - kbase);
+        const bool last = s == slices - 1;
+        const size_t lds = (size_t)32 * NP * D * P::kBytes + (size_t)kcp * 4 + (size_t)2 * 4 * 32 * NP * 4;
+        hipLaunchKernelGGL(kern, dim3(blocks), dim3(kAssignThreads), lds, st, X, n, D,
+                           Cf + (size_t)(kbase / 32) * nc * 512, cn + kbase, kcp, kbase, k, s > 0 ? 1 : 0,
+                           slices > 1 ? best_v : nullptr, a, last ? d2 : nullptr);
+    }
     return hipGetLastError();
+}
+
+template <class P, int NP>
+static hipError_t launch_assign_pipe(const float* X, int n, int D, const typename P::T* Cf, const float* cn,
+                                     int kp, int k, float* best_v, uint32_t* a, float* d2, hipStream_t st)
+{
+    if ((D / 16) % 4 == 0) return launch_assign_np<P, NP, 4>(X, n, D, Cf, cn, kp, k, best_v, a, d2, st);
+    return launch_assign_np<P, NP, 2>(X, n, D, Cf, cn, kp, k, best_v, a, d2, st);
 }
 
 template <class P>
@@ -548,15 +601,15 @@ static hipError_t launch_assign_p(const float* X, int n, int D, const float* C, 
     const int kp = (int)align_up((size_t)k, kCentreAlign);
     auto* Cf = reinterpret_cast<typename P::T*>(base + L.off_cf);
     float* cn = reinterpret_cast<float*>(base + L.off_cn);
+    float* best_v = reinterpret_cast<float*>(base + L.off_bv);
     const size_t groups = (size_t)kp * (D / 8);
     hipLaunchKernelGGL(k_km_prep<P>, dim3((unsigned)std::min<size_t>((groups + 255) / 256, 4096)), dim3(256), 0,
                        st, C, k, kp, D, Cf);
     hipLaunchKernelGGL(k_km_norms, dim3((kp + 3) / 4), dim3(256), 0, st, C, k, kp, D, cn);
     if (n == 0) return hipGetLastError();
     const int bp = tile_points(P::kBytes == 2 ? LAM_BF16 : LAM_FP32, D);
-    if (bp == 128) return launch_assign_np<P, 4>(X, n, D, Cf, cn, kp, k, a, d2, st);
-    if (bp == 64) return launch_assign_np<P, 2>(X, n, D, Cf, cn, kp, k, a, d2, st);
-    return launch_assign_np<P, 1>(X, n, D, Cf, cn, kp, k, a, d2, st);
+    if (bp == 64) return launch_assign_pipe<P, 2>(X, n, D, Cf, cn, kp, k, best_v, a, d2, st);
+    return launch_assign_pipe<P, 1>(X, n, D, Cf, cn, kp, k, best_v, a, d2, st);
 }
 
 hipError_t kmeans_assign_launch(int prec, const float* X, int n, int D, const float* C, int k, const KmLayout& L,

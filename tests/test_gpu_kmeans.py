@@ -59,7 +59,7 @@ def _dev(a):
 
 
 ASSIGN_SHAPES = [(1000, 64, 10), (4097, 512, 300), (777, 768, 65), (300, 1024, 1), (513, 32, 1280),
-                 (2000, 2048, 70), (5, 128, 3)]
+                 (2000, 2048, 70), (5, 128, 3), (2000, 32, 4500)]  # the last spans two centre slices
 
 
 @pytest.mark.parametrize("prec", PRECS)
@@ -87,6 +87,14 @@ def test_assign_exact_ties_go_to_the_lowest_index():
     for prec in PRECS:
         a, _ = ops.kmeans_assign(prec, _dev(X), _dev(C))
         assert to_np(a).max() < 40, prec
+    # duplicates on both sides of the 4096-centre slice boundary
+    far = 40.0 + rng.standard_normal((4200, 128))
+    far[4150:4190] = base
+    far[1000:1040] = base
+    for prec in PRECS:
+        a, _ = ops.kmeans_assign(prec, _dev(X), _dev(far.astype(np.float32)))
+        a = to_np(a)
+        assert a.min() >= 1000 and a.max() < 1040, prec
 
 
 @pytest.mark.parametrize("prec", PRECS)
