@@ -35,11 +35,11 @@ def lib():
         _lib.orc_num_tiles.restype = i64
         _lib.orc_num_tiles.argtypes = [i32, vp, i32, i32]
         _lib.orc_render_forward.restype = i32
-        _lib.orc_render_forward.argtypes = [i32, i32, vp, vp, vp, vp, vp, i32, vp, i32, i32] + [vp] * 7
+        _lib.orc_render_forward.argtypes = [i32, i32, vp, vp, vp, vp, vp, i32, vp, i32, i32] + [vp] * 8
         _lib.orc_render_bruteforce.restype = i32
-        _lib.orc_render_bruteforce.argtypes = [i32, i32, vp, vp, vp, vp, vp, i32, vp, vp, vp, vp]
+        _lib.orc_render_bruteforce.argtypes = [i32, i32, vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp]
         _lib.orc_render_backward.restype = i32
-        _lib.orc_render_backward.argtypes = [i32, i32, vp, vp, vp, vp, vp, i32, vp, i32, i32, vp] + [vp] * 6
+        _lib.orc_render_backward.argtypes = [i32, i32, vp, vp, vp, vp, vp, i32, vp, i32, i32, vp] + [vp] * 7
         _lib.orc_num_threads.restype = i32
     return _lib
 
@@ -112,31 +112,37 @@ def bin_sort(g: Gaussians, cams, tw=16, th=16):
 
 
 def render_forward(g: Gaussians, cams, tw=16, th=16):
+    """Query map Q (Eq. 4), depth map Z (the same blend of the centres'
+    camera-space depths), final transmittance and per-pixel bookkeeping."""
     cams = _c(cams)
     P = n_pixels(cams)
     out = dict(Q=np.zeros((P, g.d)), T_final=np.zeros(P), n_contrib=np.zeros(P, np.int32),
                n_blended=np.zeros(P, np.int32), n_pairs=np.zeros(P, np.int32),
-               margin=np.zeros(P), hash=np.zeros(P, np.uint64))
+               margin=np.zeros(P), hash=np.zeros(P, np.uint64), Z=np.zeros(P))
     lib().orc_render_forward(g.n, g.d, *g.geom_args(), _ptr(g.queries), cams.shape[0],
                              _ptr(cams), tw, th, _ptr(out["Q"]), _ptr(out["T_final"]),
                              _ptr(out["n_contrib"]), _ptr(out["n_blended"]),
-                             _ptr(out["n_pairs"]), _ptr(out["margin"]), _ptr(out["hash"]))
+                             _ptr(out["n_pairs"]), _ptr(out["margin"]), _ptr(out["hash"]),
+                             _ptr(out["Z"]))
     return out
 
 
 def render_bruteforce(g: Gaussians, cams):
     cams = _c(cams)
     P = n_pixels(cams)
-    out = dict(Q=np.zeros((P, g.d)), T_final=np.zeros(P), n_blended=np.zeros(P, np.int32))
+    out = dict(Q=np.zeros((P, g.d)), T_final=np.zeros(P), n_blended=np.zeros(P, np.int32),
+               Z=np.zeros(P))
     lib().orc_render_bruteforce(g.n, g.d, *g.geom_args(), _ptr(g.queries), cams.shape[0],
                                 _ptr(cams), _ptr(out["Q"]), _ptr(out["T_final"]),
-                                _ptr(out["n_blended"]))
+                                _ptr(out["n_blended"]), _ptr(out["Z"]))
     return out
 
 
-def render_backward(g: Gaussians, cams, dQ, tw=16, th=16, with_rec: bool = False):
+def render_backward(g: Gaussians, cams, dQ, tw=16, th=16, with_rec: bool = False, dZ=None):
+    """Adjoint for the upstream gradients dQ [P, d] and (optional) dZ [P]."""
     cams = _c(cams)
     dQ = _c(dQ, np.float64)
+    dZ = None if dZ is None else _c(dZ, np.float64)
     n, d = g.n, g.d
     out = dict(means=np.zeros((n, 3)), log_scales=np.zeros((n, 3)), quats=np.zeros((n, 4)),
                opacity_logits=np.zeros(n), queries=np.zeros((n, d)))
@@ -144,7 +150,7 @@ def render_backward(g: Gaussians, cams, dQ, tw=16, th=16, with_rec: bool = False
     lib().orc_render_backward(n, d, *g.geom_args(), _ptr(g.queries), cams.shape[0], _ptr(cams),
                               tw, th, _ptr(dQ), _ptr(out["means"]), _ptr(out["log_scales"]),
                               _ptr(out["quats"]), _ptr(out["opacity_logits"]),
-                              _ptr(out["queries"]), _ptr(rec))
+                              _ptr(out["queries"]), _ptr(rec), _ptr(dZ))
     if with_rec:
         out["rec"] = rec
     return out

@@ -350,14 +350,17 @@ static inline uint64_t mix64(uint64_t h, uint64_t v)
 }
 
 /* Blend one pixel over an ordered candidate list.  ``list`` holds record ids;
- * when ``contribs`` is non-NULL the blended pairs are recorded for the adjoint. */
+ * when ``contribs`` is non-NULL the blended pairs are recorded for the adjoint.
+ * With Zp non-NULL the same weights blend the camera-space depth of each
+ * record's centre (Sec. III-A: depth is rendered by the same alpha blending). */
 static void blend_pixel(const scene_t* S, const float* queries, int px, int py,
-                        const uint32_t* list, int64_t len, double* Q, double* Tfin,
+                        const uint32_t* list, int64_t len, double* Q, double* Zp, double* Tfin,
                         int32_t* ncontrib, int32_t* nblend, int32_t* npairs, double* margin,
                         uint64_t* hash, contrib_t* contribs)
 {
     int d = S->d;
     for (int k = 0; k < d; ++k) Q[k] = 0.0;
+    double Z = 0.0;
     double T = 1.0, mg = INFINITY;
     /* amp bounds how a relative error in each alpha grows in T: d(ln T) = -sum alpha/(1-alpha) d(ln alpha) */
     double amp = 1.0;
@@ -381,6 +384,7 @@ static void blend_pixel(const scene_t* S, const float* queries, int px, int py,
         int64_t gi = list[k] % S->n;
         const float* q = queries + gi * d;
         for (int j = 0; j < d; ++j) Q[j] += alpha * T * (double)q[j];
+        Z += alpha * T * P->z;
         if (contribs) {
             contribs[nb].rec = list[k];
             contribs[nb].alpha = alpha;
@@ -397,6 +401,7 @@ static void blend_pixel(const scene_t* S, const float* queries, int px, int py,
         ++nb;
     }
     *Tfin = T;
+    if (Zp) *Zp = Z;
     if (ncontrib) *ncontrib = last;
     if (nblend) *nblend = nb;
     if (npairs) *npairs = np;
@@ -499,7 +504,7 @@ int orc_render_forward(int n, int d, const float* means, const float* log_scales
                        const float* quats, const float* logits, const float* queries,
                        int n_cams, const float* cams, int tw, int th, double* Q,
                        double* T_final, int32_t* n_contrib, int32_t* n_blended,
-                       int32_t* n_pairs, double* margin, uint64_t* hash)
+                       int32_t* n_pairs, double* margin, uint64_t* hash, double* Z)
 {
     scene_t S;
     memset(&S, 0, sizeof S);
@@ -516,7 +521,7 @@ int orc_render_forward(int n, int d, const float* means, const float* log_scales
         pixel_coords(&S, p, &c, &x, &y);
         int64_t t = S.tile_off[c] + (int64_t)(y / th) * S.tiles_x[c] + x / tw;
         uint32_t s0 = B.ranges[2 * t], s1 = B.ranges[2 * t + 1];
-        blend_pixel(&S, queries, x, y, ids + s0, (int64_t)s1 - s0, Q + p * d, T_final + p,
+        blend_pixel(&S, queries, x, y, ids + s0, (int64_t)s1 - s0, Q + p * d, Z ? Z + p : NULL, T_final + p,
                     n_contrib ? n_contrib + p : NULL, n_blended ? n_blended + p : NULL,
                     n_pairs ? n_pairs + p : NULL, margin ? margin + p : NULL,
                     hash ? hash + p : NULL, NULL);
@@ -540,7 +545,7 @@ static int rec_cmp_depth(const void* pa, const void* pb, void* ctx)
 int orc_render_bruteforce(int n, int d, const float* means, const float* log_scales,
                           const float* quats, const float* logits, const float* queries,
                           int n_cams, const float* cams, double* Q, double* T_final,
-                          int32_t* n_blended)
+                          int32_t* n_blended, double* Z)
 {
     scene_t S;
     memset(&S, 0, sizeof S);
@@ -557,7 +562,7 @@ int orc_render_bruteforce(int n, int d, const float* means, const float* log_sca
         for (int64_t q = 0; q < (int64_t)W * H; ++q) {
             int64_t p = S.pix_off[c] + q;
             blend_pixel(&S, queries, (int)(q % W), (int)(q / W), order, m, Q + p * d,
-                        T_final + p, NULL, n_blended ? n_blended + p : NULL, NULL, NULL, NULL,
+                        Z ? Z + p : NULL, T_final + p, NULL, n_blended ? n_blended + p : NULL, NULL, NULL, NULL,
                         NULL);
         }
         free(order);
@@ -677,15 +682,18 @@ static void adjoint_record(const proj_t* P, const cam_t* cam, const double g[6],
     for (int k = 0; k < 4; ++k) dquat[k] += (dq[k] - P->qn[k] * dot) / P->qnorm;
 }
 
-/* Adjoint of the tile-binned render for a given upstream gradient dQ [P, d].
+/* Adjoint of the tile-binned render for a given upstream gradient dQ [P, d]
+ * and, when dZ [P] is non-NULL, of the depth render.
  * Transmittance is re-derived forward (products), not by division.
  * Outputs are overwritten.  d_rec (nullable) receives the per-record
- * screen-space gradient [R, 6] = (du, dv, dA, dB, dC, dopacity). */
+ * screen-space gradient [R, 6] = (du, dv, dA, dB, dC, dopacity).  The depth of
+ * a record is z = row 3 of the world->camera transform applied to the mean,
+ * so its gradient reaches the mean through that row. */
 int orc_render_backward(int n, int d, const float* means, const float* log_scales,
                         const float* quats, const float* logits, const float* queries,
                         int n_cams, const float* cams, int tw, int th, const double* dQ,
                         double* d_means, double* d_log_scales, double* d_quats,
-                        double* d_logits, double* d_queries, double* d_rec)
+                        double* d_logits, double* d_queries, double* d_rec, const double* dZ)
 {
     scene_t S;
     memset(&S, 0, sizeof S);
@@ -700,6 +708,7 @@ int orc_render_backward(int n, int d, const float* means, const float* log_scale
     int nth = omp_get_max_threads();
     double* acc_rec = (double*)calloc((size_t)nth * (size_t)(R > 0 ? R : 1) * 6, sizeof(double));
     double* acc_q = (double*)calloc((size_t)nth * (size_t)(n > 0 ? n : 1) * d, sizeof(double));
+    double* acc_z = (double*)calloc((size_t)nth * (size_t)(R > 0 ? R : 1), sizeof(double));
     int64_t maxlen = 0;
     for (int64_t t = 0; t < S.tile_off[n_cams]; ++t) {
         int64_t len = (int64_t)B.ranges[2 * t + 1] - B.ranges[2 * t];
@@ -710,6 +719,7 @@ int orc_render_backward(int n, int d, const float* means, const float* log_scale
         int tid = omp_get_thread_num();
         double* my_rec = acc_rec + (size_t)tid * R * 6;
         double* my_q = acc_q + (size_t)tid * n * d;
+        double* my_z = acc_z + (size_t)tid * R;
         contrib_t* cs = (contrib_t*)malloc((size_t)(maxlen > 0 ? maxlen : 1) * sizeof(contrib_t));
         double* Qp = (double*)malloc((size_t)d * sizeof(double));
         double* suffix = (double*)malloc((size_t)d * sizeof(double));
@@ -721,11 +731,13 @@ int orc_render_backward(int n, int d, const float* means, const float* log_scale
             uint32_t s0 = B.ranges[2 * t], s1 = B.ranges[2 * t + 1];
             double Tf;
             int32_t nb;
-            blend_pixel(&S, queries, x, y, ids + s0, (int64_t)s1 - s0, Qp, &Tf, NULL, &nb, NULL,
+            blend_pixel(&S, queries, x, y, ids + s0, (int64_t)s1 - s0, Qp, NULL, &Tf, NULL, &nb, NULL,
                         NULL, NULL, cs);
             const double* g = dQ + p * d;
-            /* suffix = sum over later blended m of alpha_m T_m q_m */
+            const double gz = dZ ? dZ[p] : 0.0;
+            /* suffix = sum over later blended m of alpha_m T_m q_m (and of z_m) */
             for (int j = 0; j < d; ++j) suffix[j] = 0.0;
+            double suffix_z = 0.0;
             for (int k = nb - 1; k >= 0; --k) {
                 const contrib_t* e = &cs[k];
                 int64_t gi = e->rec % n;
@@ -737,6 +749,12 @@ int orc_render_backward(int n, int d, const float* means, const float* log_scale
                     my_q[gi * d + j] += e->alpha * e->T * g[j];
                 }
                 for (int j = 0; j < d; ++j) suffix[j] += e->alpha * e->T * (double)q[j];
+                if (dZ) {
+                    const double z = S.proj[e->rec].z;
+                    dal += (e->T * z - suffix_z / (1.0 - e->alpha)) * gz;
+                    my_z[e->rec] += e->alpha * e->T * gz;
+                    suffix_z += e->alpha * e->T * z;
+                }
                 if (e->a < ORC_ALPHA_MAX) {
                     const proj_t* P = &S.proj[e->rec];
                     double dpow = dal * e->a; /* alpha = o exp(power) */
@@ -758,6 +776,9 @@ int orc_render_backward(int n, int d, const float* means, const float* log_scale
     double* rec_g = (double*)calloc((size_t)(R > 0 ? R : 1) * 6, sizeof(double));
     for (int t = 0; t < nth; ++t)
         for (int64_t k = 0; k < R * 6; ++k) rec_g[k] += acc_rec[(size_t)t * R * 6 + k];
+    double* rec_z = (double*)calloc((size_t)(R > 0 ? R : 1), sizeof(double));
+    for (int t = 0; t < nth; ++t)
+        for (int64_t k = 0; k < R; ++k) rec_z[k] += acc_z[(size_t)t * R + k];
     memset(d_queries, 0, (size_t)n * d * sizeof(double));
     for (int t = 0; t < nth; ++t)
         for (int64_t k = 0; k < (int64_t)n * d; ++k) d_queries[k] += acc_q[(size_t)t * n * d + k];
@@ -770,6 +791,8 @@ int orc_render_backward(int n, int d, const float* means, const float* log_scale
             const proj_t* P = &S.proj[(int64_t)c * n + i];
             if (!P->vis) continue;
             adjoint_record(P, &S.cams[c], rec_g + ((int64_t)c * n + i) * 6, dm, dl, dq, &dlg);
+            const double gzr = rec_z[(int64_t)c * n + i];
+            for (int k = 0; k < 3; ++k) dm[k] += gzr * S.cams[c].vm[8 + k];
         }
         for (int k = 0; k < 3; ++k) d_means[3 * i + k] = dm[k];
         for (int k = 0; k < 3; ++k) d_log_scales[3 * i + k] = dl[k];
@@ -777,8 +800,10 @@ int orc_render_backward(int n, int d, const float* means, const float* log_scale
         d_logits[i] = dlg;
     }
     free(rec_g);
+    free(rec_z);
     free(acc_rec);
     free(acc_q);
+    free(acc_z);
     free(ids);
     bins_free(&B);
     scene_free(&S);

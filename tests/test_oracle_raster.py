@@ -281,10 +281,12 @@ def test_transmittance_bounds_config0():
     assert T[order][-1] <= T[order][0]
 
 
-def _fd_check(g, cams, seed, hrel=1e-5, tol=2e-6, tile=(16, 16)):
+def _fd_check(g, cams, seed, hrel=1e-5, tol=2e-6, tile=(16, 16), depth=False):
     f = R.render_forward(g, cams, *tile)
-    w = np.random.default_rng(seed).standard_normal(f["Q"].shape)
-    gr = R.render_backward(g, cams, w, *tile)
+    rng = np.random.default_rng(seed)
+    w = rng.standard_normal(f["Q"].shape)
+    wz = rng.standard_normal(f["Z"].shape) if depth else np.zeros(f["Z"].shape)
+    gr = R.render_backward(g, cams, w, *tile, dZ=wz if depth else None)
     checked = 0
     for name in ["means", "log_scales", "quats", "opacity_logits", "queries"]:
         arr = getattr(g, name)
@@ -300,7 +302,8 @@ def _fd_check(g, cams, seed, hrel=1e-5, tol=2e-6, tile=(16, 16)):
             op, om = R.render_forward(gp, cams, *tile), R.render_forward(gm, cams, *tile)
             if not (np.array_equal(op["hash"], f["hash"]) and np.array_equal(om["hash"], f["hash"])):
                 continue  # a decision flipped inside the stencil: not differentiable there
-            fd = ((op["Q"] * w).sum() - (om["Q"] * w).sum()) / (hp + hm)
+            fd = (((op["Q"] * w).sum() + (op["Z"] * wz).sum()) -
+                  ((om["Q"] * w).sum() + (om["Z"] * wz).sum())) / (hp + hm)
             errs.append(abs(fd - gr[name][idx]))
             mags.append(abs(gr[name][idx]))
         errs, mags = np.array(errs), np.array(mags)
@@ -336,3 +339,55 @@ def test_fd_gradients_with_fov_clamp_active():
     rx = p["z"] * 0 + (g.means[:, 0] / g.means[:, 2])
     assert np.sum((np.abs(rx) > lim) & (p["vis"] == 1)) >= 3
     _fd_check(g, cams, 6, tol=5e-6)
+
+
+# ---------------------------------------------------------------- depth render
+
+def test_depth_at_centre_and_two_gaussians_closed_form():
+    # Sec. III-A: depth is blended with the weights of Eq. 2.  On the axis the
+    # centre pixel sees alpha = opacity, so one Gaussian gives o z and two give
+    # a1 z1 + (1 - a1) a2 z2.
+    cams = cams_of(CAM0)
+    p = _pix(CAM0, 40, 30)
+    g = _on_axis([2.0], [0.6], [np.ones(4)])
+    out = R.render_forward(g, cams)
+    o = 1 / (1 + np.exp(-float(np.float32(logit(0.6)))))
+    assert out["Z"][p] == pytest.approx(o * 2.0, rel=1e-14)
+    g = _on_axis([1.5, 2.5], [0.3, 0.7], [np.ones(4), np.ones(4)])
+    out = R.render_forward(g, cams)
+    a1 = 1 / (1 + np.exp(-float(np.float32(logit(0.3)))))
+    a2 = 1 / (1 + np.exp(-float(np.float32(logit(0.7)))))
+    assert out["Z"][p] == pytest.approx(a1 * 1.5 + (1 - a1) * a2 * 2.5, rel=1e-14)
+
+
+def test_depth_is_the_query_blend_of_the_centre_depths():
+    # With each Gaussian's query set to its camera-space depth (one camera), the
+    # pinned query blend must reproduce the depth render.
+    g, cams = tiny_scene(4, n=60, w=32, h=32, f=28.0)
+    z = R.project(g, cams)["z"]
+    gz = copy.deepcopy(g)
+    gz.queries = np.ascontiguousarray(z[:, None].astype(np.float32))
+    out = R.render_forward(g, cams)
+    ref = R.render_forward(gz, cams)
+    np.testing.assert_allclose(out["Z"], ref["Q"][:, 0], rtol=1e-6, atol=1e-12)
+    assert (out["Z"] > 0).sum() > 200
+
+
+def test_bruteforce_depth_equals_tile_binned():
+    g, cams = tiny_scene(2, n=50, w=32, h=32, f=28.0)
+    bf = R.render_bruteforce(g, cams)
+    tb = R.render_forward(g, cams, 8, 8)
+    assert np.array_equal(bf["Z"], tb["Z"])
+
+
+def test_fd_gradients_with_depth_identity_camera():
+    g, cams = tiny_scene(3, n=30)
+    assert _fd_check(g, cams, 7, depth=True) > 300
+
+
+def test_fd_gradients_with_depth_rotated_two_views():
+    pose = scenes.look_at_origin((1.0, 0.0, -2.5))
+    g, _ = tiny_scene(11, n=25)
+    g.means[:, 2] -= 1.0
+    cams = cams_of(scenes.pinhole(30, 24, 24.0, pose), scenes.pinhole(26, 20, 20.0))
+    assert _fd_check(g, cams, 8, tile=(8, 8), depth=True) > 250
