@@ -4,6 +4,8 @@
  *
  *   render_forward   Q = R_f(G, T)                       Sec. III-B, Eq. 4 (blend of Eq. 2)
  *   render_backward  dL/dQ -> dL/d(means, log-scales, quaternions, opacity logits, queries)
+ *   render_rgbd_*    the same with colour and depth rendered in the pass     Sec. III-A, Eq. 2
+ *   rgbd_l1_loss     the L1 colour and depth terms of the mapping objective   Eq. 7-9
  *   decode_loss      F = softmax(Q K^T / sqrt(d)) V, L = mean(1 - cos(F, T)) + lambda ||K - K0||^2,
  *                    and dL/dQ, dL/dK, dL/dV                    Sec. III-B, Eq. 5 and Eq. 6
  *   decode_forward   F alone (inference form of Eq. 5)
@@ -132,6 +134,45 @@ lam_status lam_render_backward(const float* means, const float* log_scales, cons
                                float* d_quats, float* d_opacity_logits, float* d_queries,
                                void* ws, uint64_t ws_bytes, uint64_t instance_capacity,
                                void* stream);
+
+/* Colour and depth rendering (Sec. III-A: view-independent colour c_i blended
+ * by Eq. 2; depth blended with the same weights from the camera-space depth
+ * of each Gaussian's centre) in the same pass as the query map.  Arguments as
+ * lam_render_forward / lam_render_backward plus: colors [N, 3] (device,
+ * float32), rgb [P, 3] and depth [P] (device outputs, overwritten); in the
+ * backward d_rgb [P, 3] and d_depth [P] (upstream gradients) and d_colors
+ * [N, 3] (output, overwritten).  The depth gradient reaches the means through
+ * the third row of each view's world->camera transform.  The workspace is the
+ * one lam_render_workspace_size reports; the backward reads what the forward
+ * of the same call sequence left in it.
+ * Errors: LAM_ERR_INVALID_ARG, LAM_ERR_UNSUPPORTED, LAM_ERR_HIP. */
+lam_status lam_render_rgbd_forward(const float* means, const float* log_scales, const float* quats,
+                                   const float* opacity_logits, const float* queries, const float* colors,
+                                   int n_gauss, int d, const float* cams, int n_cams, int tile_w, int tile_h,
+                                   float* Q, float* rgb, float* depth, float* T_final, void* ws,
+                                   uint64_t ws_bytes, uint64_t instance_capacity, void* stream);
+lam_status lam_render_rgbd_backward(const float* means, const float* log_scales, const float* quats,
+                                    const float* opacity_logits, const float* queries, const float* colors,
+                                    int n_gauss, int d, const float* cams, int n_cams, int tile_w, int tile_h,
+                                    const float* dQ, const float* d_rgb, const float* d_depth, float* d_means,
+                                    float* d_log_scales, float* d_quats, float* d_opacity_logits,
+                                    float* d_queries, float* d_colors, void* ws, uint64_t ws_bytes,
+                                    uint64_t instance_capacity, void* stream);
+
+/* The L1 terms of the mapping objective (Eq. 7-9):
+ *   L = lambda_rgb mean_{p,c} |rgb - rgb_obs| + lambda_depth mean_{p: depth_obs > 0} |depth - depth_obs|
+ * (an observed depth <= 0 marks a pixel without a measurement; with none the
+ * depth term is zero) and dL/drgb, dL/ddepth (the sign, zero at a tie).  The
+ * paper's weights: lambda_I1 = 0.2 (times lambda_rgb) and lambda_d = 0.1; its
+ * SSIM term is not computed here.  Device arrays: rgb, rgb_obs [n, 3], depth,
+ * depth_obs [n]; outputs loss [1], d_rgb [n, 3], d_depth [n] (overwritten).
+ * Workspace: lam_rgbd_l1_workspace_size bytes.  Deterministic.
+ * Errors: LAM_ERR_INVALID_ARG (null pointers, n < 0, a negative weight,
+ * workspace too small), LAM_ERR_HIP. */
+lam_status lam_rgbd_l1_workspace_size(int n, uint64_t* bytes);
+lam_status lam_rgbd_l1_loss(const float* rgb, const float* rgb_obs, const float* depth, const float* depth_obs,
+                            int n, float lambda_rgb, float lambda_depth, float* loss, float* d_rgb,
+                            float* d_depth, void* ws, uint64_t ws_bytes, void* stream);
 
 /* How the compositing kernels (forward and backward) walk the tiles,
  * process-wide: 0 = one workgroup per tile; 1 = persistent: as many
@@ -318,7 +359,7 @@ lam_status lam_stream_kmeans(int precision, const float* F, int n, int D, const 
 /* Turns per-kernel timing on or off (process-wide, off by default).  While on,
  * the main kernels (names: "raster_fwd", "raster_bwd", "decode_rows",
  * "decode_tn", "render_sort", "preprocess", "preprocess_bwd", "tied_prep",
- * "tied_grads", "kmeans") are bracketed by
+ * "tied_grads", "kmeans", "rgbd_l1") are bracketed by
  * HIP events recorded on their launch stream.  Not for use under graph capture. */
 lam_status lam_profile_enable(int on);
 

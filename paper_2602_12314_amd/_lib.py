@@ -67,6 +67,12 @@ def lib():
             "lam_decode_tied_workspace_size": (i32, [i32, i32, i32, i32, i32, pu64]),
             "lam_decode_tied_loss": (i32, [i32, vp, i32, i32, vp, vp, i32, i32, vp, vp, C.POINTER(TiedParams),
                                            vp, vp, vp, vp, vp, u64, vp]),
+            "lam_render_rgbd_forward": (i32, [vp, vp, vp, vp, vp, vp, i32, i32, vp, i32, i32, i32, vp, vp, vp,
+                                              vp, vp, u64, u64, vp]),
+            "lam_render_rgbd_backward": (i32, [vp, vp, vp, vp, vp, vp, i32, i32, vp, i32, i32, i32, vp, vp, vp,
+                                               vp, vp, vp, vp, vp, vp, vp, u64, u64, vp]),
+            "lam_rgbd_l1_workspace_size": (i32, [i32, pu64]),
+            "lam_rgbd_l1_loss": (i32, [vp, vp, vp, vp, i32, f32, f32, vp, vp, vp, vp, u64, vp]),
             "lam_kmeans_workspace_size": (i32, [i32, i32, i32, i32, pu64]),
             "lam_kmeans_assign": (i32, [i32, vp, i32, i32, vp, i32, vp, vp, vp, u64, vp]),
             "lam_kmeans_lloyd": (i32, [i32, vp, vp, i32, i32, vp, i32, i32, vp, vp, vp, vp, u64, vp]),
@@ -146,6 +152,43 @@ def render_backward(g, cams, tile_w, tile_h, dQ, grads, ws, capacity, stream=Non
                                     _p(grads.opacity_logits), _p(grads.queries), _p(ws),
                                     ws.numel() * ws.element_size(), capacity, _stream(stream)),
           "lam_render_backward")
+
+
+def render_rgbd_forward(g, colors, cams, tile_w, tile_h, Q, rgb, depth, T_final, ws, capacity, stream=None):
+    cams = _cams(cams)
+    check(lib().lam_render_rgbd_forward(_p(g.means), _p(g.log_scales), _p(g.quats), _p(g.opacity_logits),
+                                        _p(g.queries), _p(colors), g.means.shape[0], g.queries.shape[1],
+                                        cams.ctypes.data_as(C.c_void_p), cams.shape[0], tile_w, tile_h,
+                                        _p(Q), _p(rgb), _p(depth), _p(T_final), _p(ws),
+                                        ws.numel() * ws.element_size(), capacity, _stream(stream)),
+          "lam_render_rgbd_forward")
+
+
+def render_rgbd_backward(g, colors, cams, tile_w, tile_h, dQ, d_rgb, d_depth, grads, d_colors, ws, capacity,
+                         stream=None):
+    cams = _cams(cams)
+    check(lib().lam_render_rgbd_backward(_p(g.means), _p(g.log_scales), _p(g.quats), _p(g.opacity_logits),
+                                         _p(g.queries), _p(colors), g.means.shape[0], g.queries.shape[1],
+                                         cams.ctypes.data_as(C.c_void_p), cams.shape[0], tile_w, tile_h,
+                                         _p(dQ), _p(d_rgb), _p(d_depth), _p(grads.means),
+                                         _p(grads.log_scales), _p(grads.quats), _p(grads.opacity_logits),
+                                         _p(grads.queries), _p(d_colors), _p(ws),
+                                         ws.numel() * ws.element_size(), capacity, _stream(stream)),
+          "lam_render_rgbd_backward")
+
+
+def rgbd_l1_workspace_size(n) -> int:
+    out = C.c_uint64()
+    check(lib().lam_rgbd_l1_workspace_size(int(n), C.byref(out)), "lam_rgbd_l1_workspace_size")
+    return int(out.value)
+
+
+def rgbd_l1_loss(rgb, rgb_obs, depth, depth_obs, lambda_rgb, lambda_depth, loss, d_rgb, d_depth, ws,
+                 stream=None):
+    check(lib().lam_rgbd_l1_loss(_p(rgb), _p(rgb_obs), _p(depth), _p(depth_obs), depth.shape[0],
+                                 float(lambda_rgb), float(lambda_depth), _p(loss), _p(d_rgb), _p(d_depth),
+                                 _p(ws), ws.numel() * ws.element_size(), _stream(stream)),
+          "lam_rgbd_l1_loss")
 
 
 def render_counters(ws, stream=None):

@@ -116,6 +116,7 @@ lam_status render_layout(int n_gauss, int d, const float* cams, int n_cams, int 
     L->n_contrib = (uint32_t*)take(pixels * 4);
     L->t_final = (float*)take(pixels * 4);
     L->rec_grad = (float*)take(R * 24);
+    L->rec_dz = (float*)take(R * 4);
     L->bytes = off;
     return LAM_OK;
 }
@@ -241,6 +242,85 @@ lam_status lam_render_backward(const float* means, const float* log_scales, cons
     A.d_quats = d_quats;
     A.d_logits = d_opacity_logits;
     A.d_queries = d_queries;
+    hipError_t e = render_backward_launch(A, L, (hipStream_t)stream);
+    return e == hipSuccess ? LAM_OK : LAM_ERR_HIP;
+}
+
+lam_status lam_render_rgbd_forward(const float* means, const float* log_scales, const float* quats,
+                                   const float* opacity_logits, const float* queries, const float* colors,
+                                   int n_gauss, int d, const float* cams, int n_cams, int tile_w, int tile_h,
+                                   float* Q, float* rgb, float* depth, float* T_final, void* ws,
+                                   uint64_t ws_bytes, uint64_t instance_capacity, void* stream)
+{
+    lam_status s = check_gauss(means, log_scales, quats, opacity_logits, queries, n_gauss);
+    if (s != LAM_OK) return s;
+    if (!ptr_ok(colors, n_gauss)) return LAM_ERR_INVALID_ARG;
+    RenderLayout L;
+    s = render_layout(n_gauss, d, cams, n_cams, tile_w, tile_h, instance_capacity, ws, &L);
+    if (s != LAM_OK) return s;
+    if (!ws || ws_bytes < L.bytes) return LAM_ERR_INVALID_ARG;
+    if (!ptr_ok(Q, L.pixels) || !ptr_ok(T_final, L.pixels) || !ptr_ok(rgb, L.pixels) ||
+        !ptr_ok(depth, L.pixels))
+        return LAM_ERR_INVALID_ARG;
+    if (!aligned16(Q) || !aligned16(queries)) return LAM_ERR_INVALID_ARG;
+    RenderArgs A{};
+    A.n = n_gauss;
+    A.d = d;
+    A.means = means;
+    A.log_scales = log_scales;
+    A.quats = quats;
+    A.logits = opacity_logits;
+    A.queries = queries;
+    A.Q = Q;
+    A.T_final = T_final;
+    A.rgbd = true;
+    A.colors = colors;
+    A.rgb = rgb;
+    A.depth = depth;
+    hipError_t e = render_forward_launch(A, L, (hipStream_t)stream);
+    return e == hipSuccess ? LAM_OK : LAM_ERR_HIP;
+}
+
+lam_status lam_render_rgbd_backward(const float* means, const float* log_scales, const float* quats,
+                                    const float* opacity_logits, const float* queries, const float* colors,
+                                    int n_gauss, int d, const float* cams, int n_cams, int tile_w, int tile_h,
+                                    const float* dQ, const float* d_rgb, const float* d_depth, float* d_means,
+                                    float* d_log_scales, float* d_quats, float* d_opacity_logits,
+                                    float* d_queries, float* d_colors, void* ws, uint64_t ws_bytes,
+                                    uint64_t instance_capacity, void* stream)
+{
+    lam_status s = check_gauss(means, log_scales, quats, opacity_logits, queries, n_gauss);
+    if (s != LAM_OK) return s;
+    if (!ptr_ok(colors, n_gauss) || !ptr_ok(d_colors, n_gauss)) return LAM_ERR_INVALID_ARG;
+    if (!ptr_ok(d_means, n_gauss) || !ptr_ok(d_log_scales, n_gauss) || !ptr_ok(d_quats, n_gauss) ||
+        !ptr_ok(d_opacity_logits, n_gauss) || !ptr_ok(d_queries, n_gauss))
+        return LAM_ERR_INVALID_ARG;
+    RenderLayout L;
+    s = render_layout(n_gauss, d, cams, n_cams, tile_w, tile_h, instance_capacity, ws, &L);
+    if (s != LAM_OK) return s;
+    if (!ws || ws_bytes < L.bytes) return LAM_ERR_INVALID_ARG;
+    if (!ptr_ok(dQ, L.pixels) || !ptr_ok(d_rgb, L.pixels) || !ptr_ok(d_depth, L.pixels))
+        return LAM_ERR_INVALID_ARG;
+    if (!aligned16(dQ) || !aligned16(queries)) return LAM_ERR_INVALID_ARG;
+    RenderArgs A{};
+    A.n = n_gauss;
+    A.d = d;
+    A.means = means;
+    A.log_scales = log_scales;
+    A.quats = quats;
+    A.logits = opacity_logits;
+    A.queries = queries;
+    A.dQ = dQ;
+    A.d_means = d_means;
+    A.d_log_scales = d_log_scales;
+    A.d_quats = d_quats;
+    A.d_logits = d_opacity_logits;
+    A.d_queries = d_queries;
+    A.rgbd = true;
+    A.colors = colors;
+    A.d_rgb = d_rgb;
+    A.d_depth = d_depth;
+    A.d_colors = d_colors;
     hipError_t e = render_backward_launch(A, L, (hipStream_t)stream);
     return e == hipSuccess ? LAM_OK : LAM_ERR_HIP;
 }

@@ -40,6 +40,13 @@ struct RenderArgs {
     const float* dQ;      // backward input
     const float* T_final_in;  // backward: transmittance saved in the workspace
     float *d_means, *d_log_scales, *d_quats, *d_logits, *d_queries;
+    // colour and depth (Sec. III-A), rendered when rgbd: colors [N, 3] in,
+    // rgb [P, 3] and depth [P] out; d_rgb, d_depth in, d_colors out
+    bool rgbd = false;
+    const float* colors = nullptr;
+    float *rgb = nullptr, *depth = nullptr;
+    const float *d_rgb = nullptr, *d_depth = nullptr;
+    float* d_colors = nullptr;
 };
 
 // Workspace carve-up (all pointers into the caller's buffer).
@@ -62,6 +69,7 @@ struct RenderLayout {
     uint32_t* n_contrib;
     float* t_final;
     float* rec_grad;
+    float* rec_dz;  // per-record gradient of the rendered depth
 };
 
 hipError_t render_forward_launch(const RenderArgs& A, const RenderLayout& L, hipStream_t st);

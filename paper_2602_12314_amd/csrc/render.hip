@@ -201,22 +201,37 @@ __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ key
 
 constexpr int kChunk = 256;
 
-template <int DQ>
+// RGBD: each staged entry also carries (colour r, g, b, camera-space depth z)
+// of its record, blended with the same weights as the query (Eq. 2: colour;
+// depth by the same alpha blending).
+template <int DQ, bool RGBD>
 struct TileStage {
     float4 r0[kChunk];
     float4 r1[kChunk];
     uint2 fp[kChunk];
     uint32_t rec[kChunk];
     float q[kChunk * DQ];
+    float4 x[RGBD ? kChunk : 1];
 };
 
-template <int DQ>
-__device__ inline void stage_chunk(TileStage<DQ>& st, int k, uint32_t end, int base_tile_c,
+// Colour and depth of one record; the depth is the float32 camera-space z the
+// depth sort keys hold (positive, so its bits are the key).
+__device__ inline float4 rgbz(const float* __restrict__ colors, const uint32_t* __restrict__ depth_key,
+                              uint32_t r, uint32_t g)
+{
+    return make_float4(colors[3 * (size_t)g], colors[3 * (size_t)g + 1], colors[3 * (size_t)g + 2],
+                       __uint_as_float(depth_key[r]));
+}
+
+template <int DQ, bool RGBD>
+__device__ inline void stage_chunk(TileStage<DQ, RGBD>& st, int k, uint32_t end, int base_tile_c,
                                    int N, const uint32_t* __restrict__ tile_recs,
                                    const float4* __restrict__ rec0,
                                    const float4* __restrict__ rec1,
                                    const uint2* __restrict__ foot,
-                                   const float* __restrict__ queries)
+                                   const float* __restrict__ queries,
+                                   const float* __restrict__ colors,
+                                   const uint32_t* __restrict__ depth_key)
 {
     const int t = threadIdx.x;
     if ((uint32_t)k < end) {
@@ -230,16 +245,18 @@ __device__ inline void stage_chunk(TileStage<DQ>& st, int k, uint32_t end, int b
         float4* qd = reinterpret_cast<float4*>(st.q + t * DQ);
 #pragma unroll
         for (int j = 0; j < DQ / 4; ++j) qd[j] = qs[j];
+        if constexpr (RGBD) st.x[t] = rgbz(colors, depth_key, r, g);
     }
 }
 
-template <int DQ>
+template <int DQ, bool RGBD>
 __device__ inline void raster_fwd_tile(
-    TileStage<DQ>& st, const int tile, const CamSet& cs, int N, const uint2* __restrict__ ranges,
+    TileStage<DQ, RGBD>& st, const int tile, const CamSet& cs, int N, const uint2* __restrict__ ranges,
     const uint32_t* __restrict__ tile_recs, const float4* __restrict__ rec0,
     const float4* __restrict__ rec1, const uint2* __restrict__ foot,
     const float* __restrict__ queries, float* __restrict__ Q, float* __restrict__ T_final,
-    float* __restrict__ T_save, uint32_t* __restrict__ n_contrib)
+    float* __restrict__ T_save, uint32_t* __restrict__ n_contrib, const float* __restrict__ colors,
+    const uint32_t* __restrict__ depth_key, float* __restrict__ rgb, float* __restrict__ depth)
 {
     const int c = cam_of_tile(cs, tile);
     const Cam& cam = cs.c[c];
@@ -253,6 +270,7 @@ __device__ inline void raster_fwd_tile(
     float acc[DQ];
 #pragma unroll
     for (int j = 0; j < DQ; ++j) acc[j] = 0.0f;
+    float4 accx = make_float4(0.f, 0.f, 0.f, 0.f);
     float T = 1.0f;
     uint32_t last = 0;
     bool done = !inside;
@@ -262,8 +280,8 @@ __device__ inline void raster_fwd_tile(
     const uint32_t chunk = blockDim.x;
     for (uint32_t base = rg.x; base < rg.y; base += chunk) {
         if (__syncthreads_count(done) == (int)blockDim.x) break;
-        stage_chunk<DQ>(st, (int)(base + threadIdx.x), rg.y, c, N, tile_recs, rec0, rec1, foot,
-                        queries);
+        stage_chunk<DQ, RGBD>(st, (int)(base + threadIdx.x), rg.y, c, N, tile_recs, rec0, rec1, foot,
+                              queries, colors, depth_key);
         __syncthreads();
         const int cnt = (int)min(chunk, rg.y - base);
         for (int j = 0; j < cnt && !done; ++j) {
@@ -288,6 +306,13 @@ __device__ inline void raster_fwd_tile(
             const float* q = st.q + j * DQ;
 #pragma unroll
             for (int k = 0; k < DQ; ++k) acc[k] += wgt * q[k];
+            if constexpr (RGBD) {
+                const float4 x = st.x[j];
+                accx.x += wgt * x.x;
+                accx.y += wgt * x.y;
+                accx.z += wgt * x.z;
+                accx.w += wgt * x.w;
+            }
             T = Tn;
             last = base - rg.x + j + 1;
         }
@@ -301,24 +326,31 @@ __device__ inline void raster_fwd_tile(
         T_final[p] = T;
         T_save[p] = T;
         n_contrib[p] = last;
+        if constexpr (RGBD) {
+            rgb[3 * p] = accx.x;
+            rgb[3 * p + 1] = accx.y;
+            rgb[3 * p + 2] = accx.z;
+            depth[p] = accx.w;
+        }
     }
 }
 
 // PERSIST = false: one workgroup per tile.  PERSIST = true: a grid of resident
 // workgroups takes tiles from the queue counter until all are done, which
 // evens out views of uneven size and tiles of uneven list length.
-template <int DQ, bool PERSIST>
+template <int DQ, bool PERSIST, bool RGBD>
 __global__ __launch_bounds__(256) void k_raster_fwd(
     CamSet cs, int N, const uint2* __restrict__ ranges, const uint32_t* __restrict__ tile_recs,
     const float4* __restrict__ rec0, const float4* __restrict__ rec1,
     const uint2* __restrict__ foot, const float* __restrict__ queries, float* __restrict__ Q,
     float* __restrict__ T_final, float* __restrict__ T_save, uint32_t* __restrict__ n_contrib,
-    uint32_t* __restrict__ queue)
+    uint32_t* __restrict__ queue, const float* __restrict__ colors,
+    const uint32_t* __restrict__ depth_key, float* __restrict__ rgb, float* __restrict__ depth)
 {
-    __shared__ TileStage<DQ> st;
+    __shared__ TileStage<DQ, RGBD> st;
     if (!PERSIST) {
-        raster_fwd_tile<DQ>(st, blockIdx.x, cs, N, ranges, tile_recs, rec0, rec1, foot, queries, Q,
-                            T_final, T_save, n_contrib);
+        raster_fwd_tile<DQ, RGBD>(st, blockIdx.x, cs, N, ranges, tile_recs, rec0, rec1, foot, queries, Q,
+                                  T_final, T_save, n_contrib, colors, depth_key, rgb, depth);
         return;
     }
     __shared__ int s_tile;
@@ -328,8 +360,8 @@ __global__ __launch_bounds__(256) void k_raster_fwd(
         __syncthreads();
         const int tile = __builtin_amdgcn_readfirstlane(s_tile);
         if (tile >= cs.total_tiles) break;
-        raster_fwd_tile<DQ>(st, tile, cs, N, ranges, tile_recs, rec0, rec1, foot, queries, Q, T_final,
-                            T_save, n_contrib);
+        raster_fwd_tile<DQ, RGBD>(st, tile, cs, N, ranges, tile_recs, rec0, rec1, foot, queries, Q, T_final,
+                                  T_save, n_contrib, colors, depth_key, rgb, depth);
     }
 }
 
@@ -354,15 +386,19 @@ __device__ inline void halving_sum(float* v, unsigned lane)
     }
 }
 
-// rec_grad[r] = (du, dv, dA, dB, dC, dopacity) accumulated over pixels.
-template <int DQ>
+// rec_grad[r] = (du, dv, dA, dB, dC, dopacity) accumulated over pixels; with
+// RGBD also d_colors[g] and rec_dz[r] (the gradient of the record's depth).
+template <int DQ, bool RGBD>
 __device__ inline void raster_bwd_tile(
-    TileStage<DQ>& st, uint32_t& s_max, const int tile, const CamSet& cs, int N,
+    TileStage<DQ, RGBD>& st, uint32_t& s_max, const int tile, const CamSet& cs, int N,
     const uint2* __restrict__ ranges, const uint32_t* __restrict__ tile_recs,
     const float4* __restrict__ rec0, const float4* __restrict__ rec1,
     const uint2* __restrict__ foot, const float* __restrict__ queries,
     const float* __restrict__ T_final, const uint32_t* __restrict__ n_contrib,
-    const float* __restrict__ dQ, float* __restrict__ rec_grad, float* __restrict__ d_queries)
+    const float* __restrict__ dQ, float* __restrict__ rec_grad, float* __restrict__ d_queries,
+    const float* __restrict__ colors, const uint32_t* __restrict__ depth_key,
+    const float* __restrict__ d_rgb, const float* __restrict__ d_depth, float* __restrict__ d_colors,
+    float* __restrict__ rec_dz)
 {
     const int c = cam_of_tile(cs, tile);
     const Cam& cam = cs.c[c];
@@ -375,10 +411,12 @@ __device__ inline void raster_bwd_tile(
     const unsigned lane = __lane_id();
 
     float g[DQ], behind[DQ];
+    float4 gx = make_float4(0.f, 0.f, 0.f, 0.f), behindx = gx;
     float T = 1.0f;
     uint32_t last = 0;
     if (inside) {
         const size_t p = (size_t)cam.pix_base + (size_t)py * cam.w + px;
+        if constexpr (RGBD) gx = make_float4(d_rgb[3 * p], d_rgb[3 * p + 1], d_rgb[3 * p + 2], d_depth[p]);
         const float4* gi = reinterpret_cast<const float4*>(dQ + p * DQ);
 #pragma unroll
         for (int k = 0; k < DQ / 4; ++k) {
@@ -404,8 +442,8 @@ __device__ inline void raster_bwd_tile(
     for (int end = (int)maxlast; end > 0; end -= chunk) {
         const int start = end > chunk ? end - chunk : 0;
         __syncthreads();
-        stage_chunk<DQ>(st, (int)(rg.x + start + threadIdx.x), rg.x + end, c, N, tile_recs, rec0,
-                        rec1, foot, queries);
+        stage_chunk<DQ, RGBD>(st, (int)(rg.x + start + threadIdx.x), rg.x + end, c, N, tile_recs, rec0,
+                              rec1, foot, queries, colors, depth_key);
         __syncthreads();
         for (int j = end - 1; j >= start; --j) {
             const int sj = j - start;
@@ -434,6 +472,15 @@ __device__ inline void raster_bwd_tile(
                             dal += (q[k] - behind[k]) * g[k];
                             behind[k] = al * q[k] + (1.0f - al) * behind[k];
                         }
+                        if constexpr (RGBD) {
+                            const float4 x = st.x[sj];
+                            dal += (x.x - behindx.x) * gx.x + (x.y - behindx.y) * gx.y +
+                                   (x.z - behindx.z) * gx.z + (x.w - behindx.w) * gx.w;
+                            behindx.x = al * x.x + (1.0f - al) * behindx.x;
+                            behindx.y = al * x.y + (1.0f - al) * behindx.y;
+                            behindx.z = al * x.z + (1.0f - al) * behindx.z;
+                            behindx.w = al * x.w + (1.0f - al) * behindx.w;
+                        }
                         dal *= T;
                         if (oG < kAlphaMax) {
                             const float dp = dal * oG;
@@ -448,45 +495,60 @@ __device__ inline void raster_bwd_tile(
                 }
             }
             if (__ballot(hit) == 0ull) continue;
-            // 6 screen-space terms and DQ query terms, padded to NV, summed over the
-            // wave by halving: at each step a lane keeps half of its values and adds
-            // the partner's copy of that half, so after log2(64) steps lane l holds
-            // the total of value (l >> 1) (NV = 32) or l (NV = 64).
-            constexpr int NV = (6 + DQ <= 32) ? 32 : 64;
+            // 6 screen-space terms, DQ query terms (and with RGBD 3 colour terms
+            // and the depth term), padded to NV, summed over the wave by halving:
+            // at each step a lane keeps half of its values and adds the partner's
+            // copy of that half, so after log2(64) steps lane l holds the total of
+            // value (l >> 1) (NV = 32) or l (NV = 64).
+            constexpr int NX = RGBD ? 4 : 0;
+            constexpr int NT = 6 + DQ + NX;
+            constexpr int NV = (NT <= 32) ? 32 : 64;
             float v[NV];
             v[0] = gu; v[1] = gv; v[2] = gA; v[3] = gB; v[4] = gC; v[5] = gO;
 #pragma unroll
             for (int k = 0; k < DQ; ++k) v[6 + k] = wq * g[k];
+            if constexpr (RGBD) {
+                v[6 + DQ] = wq * gx.x;
+                v[7 + DQ] = wq * gx.y;
+                v[8 + DQ] = wq * gx.z;
+                v[9 + DQ] = wq * gx.w;
+            }
 #pragma unroll
-            for (int k = 6 + DQ; k < NV; ++k) v[k] = 0.0f;
+            for (int k = NT; k < NV; ++k) v[k] = 0.0f;
             halving_sum<NV, 32>(v, lane);
             if (NV == 32) v[0] += __shfl_xor(v[0], 1, kWave);
             const int idx = NV == 32 ? (int)(lane >> 1) : (int)lane;
-            const bool owner = (NV == 64 || (lane & 1) == 0) && idx < 6 + DQ && v[0] != 0.0f;
+            const bool owner = (NV == 64 || (lane & 1) == 0) && idx < NT && v[0] != 0.0f;
             if (owner) {
                 const uint32_t r = st.rec[sj];
+                const size_t gi = (size_t)(r - (uint32_t)c * (uint32_t)N);
                 float* dst = idx < 6 ? rec_grad + (size_t)r * 6 + idx
-                                     : d_queries + (size_t)(r - (uint32_t)c * (uint32_t)N) * DQ + (idx - 6);
+                           : idx < 6 + DQ ? d_queries + gi * DQ + (idx - 6)
+                           : idx < 9 + DQ ? d_colors + gi * 3 + (idx - 6 - DQ)
+                                          : rec_dz + r;
                 unsafeAtomicAdd(dst, v[0]);
             }
         }
     }
 }
 
-template <int DQ, bool PERSIST>
+template <int DQ, bool PERSIST, bool RGBD>
 __global__ __launch_bounds__(256) void k_raster_bwd(
     CamSet cs, int N, const uint2* __restrict__ ranges, const uint32_t* __restrict__ tile_recs,
     const float4* __restrict__ rec0, const float4* __restrict__ rec1,
     const uint2* __restrict__ foot, const float* __restrict__ queries,
     const float* __restrict__ T_final, const uint32_t* __restrict__ n_contrib,
     const float* __restrict__ dQ, float* __restrict__ rec_grad, float* __restrict__ d_queries,
-    uint32_t* __restrict__ queue)
+    uint32_t* __restrict__ queue, const float* __restrict__ colors,
+    const uint32_t* __restrict__ depth_key, const float* __restrict__ d_rgb,
+    const float* __restrict__ d_depth, float* __restrict__ d_colors, float* __restrict__ rec_dz)
 {
-    __shared__ TileStage<DQ> st;
+    __shared__ TileStage<DQ, RGBD> st;
     __shared__ uint32_t s_max;
     if (!PERSIST) {
-        raster_bwd_tile<DQ>(st, s_max, blockIdx.x, cs, N, ranges, tile_recs, rec0, rec1, foot, queries,
-                            T_final, n_contrib, dQ, rec_grad, d_queries);
+        raster_bwd_tile<DQ, RGBD>(st, s_max, blockIdx.x, cs, N, ranges, tile_recs, rec0, rec1, foot, queries,
+                                  T_final, n_contrib, dQ, rec_grad, d_queries, colors, depth_key, d_rgb,
+                                  d_depth, d_colors, rec_dz);
         return;
     }
     __shared__ int s_tile;
@@ -496,21 +558,24 @@ __global__ __launch_bounds__(256) void k_raster_bwd(
         __syncthreads();
         const int tile = __builtin_amdgcn_readfirstlane(s_tile);
         if (tile >= cs.total_tiles) break;
-        raster_bwd_tile<DQ>(st, s_max, tile, cs, N, ranges, tile_recs, rec0, rec1, foot, queries,
-                            T_final, n_contrib, dQ, rec_grad, d_queries);
+        raster_bwd_tile<DQ, RGBD>(st, s_max, tile, cs, N, ranges, tile_recs, rec0, rec1, foot, queries,
+                                  T_final, n_contrib, dQ, rec_grad, d_queries, colors, depth_key, d_rgb,
+                                  d_depth, d_colors, rec_dz);
     }
 }
 
 // ------------------------------------------------------ preprocess adjoint
 
 // Chains rec_grad of every camera back to the raw parameters of Gaussian i
-// (FP32, matrix form of the chain rule).  Outputs are overwritten.
+// (FP32, matrix form of the chain rule), and rec_dz (nullable: the gradient of
+// each record's rendered depth z = row 3 of the view transform applied to the
+// mean) to the mean.  Outputs are overwritten.
 __global__ __launch_bounds__(256) void k_preprocess_bwd(
     CamSet cs, int N, const float* __restrict__ means, const float* __restrict__ log_scales,
     const float* __restrict__ quats, const float* __restrict__ logits,
     const uint32_t* __restrict__ ntiles, const float* __restrict__ rec_grad,
-    float* __restrict__ d_means, float* __restrict__ d_log_scales, float* __restrict__ d_quats,
-    float* __restrict__ d_logits)
+    const float* __restrict__ rec_dz, float* __restrict__ d_means, float* __restrict__ d_log_scales,
+    float* __restrict__ d_quats, float* __restrict__ d_logits)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
@@ -601,6 +666,7 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
         gz += (GJ[0][2] * cam.fx * tx + GJ[1][2] * cam.fy * ty) * iz * iz;
         if (inx) { gx += -GJ[0][2] * cam.fx * iz * iz; gz += GJ[0][2] * cam.fx * cx * iz * iz * iz; }
         if (iny) { gy += -GJ[1][2] * cam.fy * iz * iz; gz += GJ[1][2] * cam.fy * cy * iz * iz * iz; }
+        if (rec_dz) gz += rec_dz[r];
         for (int k = 0; k < 3; ++k) gmean[k] += W[0][k] * gx + W[1][k] * gy + W[2][k] * gz;
     }
     // S3 = M M^T: G_M = 2 G_S3 M ; M = R diag(s)
@@ -713,8 +779,11 @@ hipError_t render_forward_launch(const RenderArgs& A, const RenderLayout& L, hip
     if (cs.total_tiles > 0) {
         const bool pers = use_persistent(cs);
         const int threads = cs.tile_w * cs.tile_h;
-        auto kern = A.d == 16 ? (pers ? k_raster_fwd<16, true> : k_raster_fwd<16, false>)
-                              : (pers ? k_raster_fwd<32, true> : k_raster_fwd<32, false>);
+        const bool rgbd = A.rgbd;
+        auto kern = rgbd ? (A.d == 16 ? (pers ? k_raster_fwd<16, true, true> : k_raster_fwd<16, false, true>)
+                                      : (pers ? k_raster_fwd<32, true, true> : k_raster_fwd<32, false, true>))
+                         : (A.d == 16 ? (pers ? k_raster_fwd<16, true, false> : k_raster_fwd<16, false, false>)
+                                      : (pers ? k_raster_fwd<32, true, false> : k_raster_fwd<32, false, false>));
         int grid = cs.total_tiles;
         if (pers) {
             e = launch_fill_u32(L.counters + 2, 1, 0u, st);
@@ -724,7 +793,8 @@ hipError_t render_forward_launch(const RenderArgs& A, const RenderLayout& L, hip
         ProfScope ps("raster_fwd", st);
         hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), 0, st, cs, A.n, (const uint2*)L.ranges,
                            trecs, (const float4*)L.rec0, (const float4*)L.rec1, (const uint2*)L.foot,
-                           A.queries, A.Q, A.T_final, L.t_final, L.n_contrib, L.counters + 2);
+                           A.queries, A.Q, A.T_final, L.t_final, L.n_contrib, L.counters + 2, A.colors,
+                           (const uint32_t*)L.depth_key, A.rgb, A.depth);
     }
     return hipGetLastError();
 }
@@ -737,12 +807,20 @@ hipError_t render_backward_launch(const RenderArgs& A, const RenderLayout& L, hi
     if (e != hipSuccess) return e;
     e = launch_fill_u32(reinterpret_cast<uint32_t*>(A.d_queries), (size_t)A.n * A.d, 0u, st);
     if (e != hipSuccess) return e;
+    const bool rgbd = A.rgbd;
+    if (rgbd) {
+        e = launch_fill_u32(reinterpret_cast<uint32_t*>(A.d_colors), (size_t)A.n * 3, 0u, st);
+        if (e == hipSuccess) e = launch_fill_u32(reinterpret_cast<uint32_t*>(L.rec_dz), (size_t)L.records, 0u, st);
+        if (e != hipSuccess) return e;
+    }
     const uint32_t* trecs = L.tile_in_b ? L.ivals_b : L.ivals_a;
     if (cs.total_tiles > 0) {
         const bool pers = use_persistent(cs);
         const int threads = cs.tile_w * cs.tile_h;
-        auto kern = A.d == 16 ? (pers ? k_raster_bwd<16, true> : k_raster_bwd<16, false>)
-                              : (pers ? k_raster_bwd<32, true> : k_raster_bwd<32, false>);
+        auto kern = rgbd ? (A.d == 16 ? (pers ? k_raster_bwd<16, true, true> : k_raster_bwd<16, false, true>)
+                                      : (pers ? k_raster_bwd<32, true, true> : k_raster_bwd<32, false, true>))
+                         : (A.d == 16 ? (pers ? k_raster_bwd<16, true, false> : k_raster_bwd<16, false, false>)
+                                      : (pers ? k_raster_bwd<32, true, false> : k_raster_bwd<32, false, false>));
         int grid = cs.total_tiles;
         if (pers) {
             e = launch_fill_u32(L.counters + 3, 1, 0u, st);
@@ -753,14 +831,15 @@ hipError_t render_backward_launch(const RenderArgs& A, const RenderLayout& L, hi
         hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), 0, st, cs, A.n, (const uint2*)L.ranges,
                            trecs, (const float4*)L.rec0, (const float4*)L.rec1, (const uint2*)L.foot,
                            A.queries, (const float*)L.t_final, (const uint32_t*)L.n_contrib, A.dQ,
-                           L.rec_grad, A.d_queries, L.counters + 3);
+                           L.rec_grad, A.d_queries, L.counters + 3, A.colors, (const uint32_t*)L.depth_key,
+                           A.d_rgb, A.d_depth, A.d_colors, L.rec_dz);
     }
     if (A.n > 0) {
         ProfScope ps("preprocess_bwd", st);
         hipLaunchKernelGGL(k_preprocess_bwd, dim3((A.n + 255) / 256), dim3(256), 0, st, cs, A.n,
                            A.means, A.log_scales, A.quats, A.logits, (const uint32_t*)L.ntiles,
-                           (const float*)L.rec_grad, A.d_means, A.d_log_scales, A.d_quats,
-                           A.d_logits);
+                           (const float*)L.rec_grad, rgbd ? (const float*)L.rec_dz : nullptr, A.d_means,
+                           A.d_log_scales, A.d_quats, A.d_logits);
     }
     return hipGetLastError();
 }

@@ -10,6 +10,9 @@
 - ``TiedDecoder``: the paper's tied decode and full feature loss (Eq. 5-6:
   cosine logits of Q W against the atoms D at temperature tau, V = D, and the
   cosine, L2 and hinge trust-region terms) with gradients to Q, W and D.
+- ``Renderer.forward_rgbd`` / ``backward_rgbd`` and ``rgbd_l1_loss``: colour
+  and depth blended in the same pass as the queries (Sec. III-A) and the L1
+  colour and depth terms of the mapping objective (Eq. 7-9).
 - ``StreamKMeans``: the dictionary initialisation of Eq. 10 (weighted
   micro-centres of the keyframe's embeddings, merged with the weighted global
   centres and re-clustered to K), plus plain ``assign`` / ``lloyd`` calls.
@@ -115,6 +118,36 @@ class Renderer:
         _lib.render_backward(gg, self.cams, self.tile_w, self.tile_h, _contig(dQ), out, self.ws,
                              self.capacity)
         return out
+
+    def forward_rgbd(self, g: Gaussians, colors, check: bool = True):
+        """Q, rgb [P, 3], depth [P], T_final: the query map with colour and depth
+        blended in the same pass (Sec. III-A)."""
+        P = self.n_pixels
+        Q = torch.empty((P, self.d), dtype=torch.float32, device=self.device)
+        rgb = torch.empty((P, 3), dtype=torch.float32, device=self.device)
+        depth = torch.empty((P,), dtype=torch.float32, device=self.device)
+        T_final = torch.empty((P,), dtype=torch.float32, device=self.device)
+        gg = Gaussians(*[_contig(t) for t in g.tensors()])
+        colors = _contig(colors)
+        for _ in range(3):
+            _lib.render_rgbd_forward(gg, colors, self.cams, self.tile_w, self.tile_h, Q, rgb, depth, T_final,
+                                     self.ws, self.capacity)
+            if not check:
+                break
+            need, over = self.counters()
+            if not over:
+                break
+            self._alloc(int(need * self.headroom) + 4096)
+        return Q, rgb, depth, T_final
+
+    def backward_rgbd(self, g: Gaussians, colors, dQ, d_rgb, d_depth):
+        """Gradients (Gaussians, d_colors) for upstream dQ, d_rgb, d_depth."""
+        gg = Gaussians(*[_contig(t) for t in g.tensors()])
+        out = gg.zeros_like()
+        d_colors = torch.empty((self.n_gauss, 3), dtype=torch.float32, device=self.device)
+        _lib.render_rgbd_backward(gg, _contig(colors), self.cams, self.tile_w, self.tile_h, _contig(dQ),
+                                  _contig(d_rgb), _contig(d_depth), out, d_colors, self.ws, self.capacity)
+        return out, d_colors
 
     def debug_views(self):
         return _lib.render_debug_views(self.ws, self.n_gauss, self.d, self.cams, self.tile_w,
@@ -250,6 +283,21 @@ class TiedDecoder:
         _lib.decode_tied_loss(self.precision, _contig(Q), _contig(W), _contig(D), _contig(target), _contig(D0),
                               params, loss, dQ, dW, dD, self.ws)
         return loss, dQ, dW, dD
+
+
+PAPER_RGBD_WEIGHTS = dict(lambda_rgb=0.2, lambda_depth=0.1)  # lambda_I1 (lambda_rgb = 1) and lambda_d
+
+
+def rgbd_l1_loss(rgb, rgb_obs, depth, depth_obs, lambda_rgb=0.2, lambda_depth=0.1):
+    """(loss, d_rgb, d_depth) of the L1 colour and depth terms (Eq. 7-9)."""
+    rgb, rgb_obs, depth, depth_obs = (_contig(t) for t in (rgb, rgb_obs, depth, depth_obs))
+    dev = rgb.device
+    ws = torch.empty(_lib.rgbd_l1_workspace_size(depth.shape[0]), dtype=torch.uint8, device=dev)
+    loss = torch.empty(1, dtype=torch.float32, device=dev)
+    d_rgb = torch.empty_like(rgb)
+    d_depth = torch.empty_like(depth)
+    _lib.rgbd_l1_loss(rgb, rgb_obs, depth, depth_obs, lambda_rgb, lambda_depth, loss, d_rgb, d_depth, ws)
+    return loss, d_rgb, d_depth
 
 
 MICRO_FACTOR = 5  # micro-centres per global centre (the paper's "5 by default")
