@@ -231,6 +231,9 @@ def run(args):
     kmeans = None
     if not args.no_kmeans:
         kmeans = kmeans_leg(ops, prec, spec, tgt, dev)
+    rgbd = None
+    if not args.no_rgbd:
+        rgbd = rgbd_leg(ops, r, g, dec, K, V, tgt, K0, spec, dev, args.steps)
 
     out = {
         "metric": "feature-pixels/s fwd+bwd",
@@ -262,6 +265,7 @@ def run(args):
         "stage2": stage2,
         "tied_decode": tied,
         "stream_kmeans": kmeans,
+        "rgbd_step": rgbd,
     }
 
     # roofline of the dominant kernel, with algorithmic work from the oracle's pair counts
@@ -340,6 +344,45 @@ def tied_leg(ops, prec, spec, Q, V, tgt, dev, reps=10):
             "params": dict(ops.PAPER_TIED_PARAMS), "loss": float(loss)}
 
 
+def rgbd_leg(ops, r, g, dec, K, V, tgt, K0, spec, dev, steps, warmup=3):
+    """The Stage-I step with colour and depth supervision (Eq. 9 without its
+    SSIM term): query, colour and depth maps in one compositing pass, the decode
+    with the feature loss, the L1 colour and depth terms with the paper's
+    weights, and one backward pass through queries, colour and depth.  Colours
+    are seeded uniform; the observed image is uniform noise and the observed
+    depth the rendered depth plus noise with 10 % holes."""
+    import torch
+    n = spec.n_pixels
+    gen = torch.Generator(device=dev).manual_seed(11)
+    colors = torch.rand((spec.n_gauss, 3), device=dev, generator=gen)
+    _, rgb, depth, _ = r.forward_rgbd(g, colors)
+    rgb_obs = torch.rand(rgb.shape, device=dev, generator=gen)
+    depth_obs = depth + 0.05 * torch.randn(depth.shape, device=dev, generator=gen)
+    depth_obs[torch.rand(depth.shape, device=dev, generator=gen) < 0.1] = 0.0
+    w = ops.PAPER_RGBD_WEIGHTS
+
+    def step():
+        Q, rgb, depth, _ = r.forward_rgbd(g, colors, check=False)
+        lf, dQ, _, _ = dec.loss_and_grads(Q, K, V, tgt, K0, spec.lambda_tr)
+        lp, d_rgb, d_depth = ops.rgbd_l1_loss(rgb, rgb_obs, depth, depth_obs, w["lambda_rgb"],
+                                              w["lambda_depth"])
+        r.backward_rgbd(g, colors, dQ, d_rgb, d_depth)
+        return lf, lp
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    assert not r.counters()[1]
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        lf, lp = step()
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / steps
+    return {"ms": sec * 1e3, "value": n / sec,
+            "unit": "feature-pixels/s (queries, colour and depth rendered; feature and L1 colour/depth losses)",
+            "weights": dict(w), "loss_feature": float(lf), "loss_rgbd": float(lp)}
+
+
 def kmeans_leg(ops, prec, spec, tgt, dev, reps=3, iters=10):
     """The streaming K-means dictionary initialisation (Eq. 10) on this
     workload's embedding map: m = 5 K micro-centres from seeded random rows,
@@ -375,19 +418,23 @@ def kmeans_leg(ops, prec, spec, tgt, dev, reps=3, iters=10):
     a = torch.empty(n, dtype=torch.int32, device=dev)
     _lib.kmeans_assign(kprec, tgt, C, a, None, ws)
     torch.cuda.synchronize()
-    e0.record(st)
+    L = _lib.lib()
+    L.lam_profile_enable(1)
+    _read_prof(L, "kmeans_assign")
     for _ in range(10):
         _lib.kmeans_assign(kprec, tgt, C, a, None, ws)
-    e1.record(st)
     torch.cuda.synchronize()
-    amsec = e0.elapsed_time(e1) / 10
+    tot, cnt = _read_prof(L, "kmeans_assign")  # the distance kernel alone, HIP events on its stream
+    L.lam_profile_enable(0)
+    amsec = tot / max(cnt, 1)
     flops = 2.0 * n * m * Dd
     peak = PEAKS["fp32_mfma_tflops" if kprec == "fp32" else "bf16_tflops"]
     ach = flops / (amsec * 1e-3) / 1e12
     return {"ms": step_ms, "value": n / (step_ms * 1e-3), "unit": "embeddings/s (Eq. 10 streaming step)",
             "precision": kprec, "n": n, "D": Dd, "K": K, "micro": m, "iters_local": iters, "iters_global": iters,
             "assign": {"ms": amsec, "bound": "mfma", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
-                       "frac": ach / peak, "flops": flops}}
+                       "frac": ach / peak, "flops": flops, "bytes": 4.0 * n * Dd + 4.0 * n,
+                       "traffic": traffic_for("kmeans_assign", spec.name)}}
 
 
 def _read_prof(L, name):
@@ -467,6 +514,7 @@ def main():
     ap.add_argument("--no-stage2", action="store_true", help="skip the Stage-II decode-only leg")
     ap.add_argument("--no-tied", action="store_true", help="skip the tied-decode leg")
     ap.add_argument("--no-kmeans", action="store_true", help="skip the streaming K-means leg")
+    ap.add_argument("--no-rgbd", action="store_true", help="skip the colour + depth step leg")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (scales HBM byte counters)")
     args = ap.parse_args()

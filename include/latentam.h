@@ -359,7 +359,7 @@ lam_status lam_stream_kmeans(int precision, const float* F, int n, int D, const 
 /* Turns per-kernel timing on or off (process-wide, off by default).  While on,
  * the main kernels (names: "raster_fwd", "raster_bwd", "decode_rows",
  * "decode_tn", "render_sort", "preprocess", "preprocess_bwd", "tied_prep",
- * "tied_grads", "kmeans", "rgbd_l1") are bracketed by
+ * "tied_grads", "kmeans", "kmeans_assign", "rgbd_l1") are bracketed by
  * HIP events recorded on their launch stream.  Not for use under graph capture. */
 lam_status lam_profile_enable(int on);
 

@@ -34,7 +34,7 @@ typedef float f32x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-constexpr int kChunk = 256;     // sorted points per update chunk
+constexpr int kChunk = 128;     // sorted points per update chunk
 constexpr int kNcw = 2;         // 32-centre row blocks per wave step
 constexpr int kCentreAlign = 32 * kNcw;
 constexpr int kPipe = 4;        // centre fragments in flight per wave
@@ -381,7 +381,7 @@ __global__ __launch_bounds__(128) void k_km_chunks(const float* __restrict__ X, 
     for (int g = 0; g < CG; ++g) acc[g] = make_float4(0.f, 0.f, 0.f, 0.f);
     float wsum = 0.0f;
     int rs = 0;
-    constexpr int U = 8;
+    constexpr int U = 16;  // rows in flight per thread
     for (int i0 = 0; i0 < len; i0 += U) {
         float4 v[U][CG];
 #pragma unroll
@@ -575,6 +575,7 @@ static hipError_t launch_assign_np(const float* X, int n, int D, const typename 
     const int blocks = (n + 32 * NP - 1) / (32 * NP);
     const int nc = D / 16;
     const int slices = (kp + kSlice - 1) / kSlice;
+    ProfScope ps("kmeans_assign", st);
     for (int s = 0; s < slices; ++s) {
         const int kbase = s * kSlice, kcp = std::min(kSlice, kp - kbase);
         const bool last = s == slices - 1;

@@ -9,7 +9,7 @@
         mean value per dispatch of every counter of a ``--pmc`` run, by kernel.
 
     python -m paper_2602_12314_amd.profiling traffic --workload NAME \\
-            --fetch DIR --write DIR --copy-fetch DIR --copy-write DIR --copy-bytes N
+            --fetch DIR --write DIR --copy-fetch DIR --copy-write DIR --copy-bytes N [--only STAGES]
         HBM bytes per launch of each kernel from two ``--pmc FETCH_SIZE`` /
         ``--pmc WRITE_SIZE`` runs, each counter scaled by what it reads for a
         plain device copy of N bytes (``bench.py --copy-calibration N`` under the
@@ -40,6 +40,7 @@ STAGES = {
     "decode_tn": ("k_dec_dv", ["decode.hip", "common.h", "kernels.h"]),
     "raster_fwd": ("k_raster_fwd", ["render.hip", "common.h", "kernels.h"]),
     "raster_bwd": ("k_raster_bwd", ["render.hip", "common.h", "kernels.h"]),
+    "kmeans_assign": ("k_km_assign", ["kmeans.hip", "kmeans.h", "common.h", "kernels.h"]),
 }
 
 
@@ -53,7 +54,7 @@ def source_hash(files) -> str:
 
 
 def short(name: str) -> str:
-    name = name.replace("lam::", "").replace("void ", "")
+    name = name.replace("lam::", "").replace("km::", "").replace("void ", "")
     i = name.find("(")
     return name[:i] if i > 0 else name
 
@@ -71,13 +72,20 @@ def kernel_stats(d):
              float(r["AverageNs"]) / 1e3, float(r["Percentage"])) for r in rows]
 
 
-def counter_means(d, counter):
-    """Mean counter value per dispatch, by kernel."""
+def counter_means(d, counter, largest_grid=False):
+    """Mean counter value per dispatch, by kernel (with largest_grid, over the
+    dispatches of the kernel's largest grid only)."""
     acc = defaultdict(list)
     for r in csv.DictReader(open(_one(d, "*counter_collection.csv"))):
         if r.get("Counter_Name") == counter:
-            acc[short(r["Kernel_Name"])].append(float(r["Counter_Value"]))
-    return {k: sum(v) / len(v) for k, v in acc.items()}
+            acc[short(r["Kernel_Name"])].append((int(r.get("Grid_Size") or 0), float(r["Counter_Value"])))
+    out = {}
+    for k, v in acc.items():
+        if largest_grid:
+            gmax = max(g for g, _ in v)
+            v = [x for x in v if x[0] == gmax]
+        out[k] = sum(x for _, x in v) / len(v)
+    return out
 
 
 def copy_factor(d, counter, copy_bytes):
@@ -103,6 +111,9 @@ def main(argv=None):
         t.add_argument("--" + k, required=True)
     t.add_argument("--copy-bytes", type=int, required=True)
     t.add_argument("--json", default=None)
+    t.add_argument("--only", default=None, help="comma-separated stage names to record (default: all found)")
+    t.add_argument("--largest-grid", action="store_true",
+                   help="average only the dispatches of each kernel's largest grid")
     a = ap.parse_args(argv)
     if a.cmd == "stats":
         print("| kernel | calls | total us | avg us | % |")
@@ -121,8 +132,8 @@ def main(argv=None):
         return 0
     ff = copy_factor(a.copy_fetch, "FETCH_SIZE", a.copy_bytes)
     fw = copy_factor(a.copy_write, "WRITE_SIZE", a.copy_bytes)
-    fetch = counter_means(a.fetch, "FETCH_SIZE")
-    write = counter_means(a.write, "WRITE_SIZE")
+    fetch = counter_means(a.fetch, "FETCH_SIZE", a.largest_grid)
+    write = counter_means(a.write, "WRITE_SIZE", a.largest_grid)
     print(f"copy calibration: FETCH_SIZE x {ff:.3f}, WRITE_SIZE x {fw:.3f} "
           f"({a.copy_bytes} bytes copied per launch)")
     print("| kernel | FETCH_SIZE KiB | WRITE_SIZE KiB | HBM bytes per launch (scaled) |")
@@ -136,7 +147,10 @@ def main(argv=None):
         except (OSError, ValueError):
             rec = {}
         ent = rec.setdefault(a.workload, {})
+        only = set(a.only.split(",")) if a.only else None
         for stage, (prefix, files) in STAGES.items():
+            if only is not None and stage not in only:
+                continue
             ks = [k for k in set(fetch) & set(write) if k.startswith(prefix)]
             if len(ks) != 1:
                 continue
