@@ -345,9 +345,9 @@ def tied_leg(ops, prec, spec, Q, V, tgt, dev, reps=10):
 
 
 def rgbd_leg(ops, r, g, dec, K, V, tgt, K0, spec, dev, steps, warmup=3):
-    """The Stage-I step with colour and depth supervision (Eq. 9 without its
-    SSIM term): query, colour and depth maps in one compositing pass, the decode
-    with the feature loss, the L1 colour and depth terms with the paper's
+    """The Stage-I step with colour and depth supervision (Eq. 7-9): query,
+    colour and depth maps in one compositing pass, the decode with the feature
+    loss, the L1 colour and depth terms and the SSIM term with the paper's
     weights, and one backward pass through queries, colour and depth.  Colours
     are seeded uniform; the observed image is uniform noise and the observed
     depth the rendered depth plus noise with 10 % holes."""
@@ -366,8 +366,9 @@ def rgbd_leg(ops, r, g, dec, K, V, tgt, K0, spec, dev, steps, warmup=3):
         lf, dQ, _, _ = dec.loss_and_grads(Q, K, V, tgt, K0, spec.lambda_tr)
         lp, d_rgb, d_depth = ops.rgbd_l1_loss(rgb, rgb_obs, depth, depth_obs, w["lambda_rgb"],
                                               w["lambda_depth"])
+        ls, _ = ops.ssim_loss(rgb, rgb_obs, r.cams, w["lambda_ssim"], d_rgb=d_rgb)
         r.backward_rgbd(g, colors, dQ, d_rgb, d_depth)
-        return lf, lp
+        return lf, lp + ls
 
     for _ in range(warmup):
         step()
@@ -379,7 +380,7 @@ def rgbd_leg(ops, r, g, dec, K, V, tgt, K0, spec, dev, steps, warmup=3):
     torch.cuda.synchronize()
     sec = (time.perf_counter() - t0) / steps
     return {"ms": sec * 1e3, "value": n / sec,
-            "unit": "feature-pixels/s (queries, colour and depth rendered; feature and L1 colour/depth losses)",
+            "unit": "feature-pixels/s (queries, colour and depth rendered; feature, L1 colour/depth and SSIM losses)",
             "weights": dict(w), "loss_feature": float(lf), "loss_rgbd": float(lp)}
 
 

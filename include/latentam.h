@@ -6,6 +6,7 @@
  *   render_backward  dL/dQ -> dL/d(means, log-scales, quaternions, opacity logits, queries)
  *   render_rgbd_*    the same with colour and depth rendered in the pass     Sec. III-A, Eq. 2
  *   rgbd_l1_loss     the L1 colour and depth terms of the mapping objective   Eq. 7-9
+ *   ssim_loss        the SSIM term of the photometric loss                    Eq. 7
  *   decode_loss      F = softmax(Q K^T / sqrt(d)) V, L = mean(1 - cos(F, T)) + lambda ||K - K0||^2,
  *                    and dL/dQ, dL/dK, dL/dV                    Sec. III-B, Eq. 5 and Eq. 6
  *   decode_forward   F alone (inference form of Eq. 5)
@@ -164,11 +165,28 @@ lam_status lam_render_rgbd_backward(const float* means, const float* log_scales,
  * (an observed depth <= 0 marks a pixel without a measurement; with none the
  * depth term is zero) and dL/drgb, dL/ddepth (the sign, zero at a tie).  The
  * paper's weights: lambda_I1 = 0.2 (times lambda_rgb) and lambda_d = 0.1; its
- * SSIM term is not computed here.  Device arrays: rgb, rgb_obs [n, 3], depth,
+ * SSIM term is lam_ssim_loss.  Device arrays: rgb, rgb_obs [n, 3], depth,
  * depth_obs [n]; outputs loss [1], d_rgb [n, 3], d_depth [n] (overwritten).
  * Workspace: lam_rgbd_l1_workspace_size bytes.  Deterministic.
  * Errors: LAM_ERR_INVALID_ARG (null pointers, n < 0, a negative weight,
  * workspace too small), LAM_ERR_HIP. */
+/* The SSIM term of Eq. 7, read as 3D Gaussian Splatting's: structural
+ * similarity per colour channel with an 11 x 11 Gaussian window (standard
+ * deviation 1.5, normalised), C1 = 0.01^2, C2 = 0.03^2, zero padding at the
+ * border, every view its own image (cams: host camera rows as for the render
+ * calls; only width and height are read; rgb rows are the views concatenated,
+ * each row-major):
+ *   loss = lambda (1 - mean over pixels and channels of SSIM(rgb, rgb_obs))
+ * and lambda dSSIM-loss/drgb, written to d_rgb [P, 3] (added to it when
+ * accumulate is non-zero, so it can follow lam_rgbd_l1_loss).  The paper's
+ * weight: lambda_I2 = 0.8 (times lambda_rgb).  Workspace:
+ * lam_ssim_workspace_size bytes (9 floats per pixel).  Deterministic.
+ * Errors: LAM_ERR_INVALID_ARG (null pointers, bad camera rows, negative
+ * lambda, workspace too small), LAM_ERR_HIP. */
+lam_status lam_ssim_workspace_size(const float* cams, int n_cams, uint64_t* bytes);
+lam_status lam_ssim_loss(const float* rgb, const float* rgb_obs, const float* cams, int n_cams, float lambda,
+                         float* loss, float* d_rgb, int accumulate, void* ws, uint64_t ws_bytes, void* stream);
+
 lam_status lam_rgbd_l1_workspace_size(int n, uint64_t* bytes);
 lam_status lam_rgbd_l1_loss(const float* rgb, const float* rgb_obs, const float* depth, const float* depth_obs,
                             int n, float lambda_rgb, float lambda_depth, float* loss, float* d_rgb,
@@ -359,7 +377,7 @@ lam_status lam_stream_kmeans(int precision, const float* F, int n, int D, const 
 /* Turns per-kernel timing on or off (process-wide, off by default).  While on,
  * the main kernels (names: "raster_fwd", "raster_bwd", "decode_rows",
  * "decode_tn", "render_sort", "preprocess", "preprocess_bwd", "tied_prep",
- * "tied_grads", "kmeans", "kmeans_assign", "rgbd_l1") are bracketed by
+ * "tied_grads", "kmeans", "kmeans_assign", "rgbd_l1", "ssim") are bracketed by
  * HIP events recorded on their launch stream.  Not for use under graph capture. */
 lam_status lam_profile_enable(int on);
 

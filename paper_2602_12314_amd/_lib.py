@@ -72,6 +72,8 @@ def lib():
             "lam_render_rgbd_backward": (i32, [vp, vp, vp, vp, vp, vp, i32, i32, vp, i32, i32, i32, vp, vp, vp,
                                                vp, vp, vp, vp, vp, vp, vp, u64, u64, vp]),
             "lam_rgbd_l1_workspace_size": (i32, [i32, pu64]),
+            "lam_ssim_workspace_size": (i32, [vp, i32, pu64]),
+            "lam_ssim_loss": (i32, [vp, vp, vp, i32, f32, vp, vp, i32, vp, u64, vp]),
             "lam_rgbd_l1_loss": (i32, [vp, vp, vp, vp, i32, f32, f32, vp, vp, vp, vp, u64, vp]),
             "lam_kmeans_workspace_size": (i32, [i32, i32, i32, i32, pu64]),
             "lam_kmeans_assign": (i32, [i32, vp, i32, i32, vp, i32, vp, vp, vp, u64, vp]),
@@ -189,6 +191,21 @@ def rgbd_l1_loss(rgb, rgb_obs, depth, depth_obs, lambda_rgb, lambda_depth, loss,
                                  float(lambda_rgb), float(lambda_depth), _p(loss), _p(d_rgb), _p(d_depth),
                                  _p(ws), ws.numel() * ws.element_size(), _stream(stream)),
           "lam_rgbd_l1_loss")
+
+
+def ssim_workspace_size(cams) -> int:
+    cams = _cams(cams)
+    out = C.c_uint64()
+    check(lib().lam_ssim_workspace_size(cams.ctypes.data_as(C.c_void_p), cams.shape[0], C.byref(out)),
+          "lam_ssim_workspace_size")
+    return int(out.value)
+
+
+def ssim_loss(rgb, rgb_obs, cams, lam, loss, d_rgb, accumulate, ws, stream=None):
+    cams = _cams(cams)
+    check(lib().lam_ssim_loss(_p(rgb), _p(rgb_obs), cams.ctypes.data_as(C.c_void_p), cams.shape[0], float(lam),
+                              _p(loss), _p(d_rgb), 1 if accumulate else 0, _p(ws), ws.numel() * ws.element_size(),
+                              _stream(stream)), "lam_ssim_loss")
 
 
 def render_counters(ws, stream=None):

@@ -10,9 +10,10 @@
 - ``TiedDecoder``: the paper's tied decode and full feature loss (Eq. 5-6:
   cosine logits of Q W against the atoms D at temperature tau, V = D, and the
   cosine, L2 and hinge trust-region terms) with gradients to Q, W and D.
-- ``Renderer.forward_rgbd`` / ``backward_rgbd`` and ``rgbd_l1_loss``: colour
-  and depth blended in the same pass as the queries (Sec. III-A) and the L1
-  colour and depth terms of the mapping objective (Eq. 7-9).
+- ``Renderer.forward_rgbd`` / ``backward_rgbd``, ``rgbd_l1_loss`` and
+  ``ssim_loss``: colour and depth blended in the same pass as the queries
+  (Sec. III-A), the L1 colour and depth terms and the SSIM term of the mapping
+  objective (Eq. 7-9).
 - ``StreamKMeans``: the dictionary initialisation of Eq. 10 (weighted
   micro-centres of the keyframe's embeddings, merged with the weighted global
   centres and re-clustered to K), plus plain ``assign`` / ``lloyd`` calls.
@@ -285,7 +286,7 @@ class TiedDecoder:
         return loss, dQ, dW, dD
 
 
-PAPER_RGBD_WEIGHTS = dict(lambda_rgb=0.2, lambda_depth=0.1)  # lambda_I1 (lambda_rgb = 1) and lambda_d
+PAPER_RGBD_WEIGHTS = dict(lambda_rgb=0.2, lambda_depth=0.1, lambda_ssim=0.8)  # lambda_I1, lambda_d, lambda_I2
 
 
 def rgbd_l1_loss(rgb, rgb_obs, depth, depth_obs, lambda_rgb=0.2, lambda_depth=0.1):
@@ -298,6 +299,19 @@ def rgbd_l1_loss(rgb, rgb_obs, depth, depth_obs, lambda_rgb=0.2, lambda_depth=0.
     d_depth = torch.empty_like(depth)
     _lib.rgbd_l1_loss(rgb, rgb_obs, depth, depth_obs, lambda_rgb, lambda_depth, loss, d_rgb, d_depth, ws)
     return loss, d_rgb, d_depth
+
+
+def ssim_loss(rgb, rgb_obs, cams, lam=0.8, d_rgb=None):
+    """(loss, d_rgb) of lam (1 - SSIM) (Eq. 7); with d_rgb given the gradient is
+    added to it (e.g. after rgbd_l1_loss)."""
+    rgb, rgb_obs = _contig(rgb), _contig(rgb_obs)
+    ws = torch.empty(_lib.ssim_workspace_size(cams), dtype=torch.uint8, device=rgb.device)
+    loss = torch.empty(1, dtype=torch.float32, device=rgb.device)
+    acc = d_rgb is not None
+    if d_rgb is None:
+        d_rgb = torch.empty_like(rgb)
+    _lib.ssim_loss(rgb, rgb_obs, cams, lam, loss, d_rgb, acc, ws)
+    return loss, d_rgb
 
 
 MICRO_FACTOR = 5  # micro-centres per global centre (the paper's "5 by default")

@@ -166,3 +166,38 @@ def test_l1_loss_parity(n, holes):
     assert abs(float(loss) - ref["loss"]) <= 1e-5 * max(abs(ref["loss"]), 1e-30) + 1e-12
     np.testing.assert_allclose(to_np(d_rgb), ref["d_rgb"], rtol=1e-6, atol=0)
     np.testing.assert_allclose(to_np(d_depth), ref["d_depth"], rtol=1e-6, atol=0)
+
+
+SSIM_VIEWS = {"640x480": [(640, 480)], "ragged_three_views": [(37, 29), (70, 45), (5, 3)]}
+
+
+@pytest.mark.parametrize("views", list(SSIM_VIEWS))
+def test_ssim_parity(views):
+    from oracle import ssim_oracle as SS
+    from paper_2602_12314_amd import ops
+    sizes = SSIM_VIEWS[views]
+    cams = cams_of(*[scenes.pinhole(w, h, 50.0) for w, h in sizes])
+    P = sum(w * h for w, h in sizes)
+    rng = np.random.default_rng(P)
+    x = rng.uniform(0, 1, (P, 3)).astype(np.float32)
+    y = np.clip(x + 0.15 * rng.standard_normal((P, 3)), 0, 1).astype(np.float32)
+    say(f"[ssim] views={views} P={P}")
+    loss, d = ops.ssim_loss(_dev(x), _dev(y), cams, 0.8)
+    ref = SS.ssim_loss(x, y, sizes)
+    rl = 0.8 * ref["loss"]
+    say(f"  loss {float(loss):.7f} ref {rl:.7f}; grad rel err {rel_err(to_np(d), 0.8 * ref['d_rgb']):.3e}")
+    assert abs(float(loss) - rl) < 1e-5 * max(1.0, abs(rl))
+    assert rel_err(to_np(d), 0.8 * ref["d_rgb"]) < 1e-4
+    # accumulate: added to what is there
+    base = torch.ones((P, 3), device="cuda")
+    _, d2 = ops.ssim_loss(_dev(x), _dev(y), cams, 0.8, d_rgb=base)
+    np.testing.assert_allclose(to_np(d2), 1.0 + to_np(d), rtol=0, atol=1e-6)
+
+
+def test_ssim_identical_images():
+    from paper_2602_12314_amd import ops
+    cams = cams_of(scenes.pinhole(33, 20, 30.0))
+    x = np.random.default_rng(1).uniform(0, 1, (33 * 20, 3)).astype(np.float32)
+    loss, d = ops.ssim_loss(_dev(x), _dev(x), cams, 1.0)
+    assert abs(float(loss)) < 1e-5
+    assert float(np.abs(to_np(d)).max()) < 1e-5
