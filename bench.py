@@ -140,11 +140,20 @@ def run(args):
     T = torch.empty((n,), device=dev)
     grads = g.zeros_like()
 
-    def make_step(dec):
+    # The dictionary gradients (dV, dK, their reductions, the loss) run on a
+    # second stream beside the render backward, which needs only dQ.
+    side = None if args.no_overlap else torch.cuda.Stream(device=dev)
+
+    def make_step(dec, overlap=True):
         def step():
             r.forward(g, Q, T, check=False)
-            loss, dQ, dK, dV = dec.loss_and_grads(Q, K, V, tgt, K0, spec.lambda_tr)
-            r.backward(g, dQ, out=grads)
+            if side is not None and overlap:
+                loss, dQ, dK, dV = dec.loss_and_grads(Q, K, V, tgt, K0, spec.lambda_tr, dict_stream=side)
+                r.backward(g, dQ, out=grads)
+                torch.cuda.current_stream().wait_stream(side)
+            else:
+                loss, dQ, dK, dV = dec.loss_and_grads(Q, K, V, tgt, K0, spec.lambda_tr)
+                r.backward(g, dQ, out=grads)
             return loss
         return step
 
@@ -180,7 +189,7 @@ def run(args):
 
     def graph_timed(dec, steps, warmup):
         holder = {}
-        base = make_step(dec)
+        base = make_step(dec, overlap=args.graph_overlap)
 
         def step():
             holder["loss"] = base()
@@ -233,7 +242,7 @@ def run(args):
         kmeans = kmeans_leg(ops, prec, spec, tgt, dev)
     rgbd = None
     if not args.no_rgbd:
-        rgbd = rgbd_leg(ops, r, g, dec, K, V, tgt, K0, spec, dev, args.steps)
+        rgbd = rgbd_leg(ops, r, g, dec, K, V, tgt, K0, spec, dev, args.steps, side=side)
 
     out = {
         "metric": "feature-pixels/s fwd+bwd",
@@ -255,6 +264,7 @@ def run(args):
                    "tile": args.tile, "decode_shape": decode_shape, "tile_pairs": pairs},
         "stage_ms": {k: round(v, 4) for k, v in prof.items()},
         "launch": "hip_graph_replay" if args.graph else "eager",
+        "dict_gradients_on_second_stream": side is not None and (not args.graph or args.graph_overlap),
         "eager_ms_per_step": eager_sec * 1e3,
         "autotune_ms": tune,
         "loss": loss,
@@ -344,7 +354,7 @@ def tied_leg(ops, prec, spec, Q, V, tgt, dev, reps=10):
             "params": dict(ops.PAPER_TIED_PARAMS), "loss": float(loss)}
 
 
-def rgbd_leg(ops, r, g, dec, K, V, tgt, K0, spec, dev, steps, warmup=3):
+def rgbd_leg(ops, r, g, dec, K, V, tgt, K0, spec, dev, steps, warmup=3, side=None):
     """The Stage-I step with colour and depth supervision (Eq. 7-9): query,
     colour and depth maps in one compositing pass, the decode with the feature
     loss, the L1 colour and depth terms and the SSIM term with the paper's
@@ -363,11 +373,13 @@ def rgbd_leg(ops, r, g, dec, K, V, tgt, K0, spec, dev, steps, warmup=3):
 
     def step():
         Q, rgb, depth, _ = r.forward_rgbd(g, colors, check=False)
-        lf, dQ, _, _ = dec.loss_and_grads(Q, K, V, tgt, K0, spec.lambda_tr)
+        lf, dQ, _, _ = dec.loss_and_grads(Q, K, V, tgt, K0, spec.lambda_tr, dict_stream=side)
         lp, d_rgb, d_depth = ops.rgbd_l1_loss(rgb, rgb_obs, depth, depth_obs, w["lambda_rgb"],
                                               w["lambda_depth"])
         ls, _ = ops.ssim_loss(rgb, rgb_obs, r.cams, w["lambda_ssim"], d_rgb=d_rgb)
         r.backward_rgbd(g, colors, dQ, d_rgb, d_depth)
+        if side is not None:
+            torch.cuda.current_stream().wait_stream(side)
         return lf, lp + ls
 
     for _ in range(warmup):
@@ -516,6 +528,10 @@ def main():
     ap.add_argument("--no-tied", action="store_true", help="skip the tied-decode leg")
     ap.add_argument("--no-kmeans", action="store_true", help="skip the streaming K-means leg")
     ap.add_argument("--no-rgbd", action="store_true", help="skip the colour + depth step leg")
+    ap.add_argument("--graph-overlap", action="store_true",
+                    help="with --graph, capture the second stream into the graph too")
+    ap.add_argument("--no-overlap", action="store_true",
+                    help="run the dictionary gradients on the step's own stream (no second stream)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (scales HBM byte counters)")
     args = ap.parse_args()

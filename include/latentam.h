@@ -253,6 +253,21 @@ lam_status lam_decode_loss(int precision, const float* Q, int n, int d, const fl
                            float lambda_tr, float* loss, float* dQ, float* dK, float* dV,
                            float* row_cos, void* ws, uint64_t ws_bytes, void* stream);
 
+/* lam_decode_loss with its second half on another stream: dQ and row_cos are
+ * written in order on ``stream``; the dictionary gradients (dK, dV, their
+ * split-K reductions) and the loss are computed on ``dict_stream`` (a
+ * hipStream_t of default priority), which first waits for the rows kernel on
+ * ``stream``.  Work the caller queues on ``stream`` after this call (the render
+ * backward, which needs dQ only) then runs beside them.  loss, dK and dV are
+ * ready in ``dict_stream`` order; make ``stream`` wait for ``dict_stream``
+ * before reading them or passing the same workspace to another call.
+ * Otherwise identical to lam_decode_loss (same results bit for bit). */
+lam_status lam_decode_loss_overlap(int precision, const float* Q, int n, int d, const float* K,
+                                   const float* V, int M, int D, const float* target, const float* K0,
+                                   float lambda_tr, float* loss, float* dQ, float* dK, float* dV,
+                                   float* row_cos, void* ws, uint64_t ws_bytes, void* stream,
+                                   void* dict_stream);
+
 /* Inference decode (Eq. 5): F device [n, D] = softmax(Q K^T / sqrt(d)) V.
  * Errors: LAM_ERR_INVALID_ARG, LAM_ERR_UNSUPPORTED, LAM_ERR_HIP. */
 lam_status lam_decode_forward(int precision, const float* Q, int n, int d, const float* K,

@@ -61,6 +61,8 @@ def lib():
             "lam_decode_workspace_size": (i32, [i32, i32, i32, i32, i32, pu64]),
             "lam_decode_loss": (i32, [i32, vp, i32, i32, vp, vp, i32, i32, vp, vp, f32, vp, vp, vp, vp,
                                       vp, vp, u64, vp]),
+            "lam_decode_loss_overlap": (i32, [i32, vp, i32, i32, vp, vp, i32, i32, vp, vp, f32, vp, vp, vp, vp,
+                                              vp, vp, u64, vp, vp]),
             "lam_decode_forward": (i32, [i32, vp, i32, i32, vp, vp, i32, i32, vp, vp, u64, vp]),
             "lam_decode_backward": (i32, [i32, vp, i32, i32, vp, vp, i32, i32, vp, vp, vp, vp, vp, u64,
                                           vp]),
@@ -249,6 +251,17 @@ def decode_loss(precision, Q, K, V, target, K0, lambda_tr, loss, dQ, dK, dV, row
                                 _p(target), _p(K0), float(lambda_tr), _p(loss), _p(dQ), _p(dK), _p(dV),
                                 _p(row_cos), _p(ws), ws.numel() * ws.element_size(), _stream(stream)),
           "lam_decode_loss")
+
+
+def decode_loss_overlap(precision, Q, K, V, target, K0, lambda_tr, loss, dQ, dK, dV, row_cos, ws, dict_stream,
+                        stream=None):
+    n, d = Q.shape
+    M, D = V.shape
+    check(lib().lam_decode_loss_overlap(PRECISIONS.get(precision, precision), _p(Q), n, d, _p(K), _p(V), M, D,
+                                        _p(target), _p(K0), float(lambda_tr), _p(loss), _p(dQ), _p(dK), _p(dV),
+                                        _p(row_cos), _p(ws), ws.numel() * ws.element_size(), _stream(stream),
+                                        _stream(dict_stream)),
+          "lam_decode_loss_overlap")
 
 
 def decode_forward(precision, Q, K, V, F, ws, stream=None):

@@ -18,6 +18,8 @@
 // fragment is one 16-byte load: dK = dS^T Q (k_dec_tn) and dV = P~^T G
 // (k_dec_dv), which rebuilds P~ from Q, K and the saved row max rather than
 // reading it.  The softmax is recomputed in the backward part, never stored.
+#include <mutex>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -1271,8 +1273,23 @@ static hipError_t launch_rows(const RowsArgs& ra, int nb, int D, int d, int Mp, 
     return hipErrorInvalidValue;
 }
 
+// One event per device (created on first use) marks the end of the rows
+// kernel for a second stream to wait on.  A wait refers to the record made
+// before it, so reusing the event across calls is safe.
+static hipEvent_t fork_event()
+{
+    static std::mutex mu;
+    static hipEvent_t ev[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!ev[dev] && hipEventCreateWithFlags(&ev[dev], hipEventDisableTiming) != hipSuccess) ev[dev] = nullptr;
+    return ev[dev];
+}
+
 template <class P, bool F8>
-static hipError_t run_decode(const DecodeArgs& A, const DecodeLayout& L, int mode, hipStream_t st)
+static hipError_t run_decode(const DecodeArgs& A, const DecodeLayout& L, int mode, hipStream_t st,
+                             hipStream_t st_dict)
 {
     using T = typename P::T;
     char* base = reinterpret_cast<char*>(L.base);
@@ -1328,6 +1345,17 @@ static hipError_t run_decode(const DecodeArgs& A, const DecodeLayout& L, int mod
         if (e != hipSuccess) return e;
     }
     if (mode == MODE_INFER) return hipGetLastError();
+    // The dictionary part (dV, dK, their reductions and the loss) reads only
+    // the workspace; on a second stream it runs beside whatever the caller
+    // queues on st after dQ (the render backward).
+    if (st_dict != st) {
+        hipEvent_t ev = fork_event();
+        if (!ev) return hipErrorInvalidValue;
+        e = hipEventRecord(ev, st);
+        if (e == hipSuccess) e = hipStreamWaitEvent(st_dict, ev, 0);
+        if (e != hipSuccess) return e;
+        st = st_dict;
+    }
     float* part = reinterpret_cast<float*>(base + L.off_part);
     // dV = P~^T G over all pixels, P~ rebuilt from Q, K and the saved row max
     {
@@ -1363,25 +1391,26 @@ static hipError_t run_decode(const DecodeArgs& A, const DecodeLayout& L, int mod
     return hipGetLastError();
 }
 
-hipError_t decode_loss_launch(const DecodeArgs& A, const DecodeLayout& L, hipStream_t st)
+hipError_t decode_loss_launch(const DecodeArgs& A, const DecodeLayout& L, hipStream_t st, hipStream_t st_dict)
 {
-    if (A.prec == LAM_FP32) return run_decode<TF32, false>(A, L, MODE_LOSS, st);
-    if (A.prec == LAM_FP8_E4M3) return run_decode<TBF16, true>(A, L, MODE_LOSS, st);
-    return run_decode<TBF16, false>(A, L, MODE_LOSS, st);
+    if (!st_dict) st_dict = st;
+    if (A.prec == LAM_FP32) return run_decode<TF32, false>(A, L, MODE_LOSS, st, st_dict);
+    if (A.prec == LAM_FP8_E4M3) return run_decode<TBF16, true>(A, L, MODE_LOSS, st, st_dict);
+    return run_decode<TBF16, false>(A, L, MODE_LOSS, st, st_dict);
 }
 
 hipError_t decode_forward_launch(const DecodeArgs& A, const DecodeLayout& L, hipStream_t st)
 {
-    if (A.prec == LAM_FP32) return run_decode<TF32, false>(A, L, MODE_INFER, st);
-    if (A.prec == LAM_FP8_E4M3) return run_decode<TBF16, true>(A, L, MODE_INFER, st);
-    return run_decode<TBF16, false>(A, L, MODE_INFER, st);
+    if (A.prec == LAM_FP32) return run_decode<TF32, false>(A, L, MODE_INFER, st, st);
+    if (A.prec == LAM_FP8_E4M3) return run_decode<TBF16, true>(A, L, MODE_INFER, st, st);
+    return run_decode<TBF16, false>(A, L, MODE_INFER, st, st);
 }
 
 hipError_t decode_backward_launch(const DecodeArgs& A, const DecodeLayout& L, hipStream_t st)
 {
-    if (A.prec == LAM_FP32) return run_decode<TF32, false>(A, L, MODE_ADJ, st);
-    if (A.prec == LAM_FP8_E4M3) return run_decode<TBF16, true>(A, L, MODE_ADJ, st);
-    return run_decode<TBF16, false>(A, L, MODE_ADJ, st);
+    if (A.prec == LAM_FP32) return run_decode<TF32, false>(A, L, MODE_ADJ, st, st);
+    if (A.prec == LAM_FP8_E4M3) return run_decode<TBF16, true>(A, L, MODE_ADJ, st, st);
+    return run_decode<TBF16, false>(A, L, MODE_ADJ, st, st);
 }
 
 }  // namespace lam
@@ -1436,6 +1465,25 @@ lam_status lam_decode_loss(int precision, const float* Q, int n, int d, const fl
     A.Q = Q; A.K = K; A.V = V; A.target = target; A.K0 = K0; A.lambda_tr = lambda_tr;
     A.loss = loss; A.dQ = dQ; A.dK = dK; A.dV = dV; A.row_cos = row_cos;
     return decode_loss_launch(A, L, (hipStream_t)stream) == hipSuccess ? LAM_OK : LAM_ERR_HIP;
+}
+
+lam_status lam_decode_loss_overlap(int precision, const float* Q, int n, int d, const float* K, const float* V,
+                                   int M, int D, const float* target, const float* K0, float lambda_tr,
+                                   float* loss, float* dQ, float* dK, float* dV, float* row_cos, void* ws,
+                                   uint64_t ws_bytes, void* stream, void* dict_stream)
+{
+    DecodeLayout L{};
+    lam_status s = dec_common(precision, n, d, M, D, ws, ws_bytes, &L);
+    if (s != LAM_OK) return s;
+    if (!dec_ptrs_ok(Q, n, K, V) || !loss || !dK || !dV || (n > 0 && !target)) return LAM_ERR_INVALID_ARG;
+    if (!a16(target) || !a16(dQ)) return LAM_ERR_INVALID_ARG;
+    if (lambda_tr != 0.0f && !K0) return LAM_ERR_INVALID_ARG;
+    DecodeArgs A{};
+    A.prec = precision; A.n = n; A.d = d; A.M = M; A.D = D;
+    A.Q = Q; A.K = K; A.V = V; A.target = target; A.K0 = K0; A.lambda_tr = lambda_tr;
+    A.loss = loss; A.dQ = dQ; A.dK = dK; A.dV = dV; A.row_cos = row_cos;
+    return decode_loss_launch(A, L, (hipStream_t)stream, (hipStream_t)dict_stream) == hipSuccess ? LAM_OK
+                                                                                                   : LAM_ERR_HIP;
 }
 
 lam_status lam_decode_forward(int precision, const float* Q, int n, int d, const float* K, const float* V,

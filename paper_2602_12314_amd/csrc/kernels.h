@@ -98,7 +98,10 @@ struct DecodeLayout {
 
 bool decode_layout(int prec, int n, int d, int M, int D, DecodeLayout* L);
 void set_decode_shape(int mode);
-hipError_t decode_loss_launch(const DecodeArgs& A, const DecodeLayout& L, hipStream_t st);
+// With st_dict (not null and not st) the dictionary gradients and the loss run
+// on st_dict after the rows kernel on st; the caller joins the two streams.
+hipError_t decode_loss_launch(const DecodeArgs& A, const DecodeLayout& L, hipStream_t st,
+                              hipStream_t st_dict = nullptr);
 hipError_t decode_forward_launch(const DecodeArgs& A, const DecodeLayout& L, hipStream_t st);
 hipError_t decode_backward_launch(const DecodeArgs& A, const DecodeLayout& L, hipStream_t st);
 

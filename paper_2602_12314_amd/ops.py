@@ -182,16 +182,25 @@ class Decoder:
         self.ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
         self.device = torch.device(device)
 
-    def loss_and_grads(self, Q, K, V, target, K0, lambda_tr, want_dQ=True, row_cos=None):
+    def loss_and_grads(self, Q, K, V, target, K0, lambda_tr, want_dQ=True, row_cos=None, dict_stream=None):
+        """Loss and gradients (Eq. 5-6).  With ``dict_stream`` (a torch stream)
+        the dictionary gradients and the loss are computed there, beside what
+        the caller queues next on the current stream; join the streams before
+        reading loss, dK, dV or changing the inputs."""
         n, d, M, D = self.shape
         dev = self.device
         loss = torch.empty(1, dtype=torch.float32, device=dev)
         dQ = torch.empty((n, d), dtype=torch.float32, device=dev) if want_dQ else None
         dK = torch.empty((M, d), dtype=torch.float32, device=dev)
         dV = torch.empty((M, D), dtype=torch.float32, device=dev)
-        _lib.decode_loss(self.precision, _contig(Q), _contig(K), _contig(V), _contig(target),
-                         None if K0 is None else _contig(K0), lambda_tr, loss, dQ, dK, dV, row_cos,
-                         self.ws)
+        args = (_contig(Q), _contig(K), _contig(V), _contig(target), None if K0 is None else _contig(K0))
+        if dict_stream is None:
+            _lib.decode_loss(self.precision, *args, lambda_tr, loss, dQ, dK, dV, row_cos, self.ws)
+        else:
+            _lib.decode_loss_overlap(self.precision, *args, lambda_tr, loss, dQ, dK, dV, row_cos, self.ws,
+                                     dict_stream.cuda_stream)
+            for t in (loss, dK, dV, self.ws) + tuple(a for a in args if a is not None):
+                t.record_stream(dict_stream)
         return loss, dQ, dK, dV
 
     def forward(self, Q, K, V, F=None):

@@ -268,3 +268,24 @@ def test_full_640x480_workload(prec):
         c = _min_cos(F, ref["F"])
         say(f"  min cos {c:.6f}")
         assert c >= 0.999
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_overlap_on_a_second_stream_is_bit_identical(prec):
+    """lam_decode_loss_overlap: the dictionary gradients on a second stream
+    (beside work queued after the call) equal lam_decode_loss bit for bit."""
+    n, d, M, D = 5000, 16, 256, 512
+    say(f"[overlap] {prec} n={n}")
+    Q, K, V, T, K0 = _inputs(8, n, d, M, D)
+    dec = _decoder(prec, n, d, M, D)
+    q, k, v, t, k0 = _cuda(Q, K, V, T, K0)
+    ref = dec.loss_and_grads(q, k, v, t, k0, 0.1)
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    for _ in range(3):
+        out = dec.loss_and_grads(q, k, v, t, k0, 0.1, dict_stream=side)
+        busy = torch.randn((2048, 2048), device="cuda") @ torch.randn((2048, 2048), device="cuda")  # work after
+        torch.cuda.current_stream().wait_stream(side)
+        for a, b in zip(out, ref):
+            assert torch.equal(a, b)
+        del busy
