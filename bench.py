@@ -522,19 +522,22 @@ def main():
     ap.add_argument("--tile", default="16x16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--autotune", action="store_true", help="pick the render tile shape by timing")
-    ap.add_argument("--graph", action="store_true", help="time replays of the HIP-graph-captured step")
+    ap.add_argument("--graph", action="store_true",
+                    help="time replays of the HIP-graph-captured step (the default; see --eager)")
+    ap.add_argument("--eager", action="store_true",
+                    help="time eager launches instead of HIP-graph replays of the captured step")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 decode comparison leg")
     ap.add_argument("--no-stage2", action="store_true", help="skip the Stage-II decode-only leg")
     ap.add_argument("--no-tied", action="store_true", help="skip the tied-decode leg")
     ap.add_argument("--no-kmeans", action="store_true", help="skip the streaming K-means leg")
     ap.add_argument("--no-rgbd", action="store_true", help="skip the colour + depth step leg")
-    ap.add_argument("--graph-overlap", action="store_true",
-                    help="with --graph, capture the second stream into the graph too")
     ap.add_argument("--no-overlap", action="store_true",
                     help="run the dictionary gradients on the step's own stream (no second stream)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (scales HBM byte counters)")
     args = ap.parse_args()
+    args.graph = not args.eager
+    args.graph_overlap = not args.no_overlap
     if args.copy_calibration:
         import torch
         a = torch.empty(args.copy_calibration // 4, dtype=torch.float32, device="cuda").uniform_()

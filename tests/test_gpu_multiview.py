@@ -86,7 +86,11 @@ def test_local_map_8_views_parity():
 
 
 @pytest.mark.parametrize("prec", ["bf16", "fp32"])
-def test_graph_captured_step_replays(prec):
+@pytest.mark.parametrize("overlap", [False, True])
+def test_graph_captured_step_replays(prec, overlap):
+    """The whole step captured into a HIP graph (with overlap: the dictionary
+    gradients on a second stream, forked and joined inside the graph) replays
+    to the eager results, with eager work clobbering the buffers in between."""
     ops = _ops()
     s = _small_views(seed=6)
     sp = s.spec
@@ -100,13 +104,17 @@ def test_graph_captured_step_replays(prec):
     T = torch.empty((n,), device=dev)
     grads = g.zeros_like()
     r.forward(g, Q, T)  # sizes the capacity (blocking check) before capture
-    say(f"[graph] capture {prec}")
+    say(f"[graph] capture {prec} overlap={overlap}")
     outs = {}
+
+    side = torch.cuda.Stream() if overlap else None
 
     def step():
         r.forward(g, Q, T, check=False)
-        loss, dQ, dK, dV = dec.loss_and_grads(Q, K, V, tgt, K0, 0.1)
+        loss, dQ, dK, dV = dec.loss_and_grads(Q, K, V, tgt, K0, 0.1, dict_stream=side)
         r.backward(g, dQ, out=grads)
+        if side is not None:
+            torch.cuda.current_stream().wait_stream(side)
         outs.update(loss=loss, dK=dK, dV=dV)
 
     step()
