@@ -180,31 +180,46 @@ __global__ __launch_bounds__(256) void k_tied_gram_q(const float* __restrict__ Q
 }
 
 // A[a][b] = sum over the splits of part[s][a][b] (fixed order).
+// One wave per entry: the lanes stride over the split partials, then a wave
+// sum (fixed order, so the result is deterministic).
 __global__ __launch_bounds__(256) void k_tied_areduce(const float* __restrict__ part, int splits, int pairs,
                                                       float* __restrict__ A)
 {
-    const int e = blockIdx.x * 256 + threadIdx.x;
-    if (e >= pairs) return;
+    const int e = blockIdx.x * (256 / kWave) + (int)(threadIdx.x / kWave);
+    const int lane = threadIdx.x & (kWave - 1);
+    if (e >= pairs) return;  // whole waves
     float s = 0.f;
-    for (int k = 0; k < splits; ++k) s += part[(size_t)k * pairs + e];
-    A[e] = s;
+    for (int k = lane; k < splits; k += kWave) s += part[(size_t)k * pairs + e];
+    s = wave_allsum(s);
+    if (lane == 0) A[e] = s;
 }
 
 // dW[a][f] = sum_j dK[j][a] D[j][f] / gD[j] + sum_b A[a][b] W[b][f].
+// Workgroup (f block of 64, a): wave w sums atoms j = w, w + 4, ...; the four
+// partial sums meet in LDS in wave order.
 __global__ __launch_bounds__(256) void k_tied_dw(const float* __restrict__ dK, const float* __restrict__ D,
                                                  const float* __restrict__ gD, const float* __restrict__ A,
                                                  const float* __restrict__ W, int ds, int M, int df,
                                                  float* __restrict__ dW)
 {
-    const int idx = blockIdx.x * 256 + threadIdx.x;
-    if (idx >= ds * df) return;
-    const int a = idx / df, f = idx % df;
+    __shared__ float red[256 / kWave][kWave];
+    const int a = blockIdx.y, w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+    const int f = blockIdx.x * kWave + lane;
+    const bool ok = f < df;
     float s = 0.f;
-#pragma unroll 8
-    for (int j = 0; j < M; ++j) s += dK[(size_t)j * ds + a] * (D[(size_t)j * df + f] / gD[j]);
-#pragma unroll 8
-    for (int b = 0; b < ds; ++b) s += A[a * ds + b] * W[(size_t)b * df + f];
-    dW[idx] = s;
+    if (ok) {
+#pragma unroll 4
+        for (int j = w; j < M; j += 256 / kWave) s += dK[(size_t)j * ds + a] * (D[(size_t)j * df + f] / gD[j]);
+    }
+    red[w][lane] = s;
+    __syncthreads();
+    if (w == 0 && ok) {
+        float t = red[0][lane];
+#pragma unroll
+        for (int k = 1; k < 256 / kWave; ++k) t += red[k][lane];
+        for (int b = 0; b < ds; ++b) t += A[a * ds + b] * W[(size_t)b * df + f];
+        dW[(size_t)a * df + f] = t;
+    }
 }
 
 // One workgroup per atom j: dB = dK_j W, B = D_j / gD_j,
@@ -349,9 +364,9 @@ hipError_t tied_loss_launch(const TiedArgs& T, const TiedLayout& L, void* base_,
                                apart);
         }
     }
-    hipLaunchKernelGGL(k_tied_areduce, dim3((ds * ds + 255) / 256), dim3(256), 0, st, (const float*)apart, splits,
+    hipLaunchKernelGGL(k_tied_areduce, dim3((ds * ds + 3) / 4), dim3(256), 0, st, (const float*)apart, splits,
                        ds * ds, Am);
-    hipLaunchKernelGGL(k_tied_dw, dim3((ds * df + 255) / 256), dim3(256), 0, st, (const float*)dK, T.D,
+    hipLaunchKernelGGL(k_tied_dw, dim3((df + kWave - 1) / kWave, ds), dim3(256), 0, st, (const float*)dK, T.D,
                        (const float*)gD, (const float*)Am, T.W, ds, M, df, T.dW);
     hipLaunchKernelGGL(k_tied_dd, dim3(M), dim3(256), (size_t)(df + 512) * 4, st, (const float*)dK,
                        (const float*)dV, T.D, T.D0, (const float*)gD, T.W, ds, df, T.lam_D, T.delta, T.dD, pen);
