@@ -77,7 +77,7 @@ def dv_splits(n: int, Mp: int, D: int) -> int:
     """Split-K count of the dV reduction (decode_layout's rule): enough
     workgroups to fill 256 CUs twice, a multiple of 8, at most the block count."""
     nb = max(((n + 63) // 64) * 2, 1)
-    tiles = ((Mp + 127) // 128) * ((D + 127) // 128)
+    tiles = ((Mp + 127) // 128) * (D // (256 if D % 256 == 0 else 128))
     s = (512 + tiles - 1) // tiles
     s = (s + 7) // 8 * 8
     if s > nb:

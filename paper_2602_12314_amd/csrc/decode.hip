@@ -935,7 +935,17 @@ __global__ __launch_bounds__(256) void k_dec_tn(const void* At_, int rowsA, cons
 // are directly the A fragment of pixel chunk k in perm16 order, the order in
 // which k_dec_rows stores G^T.  Waves 2 x 2, each 64 atoms x 64 features; two
 // blocks of Q, m2 and G^T fragments in flight; splits mapped as in k_dec_tn.
-template <class P, int DQ>
+// dV split-K GEMM.  A workgroup owns 128 atoms x 128 QT feature columns and a
+// range of pixel blocks.  Per block, wave w rebuilds P~ for atom tile w only
+// (S = Q K^T with the pixel as the MFMA row, so each lane holds one atom and
+// 16 pixels in perm16 order, then exp2 against the saved row max) and leaves
+// it in LDS as the A fragments of the dV product; after one barrier every
+// wave multiplies all four atom tiles by the G^T fragments of its own 32 QT
+// columns.  P~ is thus computed once per (atom, pixel) and feature-column
+// tile, and the LDS slots alternate between blocks so one barrier per block
+// suffices (a wave can write slot b + 1 while a slower one still reads slot b,
+// and cannot reach slot b + 2 before that wave has passed the barrier of b + 1).
+template <class P, int DQ, int QT>
 __global__ __launch_bounds__(256) void k_dec_dv(const float* __restrict__ Q, int n, const void* Kb_, int M,
                                                 const float* __restrict__ m2, float scale_log2, const void* Gt_,
                                                 int Mp, int D, int nblocks, int splits, int tiles_i, int tiles_j,
@@ -944,6 +954,7 @@ __global__ __launch_bounds__(256) void k_dec_dv(const float* __restrict__ Q, int
     using T = typename P::T;
     using Frag = typename P::Frag;
     constexpr int NQ = DQ / 16;
+    __shared__ __align__(32) T pf[2][4][2][kWave * 8];
     const T* Kb = reinterpret_cast<const T*>(Kb_);
     const T* Gt = reinterpret_cast<const T*>(Gt_);
     const int ntiles = tiles_i * tiles_j;
@@ -951,35 +962,33 @@ __global__ __launch_bounds__(256) void k_dec_dv(const float* __restrict__ Q, int
     const int xcd = b % 8, idx = b / 8;
     const int split = (idx / ntiles) * 8 + xcd;
     const int tile = idx % ntiles;
-    if (split >= splits) return;
+    if (split >= splits) return;  // whole workgroups
     const int ti = tile / tiles_j, tj = tile % tiles_j;
     const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int col = lane & 31, h = lane >> 5;
-    const int i0 = (ti * 2 + w / 2) * 64, j0 = (tj * 2 + w % 2) * 64;
-    if (i0 >= Mp || j0 >= D) return;
+    const int i0 = ti * 128;                       // the workgroup's atoms
+    const int j0 = (tj * 4 + w) * 32 * QT;         // this wave's feature columns
+    const int ntv = min(4, (Mp - i0) / 32);        // atom tiles inside Mp (Mp is a multiple of 64)
+    const bool mine_ok = w < ntv;                  // the atom tile this wave rebuilds
     const int per = (nblocks + splits - 1) / splits;
     const int b0 = split * per, b1 = min(nblocks, b0 + per);
 
-    Frag kf[2][NQ];
-    bool atom_ok[2];
+    Frag kf[NQ];
+    const bool atom_ok = mine_ok && i0 + 32 * w + col < M;
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
-        atom_ok[t] = i0 + 32 * t + col < M;
+    for (int c = 0; c < NQ; ++c) kf[c] = load_frag<P>(Kb, mine_ok ? i0 / 32 + w : 0, c, NQ, lane);
+    f32x16 acc[4][QT];
 #pragma unroll
-        for (int c = 0; c < NQ; ++c) kf[t][c] = load_frag<P>(Kb, i0 / 32 + t, c, NQ, lane);
-    }
-    f32x16 acc[2][2];
+    for (int t = 0; t < 4; ++t)
 #pragma unroll
-    for (int t = 0; t < 2; ++t)
-#pragma unroll
-        for (int q = 0; q < 2; ++q) acc[t][q] = f32x16{};
+        for (int q = 0; q < QT; ++q) acc[t][q] = f32x16{};
 
     // one block's operands: Q rows of pixel col (zero past n), the row max of
-    // the lane's 16 pixels, and the G^T fragments of its two feature tiles
+    // the lane's 16 pixels, and the G^T fragments of this wave's columns
     struct Blk {
         float4 q[NQ][2];
         float4 m[4];
-        Frag g[2][2];
+        Frag g[QT][2];
     };
     auto load = [&](int blk, Blk& B) {
         const int px = blk * kPx + col;
@@ -993,38 +1002,47 @@ __global__ __launch_bounds__(256) void k_dec_dv(const float* __restrict__ Q, int
         for (int g4 = 0; g4 < 4; ++g4)
             B.m[g4] = *reinterpret_cast<const float4*>(m2 + (size_t)blk * kPx + 8 * g4 + 4 * h);
 #pragma unroll
-        for (int q = 0; q < 2; ++q)
+        for (int q = 0; q < QT; ++q)
 #pragma unroll
             for (int k = 0; k < 2; ++k)
                 B.g[q][k] = P::load(Gt + ((size_t)blk * D + j0 + 32 * q + col) * kPx + 16 * k + 8 * h);
     };
     auto compute = [&](int blk, const Blk& B) {
-        const bool valid = blk * kPx + col < n;
-        Frag qf[NQ];
+        const int slot = blk & 1;
+        {
+            const bool valid = blk * kPx + col < n;
+            Frag qf[NQ];
 #pragma unroll
-        for (int c = 0; c < NQ; ++c) {
-            const float v[8] = {B.q[c][0].x, B.q[c][0].y, B.q[c][0].z, B.q[c][0].w,
-                                B.q[c][1].x, B.q[c][1].y, B.q[c][1].z, B.q[c][1].w};
-            float z[8];
+            for (int c = 0; c < NQ; ++c) {
+                const float v[8] = {B.q[c][0].x, B.q[c][0].y, B.q[c][0].z, B.q[c][0].w,
+                                    B.q[c][1].x, B.q[c][1].y, B.q[c][1].z, B.q[c][1].w};
+                float z[8];
 #pragma unroll
-            for (int e = 0; e < 8; ++e) z[e] = valid ? v[e] : 0.0f;
-            qf[c] = P::from_f32(z);
-        }
-        const float mr[16] = {B.m[0].x, B.m[0].y, B.m[0].z, B.m[0].w, B.m[1].x, B.m[1].y, B.m[1].z, B.m[1].w,
-                              B.m[2].x, B.m[2].y, B.m[2].z, B.m[2].w, B.m[3].x, B.m[3].y, B.m[3].z, B.m[3].w};
+                for (int e = 0; e < 8; ++e) z[e] = valid ? v[e] : 0.0f;
+                qf[c] = P::from_f32(z);
+            }
+            const float mr[16] = {B.m[0].x, B.m[0].y, B.m[0].z, B.m[0].w, B.m[1].x, B.m[1].y, B.m[1].z, B.m[1].w,
+                                  B.m[2].x, B.m[2].y, B.m[2].z, B.m[2].w, B.m[3].x, B.m[3].y, B.m[3].z, B.m[3].w};
+            f32x16 sacc = {};
 #pragma unroll
-        for (int t = 0; t < 2; ++t) {
-            f32x16 s = {};
-#pragma unroll
-            for (int c = 0; c < NQ; ++c) P::mma(s, qf[c], kf[t][c]);
+            for (int c = 0; c < NQ; ++c) P::mma(sacc, qf[c], kf[c]);
             float p[16];
 #pragma unroll
-            for (int r = 0; r < 16; ++r) p[r] = atom_ok[t] ? exp2_weight(s[r] * scale_log2 - mr[r]) : 0.0f;
+            for (int r = 0; r < 16; ++r) p[r] = atom_ok ? exp2_weight(sacc[r] * scale_log2 - mr[r]) : 0.0f;
 #pragma unroll
-            for (int k = 0; k < 2; ++k) {
-                const Frag af = P::from_f32(p + 8 * k);
+            for (int k = 0; k < 2; ++k)
+                *reinterpret_cast<Frag*>(&pf[slot][w][k][lane * 8]) = P::from_f32(p + 8 * k);
+        }
+        __syncthreads();
 #pragma unroll
-                for (int q = 0; q < 2; ++q) P::mma(acc[t][q], af, B.g[q][k]);
+        for (int t = 0; t < 4; ++t) {
+            if (t < ntv) {
+#pragma unroll
+                for (int k = 0; k < 2; ++k) {
+                    const Frag af = *reinterpret_cast<const Frag*>(&pf[slot][t][k][lane * 8]);
+#pragma unroll
+                    for (int q = 0; q < QT; ++q) P::mma(acc[t][q], af, B.g[q][k]);
+                }
             }
         }
     };
@@ -1042,12 +1060,13 @@ __global__ __launch_bounds__(256) void k_dec_dv(const float* __restrict__ Q, int
     }
     float* out = part + (size_t)split * Mp * D;
 #pragma unroll
-    for (int t = 0; t < 2; ++t)
+    for (int t = 0; t < 4; ++t)
+        if (t < ntv)
 #pragma unroll
-        for (int q = 0; q < 2; ++q)
+            for (int q = 0; q < QT; ++q)
 #pragma unroll
-            for (int r = 0; r < 16; ++r)
-                out[(size_t)(i0 + 32 * t + crow(r, h)) * D + j0 + 32 * q + col] = acc[t][q][r];
+                for (int r = 0; r < 16; ++r)
+                    out[(size_t)(i0 + 32 * t + crow(r, h)) * D + j0 + 32 * q + col] = acc[t][q][r];
 }
 
 // out[i][j] = sum_split part[split][i][j] (+ 2 lambda (K - K0)[i][j] for dK)
@@ -1188,6 +1207,9 @@ void set_decode_shape(int mode) { g_decode_shape = mode; }
 
 static bool wide_rows(int prec, int Mp, int D) { return g_decode_shape == 1 && wide_ok(prec, Mp, D); }
 
+// 32-column tiles per wave in the dV GEMM: two when D is a multiple of 256.
+static int dv_cols(int D) { return D % 256 == 0 ? 2 : 1; }
+
 static int pick_splits(int nblocks, int tiles)
 {
     // enough workgroups to fill 256 CUs twice, splits a multiple of 8
@@ -1212,7 +1234,7 @@ bool decode_layout(int prec, int n, int d, int M, int D, DecodeLayout* L)
     if (rows_lds(prec, Mp, D, 4, 1) > kMaxLds) return false;  // the 32 x 4 shape always fits
     L->Mp = Mp;
     L->row_blocks = nb;
-    const int tiles_v = ((Mp + 127) / 128) * ((D + 127) / 128);
+    const int tiles_v = ((Mp + 127) / 128) * (D / (128 * dv_cols(D)));
     const int tiles_k = (Mp + 255) / 256;
     const int sv = pick_splits(std::max(nb, 1), tiles_v);
     const int sk = pick_splits(std::max(nb, 1), tiles_k);
@@ -1359,10 +1381,12 @@ static hipError_t run_decode(const DecodeArgs& A, const DecodeLayout& L, int mod
     float* part = reinterpret_cast<float*>(base + L.off_part);
     // dV = P~^T G over all pixels, P~ rebuilt from Q, K and the saved row max
     {
-        const int ti = (Mp + 127) / 128, tj = (A.D + 127) / 128;
+        const int qt = dv_cols(A.D);
+        const int ti = (Mp + 127) / 128, tj = A.D / (128 * qt);
         if (nb > 0) {
             ProfScope ps("decode_tn", st);
-            auto kern = A.d == 16 ? k_dec_dv<P, 16> : k_dec_dv<P, 32>;
+            auto kern = qt == 2 ? (A.d == 16 ? k_dec_dv<P, 16, 2> : k_dec_dv<P, 32, 2>)
+                                : (A.d == 16 ? k_dec_dv<P, 16, 1> : k_dec_dv<P, 32, 1>);
             hipLaunchKernelGGL(kern, dim3(L.splits * ti * tj), dim3(256), 0, st, A.Q, A.n,
                                (const void*)Kb, A.M, (const float*)ra.M2, ra.scale_log2,
                                (const void*)(base + L.off_gf), Mp, A.D, nb, L.splits, ti, tj, part);
