@@ -256,8 +256,8 @@ lam_status lam_decode_loss(int precision, const float* Q, int n, int d, const fl
 /* lam_decode_loss with its second half on another stream: dQ and row_cos are
  * written in order on ``stream``; the dictionary gradients (dK, dV, their
  * split-K reductions) and the loss are computed on ``dict_stream`` (a
- * hipStream_t of default priority), which first waits for the rows kernel on
- * ``stream``.  Work the caller queues on ``stream`` after this call (the render
+ * hipStream_t of default priority; NULL or ``stream`` itself: no second
+ * stream), which first waits for the rows kernel on ``stream``.  Work the caller queues on ``stream`` after this call (the render
  * backward, which needs dQ only) then runs beside them.  loss, dK and dV are
  * ready in ``dict_stream`` order; make ``stream`` wait for ``dict_stream``
  * before reading them or passing the same workspace to another call.
