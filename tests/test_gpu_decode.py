@@ -289,3 +289,11 @@ def test_overlap_on_a_second_stream_is_bit_identical(prec):
         for a, b in zip(out, ref):
             assert torch.equal(a, b)
         del busy
+    # no pixels: only the trust-region term reaches dK, and the loss
+    dec0 = _decoder(prec, 0, d, M, D)
+    q0, t0 = torch.zeros((0, d), device="cuda"), torch.zeros((0, D), device="cuda")
+    l0, _, dK0, dV0 = dec0.loss_and_grads(q0, k, v, t0, k0, 0.1, dict_stream=side)
+    torch.cuda.current_stream().wait_stream(side)
+    r0 = dec0.loss_and_grads(q0, k, v, t0, k0, 0.1)
+    assert torch.equal(l0, r0[0]) and torch.equal(dK0, r0[2]) and torch.equal(dV0, r0[3])
+    assert float(dV0.abs().max()) == 0.0

@@ -201,3 +201,21 @@ def test_ssim_identical_images():
     loss, d = ops.ssim_loss(_dev(x), _dev(x), cams, 1.0)
     assert abs(float(loss)) < 1e-5
     assert float(np.abs(to_np(d)).max()) < 1e-5
+
+
+def test_rgbd_empty_scene():
+    """No Gaussians: colour and depth are zero, the transmittance one, and the
+    backward returns empty gradients."""
+    from paper_2602_12314_amd import ops
+    cams = cams_of(scenes.pinhole(40, 30, 35.0), scenes.pinhole(17, 9, 20.0))
+    P = 40 * 30 + 17 * 9
+    z = lambda *s: torch.zeros(s, dtype=torch.float32, device="cuda")
+    g = ops.Gaussians(z(0, 3), z(0, 3), z(0, 4), z(0), z(0, 16))
+    r = ops.Renderer(cams, 0, 16)
+    Q, rgb, depth, T = r.forward_rgbd(g, z(0, 3))
+    torch.cuda.synchronize()
+    assert float(Q.abs().max()) == 0 and float(rgb.abs().max()) == 0 and float(depth.abs().max()) == 0
+    assert float((T - 1).abs().max()) == 0
+    out, dcol = r.backward_rgbd(g, z(0, 3), z(P, 16), z(P, 3), z(P))
+    torch.cuda.synchronize()
+    assert dcol.shape == (0, 3) and out.means.shape == (0, 3)
