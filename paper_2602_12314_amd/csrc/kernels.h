@@ -116,7 +116,7 @@ struct TiedArgs {
 struct TiedLayout {
     DecodeLayout dec;  // the decode call's workspace, at offset 0
     uint64_t bytes;
-    size_t off_qs, off_gq, off_cq, off_dqs, off_k, off_gd, off_g, off_dk, off_dv, off_apart, off_a, off_pen,
+    size_t off_qs, off_gq, off_dqs, off_k, off_gd, off_g, off_dk, off_dv, off_apart, off_a, off_pen,
         off_loss;
 };
 

@@ -23,7 +23,6 @@
 namespace lam {
 
 constexpr float kNormEps = 1e-12f;
-constexpr int kASplits = 256;  // pixel ranges of the sum_p c_p Q_p^T Q_p reduction
 
 // Workgroup r < M: K[r][a] = <D_r, W_a> / max(|D_r|, eps) for a < DS and
 // gD[r] = max(|D_r|, eps); workgroup M + a: G[a][b] = <W_a, W_b>.  The 256
@@ -97,90 +96,70 @@ __global__ __launch_bounds__(256) void k_tied_queries(const float* __restrict__ 
         *reinterpret_cast<float4*>(Qs + (size_t)p * DS + a) = make_float4(q[a] * s, q[a + 1] * s, q[a + 2] * s, q[a + 3] * s);
 }
 
-// dQ_p from dQ'_p (through Q' = Q / (tau g)) and c_p for the W-gradient of the
-// query norm; dQ may be NULL.
+// dQ from dQ' through Q' = Q / (tau |Q W|) (c_p = the coefficient of G Q_p) and,
+// per workgroup of 256 pixels, part[block][a][b] =
+// sum over its pixels of c_p Q_p[a] Q_p[b] from the same loads (the pixels
+// are staged in LDS; thread t owns pairs t, t + 256, ...).
 template <int DS>
-__global__ __launch_bounds__(256) void k_tied_dq(const float* __restrict__ Q, const float* __restrict__ dQs, int n,
-                                                 const float* __restrict__ G, const float* __restrict__ gq,
-                                                 float tau, float* __restrict__ dQ, float* __restrict__ cq)
+__global__ __launch_bounds__(256) void k_tied_dq_gram(const float* __restrict__ Q, const float* __restrict__ dQs,
+                                                      int n, const float* __restrict__ G,
+                                                      const float* __restrict__ gq, float tau,
+                                                      float* __restrict__ dQ, float* __restrict__ part)
 {
+    constexpr int PAIRS = DS * DS, PER = (PAIRS + 255) / 256;
     __shared__ float sG[DS * DS];
+    __shared__ float sq[256][DS + 1];
+    __shared__ float sc[256];
     for (int e = threadIdx.x; e < DS * DS; e += 256) sG[e] = G[e];
     __syncthreads();
     const int p = blockIdx.x * 256 + threadIdx.x;
-    if (p >= n) return;
-    float q[DS], dq[DS];
+    float q[DS];
 #pragma unroll
-    for (int a = 0; a < DS; a += 4) {
-        const float4 v = *reinterpret_cast<const float4*>(Q + (size_t)p * DS + a);
-        const float4 u = *reinterpret_cast<const float4*>(dQs + (size_t)p * DS + a);
-        q[a] = v.x; q[a + 1] = v.y; q[a + 2] = v.z; q[a + 3] = v.w;
-        dq[a] = u.x; dq[a + 1] = u.y; dq[a + 2] = u.z; dq[a + 3] = u.w;
-    }
-    const float g = gq[p];
-    const bool active = g > kNormEps;
-    float t = 0.f;
+    for (int a = 0; a < DS; ++a) q[a] = 0.f;
+    float c = 0.f;
+    if (p < n) {
+        float dq[DS];
 #pragma unroll
-    for (int a = 0; a < DS; ++a) t += dq[a] * q[a];
-    const float inv = 1.0f / (tau * g);
-    const float c = active ? -t * inv / (g * g) : 0.0f;
-    cq[p] = c;
-    if (!dQ) return;
-#pragma unroll
-    for (int a = 0; a < DS; ++a) {
-        float gqa = 0.f;
-#pragma unroll
-        for (int b = 0; b < DS; ++b) gqa += sG[a * DS + b] * q[b];
-        dQ[(size_t)p * DS + a] = dq[a] * inv + c * gqa;
-    }
-}
-
-// part[s][a][b] = sum over pixel range s of c_p Q_p[a] Q_p[b]; thread t of the
-// workgroup owns pairs t, t + 256, ... (ds^2 <= 1024); pixels are staged in LDS.
-template <int DS>
-__global__ __launch_bounds__(256) void k_tied_gram_q(const float* __restrict__ Q, const float* __restrict__ cq, int n,
-                                                     int splits, float* __restrict__ part)
-{
-    constexpr int PAIRS = DS * DS, PER = (PAIRS + 255) / 256, CH = 256;
-    __shared__ float sq[CH][DS + 1];
-    __shared__ float sc[CH];
-    const int per = (n + splits - 1) / splits;
-    const int p0 = blockIdx.x * per, p1 = min(n, p0 + per);
-    float acc[PER];
-#pragma unroll
-    for (int k = 0; k < PER; ++k) acc[k] = 0.f;
-    for (int base = p0; base < p1; base += CH) {
-        __syncthreads();
-        const int p = base + (int)threadIdx.x;
-        if (p < p1) {
-#pragma unroll
-            for (int a = 0; a < DS; ++a) sq[threadIdx.x][a] = Q[(size_t)p * DS + a];
-            sc[threadIdx.x] = cq[p];
-        } else {
-#pragma unroll
-            for (int a = 0; a < DS; ++a) sq[threadIdx.x][a] = 0.f;
-            sc[threadIdx.x] = 0.f;
+        for (int a = 0; a < DS; a += 4) {
+            const float4 v = *reinterpret_cast<const float4*>(Q + (size_t)p * DS + a);
+            const float4 u = *reinterpret_cast<const float4*>(dQs + (size_t)p * DS + a);
+            q[a] = v.x; q[a + 1] = v.y; q[a + 2] = v.z; q[a + 3] = v.w;
+            dq[a] = u.x; dq[a + 1] = u.y; dq[a + 2] = u.z; dq[a + 3] = u.w;
         }
-        __syncthreads();
+        const float g = gq[p];
+        float t = 0.f;
 #pragma unroll
-        for (int k = 0; k < PER; ++k) {
-            const int e = (int)threadIdx.x + 256 * k;
-            if (e >= PAIRS) break;
-            const int a = e / DS, b = e % DS;
-            float s = 0.f;
-            for (int i = 0; i < CH; ++i) s += sc[i] * sq[i][a] * sq[i][b];
-            acc[k] += s;
+        for (int a = 0; a < DS; ++a) t += dq[a] * q[a];
+        const float inv = 1.0f / (tau * g);
+        c = g > kNormEps ? -t * inv / (g * g) : 0.0f;
+        if (dQ) {
+#pragma unroll
+            for (int a = 0; a < DS; ++a) {
+                float gqa = 0.f;
+#pragma unroll
+                for (int b = 0; b < DS; ++b) gqa += sG[a * DS + b] * q[b];
+                dQ[(size_t)p * DS + a] = dq[a] * inv + c * gqa;
+            }
         }
     }
+#pragma unroll
+    for (int a = 0; a < DS; ++a) sq[threadIdx.x][a] = q[a];
+    sc[threadIdx.x] = c;
+    __syncthreads();
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
         const int e = (int)threadIdx.x + 256 * k;
-        if (e < PAIRS) part[(size_t)blockIdx.x * PAIRS + e] = acc[k];
+        if (e < PAIRS) {
+            const int a = e / DS, b = e % DS;
+            float sum = 0.f;
+            for (int i = 0; i < 256; ++i) sum += sc[i] * sq[i][a] * sq[i][b];
+            part[(size_t)blockIdx.x * PAIRS + e] = sum;
+        }
     }
 }
 
-// A[a][b] = sum over the splits of part[s][a][b] (fixed order).
-// One wave per entry: the lanes stride over the split partials, then a wave
+// A[a][b] = sum over the splits of part[s][a][b].  One wave per entry: the
+// lanes stride over the split partials, then a wave
 // sum (fixed order, so the result is deterministic).
 __global__ __launch_bounds__(256) void k_tied_areduce(const float* __restrict__ part, int splits, int pairs,
                                                       float* __restrict__ A)
@@ -292,14 +271,13 @@ bool tied_layout(int prec, int n, int ds, int M, int df, TiedLayout* L)
     };
     L->off_qs = take((size_t)n * ds * 4);
     L->off_gq = take((size_t)n * 4);
-    L->off_cq = take((size_t)n * 4);
     L->off_dqs = take((size_t)n * ds * 4);
     L->off_k = take((size_t)M * ds * 4);
     L->off_gd = take((size_t)M * 4);
     L->off_g = take((size_t)ds * ds * 4);
     L->off_dk = take((size_t)M * ds * 4);
     L->off_dv = take((size_t)M * df * 4);
-    L->off_apart = take((size_t)kASplits * ds * ds * 4);
+    L->off_apart = take((size_t)std::max((n + 255) / 256, 1) * ds * ds * 4);
     L->off_a = take((size_t)ds * ds * 4);
     L->off_pen = take((size_t)M * 4);
     L->off_loss = take(4);
@@ -312,7 +290,6 @@ hipError_t tied_loss_launch(const TiedArgs& T, const TiedLayout& L, void* base_,
     char* base = reinterpret_cast<char*>(base_);
     float* Qs = reinterpret_cast<float*>(base + L.off_qs);
     float* gq = reinterpret_cast<float*>(base + L.off_gq);
-    float* cq = reinterpret_cast<float*>(base + L.off_cq);
     float* dQs = reinterpret_cast<float*>(base + L.off_dqs);
     float* K = reinterpret_cast<float*>(base + L.off_k);
     float* gD = reinterpret_cast<float*>(base + L.off_gd);
@@ -350,19 +327,14 @@ hipError_t tied_loss_launch(const TiedArgs& T, const TiedLayout& L, void* base_,
     hipError_t e = decode_loss_launch(A, DL, st);
     if (e != hipSuccess) return e;
     ProfScope ps("tied_grads", st);
-    const int splits = n > 0 ? std::min(kASplits, pblocks) : 0;
+    const int splits = n > 0 ? pblocks : 0;  // one partial per workgroup of 256 pixels
     if (n > 0) {
-        if (ds == 16) {
-            hipLaunchKernelGGL(k_tied_dq<16>, dim3(pblocks), dim3(256), 0, st, T.Q, (const float*)dQs, n,
-                               (const float*)G, (const float*)gq, T.tau, T.dQ, cq);
-            hipLaunchKernelGGL(k_tied_gram_q<16>, dim3(splits), dim3(256), 0, st, T.Q, (const float*)cq, n, splits,
-                               apart);
-        } else {
-            hipLaunchKernelGGL(k_tied_dq<32>, dim3(pblocks), dim3(256), 0, st, T.Q, (const float*)dQs, n,
-                               (const float*)G, (const float*)gq, T.tau, T.dQ, cq);
-            hipLaunchKernelGGL(k_tied_gram_q<32>, dim3(splits), dim3(256), 0, st, T.Q, (const float*)cq, n, splits,
-                               apart);
-        }
+        if (ds == 16)
+            hipLaunchKernelGGL(k_tied_dq_gram<16>, dim3(pblocks), dim3(256), 0, st, T.Q, (const float*)dQs, n,
+                               (const float*)G, (const float*)gq, T.tau, T.dQ, apart);
+        else
+            hipLaunchKernelGGL(k_tied_dq_gram<32>, dim3(pblocks), dim3(256), 0, st, T.Q, (const float*)dQs, n,
+                               (const float*)G, (const float*)gq, T.tau, T.dQ, apart);
     }
     hipLaunchKernelGGL(k_tied_areduce, dim3((ds * ds + 3) / 4), dim3(256), 0, st, (const float*)apart, splits,
                        ds * ds, Am);
