@@ -283,7 +283,24 @@ def run(args):
     cpu = None
     pairs_eval = pairs_blend = None
     if not args.no_cpu_baseline:
-        cpu, pairs_eval, pairs_blend = cpu_baseline(s, spec)
+        cpu, pairs_eval, pairs_blend, ref = cpu_baseline(s, spec)
+
+        def check(prec_):
+            # one more step, outside every timed region, against the oracle's FP64 step
+            d_ = dec if prec_ == prec else ops.Decoder(prec_, n, spec.d, spec.M, spec.D, device=dev)
+            r.forward(g, Q, T, check=False)
+            l_, dQ_, dK_, dV_ = d_.loss_and_grads(Q, K, V, tgt, K0, spec.lambda_tr)
+            gr_ = r.backward(g, dQ_)
+            torch.cuda.synchronize()
+
+            def rel(a, b):
+                a = a.detach().double().cpu().numpy()
+                return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+            return {"loss_rel_err": abs(float(l_) - ref["loss"]) / abs(ref["loss"]),
+                    "dK_rel_err": rel(dK_, ref["dK"]), "dV_rel_err": rel(dV_, ref["dV"]),
+                    "d_means_rel_err": rel(gr_.means, ref["means"]),
+                    "d_queries_rel_err": rel(gr_.queries, ref["queries"])}
+        out["oracle_check"] = {p_: check(p_) for p_ in dict.fromkeys([prec, "fp32"])}
     else:
         pairs_eval, pairs_blend = oracle_pairs(s)
     work = algorithmic_work(spec, prec, pairs_eval, pairs_blend, pairs)
@@ -495,7 +512,7 @@ def cpu_baseline(s, spec):
     t1 = time.perf_counter()
     r = DO.loss_and_grads(f["Q"], s.K, s.V, s.target, s.K0, spec.lambda_tr)
     t2 = time.perf_counter()
-    R.render_backward(g, s.cams, r["dQ"])
+    gb = R.render_backward(g, s.cams, r["dQ"])
     t3 = time.perf_counter()
     threads = R.num_threads()
     try:
@@ -510,7 +527,9 @@ def cpu_baseline(s, spec):
              "sample": f"one full {spec.name} step: render fwd {t1 - t0:.2f}s + decode/loss/grads "
                        f"{t2 - t1:.2f}s + render bwd {t3 - t2:.2f}s (C/OpenMP {threads} threads, "
                        f"numpy BLAS {blas} threads, FP64)"},
-            int(f["n_pairs"].sum()), int(f["n_blended"].sum()))
+            int(f["n_pairs"].sum()), int(f["n_blended"].sum()),
+            {"loss": float(r["loss"]), "dK": r["dK"], "dV": r["dV"], "means": gb["means"],
+             "queries": gb["queries"]})
 
 
 def main():
