@@ -353,9 +353,12 @@ def tied_leg(ops, prec, spec, Q, V, tgt, dev, reps=10):
     """The paper's tied decode (Eq. 5 with cosine logits at temperature 0.1,
     V = D) and full loss (cosine + L2 + hinge trust region, the paper's weights)
     with gradients to Q, W and D, on this workload's query map and shapes; W is
-    a random d x D projection and D0 the dictionary before one perturbation."""
+    a random d x D projection and D0 the dictionary before one perturbation.
+    The library offers this form in FP32 and BF16 only, so an E4M3 workload
+    runs it in BF16."""
     import torch
     n, d, M, Dd = spec.n_pixels, spec.d, spec.M, spec.D
+    prec = "bf16" if prec == "fp8" else prec
     g = torch.Generator(device=dev).manual_seed(3)
     W = torch.randn((d, Dd), device=dev, generator=g) / d ** 0.5
     D0 = V.clone()
@@ -369,7 +372,7 @@ def tied_leg(ops, prec, spec, Q, V, tgt, dev, reps=10):
     torch.cuda.synchronize()
     sec = (time.perf_counter() - t0) / reps
     return {"ms": sec * 1e3, "value": n / sec, "unit": "feature-pixels/s (decode + loss + dQ, dW, dD)",
-            "params": dict(ops.PAPER_TIED_PARAMS), "loss": float(loss)}
+            "precision": prec, "params": dict(ops.PAPER_TIED_PARAMS), "loss": float(loss)}
 
 
 def rgbd_leg(ops, r, g, dec, K, V, tgt, K0, spec, dev, steps, warmup=3, side=None):

@@ -302,7 +302,8 @@ typedef struct {
 /* Workspace bytes for lam_decode_tied_loss: n pixel rows, query dimension ds
  * (16 or 32), M atoms, feature dimension df (the decode's D; same limits as
  * lam_decode_workspace_size).  Host-only.
- * Errors: LAM_ERR_INVALID_ARG (null out, n < 0), LAM_ERR_UNSUPPORTED (shape). */
+ * Errors: LAM_ERR_INVALID_ARG (null out, n < 0), LAM_ERR_UNSUPPORTED (shape,
+ * or a precision other than LAM_FP32 and LAM_BF16). */
 lam_status lam_decode_tied_workspace_size(int precision, int n, int ds, int M, int df, uint64_t* bytes);
 
 /* Loss and gradients of the tied decode.  Device inputs (FP32, row-major):
@@ -310,12 +311,15 @@ lam_status lam_decode_tied_workspace_size(int precision, int n, int ds, int M, i
  * dictionary); params on the host.  Device outputs (overwritten): loss [1],
  * dQ [n, ds] (nullable: the decode-only iterations skip it), dW [ds, df],
  * dD [M, df].  precision selects the attention arithmetic as in
- * lam_decode_loss; the normalisations and the gradient chain run in FP32.
+ * lam_decode_loss, LAM_FP32 or LAM_BF16 (LAM_FP8_E4M3 is unsupported: with
+ * cosine logits over a small temperature the softmax weights sit on a few
+ * atoms, so E4M3 rounding of D is not averaged out and dQ misses its bound);
+ * the normalisations and the gradient chain run in FP32.
  * Q, target and dQ rows are read and written 16 bytes at a time (16-byte
  * aligned).  Stream-ordered, no host synchronisation.
  * Errors: LAM_ERR_INVALID_ARG (null or misaligned pointers, workspace too
- * small, tau <= 0 or a negative weight), LAM_ERR_UNSUPPORTED (shape),
- * LAM_ERR_HIP. */
+ * small, tau <= 0 or a negative weight), LAM_ERR_UNSUPPORTED (shape,
+ * precision), LAM_ERR_HIP. */
 lam_status lam_decode_tied_loss(int precision, const float* Q, int n, int ds, const float* W, const float* D,
                                 int M, int df, const float* target, const float* D0,
                                 const lam_tied_params* params, float* loss, float* dQ, float* dW, float* dD,

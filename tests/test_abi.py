@@ -123,6 +123,9 @@ def test_tied_decode_validation(L):
     base = ok.value
     assert L.lam_decode_workspace_size(1, 1000, 16, 256, 512, C.byref(ok)) == 0 and ok.value < base
     assert L.lam_decode_tied_workspace_size(1, 1000, 8, 256, 512, C.byref(ok)) == _lib.LAM_ERR_UNSUPPORTED
+    assert L.lam_decode_tied_workspace_size(0, 1000, 16, 256, 512, C.byref(ok)) == 0
+    # E4M3 is not offered for the tied decode (its dQ misses the E4M3 bound)
+    assert L.lam_decode_tied_workspace_size(2, 1000, 16, 256, 512, C.byref(ok)) == _lib.LAM_ERR_UNSUPPORTED
     assert L.lam_decode_tied_workspace_size(1, -1, 16, 256, 512, C.byref(ok)) == _lib.LAM_ERR_INVALID_ARG
     bad = _lib.TiedParams(0.0, 0.5, 0.5, 0.2, 0.1)  # tau must be positive
     p = C.c_void_p(16)
@@ -131,6 +134,9 @@ def test_tied_decode_validation(L):
     assert st == _lib.LAM_ERR_INVALID_ARG
     assert L.lam_decode_tied_loss(1, p, 10, 16, p, p, 64, 128, p, p, None, p, None, p, p, p,
                                   C.c_uint64(1 << 30), None) == _lib.LAM_ERR_INVALID_ARG
+    good = _lib.TiedParams(0.1, 0.5, 0.5, 0.2, 0.1)
+    assert L.lam_decode_tied_loss(2, p, 10, 16, p, p, 64, 128, p, p, C.byref(good), p, None, p, p, p,
+                                  C.c_uint64(1 << 30), None) == _lib.LAM_ERR_UNSUPPORTED
 
 
 def test_kmeans_validation(L):

@@ -1,0 +1,191 @@
+"""GPU parity at the full sizes of the three larger workloads (1200x680 with
+300k Gaussians; eight views with 500k; 1200x680 with 2M Gaussians and the E4M3
+decode), in the launch configurations the benchmark's autotuner picks there:
+8 x 32 tiles, and both decode block shapes (32 pixels x 4 waves, 64 x 8).
+
+Render (Eq. 2, Eq. 4 and their adjoint), the whole image against the FP64
+oracle as in the smaller cases: the sorted (tile, record) list and the tile
+ranges bit-exact, Q and T_final within 1e-4 relative on pixels whose oracle
+walk takes no threshold decision within 1e-5 of a threshold, gradients of
+<w, Q> within 1e-4.
+
+Decode and loss (Eq. 5-6): the per-pixel outputs (F, the row cosine, dQ) on
+2048 sampled pixels against the oracle run on those rows alone (a row's
+outputs depend on that row only; dQ is rescaled from the sample's mean to the
+mean over all pixels), and the reductions over every pixel through identities
+that hold at any size:
+  loss   = mean_p (1 - cos_p) + lambda ||K - K0||^2,
+  Q^T dQ = (dK - 2 lambda (K - K0))^T K   (both equal sum_pj dS_pj Q_p^T K_j / sqrt(d)),
+  V^T dV = F^T G                           (G = dL/dF, dV = P^T G, F = P V),
+the last on eight random projections with G formed from the returned F and
+the target.  Since D >= M at these sizes, V^T has full column rank and
+V^T dV w determines dV w.
+Bars: BF16 as elsewhere (row cosine within 5e-3, F's minimum cosine 0.999,
+1e-2 on dQ and the identities); E4M3 at its reachable bounds (row cosine 2e-2,
+F's mean cosine 0.999, 5e-2 on dQ and the identities).
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import decode_oracle as DO  # noqa: E402
+from oracle import raster as R  # noqa: E402
+from paper_2602_12314_amd import scenes  # noqa: E402
+from tests.gpu_helpers import AMBIGUOUS, rel_err, say, to_np, ws_u32  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+WORKLOADS = [2, 3, 4]
+TILE = (8, 32)
+BARS = {"bf16": dict(cos=5e-3, F=0.999, grad=1e-2), "fp8": dict(cos=2e-2, F=0.999, grad=5e-2)}
+
+
+def _dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float32, device="cuda")
+
+
+@pytest.mark.parametrize("cfg", WORKLOADS)
+def test_render_full_size(cfg):
+    from paper_2602_12314_amd import ops
+    sp = scenes.spec(cfg)
+    s = scenes.make_scene(sp, seed=cfg, with_target=False)
+    g = R.Gaussians.of(s)
+    say(f"[render full] {sp.name} N={g.n} pixels={sp.n_pixels} tile={TILE}")
+    gg = ops.Gaussians(_dev(g.means), _dev(g.log_scales), _dev(g.quats), _dev(g.opacity_logits),
+                       _dev(g.queries))
+    r = ops.Renderer(s.cams, g.n, g.d, tile=TILE)
+    Q, T = r.forward(gg)
+    torch.cuda.synchronize()
+    need, over = r.counters()
+    ob = R.bin_sort(g, s.cams, *TILE)
+    assert not over and need == ob["count"]
+    kp, rp, rgp, _, _, _ = r.debug_views()
+    assert np.array_equal(ws_u32(r.ws, kp, need), ob["tiles"]), "tile keys"
+    assert np.array_equal(ws_u32(r.ws, rp, need), ob["recs"]), "record order"
+    rg = ws_u32(r.ws, rgp, 2 * R.num_tiles(s.cams, *TILE)).reshape(-1, 2)
+    assert np.array_equal(rg, ob["ranges"]), "tile ranges"
+    del ob
+    ref = R.render_forward(g, s.cams, *TILE)
+    ok = ref["margin"] >= AMBIGUOUS
+    say(f"  instances {need}, ambiguous pixels {(~ok).sum()} ({(~ok).mean():.2e})")
+    assert (~ok).mean() < 0.01
+    eq = rel_err(to_np(Q)[ok], ref["Q"][ok])
+    et = rel_err(to_np(T)[ok], ref["T_final"][ok])
+    say(f"  rel err Q {eq:.3e} T_final {et:.3e}")
+    assert eq < 1e-4 and et < 1e-4
+    w = np.random.default_rng(7).standard_normal(ref["Q"].shape)
+    w[~ok] = 0.0
+    w = w.astype(np.float32)
+    out = r.backward(gg, _dev(w))
+    torch.cuda.synchronize()
+    og = R.render_backward(g, s.cams, w.astype(np.float64), *TILE)
+    for name in ["means", "log_scales", "quats", "opacity_logits", "queries"]:
+        e = rel_err(to_np(getattr(out, name)), og[name])
+        say(f"  d_{name}: rel err {e:.3e}")
+        assert e < 1e-4, name
+
+
+def _decode_inputs(sp, seed):
+    """Seeded decode inputs of a workload's sizes: Gaussian Q, K, V; K0 = K
+    plus 1 % noise; the target a piecewise structure of unit rows (sp.n_sites
+    prototypes, each row one prototype plus noise of scale sp.noise drawn from
+    a table of 4093 rows, renormalised), which costs a fraction of the scene
+    generator's Voronoi map at millions of pixels and has the same value
+    distribution row by row."""
+    rng = np.random.default_rng(seed)
+    n, d, M, D = sp.n_pixels, sp.d, sp.M, sp.D
+    Q = rng.standard_normal((n, d), dtype=np.float32)
+    K = rng.standard_normal((M, d)).astype(np.float32)
+    V = rng.standard_normal((M, D)).astype(np.float32)
+    K0 = (K + 0.01 * rng.standard_normal((M, d))).astype(np.float32)
+    protos = rng.standard_normal((sp.n_sites, D))
+    protos /= np.linalg.norm(protos, axis=1, keepdims=True)
+    protos = protos.astype(np.float32)
+    table = (sp.noise * rng.standard_normal((4093, D))).astype(np.float32)
+    lab = rng.integers(0, sp.n_sites, n)
+    T = np.empty((n, D), dtype=np.float32)
+    for s in range(0, n, 1 << 16):
+        e = min(n, s + (1 << 16))
+        t = protos[lab[s:e]] + table[(np.arange(s, e) * 7919) % 4093]
+        t /= np.linalg.norm(t, axis=1, keepdims=True)
+        T[s:e] = t
+    return Q, K, V, K0, T
+
+
+def _cosines(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return (a * b).sum(1) / (np.linalg.norm(a, axis=1) * np.linalg.norm(b, axis=1))
+
+
+def _ft_g_projected(F, T, n, W):
+    """F^T (G W), G = dL/dF of the mean cosine loss, over chunks of 65536 rows
+    (FP32 inside a chunk, about 1e-5 relative; the chunks summed in FP64):
+    G_p W = -(T_p W / den_p - c_p F_p W / |F_p|^2) / n."""
+    out = np.zeros((F.shape[1], W.shape[1]))
+    W = W.astype(np.float32)
+    for s in range(0, F.shape[0], 1 << 16):
+        f, t = F[s:s + (1 << 16)], T[s:s + (1 << 16)]
+        nf2 = np.einsum("ij,ij->i", f, f)
+        den = np.maximum(np.sqrt(nf2) * np.sqrt(np.einsum("ij,ij->i", t, t)), DO.COS_EPS)
+        c = np.einsum("ij,ij->i", f, t) / den
+        gw = -((t @ W) / den[:, None] - (c / nf2)[:, None] * (f @ W)) / n
+        out += (f.T @ gw.astype(np.float32)).astype(np.float64)
+    return out
+
+
+@pytest.mark.parametrize("cfg", WORKLOADS)
+def test_decode_full_size(cfg):
+    from paper_2602_12314_amd import _lib, ops
+    sp = scenes.spec(cfg)
+    prec = sp.precision
+    bar = BARS[prec]
+    n, d, M, D = sp.n_pixels, sp.d, sp.M, sp.D
+    say(f"[decode full] {sp.name} {prec} n={n} d={d} M={M} D={D}")
+    Q, K, V, K0, T = _decode_inputs(sp, seed=20 + cfg)
+    q, k, v, k0, t = (_dev(a) for a in (Q, K, V, K0, T))
+    rng = np.random.default_rng(30 + cfg)
+    idx = np.unique(np.concatenate([[0, n - 1], rng.choice(n, 2048, replace=False)]))
+    ref = DO.loss_and_grads(Q[idx], K, V, T[idx], K0, sp.lambda_tr)
+    scale = idx.size / n  # the sample's mean -> the mean over all n pixels
+    W = rng.standard_normal((D, 8))
+    tr = 2.0 * sp.lambda_tr * (K.astype(np.float64) - K0)
+    for shape in ("px32", "px64"):
+        _lib.set_decode_shape(shape)
+        try:
+            dec = ops.Decoder(prec, n, d, M, D)
+            row_cos = torch.empty(n, device="cuda")
+            loss, dQ, dK, dV = dec.loss_and_grads(q, k, v, t, k0, sp.lambda_tr, row_cos=row_cos)
+            F = dec.forward(q, k, v)
+            torch.cuda.synchronize()
+        finally:
+            _lib.set_decode_shape("px32")
+        say(f"  decode shape {shape}")
+        sel = torch.as_tensor(idx, device="cuda")
+        cg = to_np(row_cos)
+        ec = np.abs(cg[idx] - ref["cos"]).max()
+        cF = _cosines(to_np(F[sel]), ref["F"])
+        eq = rel_err(to_np(dQ[sel]), ref["dQ"] * scale)
+        say(f"    sampled rows: max |cos err| {ec:.2e}, F cosine min {cF.min():.6f} mean {cF.mean():.6f}, "
+            f"dQ rel err {eq:.3e}")
+        assert ec < bar["cos"]
+        assert (cF.min() if prec == "bf16" else cF.mean()) >= bar["F"]
+        assert eq < bar["grad"]
+        # loss: the same per-row cosines, reduced over all n rows
+        lref = float((1.0 - cg.astype(np.float64)).mean() + sp.lambda_tr * ((K.astype(np.float64) - K0) ** 2).sum())
+        el = abs(float(loss) - lref) / abs(lref)
+        # dK through Q^T dQ = (dK - 2 lambda (K - K0))^T K
+        dQn = to_np(dQ).astype(np.float64)
+        lhs = Q.astype(np.float64).T @ dQn
+        rhs = (to_np(dK).astype(np.float64) - tr).T @ K.astype(np.float64)
+        ek = rel_err(rhs, lhs)
+        # dV through V^T dV W = F^T G W
+        lv = V.astype(np.float64).T @ (to_np(dV).astype(np.float64) @ W)
+        rv = _ft_g_projected(to_np(F), T, n, W)
+        ev = rel_err(lv, rv)
+        say(f"    loss identity {el:.2e}, dK identity {ek:.3e}, dV identity {ev:.3e}")
+        assert el < 1e-5
+        assert ek < bar["grad"]
+        assert ev < bar["grad"]
+        del dec, row_cos, loss, dQ, dK, dV, F, dQn
