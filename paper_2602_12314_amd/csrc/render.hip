@@ -367,20 +367,49 @@ __global__ __launch_bounds__(256) void k_raster_fwd(
 
 // ------------------------------------------------------------- raster bwd
 
+// The partner's copy of x in a halving step with lane mask M (1, 2, 4 or 8),
+// through DPP inside a 16-lane row: lane ^ 1 and lane ^ 2 by quad permutes,
+// lane ^ 8 by rotating the row by 8, and for M = 4 the mirror lane within the
+// 8-lane half row (7 - i), whose M bit is also the opposite one.  A partner
+// that differs in bits below M too is as good as lane ^ M: those bits are
+// combined at the later steps all the same.
+template <int M>
+__device__ inline float partner(float x)
+{
+    constexpr int ctrl = M == 1 ? 0xB1 : M == 2 ? 0x4E : M == 4 ? 0x141 : 0x128;
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), ctrl, 0xF, 0xF, false));
+}
+
 // Transposed wave reduction of N values: at the step with lane mask M a lane
 // keeps the upper half of its values if its M bit is set, the lower half
-// otherwise, and adds the partner's (lane ^ M) copy of the half it keeps.
+// otherwise, and adds the partner's copy of the half it keeps.  For M = 32 and
+// 16 one v_permlane32_swap / v_permlane16_swap of the pair (v[k], v[k + H])
+// leaves, in every lane, its own kept value and the partner's copy of it in the
+// two results (the swap trades the upper lanes of the first operand for the
+// lower lanes of the second), so their sum is the step; the smaller masks use
+// DPP.  No LDS traffic either way.
 template <int N, int M>
 __device__ inline void halving_sum(float* v, unsigned lane)
 {
     if constexpr (N > 1 && M >= 1) {
         constexpr int H = N / 2;
-        const bool upper = (lane & M) != 0;
+        if constexpr (M == 32 || M == 16) {
 #pragma unroll
-        for (int k = 0; k < H; ++k) {
-            const float send = upper ? v[k] : v[k + H];
-            const float keep = upper ? v[k + H] : v[k];
-            v[k] = keep + __shfl_xor(send, M, kWave);
+            for (int k = 0; k < H; ++k) {
+                const auto r = M == 32 ? __builtin_amdgcn_permlane32_swap(__float_as_uint(v[k]),
+                                                                          __float_as_uint(v[k + H]), false, false)
+                                       : __builtin_amdgcn_permlane16_swap(__float_as_uint(v[k]),
+                                                                          __float_as_uint(v[k + H]), false, false);
+                v[k] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+            }
+        } else {
+            const bool upper = (lane & M) != 0;
+#pragma unroll
+            for (int k = 0; k < H; ++k) {
+                const float send = upper ? v[k] : v[k + H];
+                const float keep = upper ? v[k + H] : v[k];
+                v[k] = keep + partner<M>(send);
+            }
         }
         halving_sum<H, M / 2>(v, lane);
     }
@@ -516,7 +545,7 @@ __device__ inline void raster_bwd_tile(
 #pragma unroll
             for (int k = NT; k < NV; ++k) v[k] = 0.0f;
             halving_sum<NV, 32>(v, lane);
-            if (NV == 32) v[0] += __shfl_xor(v[0], 1, kWave);
+            if (NV == 32) v[0] += partner<1>(v[0]);
             const int idx = NV == 32 ? (int)(lane >> 1) : (int)lane;
             const bool owner = (NV == 64 || (lane & 1) == 0) && idx < NT && v[0] != 0.0f;
             if (owner) {
