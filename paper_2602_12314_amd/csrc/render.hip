@@ -492,7 +492,9 @@ __device__ inline void raster_bwd_tile(
                     const float al = oG < kAlphaMax ? oG : kAlphaMax;
                     if (al >= kAlphaMin) {
                         hit = true;
-                        T = T / (1.0f - al);
+                        // 1 - al >= 0.01: the hardware reciprocal (1 ulp) replaces the
+                        // IEEE division sequence
+                        T = T * __builtin_amdgcn_rcpf(1.0f - al);
                         wq = al * T;
                         const float* q = st.q + sj * DQ;
                         float dal = 0.0f;
