@@ -415,6 +415,22 @@ __device__ inline void halving_sum(float* v, unsigned lane)
     }
 }
 
+// Wave sum of N values (N a power of two, 8 <= N <= 64): the halving steps
+// over the masks 32 ... 64 / N, then the lanes that still differ in the lower
+// mask bits add their partners' totals.  Afterwards the lanes whose low
+// 6 - log2(N) bits are zero hold value lane >> (6 - log2(N)).
+template <int N>
+__device__ inline float wave_sum_split(float* v, unsigned lane)
+{
+    static_assert(N >= 8 && N <= 64 && (N & (N - 1)) == 0, "N must be a power of two in [8, 64]");
+    constexpr int S = N == 8 ? 3 : N == 16 ? 2 : N == 32 ? 1 : 0;
+    halving_sum<N, 32>(v, lane);
+    if constexpr (S >= 3) v[0] += partner<4>(v[0]);
+    if constexpr (S >= 2) v[0] += partner<2>(v[0]);
+    if constexpr (S >= 1) v[0] += partner<1>(v[0]);
+    return v[0];
+}
+
 // rec_grad[r] = (du, dv, dA, dB, dC, dopacity) accumulated over pixels; with
 // RGBD also d_colors[g] and rec_dz[r] (the gradient of the record's depth).
 template <int DQ, bool RGBD>
@@ -526,8 +542,28 @@ __device__ inline void raster_bwd_tile(
                 }
             }
             if (__ballot(hit) == 0ull) continue;
-            // 6 screen-space terms, DQ query terms (and with RGBD 3 colour terms
-            // and the depth term), padded to NV, summed over the wave by halving:
+            if constexpr (!RGBD) {
+                // The DQ query terms and the 6 screen-space terms (padded to 8)
+                // summed over the wave as two sets, each by halving (no padding
+                // of the query set to 32 or 64 values): lane l then holds query
+                // term l >> (6 - log2 DQ) and screen term l >> 3.
+                float vq[DQ], vs[8] = {gu, gv, gA, gB, gC, gO, 0.0f, 0.0f};
+#pragma unroll
+                for (int k = 0; k < DQ; ++k) vq[k] = wq * g[k];
+                const float sq = wave_sum_split<DQ>(vq, lane);
+                const float ss = wave_sum_split<8>(vs, lane);
+                constexpr int SQ = DQ == 16 ? 2 : 1;
+                const bool oq = (lane & ((1u << SQ) - 1u)) == 0 && sq != 0.0f;
+                const bool os = (lane & 7u) == 0 && (lane >> 3) < 6 && ss != 0.0f;
+                if (oq || os) {
+                    const uint32_t r = st.rec[sj];
+                    if (oq) unsafeAtomicAdd(d_queries + (size_t)(r - (uint32_t)c * (uint32_t)N) * DQ + (lane >> SQ), sq);
+                    if (os) unsafeAtomicAdd(rec_grad + (size_t)r * 6 + (lane >> 3), ss);
+                }
+                continue;
+            }
+            // With RGBD: 6 screen-space terms, DQ query terms, 3 colour terms
+            // and the depth term, padded to NV, summed over the wave by halving:
             // at each step a lane keeps half of its values and adds the partner's
             // copy of that half, so after log2(64) steps lane l holds the total of
             // value (l >> 1) (NV = 32) or l (NV = 64).
