@@ -513,20 +513,24 @@ __device__ inline void raster_bwd_tile(
                         T = T * __builtin_amdgcn_rcpf(1.0f - al);
                         wq = al * T;
                         const float* q = st.q + sj * DQ;
+                        // B <- al q + (1 - al) B as B + al (q - B), the difference
+                        // shared with the alpha gradient: three operations a channel
                         float dal = 0.0f;
 #pragma unroll
                         for (int k = 0; k < DQ; ++k) {
-                            dal += (q[k] - behind[k]) * g[k];
-                            behind[k] = al * q[k] + (1.0f - al) * behind[k];
+                            const float df = q[k] - behind[k];
+                            dal += df * g[k];
+                            behind[k] += al * df;
                         }
                         if constexpr (RGBD) {
                             const float4 x = st.x[sj];
-                            dal += (x.x - behindx.x) * gx.x + (x.y - behindx.y) * gx.y +
-                                   (x.z - behindx.z) * gx.z + (x.w - behindx.w) * gx.w;
-                            behindx.x = al * x.x + (1.0f - al) * behindx.x;
-                            behindx.y = al * x.y + (1.0f - al) * behindx.y;
-                            behindx.z = al * x.z + (1.0f - al) * behindx.z;
-                            behindx.w = al * x.w + (1.0f - al) * behindx.w;
+                            const float d0 = x.x - behindx.x, d1 = x.y - behindx.y;
+                            const float d2 = x.z - behindx.z, d3 = x.w - behindx.w;
+                            dal += d0 * gx.x + d1 * gx.y + d2 * gx.z + d3 * gx.w;
+                            behindx.x += al * d0;
+                            behindx.y += al * d1;
+                            behindx.z += al * d2;
+                            behindx.w += al * d3;
                         }
                         dal *= T;
                         if (oG < kAlphaMax) {
