@@ -89,13 +89,13 @@ def test_rgbd_forward_parity(case):
     assert (to_np(depth) > 0).sum() > 0.3 * depth.numel()
 
 
-@pytest.mark.parametrize("case", ["c0", "multiview_ragged", "c1"])
+@pytest.mark.parametrize("case", ["c0", "multiview_ragged", "c1", "c2_d32"])
 @pytest.mark.parametrize("tile", [(16, 16), (8, 8)])
 def test_rgbd_backward_parity(case, tile):
     from paper_2602_12314_amd import ops
     g, cams = CASES[case]()
-    if case == "c1" and tile != (16, 16):
-        pytest.skip("full-size c1 checked at 16x16")
+    if case in ("c1", "c2_d32") and tile != (16, 16):
+        pytest.skip("full-size c1 and c2 checked at 16x16")
     col = _colors(g.n, 2)
     say(f"[rgbd backward] case={case} N={g.n} tile={tile}")
     r = ops.Renderer(cams, g.n, g.d, tile=tile)
