@@ -41,6 +41,14 @@ def lib():
         _lib.orc_render_backward.restype = i32
         _lib.orc_render_backward.argtypes = [i32, i32, vp, vp, vp, vp, vp, i32, vp, i32, i32, vp] + [vp] * 7
         _lib.orc_num_threads.restype = i32
+        _lib.orc_render_window.restype = i32
+        _lib.orc_render_window.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp, i32, i32, i32, i32, vp, vp, vp]
+        _lib.orc_fd_window.restype = i32
+        _lib.orc_fd_window.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp, i32, i32, i32, i32, vp, i32, vp, vp,
+                                       C.c_double, vp, vp]
+        _lib.orc_pixel_walks.restype = i32
+        _lib.orc_pixel_walks.argtypes = [i32, i32, vp, vp, vp, vp, vp, i32, vp, i32, i32, i32, vp, i32, vp, vp,
+                                         vp, vp, vp]
     return _lib
 
 
@@ -158,3 +166,47 @@ def render_backward(g: Gaussians, cams, dQ, tw=16, th=16, with_rec: bool = False
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+# parameter index of a probe in fd_window: 0-2 mean, 3-5 log-scale, 6-9 quaternion,
+# 10 opacity logit, 11.. query
+PARAM_SLICES = {"means": (0, 3), "log_scales": (3, 6), "quats": (6, 10), "opacity_logits": (10, 11)}
+
+
+def render_window(g: Gaussians, cam, x0, y0, ww, wh):
+    """Q [ww*wh, d], T_final and decision signatures of a pixel window of one
+    camera (row-major inside the window), by the tile-free definition."""
+    cam = _c(np.asarray(cam).reshape(-1)[:22])
+    out = dict(Q=np.zeros((ww * wh, g.d)), T_final=np.zeros(ww * wh), hash=np.zeros(ww * wh, np.uint64))
+    lib().orc_render_window(g.n, g.d, *g.geom_args(), _ptr(g.queries), _ptr(cam), x0, y0, ww, wh,
+                            _ptr(out["Q"]), _ptr(out["T_final"]), _ptr(out["hash"]))
+    return out
+
+
+def fd_window(g: Gaussians, cam, x0, y0, ww, wh, w, probe_gauss, probe_param, hrel=1e-5):
+    """Central differences of sum_p w_p . Q_p over the window for each probe
+    (Gaussian, parameter index); returns (fd, ok) where ok marks probes whose
+    stencil changes no pixel's decisions."""
+    cam = _c(np.asarray(cam).reshape(-1)[:22])
+    w = _c(w, np.float64).reshape(ww * wh, g.d)
+    pg = _c(probe_gauss, np.int32)
+    pk = _c(probe_param, np.int32)
+    fd = np.zeros(len(pg))
+    ok = np.zeros(len(pg), np.int32)
+    lib().orc_fd_window(g.n, g.d, *g.geom_args(), _ptr(g.queries), _ptr(cam), x0, y0, ww, wh, _ptr(w), len(pg),
+                        _ptr(pg), _ptr(pk), float(hrel), _ptr(fd), _ptr(ok))
+    return fd, ok.astype(bool)
+
+
+def pixel_walks(g: Gaussians, cams, pixels, max_len=4096, tw=16, th=16):
+    """Per listed pixel: blended record ids, their alphas and the transmittance
+    before each (arrays [npix, max_len], valid up to count), count, T_final."""
+    cams = _c(cams)
+    px = _c(pixels, np.int64)
+    k = len(px)
+    out = dict(recs=np.full((k, max_len), -1, np.int64), alpha=np.zeros((k, max_len)),
+               T_before=np.zeros((k, max_len)), count=np.zeros(k, np.int32), T_final=np.zeros(k))
+    lib().orc_pixel_walks(g.n, g.d, *g.geom_args(), _ptr(g.queries), cams.shape[0], _ptr(cams), tw, th, k,
+                          _ptr(px), max_len, _ptr(out["recs"]), _ptr(out["alpha"]), _ptr(out["T_before"]),
+                          _ptr(out["count"]), _ptr(out["T_final"]))
+    return out

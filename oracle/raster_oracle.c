@@ -811,3 +811,211 @@ int orc_render_backward(int n, int d, const float* means, const float* log_scale
 }
 
 int orc_num_threads(void) { return omp_get_max_threads(); }
+
+/* ======================================================= pixel windows
+ *
+ * Test helpers over a rectangular window of pixels of ONE camera: the
+ * tile-free definition (every visible record in (depth key, record) order,
+ * the per-pixel footprint test inside blend_pixel), which the tile-binned
+ * render equals bitwise (pinned on tiny scenes).  Used to take central finite
+ * differences at realistic list lengths without re-rendering a whole frame. */
+
+typedef struct {
+    const proj_t* proj;
+    const uint32_t* order; /* visible records by (depth key, record) */
+    int64_t m;
+} worder_t;
+
+static int cmp_rec_key(const proj_t* pr, uint32_t a, uint32_t b)
+{
+    if (pr[a].depth_key != pr[b].depth_key) return pr[a].depth_key < pr[b].depth_key ? -1 : 1;
+    return a < b ? -1 : (a > b);
+}
+
+/* Blend every window pixel; returns sum_p w_p . Q_p (w may be NULL: 0) and
+ * writes Q [npx, d], T [npx] and the decision signatures [npx] when non-NULL. */
+static double window_eval(const scene_t* S, const float* queries, const uint32_t* order, int64_t m,
+                          int x0, int y0, int ww, int wh, const double* w, double* Qbuf, double* Tbuf,
+                          uint64_t* hash, double* Qout)
+{
+    double acc = 0.0;
+    const int d = S->d;
+    for (int yy = 0; yy < wh; ++yy)
+        for (int xx = 0; xx < ww; ++xx) {
+            const int64_t p = (int64_t)yy * ww + xx;
+            double T;
+            uint64_t h;
+            blend_pixel(S, queries, x0 + xx, y0 + yy, order, m, Qbuf, NULL, &T, NULL, NULL, NULL, NULL, &h,
+                        NULL);
+            if (hash) hash[p] = h;
+            if (Tbuf) Tbuf[p] = T;
+            if (Qout) memcpy(Qout + p * d, Qbuf, (size_t)d * sizeof(double));
+            if (w)
+                for (int j = 0; j < d; ++j) acc += w[p * d + j] * Qbuf[j];
+        }
+    return acc;
+}
+
+static int64_t visible_order(const scene_t* S, uint32_t* order)
+{
+    int64_t m = 0;
+    for (int64_t i = 0; i < S->n; ++i)
+        if (S->proj[i].vis) order[m++] = (uint32_t)i;
+    qsort_r(order, (size_t)m, sizeof(uint32_t), rec_cmp_depth, (void*)S->proj);
+    return m;
+}
+
+/* Query map, transmittance and decision signatures of the pixels
+ * [x0, x0 + ww) x [y0, y0 + wh) of the camera ``cam`` (one row). */
+int orc_render_window(int n, int d, const float* means, const float* log_scales, const float* quats,
+                      const float* logits, const float* queries, const float* cam, int x0, int y0, int ww,
+                      int wh, double* Q, double* T_final, uint64_t* hash)
+{
+    scene_t S;
+    memset(&S, 0, sizeof S);
+    scene_project(&S, n, means, log_scales, quats, logits, 1, cam, 16, 16);
+    S.d = d;
+    uint32_t* order = (uint32_t*)malloc((size_t)(n > 0 ? n : 1) * sizeof(uint32_t));
+    const int64_t m = visible_order(&S, order);
+    double* Qbuf = (double*)malloc((size_t)d * sizeof(double));
+    window_eval(&S, queries, order, m, x0, y0, ww, wh, NULL, Qbuf, T_final, hash, Q);
+    free(Qbuf);
+    free(order);
+    scene_free(&S);
+    return 0;
+}
+
+/* Central finite differences of L(theta) = sum_p w_p . Q_p(theta) over the
+ * window for a list of probes (Gaussian pg[j], parameter pk[j]); parameter
+ * index k: 0-2 mean, 3-5 log-scale, 6-9 quaternion, 10 opacity logit,
+ * 11 .. 10 + d query.  The perturbed value x +- h (h = hrel max(1, |x|)) is
+ * rounded to float32, as the inputs are float32, and the realised step is
+ * the exact difference of the two rounded values.  ok[j] = 1 when no pixel's
+ * decision signature (which records blend, in which order, which are clamped)
+ * changes inside the stencil, i.e. the functional is differentiable there. */
+int orc_fd_window(int n, int d, const float* means, const float* log_scales, const float* quats,
+                  const float* logits, const float* queries, const float* cam, int x0, int y0, int ww, int wh,
+                  const double* w, int nprobe, const int32_t* pg, const int32_t* pk, double hrel, double* fd,
+                  int32_t* ok)
+{
+    scene_t S;
+    memset(&S, 0, sizeof S);
+    scene_project(&S, n, means, log_scales, quats, logits, 1, cam, 16, 16);
+    S.d = d;
+    const int64_t npx = (int64_t)ww * wh;
+    uint32_t* order = (uint32_t*)malloc((size_t)(n > 0 ? n : 1) * sizeof(uint32_t));
+    const int64_t m = visible_order(&S, order);
+    uint64_t* h0 = (uint64_t*)malloc((size_t)(npx > 0 ? npx : 1) * sizeof(uint64_t));
+    {
+        double* Qbuf = (double*)malloc((size_t)d * sizeof(double));
+        window_eval(&S, queries, order, m, x0, y0, ww, wh, NULL, Qbuf, NULL, h0, NULL);
+        free(Qbuf);
+    }
+#pragma omp parallel
+    {
+        scene_t L = S;
+        proj_t* pr = (proj_t*)malloc((size_t)(n > 0 ? n : 1) * sizeof(proj_t));
+        memcpy(pr, S.proj, (size_t)n * sizeof(proj_t));
+        L.proj = pr;
+        float* qloc = (float*)malloc((size_t)(n > 0 ? n : 1) * d * sizeof(float));
+        memcpy(qloc, queries, (size_t)n * d * sizeof(float));
+        uint32_t* ord = (uint32_t*)malloc((size_t)(n > 0 ? n : 1) * sizeof(uint32_t));
+        uint64_t* hh = (uint64_t*)malloc((size_t)(npx > 0 ? npx : 1) * sizeof(uint64_t));
+        double* Qbuf = (double*)malloc((size_t)d * sizeof(double));
+#pragma omp for schedule(dynamic, 4)
+        for (int j = 0; j < nprobe; ++j) {
+            const int i = pg[j], k = pk[j];
+            float mu[3], ls[3], qt[4], lg = logits[i];
+            memcpy(mu, means + 3 * (size_t)i, sizeof mu);
+            memcpy(ls, log_scales + 3 * (size_t)i, sizeof ls);
+            memcpy(qt, quats + 4 * (size_t)i, sizeof qt);
+            float* slot = k < 3 ? &mu[k] : k < 6 ? &ls[k - 3] : k < 10 ? &qt[k - 6] : k == 10 ? &lg
+                                                                                      : &qloc[(size_t)i * d + (k - 11)];
+            const float xv = *slot;
+            const double h = hrel * fmax(1.0, fabs((double)xv));
+            double val[2], step[2];
+            int good = 1;
+            for (int sgn = 0; sgn < 2; ++sgn) {
+                const float xp = (float)((double)xv + (sgn == 0 ? h : -h));
+                step[sgn] = fabs((double)xp - (double)xv);
+                *slot = xp;
+                project_one(mu, ls, qt, lg, &S.cams[0], &pr[i]);
+                /* the order with record i at the place its (new) depth key takes */
+                int64_t mm = 0;
+                for (int64_t t = 0; t < m; ++t)
+                    if (order[t] != (uint32_t)i) ord[mm++] = order[t];
+                if (pr[i].vis) {
+                    int64_t pos = mm;
+                    for (int64_t t = 0; t < mm; ++t)
+                        if (cmp_rec_key(pr, (uint32_t)i, ord[t]) < 0) { pos = t; break; }
+                    memmove(ord + pos + 1, ord + pos, (size_t)(mm - pos) * sizeof(uint32_t));
+                    ord[pos] = (uint32_t)i;
+                    ++mm;
+                }
+                val[sgn] = window_eval(&L, qloc, ord, mm, x0, y0, ww, wh, w, Qbuf, NULL, hh, NULL);
+                for (int64_t p = 0; p < npx; ++p)
+                    if (hh[p] != h0[p]) { good = 0; break; }
+                *slot = xv;
+            }
+            pr[i] = S.proj[i];
+            fd[j] = (val[0] - val[1]) / (step[0] + step[1]);
+            ok[j] = good && step[0] > 0.0 && step[1] > 0.0;
+        }
+        free(pr);
+        free(qloc);
+        free(ord);
+        free(hh);
+        free(Qbuf);
+    }
+    free(h0);
+    free(order);
+    scene_free(&S);
+    return 0;
+}
+
+/* The walk of each listed pixel p (concatenated pixel order) through its
+ * tile's list: for the k-th blended record, its id, its alpha and the
+ * transmittance before it (T_k), at most max_len entries per pixel; count[i]
+ * the number blended and T_final[i] the transmittance left. */
+int orc_pixel_walks(int n, int d, const float* means, const float* log_scales, const float* quats,
+                    const float* logits, const float* queries, int n_cams, const float* cams, int tw, int th,
+                    int npix, const int64_t* pixels, int max_len, int64_t* recs, double* alpha,
+                    double* T_before, int32_t* count, double* T_final)
+{
+    scene_t S;
+    memset(&S, 0, sizeof S);
+    scene_project(&S, n, means, log_scales, quats, logits, n_cams, cams, tw, th);
+    S.d = d;
+    bins_t B;
+    scene_bin(&S, &B);
+    uint32_t* ids;
+    tile_list(&S, &B, &ids);
+    int64_t maxlen = 1;
+    for (int64_t t = 0; t < S.tile_off[n_cams]; ++t) {
+        int64_t len = (int64_t)B.ranges[2 * t + 1] - B.ranges[2 * t];
+        if (len > maxlen) maxlen = len;
+    }
+    contrib_t* cs = (contrib_t*)malloc((size_t)maxlen * sizeof(contrib_t));
+    double* Qp = (double*)malloc((size_t)(d > 0 ? d : 1) * sizeof(double));
+    for (int i = 0; i < npix; ++i) {
+        int c, x, y;
+        pixel_coords(&S, pixels[i], &c, &x, &y);
+        int64_t t = S.tile_off[c] + (int64_t)(y / th) * S.tiles_x[c] + x / tw;
+        uint32_t s0 = B.ranges[2 * t], s1 = B.ranges[2 * t + 1];
+        int32_t nb = 0;
+        blend_pixel(&S, queries, x, y, ids + s0, (int64_t)s1 - s0, Qp, NULL, &T_final[i], NULL, &nb, NULL, NULL,
+                    NULL, cs);
+        count[i] = nb;
+        for (int k = 0; k < nb && k < max_len; ++k) {
+            recs[(int64_t)i * max_len + k] = cs[k].rec;
+            alpha[(int64_t)i * max_len + k] = cs[k].alpha;
+            T_before[(int64_t)i * max_len + k] = cs[k].T;
+        }
+    }
+    free(cs);
+    free(Qp);
+    free(ids);
+    bins_free(&B);
+    scene_free(&S);
+    return 0;
+}

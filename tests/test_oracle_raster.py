@@ -391,3 +391,69 @@ def test_fd_gradients_with_depth_rotated_two_views():
     g.means[:, 2] -= 1.0
     cams = cams_of(scenes.pinhole(30, 24, 24.0, pose), scenes.pinhole(26, 20, 20.0))
     assert _fd_check(g, cams, 8, tile=(8, 8), depth=True) > 250
+
+
+# ------------------------------------------------ footprint and walk properties
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_footprint_rect_is_the_pixel_set_at_non_integer_centres(seed):
+    # The footprint of a record is exactly {px : |px - u| <= r} x {py : |py - v| <= r}
+    # intersected with the image, enumerated here pixel by pixel from the
+    # projected (u, v, r).  Off-axis centres are non-integer, so a ceil/floor
+    # slip at either end of the interval shows up.
+    pose = scenes.look_at_origin((0.7, -0.2, -2.6))
+    g, _ = tiny_scene(seed, n=400, w=61, h=47, f=40.0)
+    g.means[:, 2] += 0.4
+    cams = cams_of(scenes.pinhole(61, 47, 40.0), scenes.pinhole(45, 38, 33.0, pose))
+    p = R.project(g, cams)
+    checked = 0
+    for r in np.nonzero(p["vis"])[0]:
+        c = r // g.n
+        W, H = int(cams[c, 0]), int(cams[c, 1])
+        u, v = p["uv"][r]
+        rad = p["radius"][r]
+        xs = np.arange(W)
+        ys = np.arange(H)
+        inx = xs[np.abs(xs - u) <= rad]
+        iny = ys[np.abs(ys - v) <= rad]
+        assert len(inx) and len(iny)
+        assert list(p["rect"][r]) == [inx.min(), inx.max(), iny.min(), iny.max()], (r, u, v, rad)
+        checked += u != np.floor(u)
+    assert checked > 300
+    # and no record outside the image survives
+    for r in np.nonzero(p["vis"] == 0)[0]:
+        c = r // g.n
+        if p["z"][r] <= 0.2 or p["radius"][r] == 0:
+            continue
+        W, H = int(cams[c, 0]), int(cams[c, 1])
+        u, v = p["uv"][r]
+        rad = p["radius"][r]
+        assert not ((np.abs(np.arange(W) - u) <= rad).any() and (np.abs(np.arange(H) - v) <= rad).any())
+
+
+def test_transmittance_non_increasing_along_every_walk():
+    # Along each pixel's walk T_0 = 1, T_{k+1} = T_k (1 - alpha_k) <= T_k, every
+    # alpha in [1/255, 0.99], every T in [1e-4, 1], and T_final the product.
+    s = scenes.make_scene(scenes.spec(0), seed=3, with_target=False)
+    g = R.Gaussians.of(s)
+    P = R.n_pixels(s.cams)
+    pix = np.arange(P)
+    wk = R.pixel_walks(g, s.cams, pix, max_len=1024)
+    f = R.render_forward(g, s.cams)
+    assert np.array_equal(wk["count"], f["n_blended"])
+    assert np.array_equal(wk["T_final"], f["T_final"])
+    assert wk["count"].max() < 1024 and wk["count"].sum() > 10 * P
+    for i in range(P):
+        k = wk["count"][i]
+        if k == 0:
+            assert wk["T_final"][i] == 1.0
+            continue
+        a = wk["alpha"][i, :k]
+        T = wk["T_before"][i, :k]
+        assert T[0] == 1.0
+        assert np.all(a >= 1.0 / 255.0) and np.all(a <= 0.99)
+        assert np.all(np.diff(T) <= 0.0)
+        np.testing.assert_array_equal(T[1:], T[:-1] * (1.0 - a[:-1]))
+        assert wk["T_final"][i] == T[-1] * (1.0 - a[-1])
+        assert wk["T_final"][i] >= 1e-4 and wk["T_final"][i] <= T[-1]
+        np.testing.assert_allclose(wk["T_final"][i], np.prod(1.0 - a), rtol=1e-12)
