@@ -3,13 +3,19 @@
 
 One step = render_forward (projection, binning, sort, compositing) + the
 decode/loss call (softmax(Q K^T / sqrt d) V, cosine loss with trust region,
-and its gradients) + render_backward, for one keyframe of the 640x480
-workload (100k Gaussians, d=16, M=256, D=512) with a BF16 decode.  Inputs
-are seeded synthetic arrays resident in HBM before timing starts.
+and its gradients) + render_backward.  The headline workload is the largest
+single-GPU one: one 1200x680 keyframe of a 2M-Gaussian multi-floor map,
+d = 32, M = D = 1024, decoded in BF16 (the narrowest arithmetic that meets
+the error bar); the E4M3 and FP32 decode paths are timed beside it, and the
+640x480 keyframe (100k Gaussians, d = 16, M = 256, D = 512) is a secondary
+workload.  Inputs are seeded synthetic arrays resident in HBM before timing
+starts; the render tile shape and the decode block shape are autotuned.
 
 Prints one JSON line: feature-pixels/s, per-stage times, the roofline of the
-dominant kernel (timed with HIP events on its launch stream), the FP32 decode
-path for comparison, and the FP64 CPU oracle timed on the host.
+dominant kernel (timed with HIP events on its launch stream) against the
+algorithmic work of the method, the error of every output against the FP64
+oracle on the workload's 128 x 128 crop, and the FP64 CPU oracle timed on
+the host.
 """
 from __future__ import annotations
 
@@ -27,62 +33,60 @@ PEAKS = {  # MI355X published peaks
     "bf16_tflops": 2500.0,
     "fp8_tflops": 5000.0,
     "fp32_mfma_tflops": 157.3,
-    "fp32_vector_tflops": 157.3,
+    # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz: the library is built with
+    # packed FP32 disabled, so the packed rate (twice this) is out of reach
+    "fp32_vector_tflops": 78.6,
 }
+
+# the benchmark spec bars for the reduced-precision decode forms
+BAR_MIN_COS_F = 0.999
+BAR_GRAD_REL = 1e-2
 
 
 def _log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def algorithmic_work(spec, prec: str, pairs_eval: int, pairs_blend: int, tile_pairs: int):
-    """Algorithmic flops and HBM bytes per launch of each main kernel.
-
-    Bytes count what the kernel must move to and from HBM once: its per-pixel
-    inputs and outputs, the per-pair records of the tile lists, and the
-    operands it hands to the next kernel.  The dictionary (K, V) is read from
-    the L2 cache and counted once per launch.
-    """
-    n, d, M, D = spec.n_pixels, spec.d, spec.M, spec.D
-    N = spec.n_gauss * len(spec.cams)
-    Mp = (M + 63) // 64 * 64
-    splits = dv_splits(n, Mp, D)
-    tb = 4 if prec == "fp32" else 2  # bytes of the decode's compute type
-    dict_bytes = tb * (2 * M * D + 2 * M * d)
-    entry = 44 + 4 * d  # one tile-list entry: record id, rec0, rec1, footprint, query
+def decode_work(n, d, M, D):
+    """Algorithmic work of the decode per launch (the method's, not the design's):
+    per pixel 6 M (d + D) flops for S, F, dP, dV, dQ, dK, and (2 d + D) 4 bytes
+    (Q and the target read once, dQ written once).  The rows kernel does S, F,
+    dP and dQ (4 M (d + D)) and moves all of the per-pixel bytes; the dV kernel
+    does 2 M D; the dK kernel 2 M d."""
     return {
-        # MFMA: S = Q K^T (2Md), F = P V (2MD), dP = G V^T (2MD), dQ = dS K (2Md) per pixel.
-        # Bytes: Q and the target in (FP32); G^T, dS^T, Q^T (compute type) and the
-        # row max (FP32) out.
-        "decode_rows": dict(flops=n * 4.0 * M * (d + D), mfma=True,
-                            bytes=n * (4.0 * d + 4.0 * D + tb * (M + D + 32) + 4) + dict_bytes),
-        # MFMA: dV = P~^T G with P~ rebuilt from S = Q K^T, 2M (D + d) per pixel;
-        # bytes: G^T, Q and the row max in, the split partials out.
-        "decode_tn": dict(flops=n * 2.0 * M * (D + d), mfma=True,
-                          bytes=n * (tb * D + 4.0 * d + 4) + splits * Mp * D * 4.0),
-        # VALU: per evaluated pair 20 flops (offset, conic form, exp, opacity, clamp,
-        # transmittance); per blended pair 2d more for the query accumulation.
-        # Bytes: the tile lists, and Q, T (twice) and the contributor count per pixel.
-        "raster_fwd": dict(flops=20.0 * pairs_eval + 2.0 * d * pairs_blend, mfma=False,
-                           bytes=tile_pairs * entry + n * (4.0 * d + 12)),
-        # VALU: per blended pair 45 + 9d flops (alpha and transmittance rebuild,
-        # dq, dalpha, behind-sum update, conic/mean/opacity terms).  Bytes: the tile
-        # lists, dQ, T and the count per pixel, and the per-record gradients.
-        "raster_bwd": dict(flops=(45.0 + 9.0 * d) * pairs_blend, mfma=False,
-                           bytes=tile_pairs * entry + n * (4.0 * d + 8) + N * (24.0 + 4 * d)),
+        "decode_rows": dict(flops=4.0 * n * M * (d + D), bytes=4.0 * n * (2 * d + D), mfma=True),
+        "decode_tn": dict(flops=2.0 * n * M * D, bytes=4.0 * M * D, mfma=True),
+        "decode_total": dict(flops=6.0 * n * M * (d + D), bytes=4.0 * n * (2 * d + D), mfma=True),
     }
 
 
-def dv_splits(n: int, Mp: int, D: int) -> int:
-    """Split-K count of the dV reduction (decode_layout's rule): enough
-    workgroups to fill 256 CUs twice, a multiple of 8, at most the block count."""
-    nb = max(((n + 63) // 64) * 2, 1)
-    tiles = ((Mp + 127) // 128) * (D // (256 if D % 256 == 0 else 128))
-    s = (512 + tiles - 1) // tiles
-    s = (s + 7) // 8 * 8
-    if s > nb:
-        s = (nb + 7) // 8 * 8
-    return max(s, 8)
+def decode_issued(n, d, M, D, prec):
+    """Bytes the design adds on top: the rows kernel writes G^T, dS^T, Q^T in the
+    compute type and one row max per pixel, which the dV and dK GEMMs read back;
+    the softmax logits are recomputed (2 M d flops per pixel in each of the
+    three passes that need them)."""
+    tb = 4 if prec == "fp32" else 2
+    Mp = (M + 63) // 64 * 64
+    inter = n * (tb * (D + Mp + 32) + 4.0)
+    return {"intermediate_bytes_written": inter, "intermediate_bytes_read": inter,
+            "issued_flops_rows": n * (4.0 * M * (d + D) + 4.0 * M * d),
+            "issued_flops_dv": n * 2.0 * M * (D + d)}
+
+
+def raster_work(spec, pairs_eval: int, pairs_blend: int, tile_pairs: int):
+    """Algorithmic work of the compositing kernels: per evaluated pair 20 flops
+    (offset, conic form, exp, opacity, clamp, transmittance), per blended pair
+    2 d more forward and 45 + 9 d backward; bytes: the tile lists, the per-pixel
+    outputs and the per-record gradients."""
+    n, d = spec.n_pixels, spec.d
+    N = spec.n_gauss * len(spec.cams)
+    entry = 44 + 4 * d  # one tile-list entry: record id, rec0, rec1, footprint, query
+    return {
+        "raster_fwd": dict(flops=20.0 * pairs_eval + 2.0 * d * pairs_blend, mfma=False,
+                           bytes=tile_pairs * entry + n * (4.0 * d + 12)),
+        "raster_bwd": dict(flops=(45.0 + 9.0 * d) * pairs_blend, mfma=False,
+                           bytes=tile_pairs * entry + n * (4.0 * d + 8) + N * (24.0 + 4 * d)),
+    }
 
 
 def roofline(work: dict, ms: float, prec: str) -> dict:
@@ -103,74 +107,87 @@ def roofline(work: dict, ms: float, prec: str) -> dict:
             "unit": "TFLOP/s", "frac": ach / fpeak}
 
 
-def run(args):
-    import numpy as np
-    import torch
+PROF_STAGES = ("raster_fwd", "raster_bwd", "decode_rows", "decode_tn", "render_sort", "preprocess",
+               "preprocess_bwd")
 
-    from paper_2602_12314_amd import _lib, ops, scenes
 
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
-    dev = torch.device("cuda:0")
-    spec = scenes.spec(args.workload)
-    prec = args.precision or spec.precision
-    tw, th = (int(v) for v in args.tile.split("x"))
-    _log(f"[bench] generating workload {spec.name}")
-    s = scenes.make_scene(spec, seed=0)
-    g = ops.Gaussians.from_numpy(s, device=dev)
-    K = torch.as_tensor(s.K, device=dev)
-    V = torch.as_tensor(s.V, device=dev)
-    K0 = torch.as_tensor(s.K0, device=dev)
-    tgt = torch.as_tensor(s.target, device=dev)
-    n = spec.n_pixels
-    tune = None
-    if args.autotune:
-        from paper_2602_12314_amd import autotune
-        (tw, th), tune = autotune.best_tile(g, s.cams)
-        args.tile = f"{tw}x{th}"
-        _log(f"[bench] autotuned tile {args.tile}: {tune}")
-    decode_shape = "px32"
-    if args.autotune:
-        from paper_2602_12314_amd import autotune
-        decode_shape, dtimes = autotune.best_decode_shape(prec, n, spec.d, spec.M, spec.D)
-        _lib.set_decode_shape(decode_shape)
-        tune = {"tile_ms": tune, "decode_shape_ms": dtimes}
-        _log(f"[bench] autotuned decode shape {decode_shape}: {dtimes}")
-    r = ops.Renderer(s.cams, spec.n_gauss, spec.d, tile=(tw, th))
-    Q = torch.empty((n, spec.d), device=dev)
-    T = torch.empty((n,), device=dev)
-    grads = g.zeros_like()
+class Workload:
+    """One workload on the GPU: scene, dictionary, target, renderer, and the
+    step (render forward, decode + loss + gradients, render backward)."""
 
-    # The dictionary gradients (dV, dK, their reductions, the loss) run on a
-    # second stream beside the render backward, which needs only dQ.
-    side = None if args.no_overlap else torch.cuda.Stream(device=dev)
+    def __init__(self, idx, prec, dev, autotune=True, tile="16x16"):
+        import torch
 
-    def make_step(dec, overlap=True):
+        from paper_2602_12314_amd import _lib, ops, scenes
+        self.torch, self.ops, self._lib = torch, ops, _lib
+        self.spec = scenes.spec(idx)
+        self.prec = prec
+        self.dev = dev
+        _log(f"[bench] generating workload {self.spec.name}")
+        s = scenes.make_scene(self.spec, seed=0)
+        self.s = s
+        self.g = ops.Gaussians.from_numpy(s, device=dev)
+        self.K = torch.as_tensor(s.K, device=dev)
+        self.V = torch.as_tensor(s.V, device=dev)
+        self.K0 = torch.as_tensor(s.K0, device=dev)
+        self.tgt = torch.as_tensor(s.target, device=dev)
+        sp = self.spec
+        self.n = sp.n_pixels
+        tw, th = (int(v) for v in tile.split("x"))
+        self.tune = None
+        self.decode_shape = "px32"
+        if autotune:
+            from paper_2602_12314_amd import autotune as AT
+            (tw, th), tile_ms = AT.best_tile(self.g, s.cams)
+            self.decode_shape, dec_ms = AT.best_decode_shape(prec, self.n, sp.d, sp.M, sp.D)
+            self.tune = {"tile_ms": tile_ms, "decode_shape_ms": dec_ms}
+            _log(f"[bench] autotuned tile {tw}x{th}: {tile_ms}")
+            _log(f"[bench] autotuned decode shape {self.decode_shape}: {dec_ms}")
+        _lib.set_decode_shape(self.decode_shape)
+        self.tile = f"{tw}x{th}"
+        self.r = ops.Renderer(s.cams, sp.n_gauss, sp.d, tile=(tw, th))
+        self.Q = torch.empty((self.n, sp.d), device=dev)
+        self.T = torch.empty((self.n,), device=dev)
+        self.grads = self.g.zeros_like()
+        self.side = torch.cuda.Stream(device=dev)
+        self.r.forward(self.g, self.Q, self.T, check=True)  # sizes the pair capacity
+        torch.cuda.synchronize()
+
+    def decoder(self, prec, n=None):
+        sp = self.spec
+        return self.ops.Decoder(prec, self.n if n is None else n, sp.d, sp.M, sp.D, device=self.dev)
+
+    def make_step(self, dec, overlap):
+        r, g, Q, T, K, V, tgt, K0, lam = (self.r, self.g, self.Q, self.T, self.K, self.V, self.tgt, self.K0,
+                                          self.spec.lambda_tr)
+        torch, side, grads = self.torch, self.side, self.grads
+
         def step():
             r.forward(g, Q, T, check=False)
-            if side is not None and overlap:
-                loss, dQ, dK, dV = dec.loss_and_grads(Q, K, V, tgt, K0, spec.lambda_tr, dict_stream=side)
+            if overlap:
+                loss, dQ, dK, dV = dec.loss_and_grads(Q, K, V, tgt, K0, lam, dict_stream=side)
                 r.backward(g, dQ, out=grads)
                 torch.cuda.current_stream().wait_stream(side)
             else:
-                loss, dQ, dK, dV = dec.loss_and_grads(Q, K, V, tgt, K0, spec.lambda_tr)
+                loss, dQ, dK, dV = dec.loss_and_grads(Q, K, V, tgt, K0, lam)
                 r.backward(g, dQ, out=grads)
             return loss
         return step
 
-    def timed(dec, steps, warmup, profile):
-        # one stream: the per-kernel times are taken without a concurrent kernel
-        step = make_step(dec, overlap=False)
-        r.forward(g, Q, T, check=True)  # sizes the pair capacity
+    def timed(self, dec, steps, warmup, profile=True):
+        """Eager launches on one stream (the per-kernel times are taken without a
+        concurrent kernel): seconds per step, loss, per-stage ms."""
+        torch = self.torch
+        step = self.make_step(dec, overlap=False)
         for _ in range(warmup):
             step()
         torch.cuda.synchronize()
-        need, over = r.counters()
+        need, over = self.r.counters()
         assert not over, "pair capacity overflow after warm-up"
-        L = _lib.lib()
+        L = self._lib.lib()
         if profile:
             L.lam_profile_enable(1)
-            for name in ("raster_fwd", "raster_bwd", "decode_rows", "decode_tn", "render_sort",
-                         "preprocess", "preprocess_bwd"):
+            for name in PROF_STAGES:
                 _read_prof(L, name)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -180,22 +197,24 @@ def run(args):
         t1 = time.perf_counter()
         prof = {}
         if profile:
-            for name in ("raster_fwd", "raster_bwd", "decode_rows", "decode_tn", "render_sort",
-                         "preprocess", "preprocess_bwd"):
+            for name in PROF_STAGES:
                 tot, cnt = _read_prof(L, name)
                 if cnt:
                     prof[name] = tot / cnt
             L.lam_profile_enable(0)
-        return (t1 - t0) / steps, float(loss), prof, need
+        self.pairs = need
+        return (t1 - t0) / steps, float(loss), prof
 
-    def graph_timed(dec, steps, warmup):
+    def graph_timed(self, dec, steps, warmup, overlap):
+        """Replays of the step captured in a HIP graph (dictionary gradients on a
+        second stream inside the graph when ``overlap``)."""
+        torch = self.torch
         holder = {}
-        base = make_step(dec, overlap=args.graph_overlap)
+        base = self.make_step(dec, overlap=overlap)
 
         def step():
             holder["loss"] = base()
 
-        r.forward(g, Q, T, check=True)
         s_ = torch.cuda.Stream()
         s_.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(s_):
@@ -213,38 +232,271 @@ def run(args):
             graph.replay()
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        assert not r.counters()[1]
+        assert not self.r.counters()[1]
         return (t1 - t0) / steps, float(holder["loss"])
 
-    dec = ops.Decoder(prec, n, spec.d, spec.M, spec.D, device=dev)
+
+def crop_window(spec):
+    """The error crop of camera 0: a 128 x 128 window at the image centre
+    (x0, y0, w, h), clipped to smaller images."""
+    cam = spec.cams[0]
+    w, h = min(128, cam.width), min(128, cam.height)
+    return (cam.width - w) // 2, (cam.height - h) // 2, w, h
+
+
+def _crop_pixels(cams, crop):
+    import numpy as np
+    x0, y0, cw, ch = crop
+    W = int(cams[0, 0])
+    return ((np.arange(ch)[:, None] + y0) * W + (np.arange(cw)[None, :] + x0)).ravel()
+
+
+def oracle_reference(wl, crop):
+    """The FP64 oracle on the workload: the whole frame's render forward, the
+    decode of the crop's rows, and the render adjoint of the whole frame for
+    the oracle's dQ on the crop (zero elsewhere, and on pixels whose walk takes
+    a threshold decision within FP32 reach of the threshold).  Returns the
+    reference arrays and the oracle's own times (s)."""
+    import numpy as np
+
+    from oracle import decode_oracle as DO
+    from oracle import raster as R
+    s, sp = wl.s, wl.spec
+    pix = _crop_pixels(s.cams, crop)
+    g = R.Gaussians.of(s)
+    t0 = time.perf_counter()
+    f = R.render_forward(g, s.cams)
+    t_fwd = time.perf_counter() - t0
+    ok = f["margin"][pix] >= 1e-5
+    tgt = s.target[pix].astype(np.float64)
+    t0 = time.perf_counter()
+    d_or = DO.loss_and_grads(f["Q"][pix], s.K, s.V, tgt, s.K0, sp.lambda_tr)
+    t_dec = time.perf_counter() - t0
+    up = np.zeros((wl.n, sp.d))
+    up[pix[ok]] = d_or["dQ"][ok]
+    t0 = time.perf_counter()
+    b = R.render_backward(g, s.cams, up)
+    t_bwd = time.perf_counter() - t0
+    return dict(crop=crop, pix=pix, ok=ok, f=f, tgt=tgt, up=up, bwd=b, t_fwd=t_fwd, t_dec=t_dec, t_bwd=t_bwd,
+                pairs_eval=int(f["n_pairs"].sum()), pairs_blend=int(f["n_blended"].sum()))
+
+
+def decode_errors(F, row_cos, loss, dQ, dK, dV, ref):
+    """Errors of a decode call on the crop rows against the oracle's: F as the
+    per-row cosine with the FP64 F (minimum, 1st percentile, mean) and relative
+    L2; loss; each gradient as relative L2 and the largest element error
+    relative to the tensor's largest element."""
+    import numpy as np
+
+    def rel(a, b):
+        a = a.detach().double().cpu().numpy() if hasattr(a, "detach") else np.asarray(a, np.float64)
+        return {"rel_l2": float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)),
+                "max_elem": float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))}
+    Fg = F.detach().double().cpu().numpy()
+    Fr = ref["F"]
+    cF = (Fg * Fr).sum(1) / np.maximum(np.linalg.norm(Fg, axis=1) * np.linalg.norm(Fr, axis=1), 1e-300)
+    out = {"F_cos_min": float(cF.min()), "F_cos_p1": float(np.percentile(cF, 1)), "F_cos_mean": float(cF.mean()),
+           "F": rel(Fg, Fr),
+           "row_cos_max_abs_err": float(np.abs(row_cos.double().cpu().numpy() - ref["cos"]).max()),
+           "loss_rel_err": abs(float(loss) - ref["loss"]) / abs(ref["loss"]),
+           "dQ": rel(dQ, ref["dQ"]), "dK": rel(dK, ref["dK"]), "dV": rel(dV, ref["dV"])}
+    grad_worst = max(out[k]["rel_l2"] for k in ("dQ", "dK", "dV"))
+    out["meets_bar"] = bool(out["F_cos_min"] >= BAR_MIN_COS_F and grad_worst <= BAR_GRAD_REL)
+    return out
+
+
+def oracle_check(wl, ref, precs):
+    """One more step outside every timed region: the GPU's render (the crop,
+    and over the whole frame the contributor counts), its decode of the crop
+    rows in each precision, and its render backward for the oracle's upstream
+    gradient on the crop, against the FP64 oracle."""
+    import numpy as np
+    torch = wl.torch
+
+    from oracle import decode_oracle as DO
+    sp, pix, ok, f = wl.spec, ref["pix"], ref["ok"], ref["f"]
+    wl.r.forward(wl.g, wl.Q, wl.T, check=False)
+    torch.cuda.synchronize()
+    sel = torch.as_tensor(pix, device=wl.dev)
+    Qg = wl.Q[sel].double().cpu().numpy()
+    Qo = f["Q"][pix]
+    Tg = wl.T[sel].double().cpu().numpy()
+    To = f["T_final"][pix]
+    amb_all = f["margin"] < 1e-5
+    out = {"crop": list(ref["crop"]), "pixels": int(len(pix)), "ambiguous_pixels": int((~ok).sum()),
+           "render": {"Q_rel_l2": float(np.linalg.norm(Qg[ok] - Qo[ok]) / np.linalg.norm(Qo[ok])),
+                      "Q_max_elem": float(np.abs(Qg[ok] - Qo[ok]).max() / np.abs(Qo[ok]).max()),
+                      "T_final_rel_l2": float(np.linalg.norm(Tg[ok] - To[ok]) / np.linalg.norm(To[ok])),
+                      "T_final_max_abs": float(np.abs(Tg[ok] - To[ok]).max()),
+                      "frame_ambiguous_fraction": float(amb_all.mean())}}
+    # decode on the crop rows; the oracle takes the GPU's Q promoted to FP64
+    Qc = wl.Q[sel].contiguous()
+    Tc = wl.tgt[sel].contiguous()
+    dref = DO.loss_and_grads(Qg, wl.s.K, wl.s.V, ref["tgt"], wl.s.K0, sp.lambda_tr)
+    out["decode"] = {}
+    for prec in precs:
+        dec = wl.decoder(prec, n=len(pix))
+        rc = torch.empty(len(pix), device=wl.dev)
+        loss, dQ, dK, dV = dec.loss_and_grads(Qc, wl.K, wl.V, Tc, wl.K0, sp.lambda_tr, row_cos=rc)
+        F = dec.forward(Qc, wl.K, wl.V)
+        torch.cuda.synchronize()
+        out["decode"][prec] = decode_errors(F, rc, loss, dQ, dK, dV, dref)
+        del dec
+    # render backward for the oracle's upstream gradient on the crop
+    up32 = torch.as_tensor(ref["up"].astype(np.float32), device=wl.dev)
+    gr = wl.r.backward(wl.g, up32)
+    torch.cuda.synchronize()
+    rb = {}
+    for name in ("means", "log_scales", "quats", "opacity_logits", "queries"):
+        a = getattr(gr, name).double().cpu().numpy()
+        b = ref["bwd"][name]
+        rb["d_" + name] = {"rel_l2": float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)),
+                           "max_elem": float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))}
+    out["render_backward"] = rb
+    return out
+
+
+def cpu_baseline(wl, ref):
+    """The FP64 oracle step (render forward, decode + loss + gradients, render
+    backward) timed on the host: the whole frame's render and render adjoint,
+    and the decode of the crop's rows extrapolated per pixel to the frame; on
+    all host threads, and on one thread over the Gaussians and pixels of a
+    32 x 32 part of the crop, extrapolated per pixel."""
+    from oracle import raster as R
+    sp = wl.spec
+    x0, y0, cw, ch = ref["crop"]
+    npx = len(ref["pix"])
+    full_s = ref["t_fwd"] + ref["t_bwd"] + ref["t_dec"] * wl.n / npx
+    threads = R.num_threads()
+    try:
+        from threadpoolctl import threadpool_info
+        blas = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    except Exception:
+        blas = 1
+    one = _one_thread_sample(wl, (x0 + cw // 2 - 16, y0 + ch // 2 - 16, 32, 32))
+    return {"value": wl.n / full_s, "unit": "feature-pixels/s", "cores": max(threads, blas), "kind": "oracle",
+            "sample": (f"{sp.name}, whole frame ({wl.n} px, {sp.n_gauss} Gaussians): render fwd "
+                       f"{ref['t_fwd']:.2f}s + render bwd {ref['t_bwd']:.2f}s; decode/loss/grads of the "
+                       f"{cw}x{ch} crop's {npx} rows {ref['t_dec']:.2f}s, extrapolated per pixel: "
+                       f"{full_s:.1f}s per step (C/OpenMP {threads} threads, numpy BLAS {blas} threads, FP64)"),
+            "extrapolated": "decode part, per pixel", "one_thread": one, "host_cpu": _cpu_model(),
+            "host_threads_visible": len(os.sched_getaffinity(0))}
+
+
+def _one_thread_sample(wl, crop):
+    """The oracle step on one thread for the pixels of a small crop: the
+    projection of every Gaussian, then the Gaussians whose footprint overlaps
+    the crop rendered, decoded and differentiated; extrapolated per pixel."""
+    import numpy as np
+
+    from oracle import decode_oracle as DO
+    from oracle import raster as R
+    s, sp = wl.s, wl.spec
+    x0, y0, cw, ch = crop
+    pix = _crop_pixels(s.cams, crop)
+    prev = R.num_threads()
+    lim = None
+    try:
+        from threadpoolctl import threadpool_limits
+        lim = threadpool_limits(limits=1)
+    except Exception:
+        pass
+    R.set_num_threads(1)
+    try:
+        g = R.Gaussians.of(s)
+        t0 = time.perf_counter()
+        p = R.project(g, s.cams[:1])
+        t_proj = time.perf_counter() - t0
+        rect = p["rect"]
+        ov = (p["vis"] == 1) & (rect[:, 0] <= x0 + cw - 1) & (rect[:, 1] >= x0) & \
+             (rect[:, 2] <= y0 + ch - 1) & (rect[:, 3] >= y0)
+        idx = np.nonzero(ov)[0]
+        sub = R.Gaussians(*[np.ascontiguousarray(getattr(g, k)[idx]) for k in
+                            ("means", "log_scales", "quats", "opacity_logits", "queries")])
+        t0 = time.perf_counter()
+        f = R.render_forward(sub, s.cams[:1])
+        d = DO.loss_and_grads(f["Q"][pix], s.K, s.V, s.target[pix].astype(np.float64), s.K0, sp.lambda_tr)
+        up = np.zeros((R.n_pixels(s.cams[:1]), sp.d))
+        up[pix] = d["dQ"]
+        R.render_backward(sub, s.cams[:1], up)
+        t_crop = time.perf_counter() - t0
+    finally:
+        R.set_num_threads(prev)
+        if lim is not None:
+            lim.unregister()
+    full_s = t_proj + t_crop * wl.n / len(pix)
+    return {"value": wl.n / full_s, "unit": "feature-pixels/s", "cores": 1,
+            "sample": f"projection of all Gaussians {t_proj:.2f}s, then the {cw}x{ch} crop at ({x0}, {y0}) "
+                      f"with its {len(idx)} overlapping Gaussians {t_crop:.2f}s, extrapolated per pixel: "
+                      f"{full_s:.1f}s per step"}
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def run(args):
+    import numpy as np
+    import torch
+
+    from paper_2602_12314_amd import _lib, ops
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    prec = args.precision
+    wl = Workload(args.workload, prec, dev, autotune=not args.no_autotune, tile=args.tile)
+    sp, n = wl.spec, wl.n
+
+    dec = wl.decoder(prec)
     _log(f"[bench] timing {args.steps} steps ({prec} decode)")
-    sec, loss, prof, pairs = timed(dec, args.steps, args.warmup, profile=True)
-    eager_sec = sec
-    if args.graph:
+    eager_sec, loss, prof = wl.timed(dec, args.steps, args.warmup, profile=True)
+    sec = eager_sec
+    if not args.eager:
         _log(f"[bench] timing {args.steps} HIP-graph replays ({prec} decode)")
-        sec, loss = graph_timed(dec, args.steps, args.warmup)
-    if args.no_fp32 or prec == "fp32":
-        sec32, prof32 = (sec, prof) if prec == "fp32" else (None, {})
-    else:
-        dec32 = ops.Decoder("fp32", n, spec.d, spec.M, spec.D, device=dev)
-        fp32_steps = max(3, args.steps // 4)
-        _log(f"[bench] timing {fp32_steps} steps (fp32 decode)")
-        sec32, loss32, prof32, _ = timed(dec32, fp32_steps, 2, profile=True)
-        del dec32
+        sec, loss = wl.graph_timed(dec, args.steps, args.warmup, overlap=not args.no_overlap)
 
-    stage2 = None
-    if not args.no_stage2:
-        stage2 = stage2_leg(ops, dec, prec, spec, Q, K, V, tgt, K0, dev)
-    tied = None
-    if not args.no_tied:
-        tied = tied_leg(ops, prec, spec, Q, V, tgt, dev)
-    kmeans = None
-    if not args.no_kmeans:
-        kmeans = kmeans_leg(ops, prec, spec, tgt, dev)
-    rgbd = None
-    if not args.no_rgbd:
-        rgbd = rgbd_leg(ops, r, g, dec, K, V, tgt, K0, spec, dev, args.steps, side=side)
+    legs = {}
+    for lp in ("fp8", "fp32"):
+        if lp == prec or lp in args.skip_precisions:
+            continue
+        d2 = wl.decoder(lp)
+        st = max(3, args.steps // 4) if lp == "fp32" else args.steps
+        _log(f"[bench] timing {st} steps ({lp} decode)")
+        s2, l2, p2 = wl.timed(d2, st, 2, profile=True)
+        legs[lp] = {"value": n / s2, "ms_per_step": s2 * 1e3, "launch": "eager",
+                    "stage_ms": {k: round(v, 4) for k, v in p2.items()},
+                    "speedup_of_headline_eager": s2 / eager_sec}
+        del d2
 
+    # roofline of the dominant kernel, from the method's algorithmic work
+    check = cpu = None
+    work = decode_work(n, sp.d, sp.M, sp.D)
+    if not args.no_oracle:
+        crop = crop_window(sp)
+        _log(f"[bench] FP64 oracle: whole frame render, crop {crop} decode")
+        ref = oracle_reference(wl, crop)
+        work.update(raster_work(sp, ref["pairs_eval"], ref["pairs_blend"], wl.pairs))
+        check = oracle_check(wl, ref, [prec] + [p for p in legs])
+        for lp in legs:
+            legs[lp]["oracle_crop"] = check["decode"][lp]
+        if "fp8" in legs:
+            legs["fp8"]["bar"] = {"F_cos_min": BAR_MIN_COS_F, "grad_rel_l2": BAR_GRAD_REL}
+            legs["fp8"]["bar_met"] = check["decode"]["fp8"]["meets_bar"]
+        if not args.no_cpu_baseline:
+            _log("[bench] timing the FP64 CPU oracle (one thread)")
+            cpu = cpu_baseline(wl, ref)
+        del ref
+    dom = max((k for k in prof if k in work), key=lambda k: prof[k])
+    ms = prof[dom]
+    rl = roofline(work[dom], ms, prec)
+    dec_ms = sum(prof.get(k, 0.0) for k in ("decode_rows", "decode_tn"))
     out = {
         "metric": "feature-pixels/s fwd+bwd",
         "value": n / sec,
@@ -253,70 +505,64 @@ def run(args):
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": sec * 1e3,
-        "ms_per_keyframe": sec * 1e3 / len(spec.cams),
+        "ms_per_keyframe": sec * 1e3 / len(sp.cams),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": prec,
         "data": "synthetic",
-        "config": {"workload": spec.name, "n_gaussians": spec.n_gauss,
-                   "image": f"{s.cams[0, 0]:.0f}x{s.cams[0, 1]:.0f}", "views": len(spec.cams),
-                   "pixels": n, "d": spec.d, "M": spec.M, "D": spec.D, "decode_precision": prec,
-                   "tile": args.tile, "decode_shape": decode_shape, "tile_pairs": pairs},
+        "config": {"workload": sp.name, "n_gaussians": sp.n_gauss,
+                   "image": f"{wl.s.cams[0, 0]:.0f}x{wl.s.cams[0, 1]:.0f}", "views": len(sp.cams),
+                   "pixels": n, "d": sp.d, "M": sp.M, "D": sp.D, "decode_precision": prec,
+                   "tile": wl.tile, "decode_shape": wl.decode_shape, "tile_pairs": wl.pairs},
         "stage_ms": {k: round(v, 4) for k, v in prof.items()},
-        "launch": "hip_graph_replay" if args.graph else "eager",
-        "dict_gradients_on_second_stream": bool(args.graph and args.graph_overlap),
+        "launch": "eager" if args.eager else "hip_graph_replay",
+        "dict_gradients_on_second_stream": bool(not args.eager and not args.no_overlap),
         "eager_ms_per_step": eager_sec * 1e3,
-        "autotune_ms": tune,
+        "autotune_ms": wl.tune,
         "loss": loss,
-        "fp32_decode_path": None if sec32 is None else {
-            "value": n / sec32, "ms_per_step": sec32 * 1e3,
-            "stage_ms": {k: round(v, 4) for k, v in prof32.items()},
-            "speedup_of_reduced_precision": sec32 / sec},
-        "stage2": stage2,
-        "tied_decode": tied,
-        "stream_kmeans": kmeans,
-        "rgbd_step": rgbd,
+        "precision_legs": legs,
+        "roofline": dict(kernel=dom, **rl, kernel_ms=ms, algorithmic_bytes=work[dom]["bytes"],
+                         algorithmic_flops=work[dom]["flops"], traffic=traffic_for(dom, sp.name),
+                         issued=decode_issued(n, sp.d, sp.M, sp.D, prec) if dom.startswith("decode") else None),
+        "decode_roofline": dict(**roofline(work["decode_total"], dec_ms, prec), ms=dec_ms,
+                                kernels="decode_rows + decode_tn (+ dK GEMM and reductions not timed)"),
+        "kernels": {k: dict(ms=round(prof[k], 4), **{kk: (round(vv, 4) if isinstance(vv, float) else vv)
+                                                     for kk, vv in roofline(work[k], prof[k], prec).items()})
+                    for k in work if k in prof},
+        "oracle_check": check,
+        "cpu_baseline": cpu,
     }
-
-    # roofline of the dominant kernel, with algorithmic work from the oracle's pair counts
-    cpu = None
-    pairs_eval = pairs_blend = None
-    if not args.no_cpu_baseline:
-        cpu, pairs_eval, pairs_blend, ref = cpu_baseline(s, spec)
-
-        def check(prec_):
-            # one more step, outside every timed region, against the oracle's FP64 step
-            d_ = dec if prec_ == prec else ops.Decoder(prec_, n, spec.d, spec.M, spec.D, device=dev)
-            r.forward(g, Q, T, check=False)
-            l_, dQ_, dK_, dV_ = d_.loss_and_grads(Q, K, V, tgt, K0, spec.lambda_tr)
-            gr_ = r.backward(g, dQ_)
-            torch.cuda.synchronize()
-
-            def rel(a, b):
-                a = a.detach().double().cpu().numpy()
-                return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
-            return {"loss_rel_err": abs(float(l_) - ref["loss"]) / abs(ref["loss"]),
-                    "dK_rel_err": rel(dK_, ref["dK"]), "dV_rel_err": rel(dV_, ref["dV"]),
-                    "d_means_rel_err": rel(gr_.means, ref["means"]),
-                    "d_queries_rel_err": rel(gr_.queries, ref["queries"])}
-        out["oracle_check"] = {p_: check(p_) for p_ in dict.fromkeys([prec, "fp32"])}
-    else:
-        pairs_eval, pairs_blend = oracle_pairs(s)
-    work = algorithmic_work(spec, prec, pairs_eval, pairs_blend, pairs)
-    dom = max((k for k in prof if k in work), key=lambda k: prof[k])
-    ms = prof[dom]
-    rl = roofline(work[dom], ms, prec)
-    out["roofline"] = dict(kernel=dom, **rl, kernel_ms=ms, algorithmic_bytes=work[dom]["bytes"],
-                           algorithmic_flops=work[dom]["flops"], traffic=traffic_for(dom, spec.name))
-    out["kernels"] = {k: dict(ms=round(prof[k], 4), **{kk: (round(vv, 4) if isinstance(vv, float) else vv)
-                                                        for kk, vv in roofline(work[k], prof[k], prec).items()})
-                      for k in work if k in prof}
-    out["cpu_baseline"] = cpu
+    if not args.no_extra_legs:
+        out["stage2"] = stage2_leg(ops, dec, prec, sp, wl.Q, wl.K, wl.V, wl.tgt, wl.K0, dev)
+        out["tied_decode"] = tied_leg(ops, prec, sp, wl.Q, wl.V, wl.tgt, dev)
+        out["stream_kmeans"] = kmeans_leg(ops, prec, sp, wl.tgt, dev)
+        out["rgbd_step"] = rgbd_leg(ops, wl.r, wl.g, dec, wl.K, wl.V, wl.tgt, wl.K0, sp, dev, args.steps,
+                                    side=None if args.no_overlap else wl.side)
+    del dec
+    sec_wl = {}
+    for w2 in args.secondary:
+        if w2 == args.workload:
+            continue
+        del wl
+        torch.cuda.empty_cache()
+        wl = Workload(w2, "bf16", dev, autotune=not args.no_autotune, tile=args.tile)
+        d2 = wl.decoder("bf16")
+        e2, _, p2 = wl.timed(d2, args.steps, args.warmup, profile=True)
+        g2, _ = wl.graph_timed(d2, args.steps, args.warmup, overlap=not args.no_overlap)
+        w2k = decode_work(wl.n, wl.spec.d, wl.spec.M, wl.spec.D)
+        dom2 = max((k for k in p2 if k in w2k), key=lambda k: p2[k])
+        sec_wl[wl.spec.name] = {"value": wl.n / g2, "ms_per_step": g2 * 1e3, "eager_ms_per_step": e2 * 1e3,
+                                "decode_precision": "bf16", "tile": wl.tile, "decode_shape": wl.decode_shape,
+                                "stage_ms": {k: round(v, 4) for k, v in p2.items()},
+                                "roofline": dict(kernel=dom2, **roofline(w2k[dom2], p2[dom2], "bf16"),
+                                                 kernel_ms=p2[dom2])}
+        del d2
+    out["secondary_workloads"] = sec_wl
     print(json.dumps(out), flush=True)
 
 
-def stage2_leg(ops, dec1, prec, spec, Q, K, V, tgt, K0, dev, views=6, iters=5, reps=5):
+def stage2_leg(ops, dec1, prec, spec, Q, K, V, tgt, K0, dev, views=6, iters=5, reps=3):
     """Alg. 1 Stage II on this workload: the query maps of 1 + B = 6 views
     (here the keyframe's own map six times; the decode cost depends only on the
     shapes) stay fixed while R2 = 5 decode-only iterations (loss, dK, dV; no dQ)
@@ -344,6 +590,7 @@ def stage2_leg(ops, dec1, prec, spec, Q, K, V, tgt, K0, dev, views=6, iters=5, r
         losses = run()
     torch.cuda.synchronize()
     sec = (time.perf_counter() - t0) / reps
+    del Q6, T6, dec
     return {"views": views, "iters": iters, "pixels_per_iter": n, "ms": sec * 1e3,
             "value": n * iters / sec, "unit": "feature-pixels/s (decode + loss + dK, dV; Adam on K, V)",
             "loss_first_last": [float(losses[0]), float(losses[-1])]}
@@ -495,72 +742,31 @@ def traffic_for(kernel, workload):
     return ent.get("bytes_per_launch")
 
 
-def oracle_pairs(s):
-    from oracle import raster as R
-    f = R.render_forward(R.Gaussians.of(s), s.cams)
-    return int(f["n_pairs"].sum()), int(f["n_blended"].sum())
-
-
-def cpu_baseline(s, spec):
-    """The FP64 oracle (render forward, decode + loss + gradients, render
-    backward) on the full frame, timed on the host cores."""
-    import numpy as np
-
-    from oracle import decode_oracle as DO
-    from oracle import raster as R
-    _log("[bench] timing the FP64 CPU oracle on the full frame")
-    g = R.Gaussians.of(s)
-    t0 = time.perf_counter()
-    f = R.render_forward(g, s.cams)
-    t1 = time.perf_counter()
-    r = DO.loss_and_grads(f["Q"], s.K, s.V, s.target, s.K0, spec.lambda_tr)
-    t2 = time.perf_counter()
-    gb = R.render_backward(g, s.cams, r["dQ"])
-    t3 = time.perf_counter()
-    threads = R.num_threads()
-    try:
-        from threadpoolctl import threadpool_info
-        blas = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
-    except Exception:
-        blas = 1
-    total = t3 - t0
-    n = spec.n_pixels
-    return ({"value": n / total, "unit": "feature-pixels/s", "cores": max(threads, blas),
-             "kind": "oracle",
-             "sample": f"one full {spec.name} step: render fwd {t1 - t0:.2f}s + decode/loss/grads "
-                       f"{t2 - t1:.2f}s + render bwd {t3 - t2:.2f}s (C/OpenMP {threads} threads, "
-                       f"numpy BLAS {blas} threads, FP64)"},
-            int(f["n_pairs"].sum()), int(f["n_blended"].sum()),
-            {"loss": float(r["loss"]), "dK": r["dK"], "dV": r["dV"], "means": gb["means"],
-             "queries": gb["queries"]})
-
-
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", type=int, default=1, help="0..4 (default: the 640x480 keyframe)")
-    ap.add_argument("--precision", default=None, help="decode precision: fp32 | bf16 (default: workload's)")
-    ap.add_argument("--tile", default="16x16")
+    ap.add_argument("--workload", type=int, default=4,
+                    help="0..4 (default 4: the 1200x680 keyframe of the 2M-Gaussian map)")
+    ap.add_argument("--precision", default="bf16", help="headline decode precision: bf16 | fp8 | fp32")
+    ap.add_argument("--skip-precisions", default="", help="comma list of precision legs to skip (fp8, fp32)")
+    ap.add_argument("--secondary", default="1", help="comma list of further workloads timed in BF16")
+    ap.add_argument("--tile", default="16x16", help="render tile shape when not autotuned")
+    ap.add_argument("--no-autotune", action="store_true", help="fixed tile and decode block shape")
+    ap.add_argument("--no-oracle", action="store_true", help="skip the FP64 oracle check and CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--autotune", action="store_true", help="pick the render tile shape by timing")
-    ap.add_argument("--graph", action="store_true",
-                    help="time replays of the HIP-graph-captured step (the default; see --eager)")
     ap.add_argument("--eager", action="store_true",
                     help="time eager launches instead of HIP-graph replays of the captured step")
-    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 decode comparison leg")
-    ap.add_argument("--no-stage2", action="store_true", help="skip the Stage-II decode-only leg")
-    ap.add_argument("--no-tied", action="store_true", help="skip the tied-decode leg")
-    ap.add_argument("--no-kmeans", action="store_true", help="skip the streaming K-means leg")
-    ap.add_argument("--no-rgbd", action="store_true", help="skip the colour + depth step leg")
+    ap.add_argument("--no-extra-legs", action="store_true",
+                    help="skip the Stage-II, tied-decode, K-means and colour/depth legs")
     ap.add_argument("--no-overlap", action="store_true",
                     help="run the dictionary gradients on the step's own stream (no second stream)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (scales HBM byte counters)")
     args = ap.parse_args()
-    args.graph = not args.eager
-    args.graph_overlap = not args.no_overlap
+    args.skip_precisions = [p for p in args.skip_precisions.split(",") if p]
+    args.secondary = [int(v) for v in args.secondary.split(",") if v != ""]
     if args.copy_calibration:
         import torch
         a = torch.empty(args.copy_calibration // 4, dtype=torch.float32, device="cuda").uniform_()

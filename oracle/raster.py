@@ -41,6 +41,8 @@ def lib():
         _lib.orc_render_backward.restype = i32
         _lib.orc_render_backward.argtypes = [i32, i32, vp, vp, vp, vp, vp, i32, vp, i32, i32, vp] + [vp] * 7
         _lib.orc_num_threads.restype = i32
+        _lib.orc_set_num_threads.restype = None
+        _lib.orc_set_num_threads.argtypes = [i32]
         _lib.orc_render_window.restype = i32
         _lib.orc_render_window.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp, i32, i32, i32, i32, vp, vp, vp]
         _lib.orc_fd_window.restype = i32
@@ -166,6 +168,11 @@ def render_backward(g: Gaussians, cams, dQ, tw=16, th=16, with_rec: bool = False
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_num_threads(n: int):
+    """Threads of the oracle's OpenMP regions from now on."""
+    lib().orc_set_num_threads(int(n))
 
 
 # parameter index of a probe in fd_window: 0-2 mean, 3-5 log-scale, 6-9 quaternion,

@@ -1019,3 +1019,9 @@ int orc_pixel_walks(int n, int d, const float* means, const float* log_scales, c
     scene_free(&S);
     return 0;
 }
+
+/* Threads of the OpenMP regions above (for timing the oracle on one core). */
+void orc_set_num_threads(int n)
+{
+    if (n > 0) omp_set_num_threads(n);
+}
