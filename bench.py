@@ -135,17 +135,19 @@ class Workload:
         self.n = sp.n_pixels
         tw, th = (int(v) for v in tile.split("x"))
         self.tune = None
-        self.decode_shape = "px32"
+        self.options = {"decode_shape": "px32", "decode_splits": 0}
         if autotune:
             from paper_2602_12314_amd import autotune as AT
+            t0 = time.perf_counter()
             (tw, th), tile_ms = AT.best_tile(self.g, s.cams)
-            self.decode_shape, dec_ms = AT.best_decode_shape(prec, self.n, sp.d, sp.M, sp.D)
-            self.tune = {"tile_ms": tile_ms, "decode_shape_ms": dec_ms}
+            self.options, dec_ms = AT.best_decode_options(prec, self.n, sp.d, sp.M, sp.D)
+            self.tune = {"tile_ms": tile_ms, "decode_options_ms": dec_ms, "seconds": time.perf_counter() - t0}
             _log(f"[bench] autotuned tile {tw}x{th}: {tile_ms}")
-            _log(f"[bench] autotuned decode shape {self.decode_shape}: {dec_ms}")
-        _lib.set_decode_shape(self.decode_shape)
+            _log(f"[bench] autotuned decode options {self.options}: {dec_ms}")
+        # one library context carries the tuned launch options for every call
+        self.ctx = _lib.Context(options=self.options)
         self.tile = f"{tw}x{th}"
-        self.r = ops.Renderer(s.cams, sp.n_gauss, sp.d, tile=(tw, th))
+        self.r = ops.Renderer(s.cams, sp.n_gauss, sp.d, tile=(tw, th), ctx=self.ctx)
         self.Q = torch.empty((self.n, sp.d), device=dev)
         self.T = torch.empty((self.n,), device=dev)
         self.grads = self.g.zeros_like()
@@ -155,7 +157,7 @@ class Workload:
 
     def decoder(self, prec, n=None):
         sp = self.spec
-        return self.ops.Decoder(prec, self.n if n is None else n, sp.d, sp.M, sp.D, device=self.dev)
+        return self.ops.Decoder(prec, self.n if n is None else n, sp.d, sp.M, sp.D, device=self.dev, ctx=self.ctx)
 
     def make_step(self, dec, overlap):
         r, g, Q, T, K, V, tgt, K0, lam = (self.r, self.g, self.Q, self.T, self.K, self.V, self.tgt, self.K0,
@@ -184,11 +186,11 @@ class Workload:
         torch.cuda.synchronize()
         need, over = self.r.counters()
         assert not over, "pair capacity overflow after warm-up"
-        L = self._lib.lib()
+        ctx = self.ctx
         if profile:
-            L.lam_profile_enable(1)
+            ctx.profile_enable(True)
             for name in PROF_STAGES:
-                _read_prof(L, name)
+                ctx.profile_read(name)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(steps):
@@ -198,10 +200,10 @@ class Workload:
         prof = {}
         if profile:
             for name in PROF_STAGES:
-                tot, cnt = _read_prof(L, name)
+                tot, cnt = ctx.profile_read(name)
                 if cnt:
                     prof[name] = tot / cnt
-            L.lam_profile_enable(0)
+            ctx.profile_enable(False)
         self.pairs = need
         return (t1 - t0) / steps, float(loss), prof
 
@@ -514,7 +516,7 @@ def run(args):
         "config": {"workload": sp.name, "n_gaussians": sp.n_gauss,
                    "image": f"{wl.s.cams[0, 0]:.0f}x{wl.s.cams[0, 1]:.0f}", "views": len(sp.cams),
                    "pixels": n, "d": sp.d, "M": sp.M, "D": sp.D, "decode_precision": prec,
-                   "tile": wl.tile, "decode_shape": wl.decode_shape, "tile_pairs": wl.pairs},
+                   "tile": wl.tile, "decode_options": wl.options, "tile_pairs": wl.pairs},
         "stage_ms": {k: round(v, 4) for k, v in prof.items()},
         "launch": "eager" if args.eager else "hip_graph_replay",
         "dict_gradients_on_second_stream": bool(not args.eager and not args.no_overlap),
@@ -534,9 +536,9 @@ def run(args):
         "cpu_baseline": cpu,
     }
     if not args.no_extra_legs:
-        out["stage2"] = stage2_leg(ops, dec, prec, sp, wl.Q, wl.K, wl.V, wl.tgt, wl.K0, dev)
-        out["tied_decode"] = tied_leg(ops, prec, sp, wl.Q, wl.V, wl.tgt, dev)
-        out["stream_kmeans"] = kmeans_leg(ops, prec, sp, wl.tgt, dev)
+        out["stage2"] = stage2_leg(ops, dec, prec, sp, wl.Q, wl.K, wl.V, wl.tgt, wl.K0, dev, wl.ctx)
+        out["tied_decode"] = tied_leg(ops, prec, sp, wl.Q, wl.V, wl.tgt, dev, wl.ctx)
+        out["stream_kmeans"] = kmeans_leg(ops, prec, sp, wl.tgt, dev, wl.ctx)
         out["rgbd_step"] = rgbd_leg(ops, wl.r, wl.g, dec, wl.K, wl.V, wl.tgt, wl.K0, sp, dev, args.steps,
                                     side=None if args.no_overlap else wl.side)
     del dec
@@ -553,7 +555,7 @@ def run(args):
         w2k = decode_work(wl.n, wl.spec.d, wl.spec.M, wl.spec.D)
         dom2 = max((k for k in p2 if k in w2k), key=lambda k: p2[k])
         sec_wl[wl.spec.name] = {"value": wl.n / g2, "ms_per_step": g2 * 1e3, "eager_ms_per_step": e2 * 1e3,
-                                "decode_precision": "bf16", "tile": wl.tile, "decode_shape": wl.decode_shape,
+                                "decode_precision": "bf16", "tile": wl.tile, "decode_options": wl.options,
                                 "stage_ms": {k: round(v, 4) for k, v in p2.items()},
                                 "roofline": dict(kernel=dom2, **roofline(w2k[dom2], p2[dom2], "bf16"),
                                                  kernel_ms=p2[dom2])}
@@ -562,7 +564,7 @@ def run(args):
     print(json.dumps(out), flush=True)
 
 
-def stage2_leg(ops, dec1, prec, spec, Q, K, V, tgt, K0, dev, views=6, iters=5, reps=3):
+def stage2_leg(ops, dec1, prec, spec, Q, K, V, tgt, K0, dev, ctx, views=6, iters=5, reps=3):
     """Alg. 1 Stage II on this workload: the query maps of 1 + B = 6 views
     (here the keyframe's own map six times; the decode cost depends only on the
     shapes) stay fixed while R2 = 5 decode-only iterations (loss, dK, dV; no dQ)
@@ -571,7 +573,7 @@ def stage2_leg(ops, dec1, prec, spec, Q, K, V, tgt, K0, dev, views=6, iters=5, r
     n = Q.shape[0] * views
     Q6 = Q.repeat(views, 1).contiguous()
     T6 = tgt.repeat(views, 1).contiguous()
-    dec = ops.Decoder(prec, n, spec.d, spec.M, spec.D, device=dev)
+    dec = ops.Decoder(prec, n, spec.d, spec.M, spec.D, device=dev, ctx=ctx)
     Kp = torch.nn.Parameter(K.clone())
     Vp = torch.nn.Parameter(V.clone())
     opt = torch.optim.Adam([Kp, Vp], lr=1e-3)
@@ -596,7 +598,7 @@ def stage2_leg(ops, dec1, prec, spec, Q, K, V, tgt, K0, dev, views=6, iters=5, r
             "loss_first_last": [float(losses[0]), float(losses[-1])]}
 
 
-def tied_leg(ops, prec, spec, Q, V, tgt, dev, reps=10):
+def tied_leg(ops, prec, spec, Q, V, tgt, dev, ctx, reps=10):
     """The paper's tied decode (Eq. 5 with cosine logits at temperature 0.1,
     V = D) and full loss (cosine + L2 + hinge trust region, the paper's weights)
     with gradients to Q, W and D, on this workload's query map and shapes; W is
@@ -610,7 +612,7 @@ def tied_leg(ops, prec, spec, Q, V, tgt, dev, reps=10):
     W = torch.randn((d, Dd), device=dev, generator=g) / d ** 0.5
     D0 = V.clone()
     Dm = D0 + 0.05 * torch.randn(D0.shape, device=dev, generator=g)
-    dec = ops.TiedDecoder(prec, n, d, M, Dd, device=dev)
+    dec = ops.TiedDecoder(prec, n, d, M, Dd, device=dev, ctx=ctx)
     dec.loss_and_grads(Q, W, Dm, tgt, D0)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -643,8 +645,8 @@ def rgbd_leg(ops, r, g, dec, K, V, tgt, K0, spec, dev, steps, warmup=3, side=Non
         Q, rgb, depth, _ = r.forward_rgbd(g, colors, check=False)
         lf, dQ, _, _ = dec.loss_and_grads(Q, K, V, tgt, K0, spec.lambda_tr, dict_stream=side)
         lp, d_rgb, d_depth = ops.rgbd_l1_loss(rgb, rgb_obs, depth, depth_obs, w["lambda_rgb"],
-                                              w["lambda_depth"])
-        ls, _ = ops.ssim_loss(rgb, rgb_obs, r.cams, w["lambda_ssim"], d_rgb=d_rgb)
+                                              w["lambda_depth"], ctx=r.ctx)
+        ls, _ = ops.ssim_loss(rgb, rgb_obs, r.cams, w["lambda_ssim"], d_rgb=d_rgb, ctx=r.ctx)
         r.backward_rgbd(g, colors, dQ, d_rgb, d_depth)
         if side is not None:
             torch.cuda.current_stream().wait_stream(side)
@@ -664,7 +666,7 @@ def rgbd_leg(ops, r, g, dec, K, V, tgt, K0, spec, dev, steps, warmup=3, side=Non
             "weights": dict(w), "loss_feature": float(lf), "loss_rgbd": float(lp)}
 
 
-def kmeans_leg(ops, prec, spec, tgt, dev, reps=3, iters=10):
+def kmeans_leg(ops, prec, spec, tgt, dev, ctx, reps=3, iters=10):
     """The streaming K-means dictionary initialisation (Eq. 10) on this
     workload's embedding map: m = 5 K micro-centres from seeded random rows,
     merged into K = M global centres (the previous dictionary: K rows of an
@@ -683,7 +685,7 @@ def kmeans_leg(ops, prec, spec, tgt, dev, reps=3, iters=10):
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ms = []
     for r in range(reps + 1):
-        sk = ops.StreamKMeans(kprec, K, Dd, iters_local=iters, iters_global=iters, seed=r, device=dev)
+        sk = ops.StreamKMeans(kprec, K, Dd, iters_local=iters, iters_global=iters, seed=r, device=dev, ctx=ctx)
         sk.D, sk.W = prev, torch.full((K,), 100.0, device=dev)
         seeds = sk.rng.choice(n, size=m, replace=False)
         torch.cuda.synchronize()
@@ -695,18 +697,17 @@ def kmeans_leg(ops, prec, spec, tgt, dev, reps=3, iters=10):
             ms.append(e0.elapsed_time(e1))
     step_ms = float(np.median(ms))
     C = tgt[torch.as_tensor(rng.choice(n, m, replace=False), device=dev)].contiguous()
-    ws = torch.empty(_lib.kmeans_workspace_size(kprec, n, Dd, m), dtype=torch.uint8, device=dev)
+    ws = torch.empty(_lib.kmeans_workspace_size(kprec, n, Dd, m, ctx=ctx), dtype=torch.uint8, device=dev)
     a = torch.empty(n, dtype=torch.int32, device=dev)
-    _lib.kmeans_assign(kprec, tgt, C, a, None, ws)
+    _lib.kmeans_assign(kprec, tgt, C, a, None, ws, ctx=ctx)
     torch.cuda.synchronize()
-    L = _lib.lib()
-    L.lam_profile_enable(1)
-    _read_prof(L, "kmeans_assign")
+    ctx.profile_enable(True)
+    ctx.profile_read("kmeans_assign")
     for _ in range(10):
-        _lib.kmeans_assign(kprec, tgt, C, a, None, ws)
+        _lib.kmeans_assign(kprec, tgt, C, a, None, ws, ctx=ctx)
     torch.cuda.synchronize()
-    tot, cnt = _read_prof(L, "kmeans_assign")  # the distance kernel alone, HIP events on its stream
-    L.lam_profile_enable(0)
+    tot, cnt = ctx.profile_read("kmeans_assign")  # the distance kernel alone, HIP events on its stream
+    ctx.profile_enable(False)
     amsec = tot / max(cnt, 1)
     flops = 2.0 * n * m * Dd
     peak = PEAKS["fp32_mfma_tflops" if kprec == "fp32" else "bf16_tflops"]
@@ -716,13 +717,6 @@ def kmeans_leg(ops, prec, spec, tgt, dev, reps=3, iters=10):
             "assign": {"ms": amsec, "bound": "mfma", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
                        "frac": ach / peak, "flops": flops, "bytes": 4.0 * n * Dd + 4.0 * n,
                        "traffic": traffic_for("kmeans_assign", spec.name)}}
-
-
-def _read_prof(L, name):
-    import ctypes as C
-    tot, cnt = C.c_double(), C.c_int()
-    L.lam_profile_read(name.encode(), C.byref(tot), C.byref(cnt))
-    return tot.value, cnt.value
 
 
 def traffic_for(kernel, workload):

@@ -16,6 +16,14 @@
  *
  * Conventions shared by every entry point
  * ---------------------------------------
+ * - Every call takes a context (lam_ctx, below) made by lam_create for one
+ *   HIP device; the calls that launch work must be made with that device
+ *   current, otherwise they return LAM_ERR_INVALID_ARG.  The host-only size
+ *   queries (*_workspace_size, lam_render_debug_views) also accept NULL,
+ *   which stands for a context with the default options.  The context holds
+ *   the launch choices (tile schedule, decode block shape, split counts);
+ *   they change the speed, never the result beyond the rounding order noted
+ *   per option.  Two contexts in one process are independent.
  * - Pointers named as "device" are HIP device pointers; "host" pointers are
  *   read synchronously before the call returns.  Every device buffer belongs
  *   to the caller.  The library performs no device allocation on these paths:
@@ -65,7 +73,7 @@ extern "C" {
 
 #define LAM_CAM_FLOATS 22
 #define LAM_MAX_CAMS 16
-#define LAM_VERSION 1
+#define LAM_VERSION 2
 
 typedef enum {
     LAM_OK = 0,
@@ -78,9 +86,15 @@ typedef enum {
 typedef enum {
     LAM_FP32 = 0,     /* all products in float32 (MFMA f32) */
     LAM_BF16 = 1,     /* products on bf16 operands, float32 accumulation and softmax */
-    LAM_FP8_E4M3 = 2  /* forward products on OCP E4M3 operands with per-row float32
-                         scales (K and V per atom, Q and P per pixel); backward products
-                         in bf16; float32 accumulation and softmax */
+    LAM_FP8_E4M3 = 2  /* the forward product P V on OCP E4M3 operands: V in E4M3 with a
+                         float32 scale per atom (row), the unnormalised softmax weights
+                         (which peak at 1 per pixel) times the atom scales mapped onto
+                         the E4M3 range by one factor per call; the logits Q K^T and
+                         every backward product in bf16; float32 accumulation and
+                         softmax.  Its error against exact arithmetic is larger than
+                         bf16's: on 1200x680 frames with M = D = 1024 the smallest
+                         per-pixel cosine of F is about 0.9985 and dQ is within a few
+                         1e-2 (relative L2) */
 } lam_precision;
 
 /* Human-readable name of a status code (static storage). */
@@ -88,6 +102,50 @@ const char* lam_status_string(int status);
 
 /* Library ABI version (LAM_VERSION). */
 int lam_version(void);
+
+/* ----------------------------------------------------------------- context */
+
+typedef struct lam_ctx lam_ctx;
+
+/* Makes a context for HIP device ``device``.  ``options_json`` (nullable) is
+ * a flat JSON object of integer options, as an autotuner writes it:
+ *   "raster_schedule"  how the compositing kernels walk the tiles:
+ *                      0 = one workgroup per tile; 1 = persistent: as many
+ *                      workgroups as fit on the device take tiles from a
+ *                      counter in the workspace (evens out views of uneven
+ *                      size and tiles of uneven list length); 2 = persistent
+ *                      only when several cameras are rendered (default 2).
+ *                      Results are identical in every mode.
+ *   "decode_shape"     workgroup shape of the per-pixel decode kernel:
+ *                      0 = 32 pixels with 4 waves (default); 1 = 64 pixels
+ *                      with 8 waves, each V fragment feeding two pixel groups
+ *                      (BF16 with D a multiple of 256 up to 768, E4M3 up to
+ *                      512; other shapes keep 0).  Results agree to rounding
+ *                      (the per-pixel sums over the waves split differently).
+ *   "decode_splits"    pixel-range splits of the dV GEMM (the larger of the
+ *                      two dictionary-gradient GEMMs; a multiple of 8 in
+ *                      [8, 4096], capped at the number of 32-pixel blocks);
+ *                      0 = sized to fill the device (default).  dV agrees to
+ *                      rounding (the split sums differ); the workspace size
+ *                      depends on it.
+ * The context queries the device (compute units, occupancy of the persistent
+ * kernels) and creates one event; it allocates no device memory.
+ * Errors: LAM_ERR_INVALID_ARG (null out, bad device, unknown option or value
+ * out of range: checked before the device is touched), LAM_ERR_HIP. */
+lam_status lam_create(int device, const char* options_json, lam_ctx** out);
+
+/* Releases a context (NULL is a no-op).  Work it launched must be complete. */
+void lam_destroy(lam_ctx* ctx);
+
+/* Changes options of a live context (same JSON as lam_create; fields not
+ * named keep their values).  A call already made keeps the options it read;
+ * a workspace sized before a change of "decode_splits" may be too small
+ * afterwards (the calls then return LAM_ERR_INVALID_ARG).
+ * Errors: LAM_ERR_INVALID_ARG (null, unknown option, value out of range). */
+lam_status lam_ctx_configure(lam_ctx* ctx, const char* options_json);
+
+/* Reads one option (or "device") of a context.  Errors: LAM_ERR_INVALID_ARG. */
+lam_status lam_ctx_get(const lam_ctx* ctx, const char* key, int* value);
 
 /* ------------------------------------------------------------------ render */
 
@@ -97,7 +155,7 @@ int lam_version(void);
  * (Gaussian, tile) pairs.  Host-only, never blocks.
  * Errors: LAM_ERR_INVALID_ARG (null out, bad camera rows), LAM_ERR_UNSUPPORTED
  * (tile shape, d, more than 2^31 Gaussian-camera records). */
-lam_status lam_render_workspace_size(int n_gauss, int d, const float* cams, int n_cams,
+lam_status lam_render_workspace_size(const lam_ctx* ctx, int n_gauss, int d, const float* cams, int n_cams,
                                      int tile_w, int tile_h, uint64_t instance_capacity,
                                      uint64_t* bytes);
 
@@ -114,7 +172,7 @@ lam_status lam_render_workspace_size(int n_gauss, int d, const float* cams, int 
  * the workspace is set and Q is incomplete: read it with lam_render_counters
  * and call again with a larger workspace.
  * Errors: LAM_ERR_INVALID_ARG, LAM_ERR_UNSUPPORTED, LAM_ERR_HIP. */
-lam_status lam_render_forward(const float* means, const float* log_scales, const float* quats,
+lam_status lam_render_forward(lam_ctx* ctx, const float* means, const float* log_scales, const float* quats,
                               const float* opacity_logits, const float* queries, int n_gauss,
                               int d, const float* cams, int n_cams, int tile_w, int tile_h,
                               float* Q, float* T_final, void* ws, uint64_t ws_bytes,
@@ -128,7 +186,7 @@ lam_status lam_render_forward(const float* means, const float* log_scales, const
  * Gaussians culled in every camera get zero gradients.  Arguments other than
  * dQ and the outputs must equal those of the forward call, with the same ws.
  * Errors: LAM_ERR_INVALID_ARG, LAM_ERR_UNSUPPORTED, LAM_ERR_HIP. */
-lam_status lam_render_backward(const float* means, const float* log_scales, const float* quats,
+lam_status lam_render_backward(lam_ctx* ctx, const float* means, const float* log_scales, const float* quats,
                                const float* opacity_logits, const float* queries, int n_gauss,
                                int d, const float* cams, int n_cams, int tile_w, int tile_h,
                                const float* dQ, float* d_means, float* d_log_scales,
@@ -147,12 +205,12 @@ lam_status lam_render_backward(const float* means, const float* log_scales, cons
  * one lam_render_workspace_size reports; the backward reads what the forward
  * of the same call sequence left in it.
  * Errors: LAM_ERR_INVALID_ARG, LAM_ERR_UNSUPPORTED, LAM_ERR_HIP. */
-lam_status lam_render_rgbd_forward(const float* means, const float* log_scales, const float* quats,
+lam_status lam_render_rgbd_forward(lam_ctx* ctx, const float* means, const float* log_scales, const float* quats,
                                    const float* opacity_logits, const float* queries, const float* colors,
                                    int n_gauss, int d, const float* cams, int n_cams, int tile_w, int tile_h,
                                    float* Q, float* rgb, float* depth, float* T_final, void* ws,
                                    uint64_t ws_bytes, uint64_t instance_capacity, void* stream);
-lam_status lam_render_rgbd_backward(const float* means, const float* log_scales, const float* quats,
+lam_status lam_render_rgbd_backward(lam_ctx* ctx, const float* means, const float* log_scales, const float* quats,
                                     const float* opacity_logits, const float* queries, const float* colors,
                                     int n_gauss, int d, const float* cams, int n_cams, int tile_w, int tile_h,
                                     const float* dQ, const float* d_rgb, const float* d_depth, float* d_means,
@@ -183,27 +241,19 @@ lam_status lam_render_rgbd_backward(const float* means, const float* log_scales,
  * lam_ssim_workspace_size bytes (9 floats per pixel).  Deterministic.
  * Errors: LAM_ERR_INVALID_ARG (null pointers, bad camera rows, negative
  * lambda, workspace too small), LAM_ERR_HIP. */
-lam_status lam_ssim_workspace_size(const float* cams, int n_cams, uint64_t* bytes);
-lam_status lam_ssim_loss(const float* rgb, const float* rgb_obs, const float* cams, int n_cams, float lambda,
+lam_status lam_ssim_workspace_size(const lam_ctx* ctx, const float* cams, int n_cams, uint64_t* bytes);
+lam_status lam_ssim_loss(lam_ctx* ctx, const float* rgb, const float* rgb_obs, const float* cams, int n_cams, float lambda,
                          float* loss, float* d_rgb, int accumulate, void* ws, uint64_t ws_bytes, void* stream);
 
-lam_status lam_rgbd_l1_workspace_size(int n, uint64_t* bytes);
-lam_status lam_rgbd_l1_loss(const float* rgb, const float* rgb_obs, const float* depth, const float* depth_obs,
+lam_status lam_rgbd_l1_workspace_size(const lam_ctx* ctx, int n, uint64_t* bytes);
+lam_status lam_rgbd_l1_loss(lam_ctx* ctx, const float* rgb, const float* rgb_obs, const float* depth, const float* depth_obs,
                             int n, float lambda_rgb, float lambda_depth, float* loss, float* d_rgb,
                             float* d_depth, void* ws, uint64_t ws_bytes, void* stream);
-
-/* How the compositing kernels (forward and backward) walk the tiles,
- * process-wide: 0 = one workgroup per tile; 1 = persistent: as many
- * workgroups as fit on the device take tiles from a counter in the workspace
- * until all are done (evens out views of uneven size and tiles of uneven list
- * length); 2 = persistent only when several cameras are rendered (default).
- * The result is identical in every mode.  Errors: LAM_ERR_INVALID_ARG. */
-lam_status lam_set_raster_schedule(int mode);
 
 /* BLOCKING: waits for ``stream`` and reads the counters of the last forward
  * call on ``ws``: the number of (Gaussian, tile) pairs it needed and whether
  * it exceeded the capacity (then returns LAM_ERR_CAPACITY). */
-lam_status lam_render_counters(const void* ws, void* stream, uint64_t* instances_needed,
+lam_status lam_render_counters(lam_ctx* ctx, const void* ws, void* stream, uint64_t* instances_needed,
                                int* overflowed);
 
 /* Debug / verification view of the workspace of the last forward call: device
@@ -213,7 +263,7 @@ lam_status lam_render_counters(const void* ws, void* stream, uint64_t* instances
  * ([n_cams*N, 2] uint32: x0 | x1 << 16, y0 | y1 << 16) and per-pixel
  * contributor counts ([P] uint32).  Any output pointer may be NULL.
  * Record r = camera * N + Gaussian.  Host-only, never blocks. */
-lam_status lam_render_debug_views(const void* ws, int n_gauss, int d, const float* cams,
+lam_status lam_render_debug_views(const lam_ctx* ctx, const void* ws, int n_gauss, int d, const float* cams,
                                   int n_cams, int tile_w, int tile_h, uint64_t instance_capacity,
                                   const uint32_t** tile_keys, const uint32_t** tile_recs,
                                   const uint32_t** ranges, const uint32_t** depth_keys,
@@ -221,20 +271,15 @@ lam_status lam_render_debug_views(const void* ws, int n_gauss, int d, const floa
 
 /* ------------------------------------------------------------------ decode */
 
-/* Workgroup shape of the per-pixel decode kernel, process-wide: 0 = 32 pixels
- * with 4 waves (default); 1 = 64 pixels with 8 waves, each V fragment feeding
- * two pixel groups (BF16 with D a multiple of 256 up to 768, FP8 up to 512;
- * other shapes keep 0).  Results agree to rounding (the per-pixel sums over
- * the waves are split differently); an autotuner may pick per workload.
- * Errors: LAM_ERR_INVALID_ARG. */
-lam_status lam_set_decode_shape(int mode);
-
 /* Bytes of decode workspace for n pixel rows, query dimension d, M atoms,
- * feature dimension D.  Supported: d in {16, 32}; 1 <= M <= 2048 (FP32: the
- * atoms, padded to 64, and D both at most 1024, which is what the 160 KB of
- * LDS of a workgroup holds); D a multiple of 128 with 128 <= D <= 1024; n >= 0.
- * Host-only.  Errors: LAM_ERR_INVALID_ARG (null out), LAM_ERR_UNSUPPORTED (shape). */
-lam_status lam_decode_workspace_size(int precision, int n, int d, int M, int D, uint64_t* bytes);
+ * feature dimension D, under the context's options.  Supported: d in
+ * {16, 32}; 1 <= M <= 2048 (FP32: the atoms, padded to 64, at most 1024: a
+ * 32-pixel block's FP32 softmax weights and feature rows share the 160 KB of
+ * LDS of a workgroup); D a multiple of 128 with 128 <= D <= 1024 (a wave
+ * accumulates its quarter of a 32-pixel block's feature rows in registers);
+ * n >= 0.  Host-only.
+ * Errors: LAM_ERR_INVALID_ARG (null out), LAM_ERR_UNSUPPORTED (shape). */
+lam_status lam_decode_workspace_size(const lam_ctx* ctx, int precision, int n, int d, int M, int D, uint64_t* bytes);
 
 /* Decode and feature loss, forward and backward in one call (Eq. 5-6):
  *   F   = softmax(Q K^T / sqrt(d)) V                    (softmax over the M atoms)
@@ -248,7 +293,7 @@ lam_status lam_decode_workspace_size(int precision, int n, int d, int M, int D, 
  * Q [n,d], K [M,d], V [M,D], target [n,D] and K0 [M,d] are device inputs
  * (K0 may be NULL when lambda_tr == 0).  F itself is not stored.
  * Errors: LAM_ERR_INVALID_ARG, LAM_ERR_UNSUPPORTED, LAM_ERR_HIP. */
-lam_status lam_decode_loss(int precision, const float* Q, int n, int d, const float* K,
+lam_status lam_decode_loss(lam_ctx* ctx, int precision, const float* Q, int n, int d, const float* K,
                            const float* V, int M, int D, const float* target, const float* K0,
                            float lambda_tr, float* loss, float* dQ, float* dK, float* dV,
                            float* row_cos, void* ws, uint64_t ws_bytes, void* stream);
@@ -262,7 +307,7 @@ lam_status lam_decode_loss(int precision, const float* Q, int n, int d, const fl
  * ready in ``dict_stream`` order; make ``stream`` wait for ``dict_stream``
  * before reading them or passing the same workspace to another call.
  * Otherwise identical to lam_decode_loss (same results bit for bit). */
-lam_status lam_decode_loss_overlap(int precision, const float* Q, int n, int d, const float* K,
+lam_status lam_decode_loss_overlap(lam_ctx* ctx, int precision, const float* Q, int n, int d, const float* K,
                                    const float* V, int M, int D, const float* target, const float* K0,
                                    float lambda_tr, float* loss, float* dQ, float* dK, float* dV,
                                    float* row_cos, void* ws, uint64_t ws_bytes, void* stream,
@@ -270,14 +315,14 @@ lam_status lam_decode_loss_overlap(int precision, const float* Q, int n, int d, 
 
 /* Inference decode (Eq. 5): F device [n, D] = softmax(Q K^T / sqrt(d)) V.
  * Errors: LAM_ERR_INVALID_ARG, LAM_ERR_UNSUPPORTED, LAM_ERR_HIP. */
-lam_status lam_decode_forward(int precision, const float* Q, int n, int d, const float* K,
+lam_status lam_decode_forward(lam_ctx* ctx, int precision, const float* Q, int n, int d, const float* K,
                               const float* V, int M, int D, float* F, void* ws,
                               uint64_t ws_bytes, void* stream);
 
 /* Adjoint of lam_decode_forward: given dF device [n, D] writes dQ [n, d]
  * (nullable), dK [M, d], dV [M, D] (device, overwritten); the softmax is
  * recomputed, not stored.  Errors as above. */
-lam_status lam_decode_backward(int precision, const float* Q, int n, int d, const float* K,
+lam_status lam_decode_backward(lam_ctx* ctx, int precision, const float* Q, int n, int d, const float* K,
                                const float* V, int M, int D, const float* dF, float* dQ,
                                float* dK, float* dV, void* ws, uint64_t ws_bytes, void* stream);
 
@@ -304,7 +349,7 @@ typedef struct {
  * lam_decode_workspace_size).  Host-only.
  * Errors: LAM_ERR_INVALID_ARG (null out, n < 0), LAM_ERR_UNSUPPORTED (shape,
  * or a precision other than LAM_FP32 and LAM_BF16). */
-lam_status lam_decode_tied_workspace_size(int precision, int n, int ds, int M, int df, uint64_t* bytes);
+lam_status lam_decode_tied_workspace_size(const lam_ctx* ctx, int precision, int n, int ds, int M, int df, uint64_t* bytes);
 
 /* Loss and gradients of the tied decode.  Device inputs (FP32, row-major):
  * Q [n, ds], W [ds, df], D [M, df], target F [n, df], D0 [M, df] (the initial
@@ -320,7 +365,7 @@ lam_status lam_decode_tied_workspace_size(int precision, int n, int ds, int M, i
  * Errors: LAM_ERR_INVALID_ARG (null or misaligned pointers, workspace too
  * small, tau <= 0 or a negative weight), LAM_ERR_UNSUPPORTED (shape,
  * precision), LAM_ERR_HIP. */
-lam_status lam_decode_tied_loss(int precision, const float* Q, int n, int ds, const float* W, const float* D,
+lam_status lam_decode_tied_loss(lam_ctx* ctx, int precision, const float* Q, int n, int ds, const float* W, const float* D,
                                 int M, int df, const float* target, const float* D0,
                                 const lam_tied_params* params, float* loss, float* dQ, float* dW, float* dD,
                                 void* ws, uint64_t ws_bytes, void* stream);
@@ -352,12 +397,12 @@ lam_status lam_decode_tied_loss(int precision, const float* Q, int n, int ds, co
 
 /* Workspace bytes for lam_kmeans_assign / lam_kmeans_lloyd with up to n
  * points of dimension D and k centres.  Host-only. */
-lam_status lam_kmeans_workspace_size(int precision, int n, int D, int k, uint64_t* bytes);
+lam_status lam_kmeans_workspace_size(const lam_ctx* ctx, int precision, int n, int D, int k, uint64_t* bytes);
 
 /* Nearest centre of every point.  Device: X [n, D], C [k, D]; outputs
  * assign [n] (int32, overwritten) and d2 [n] (nullable: the squared distance
  * to that centre, float32, clamped at zero).  Stream-ordered. */
-lam_status lam_kmeans_assign(int precision, const float* X, int n, int D, const float* C, int k, int32_t* assign,
+lam_status lam_kmeans_assign(lam_ctx* ctx, int precision, const float* X, int n, int D, const float* C, int k, int32_t* assign,
                              float* d2, void* ws, uint64_t ws_bytes, void* stream);
 
 /* iters >= 1 Lloyd iterations from C0.  Device: X [n, D], weights [n]
@@ -365,13 +410,13 @@ lam_status lam_kmeans_assign(int precision, const float* X, int n, int D, const 
  * (nullable: total weight per centre under the last assignment) and
  * assign [n] (nullable: the last assignment, from which C was computed).
  * Stream-ordered. */
-lam_status lam_kmeans_lloyd(int precision, const float* X, const float* weights, int n, int D, const float* C0,
+lam_status lam_kmeans_lloyd(lam_ctx* ctx, int precision, const float* X, const float* weights, int n, int D, const float* C0,
                             int k, int iters, float* C, float* W, int32_t* assign, void* ws, uint64_t ws_bytes,
                             void* stream);
 
 /* Workspace bytes for lam_stream_kmeans.  Requires 0 <= m <= n, 0 <= Kp <= K
  * and m >= K - Kp.  Host-only. */
-lam_status lam_stream_kmeans_workspace_size(int precision, int n, int D, int Kp, int K, int m, uint64_t* bytes);
+lam_status lam_stream_kmeans_workspace_size(const lam_ctx* ctx, int precision, int n, int D, int Kp, int K, int m, uint64_t* bytes);
 
 /* One streaming step.  Device: F [n, D] the new embeddings (weight 1 each),
  * D_prev [Kp, D] and w_prev [Kp] the global centres and their weights (Kp = 0
@@ -386,24 +431,24 @@ lam_status lam_stream_kmeans_workspace_size(int precision, int n, int D, int Kp,
  * Errors: LAM_ERR_INVALID_ARG (sizes, null or misaligned pointers, a seed
  * outside [0, n), workspace too small), LAM_ERR_UNSUPPORTED (shape),
  * LAM_ERR_HIP. */
-lam_status lam_stream_kmeans(int precision, const float* F, int n, int D, const float* D_prev,
+lam_status lam_stream_kmeans(lam_ctx* ctx, int precision, const float* F, int n, int D, const float* D_prev,
                              const float* w_prev, int Kp, int K, const int32_t* seeds, int m, int iters_local,
                              int iters_global, float* D_out, float* W_out, void* ws, uint64_t ws_bytes,
                              void* stream);
 
 /* --------------------------------------------------------------- profiling */
 
-/* Turns per-kernel timing on or off (process-wide, off by default).  While on,
- * the main kernels (names: "raster_fwd", "raster_bwd", "decode_rows",
+/* Turns per-kernel timing on or off for the calls made through ``ctx`` (off
+ * by default).  While on, the main kernels (names: "raster_fwd", "raster_bwd", "decode_rows",
  * "decode_tn", "render_sort", "preprocess", "preprocess_bwd", "tied_prep",
  * "tied_grads", "kmeans", "kmeans_assign", "rgbd_l1", "ssim") are bracketed by
  * HIP events recorded on their launch stream.  Not for use under graph capture. */
-lam_status lam_profile_enable(int on);
+lam_status lam_profile_enable(lam_ctx* ctx, int on);
 
 /* BLOCKING: waits for the recorded events of kernel ``name``, returns the sum
  * of their elapsed times (ms) and how many launches were recorded, and clears
  * them.  Unknown names read as zero launches. */
-lam_status lam_profile_read(const char* name, double* total_ms, int* count);
+lam_status lam_profile_read(lam_ctx* ctx, const char* name, double* total_ms, int* count);
 
 #ifdef __cplusplus
 }

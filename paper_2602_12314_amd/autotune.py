@@ -1,17 +1,21 @@
-"""Autotuner for the render tile shape and the decode block shape.
+"""Autotuner for the render tile shape and the decode launch options.
 
 The rendered query map does not depend on the tile shape (each Gaussian is
 blended into exactly the pixels of its footprint), so the shape is a pure
 performance choice: ``best_tile`` times render forward + backward for each
 candidate on the caller's own scene and cameras and keeps the fastest.
-``best_decode_shape`` times the decode + loss + gradients call for its two
-workgroup shapes (32 pixels x 4 waves, 64 pixels x 8 waves) on inputs of the
-caller's sizes; the results agree to rounding.  Results are cached in JSON
-keyed by GPU architecture and workload shape (``$LAM_AUTOTUNE_CACHE``, default
+``best_decode_options`` times the decode + loss + gradients call for each
+combination of the context options ``decode_shape`` (32 pixels x 4 waves, 64
+pixels x 8 waves) and ``decode_splits`` (the dV GEMM's pixel-range splits) on
+inputs of the caller's sizes, each under a context of its own; the results
+agree to rounding.  The chosen options are what ``lam_create`` takes as its
+JSON argument (``Context(options=...)``).  Results are cached in JSON keyed by
+GPU architecture and workload shape (``$LAM_AUTOTUNE_CACHE``, default
 ``~/.cache/latentam/autotune.json``).
 """
 from __future__ import annotations
 
+import itertools
 import json
 import os
 import time
@@ -23,6 +27,8 @@ import torch
 from . import _lib, ops
 
 CANDIDATES = ((16, 16), (8, 8), (16, 8), (8, 16), (32, 8), (8, 32), (16, 4), (32, 4))
+DECODE_SHAPES = tuple(_lib.DECODE_SHAPES)  # px32, px64
+DECODE_SPLITS = (0, 16, 32, 64, 128)       # 0: the library's device-filling rule
 
 
 def cache_path() -> str:
@@ -30,10 +36,13 @@ def cache_path() -> str:
                           os.path.join(os.path.expanduser("~"), ".cache", "latentam", "autotune.json"))
 
 
+def _arch() -> str:
+    return torch.cuda.get_device_properties(torch.cuda.current_device()).gcnArchName.split(":")[0]
+
+
 def _key(cams: np.ndarray, n_gauss: int, d: int) -> str:
-    arch = torch.cuda.get_device_properties(torch.cuda.current_device()).gcnArchName.split(":")[0]
     views = ",".join(f"{int(c[0])}x{int(c[1])}" for c in cams)
-    return f"{arch}|N={n_gauss}|d={d}|views={views}"
+    return f"{_arch()}|N={n_gauss}|d={d}|views={views}"
 
 
 def _load() -> dict:
@@ -46,16 +55,16 @@ def _load() -> dict:
 
 def _store(db: dict):
     path = cache_path()
-    os.makedirs(os.path.dirname(path), exist_ok=True)
+    os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
     tmp = path + ".tmp"
     with open(tmp, "w") as fh:
         json.dump(db, fh, indent=1, sort_keys=True)
     os.replace(tmp, path)
 
 
-def time_tile(g: ops.Gaussians, cams, tile, reps: int = 5, warmup: int = 2) -> float:
+def time_tile(g: ops.Gaussians, cams, tile, reps: int = 5, warmup: int = 2, ctx=None) -> float:
     """Median ms of render forward + backward with a random upstream gradient."""
-    r = ops.Renderer(cams, g.n, g.d, tile=tile)
+    r = ops.Renderer(cams, g.n, g.d, tile=tile, ctx=ctx)
     Q, T = r.forward(g)
     dQ = torch.randn_like(Q)
     out = g.zeros_like()
@@ -75,14 +84,14 @@ def time_tile(g: ops.Gaussians, cams, tile, reps: int = 5, warmup: int = 2) -> f
 
 
 def best_tile(g: ops.Gaussians, cams, candidates: Iterable[Tuple[int, int]] = CANDIDATES,
-              use_cache: bool = True, reps: int = 5) -> Tuple[Tuple[int, int], dict]:
+              use_cache: bool = True, reps: int = 5, ctx=None) -> Tuple[Tuple[int, int], dict]:
     cams = np.asarray(cams, np.float32).reshape(-1, 22)
     key = _key(cams, g.n, g.d)
     db = _load() if use_cache else {}
     if use_cache and key in db:
         ent = db[key]
         return tuple(ent["tile"]), ent["ms"]
-    times = {f"{tw}x{th}": time_tile(g, cams, (tw, th), reps=reps) for tw, th in candidates}
+    times = {f"{tw}x{th}": time_tile(g, cams, (tw, th), reps=reps, ctx=ctx) for tw, th in candidates}
     best = min(times, key=times.get)
     tile = tuple(int(v) for v in best.split("x"))
     if use_cache:
@@ -91,44 +100,64 @@ def best_tile(g: ops.Gaussians, cams, candidates: Iterable[Tuple[int, int]] = CA
     return tile, times
 
 
-def time_decode_shape(precision: str, n: int, d: int, M: int, D: int, shape: str, reps: int = 5,
-                      warmup: int = 2) -> float:
-    """Median ms of decode + loss + gradients with the given block shape."""
+def _decode_inputs(n, d, M, D):
     dev = torch.device("cuda", torch.cuda.current_device())
     gen = torch.Generator(device=dev).manual_seed(0)
     Q = torch.randn((n, d), device=dev, generator=gen)
     K = torch.randn((M, d), device=dev, generator=gen)
     V = torch.randn((M, D), device=dev, generator=gen)
     T = torch.nn.functional.normalize(torch.randn((n, D), device=dev, generator=gen), dim=1)
-    dec = ops.Decoder(precision, n, d, M, D, device=dev)
-    _lib.set_decode_shape(shape)
-    try:
-        for _ in range(warmup):
-            dec.loss_and_grads(Q, K, V, T, K, 0.1)
+    return Q, K, V, T
+
+
+def time_decode_options(precision: str, n: int, d: int, M: int, D: int, options: dict, reps: int = 5,
+                        warmup: int = 2, inputs=None) -> float:
+    """Median ms of decode + loss + gradients under a context with ``options``."""
+    Q, K, V, T = inputs if inputs is not None else _decode_inputs(n, d, M, D)
+    ctx = _lib.Context(options=options)
+    dec = ops.Decoder(precision, n, d, M, D, device=Q.device, ctx=ctx)
+    for _ in range(warmup):
+        dec.loss_and_grads(Q, K, V, T, K, 0.1)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        dec.loss_and_grads(Q, K, V, T, K, 0.1)
         torch.cuda.synchronize()
-        ts = []
-        for _ in range(reps):
-            t0 = time.perf_counter()
-            dec.loss_and_grads(Q, K, V, T, K, 0.1)
-            torch.cuda.synchronize()
-            ts.append((time.perf_counter() - t0) * 1e3)
-    finally:
-        _lib.set_decode_shape("px32")
+        ts.append((time.perf_counter() - t0) * 1e3)
+    del dec
+    ctx.close()
     return float(np.median(ts))
 
 
-def best_decode_shape(precision: str, n: int, d: int, M: int, D: int, use_cache: bool = True,
-                      reps: int = 5) -> Tuple[str, dict]:
-    """Fastest decode block shape for these sizes (it is not set; call
-    ``_lib.set_decode_shape`` with the result)."""
-    arch = torch.cuda.get_device_properties(torch.cuda.current_device()).gcnArchName.split(":")[0]
-    key = f"{arch}|decode|{precision}|n={n}|d={d}|M={M}|D={D}"
+def decode_candidates(shapes=DECODE_SHAPES, splits=DECODE_SPLITS):
+    return [{"decode_shape": s, "decode_splits": k} for s, k in itertools.product(shapes, splits)]
+
+
+def _name(opt: dict) -> str:
+    return f"{opt['decode_shape']}/splits={opt['decode_splits']}"
+
+
+def best_decode_options(precision: str, n: int, d: int, M: int, D: int, use_cache: bool = True,
+                        reps: int = 5, candidates=None) -> Tuple[dict, dict]:
+    """Fastest decode options for these sizes: ({"decode_shape", "decode_splits"},
+    {candidate name: ms}).  Pass the options to ``Context(options=...)``."""
+    key = f"{_arch()}|decode|{precision}|n={n}|d={d}|M={M}|D={D}"
     db = _load() if use_cache else {}
-    if use_cache and key in db:
-        return db[key]["shape"], db[key]["ms"]
-    times = {s: time_decode_shape(precision, n, d, M, D, s, reps=reps) for s in _lib.DECODE_SHAPES}
-    best = min(times, key=times.get)
+    if use_cache and key in db and "options" in db[key]:
+        return dict(db[key]["options"]), db[key]["ms"]
+    cands = candidates if candidates is not None else decode_candidates()
+    inputs = _decode_inputs(n, d, M, D)
+    times = {}
+    for opt in cands:
+        times[_name(opt)] = time_decode_options(precision, n, d, M, D, opt, reps=reps, inputs=inputs)
+    best = min(cands, key=lambda o: times[_name(o)])
     if use_cache:
-        db[key] = {"shape": best, "ms": times}
+        db[key] = {"options": dict(best), "ms": times}
         _store(db)
-    return best, times
+    return dict(best), times
+
+
+def options_json(options: dict) -> str:
+    """The JSON text ``lam_create`` takes for these options."""
+    return json.dumps(_lib._encode_options(options), sort_keys=True)

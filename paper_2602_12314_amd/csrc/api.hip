@@ -144,21 +144,7 @@ const char* lam_status_string(int status)
 
 int lam_version(void) { return LAM_VERSION; }
 
-lam_status lam_set_raster_schedule(int mode)
-{
-    if (mode < 0 || mode > 2) return LAM_ERR_INVALID_ARG;
-    set_raster_schedule(mode);
-    return LAM_OK;
-}
-
-lam_status lam_set_decode_shape(int mode)
-{
-    if (mode < 0 || mode > 1) return LAM_ERR_INVALID_ARG;
-    set_decode_shape(mode);
-    return LAM_OK;
-}
-
-lam_status lam_render_workspace_size(int n_gauss, int d, const float* cams, int n_cams,
+lam_status lam_render_workspace_size(const lam_ctx* ctx, int n_gauss, int d, const float* cams, int n_cams,
                                      int tile_w, int tile_h, uint64_t instance_capacity,
                                      uint64_t* bytes)
 {
@@ -181,12 +167,13 @@ static lam_status check_gauss(const float* means, const float* log_scales, const
     return LAM_OK;
 }
 
-lam_status lam_render_forward(const float* means, const float* log_scales, const float* quats,
+lam_status lam_render_forward(lam_ctx* ctx, const float* means, const float* log_scales, const float* quats,
                               const float* opacity_logits, const float* queries, int n_gauss,
                               int d, const float* cams, int n_cams, int tile_w, int tile_h,
                               float* Q, float* T_final, void* ws, uint64_t ws_bytes,
                               uint64_t instance_capacity, void* stream)
 {
+    if (!ctx_ok(ctx)) return LAM_ERR_INVALID_ARG;
     lam_status s = check_gauss(means, log_scales, quats, opacity_logits, queries, n_gauss);
     if (s != LAM_OK) return s;
     RenderLayout L;
@@ -205,11 +192,11 @@ lam_status lam_render_forward(const float* means, const float* log_scales, const
     A.queries = queries;
     A.Q = Q;
     A.T_final = T_final;
-    hipError_t e = render_forward_launch(A, L, (hipStream_t)stream);
+    hipError_t e = render_forward_launch(ctx, A, L, (hipStream_t)stream);
     return e == hipSuccess ? LAM_OK : LAM_ERR_HIP;
 }
 
-lam_status lam_render_backward(const float* means, const float* log_scales, const float* quats,
+lam_status lam_render_backward(lam_ctx* ctx, const float* means, const float* log_scales, const float* quats,
                                const float* opacity_logits, const float* queries, int n_gauss,
                                int d, const float* cams, int n_cams, int tile_w, int tile_h,
                                const float* dQ, float* d_means, float* d_log_scales,
@@ -217,6 +204,7 @@ lam_status lam_render_backward(const float* means, const float* log_scales, cons
                                void* ws, uint64_t ws_bytes, uint64_t instance_capacity,
                                void* stream)
 {
+    if (!ctx_ok(ctx)) return LAM_ERR_INVALID_ARG;
     lam_status s = check_gauss(means, log_scales, quats, opacity_logits, queries, n_gauss);
     if (s != LAM_OK) return s;
     if (!ptr_ok(d_means, n_gauss) || !ptr_ok(d_log_scales, n_gauss) || !ptr_ok(d_quats, n_gauss) ||
@@ -242,16 +230,17 @@ lam_status lam_render_backward(const float* means, const float* log_scales, cons
     A.d_quats = d_quats;
     A.d_logits = d_opacity_logits;
     A.d_queries = d_queries;
-    hipError_t e = render_backward_launch(A, L, (hipStream_t)stream);
+    hipError_t e = render_backward_launch(ctx, A, L, (hipStream_t)stream);
     return e == hipSuccess ? LAM_OK : LAM_ERR_HIP;
 }
 
-lam_status lam_render_rgbd_forward(const float* means, const float* log_scales, const float* quats,
+lam_status lam_render_rgbd_forward(lam_ctx* ctx, const float* means, const float* log_scales, const float* quats,
                                    const float* opacity_logits, const float* queries, const float* colors,
                                    int n_gauss, int d, const float* cams, int n_cams, int tile_w, int tile_h,
                                    float* Q, float* rgb, float* depth, float* T_final, void* ws,
                                    uint64_t ws_bytes, uint64_t instance_capacity, void* stream)
 {
+    if (!ctx_ok(ctx)) return LAM_ERR_INVALID_ARG;
     lam_status s = check_gauss(means, log_scales, quats, opacity_logits, queries, n_gauss);
     if (s != LAM_OK) return s;
     if (!ptr_ok(colors, n_gauss)) return LAM_ERR_INVALID_ARG;
@@ -277,11 +266,11 @@ lam_status lam_render_rgbd_forward(const float* means, const float* log_scales, 
     A.colors = colors;
     A.rgb = rgb;
     A.depth = depth;
-    hipError_t e = render_forward_launch(A, L, (hipStream_t)stream);
+    hipError_t e = render_forward_launch(ctx, A, L, (hipStream_t)stream);
     return e == hipSuccess ? LAM_OK : LAM_ERR_HIP;
 }
 
-lam_status lam_render_rgbd_backward(const float* means, const float* log_scales, const float* quats,
+lam_status lam_render_rgbd_backward(lam_ctx* ctx, const float* means, const float* log_scales, const float* quats,
                                     const float* opacity_logits, const float* queries, const float* colors,
                                     int n_gauss, int d, const float* cams, int n_cams, int tile_w, int tile_h,
                                     const float* dQ, const float* d_rgb, const float* d_depth, float* d_means,
@@ -289,6 +278,7 @@ lam_status lam_render_rgbd_backward(const float* means, const float* log_scales,
                                     float* d_queries, float* d_colors, void* ws, uint64_t ws_bytes,
                                     uint64_t instance_capacity, void* stream)
 {
+    if (!ctx_ok(ctx)) return LAM_ERR_INVALID_ARG;
     lam_status s = check_gauss(means, log_scales, quats, opacity_logits, queries, n_gauss);
     if (s != LAM_OK) return s;
     if (!ptr_ok(colors, n_gauss) || !ptr_ok(d_colors, n_gauss)) return LAM_ERR_INVALID_ARG;
@@ -321,14 +311,14 @@ lam_status lam_render_rgbd_backward(const float* means, const float* log_scales,
     A.d_rgb = d_rgb;
     A.d_depth = d_depth;
     A.d_colors = d_colors;
-    hipError_t e = render_backward_launch(A, L, (hipStream_t)stream);
+    hipError_t e = render_backward_launch(ctx, A, L, (hipStream_t)stream);
     return e == hipSuccess ? LAM_OK : LAM_ERR_HIP;
 }
 
-lam_status lam_render_counters(const void* ws, void* stream, uint64_t* instances_needed,
+lam_status lam_render_counters(lam_ctx* ctx, const void* ws, void* stream, uint64_t* instances_needed,
                                int* overflowed)
 {
-    if (!ws || !instances_needed || !overflowed) return LAM_ERR_INVALID_ARG;
+    if (!ctx_ok(ctx) || !ws || !instances_needed || !overflowed) return LAM_ERR_INVALID_ARG;
     uint32_t c[2] = {0, 0};
     if (hipMemcpyAsync(c, ws, sizeof(c), hipMemcpyDeviceToHost, (hipStream_t)stream) != hipSuccess)
         return LAM_ERR_HIP;
@@ -338,7 +328,7 @@ lam_status lam_render_counters(const void* ws, void* stream, uint64_t* instances
     return c[1] ? LAM_ERR_CAPACITY : LAM_OK;
 }
 
-lam_status lam_render_debug_views(const void* ws, int n_gauss, int d, const float* cams,
+lam_status lam_render_debug_views(const lam_ctx* ctx, const void* ws, int n_gauss, int d, const float* cams,
                                   int n_cams, int tile_w, int tile_h, uint64_t instance_capacity,
                                   const uint32_t** tile_keys, const uint32_t** tile_recs,
                                   const uint32_t** ranges, const uint32_t** depth_keys,

@@ -1198,29 +1198,23 @@ static bool wide_ok(int prec, int Mp, int D)
     return prec != LAM_FP32 && D % 256 == 0 && D / 256 <= max_nt && rows_lds(prec, Mp, D, 8, 2) <= kMaxLds;
 }
 
-// Decode block shape, process-wide: 0 = 32 pixels x 4 waves (default), 1 = 64
-// pixels x 8 waves where wide_ok allows (else 32 x 4).  Same results up to the
-// order of the per-pixel sums over the waves.
-static int g_decode_shape = 0;
-
-void set_decode_shape(int mode) { g_decode_shape = mode; }
-
-static bool wide_rows(int prec, int Mp, int D) { return g_decode_shape == 1 && wide_ok(prec, Mp, D); }
 
 // 32-column tiles per wave in the dV GEMM: two when D is a multiple of 256.
 static int dv_cols(int D) { return D % 256 == 0 ? 2 : 1; }
 
-static int pick_splits(int nblocks, int tiles)
+// Pixel-range splits of a dictionary GEMM with ``tiles`` output tiles: the
+// context's choice, else enough workgroups to fill 256 CUs twice; a multiple
+// of 8, at most the (even) number of 32-pixel blocks rounded up to 8.
+static int pick_splits(int nblocks, int tiles, int want)
 {
-    // enough workgroups to fill 256 CUs twice, splits a multiple of 8
-    int s = (512 + tiles - 1) / tiles;
+    int s = want > 0 ? want : (512 + tiles - 1) / tiles;
     s = ((s + 7) / 8) * 8;
     if (s > nblocks) s = ((nblocks + 7) / 8) * 8;
     if (s < 8) s = 8;
     return s;
 }
 
-bool decode_layout(int prec, int n, int d, int M, int D, DecodeLayout* L)
+bool decode_layout(const lam_ctx* ctx, int prec, int n, int d, int M, int D, DecodeLayout* L)
 {
     if (prec != LAM_FP32 && prec != LAM_BF16 && prec != LAM_FP8_E4M3) return false;
     if ((d != 16 && d != 32) || M < 1 || M > 2048 || D < 128 || D > 1024 || D % 128 != 0 || n < 0)
@@ -1234,10 +1228,14 @@ bool decode_layout(int prec, int n, int d, int M, int D, DecodeLayout* L)
     if (rows_lds(prec, Mp, D, 4, 1) > kMaxLds) return false;  // the 32 x 4 shape always fits
     L->Mp = Mp;
     L->row_blocks = nb;
+    // block shape (Same results up to the order of the per-pixel sums over the
+    // waves): 64 pixels x 8 waves where wide_ok allows and the context asks
+    L->wide = ctx->decode_shape.load() == 1 && wide_ok(prec, Mp, D);
     const int tiles_v = ((Mp + 127) / 128) * (D / (128 * dv_cols(D)));
     const int tiles_k = (Mp + 255) / 256;
-    const int sv = pick_splits(std::max(nb, 1), tiles_v);
-    const int sk = pick_splits(std::max(nb, 1), tiles_k);
+    // the context may set the dV GEMM's splits (the larger GEMM); dK's keep the rule
+    const int sv = pick_splits(std::max(nb, 1), tiles_v, ctx->decode_splits.load());
+    const int sk = pick_splits(std::max(nb, 1), tiles_k, 0);
     L->splits = sv;
     L->splits_k = sk;
     size_t off = 0;
@@ -1262,22 +1260,17 @@ bool decode_layout(int prec, int n, int d, int M, int D, DecodeLayout* L)
 }
 
 template <class P, int MODE, bool F8>
-static hipError_t launch_rows(const RowsArgs& ra, int nb, int D, int d, int Mp, int prec, hipStream_t st)
+static hipError_t launch_rows(lam_ctx* ctx, const RowsArgs& ra, bool wide, int nb, int D, int d, int Mp, int prec,
+                              hipStream_t st)
 {
-    const bool wide = wide_rows(prec, Mp, D);
     const int NW = wide ? 8 : 4, NPG = wide ? 2 : 1;
     const int NT = D / (32 * NW);
     const size_t lds = rows_lds(prec, Mp, D, NW, NPG);
 #define LAM_ROWS(NWV, NPGV, NTV, DQV)                                                                \
     if (NW == NWV && NT == NTV && d == DQV) {                                                        \
         auto kern = k_dec_rows<P, NTV, DQV, MODE, F8, NWV, NPGV>;                                     \
-        static size_t lds_set = 0; /* raised only when needed, so captured replays make no call */    \
-        if (lds > lds_set) {                                                                         \
-            if (hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,   \
-                                    (int)lds) != hipSuccess)                                         \
-                return hipErrorInvalidValue;                                                         \
-            lds_set = lds;                                                                           \
-        }                                                                                            \
+        const hipError_t el = ctx_ensure_lds(ctx, (const void*)kern, lds);                           \
+        if (el != hipSuccess) return el;                                                             \
         hipLaunchKernelGGL(kern, dim3(nb / NPGV), dim3(NWV * kWave), lds, st, ra);                  \
         return hipGetLastError();                                                                    \
     }
@@ -1295,22 +1288,8 @@ static hipError_t launch_rows(const RowsArgs& ra, int nb, int D, int d, int Mp, 
     return hipErrorInvalidValue;
 }
 
-// One event per device (created on first use) marks the end of the rows
-// kernel for a second stream to wait on.  A wait refers to the record made
-// before it, so reusing the event across calls is safe.
-static hipEvent_t fork_event()
-{
-    static std::mutex mu;
-    static hipEvent_t ev[64] = {};
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
-    std::lock_guard<std::mutex> lk(mu);
-    if (!ev[dev] && hipEventCreateWithFlags(&ev[dev], hipEventDisableTiming) != hipSuccess) ev[dev] = nullptr;
-    return ev[dev];
-}
-
 template <class P, bool F8>
-static hipError_t run_decode(const DecodeArgs& A, const DecodeLayout& L, int mode, hipStream_t st,
+static hipError_t run_decode(lam_ctx* ctx, const DecodeArgs& A, const DecodeLayout& L, int mode, hipStream_t st,
                              hipStream_t st_dict)
 {
     using T = typename P::T;
@@ -1360,18 +1339,20 @@ static hipError_t run_decode(const DecodeArgs& A, const DecodeLayout& L, int mod
     }
     hipError_t e = hipSuccess;
     if (nb > 0) {
-        ProfScope ps("decode_rows", st);
-        if (mode == MODE_INFER) e = launch_rows<P, MODE_INFER, F8>(ra, nb, A.D, A.d, Mp, A.prec, st);
-        else if (mode == MODE_LOSS) e = launch_rows<P, MODE_LOSS, F8>(ra, nb, A.D, A.d, Mp, A.prec, st);
-        else e = launch_rows<P, MODE_ADJ, F8>(ra, nb, A.D, A.d, Mp, A.prec, st);
+        ProfScope ps(ctx, "decode_rows", st);
+        if (mode == MODE_INFER) e = launch_rows<P, MODE_INFER, F8>(ctx, ra, L.wide, nb, A.D, A.d, Mp, A.prec, st);
+        else if (mode == MODE_LOSS) e = launch_rows<P, MODE_LOSS, F8>(ctx, ra, L.wide, nb, A.D, A.d, Mp, A.prec, st);
+        else e = launch_rows<P, MODE_ADJ, F8>(ctx, ra, L.wide, nb, A.D, A.d, Mp, A.prec, st);
         if (e != hipSuccess) return e;
     }
     if (mode == MODE_INFER) return hipGetLastError();
     // The dictionary part (dV, dK, their reductions and the loss) reads only
     // the workspace; on a second stream it runs beside whatever the caller
     // queues on st after dQ (the render backward).
+    // (the context's event marks the end of the rows kernel; a wait refers to
+    // the record made before it, so reusing the event across calls is safe)
     if (st_dict != st) {
-        hipEvent_t ev = fork_event();
+        hipEvent_t ev = ctx->fork;
         if (!ev) return hipErrorInvalidValue;
         e = hipEventRecord(ev, st);
         if (e == hipSuccess) e = hipStreamWaitEvent(st_dict, ev, 0);
@@ -1384,7 +1365,7 @@ static hipError_t run_decode(const DecodeArgs& A, const DecodeLayout& L, int mod
         const int qt = dv_cols(A.D);
         const int ti = (Mp + 127) / 128, tj = A.D / (128 * qt);
         if (nb > 0) {
-            ProfScope ps("decode_tn", st);
+            ProfScope ps(ctx, "decode_tn", st);
             auto kern = qt == 2 ? (A.d == 16 ? k_dec_dv<P, 16, 2> : k_dec_dv<P, 32, 2>)
                                 : (A.d == 16 ? k_dec_dv<P, 16, 1> : k_dec_dv<P, 32, 1>);
             hipLaunchKernelGGL(kern, dim3(L.splits * ti * tj), dim3(256), 0, st, A.Q, A.n,
@@ -1415,26 +1396,27 @@ static hipError_t run_decode(const DecodeArgs& A, const DecodeLayout& L, int mod
     return hipGetLastError();
 }
 
-hipError_t decode_loss_launch(const DecodeArgs& A, const DecodeLayout& L, hipStream_t st, hipStream_t st_dict)
+hipError_t decode_loss_launch(lam_ctx* ctx, const DecodeArgs& A, const DecodeLayout& L, hipStream_t st,
+                              hipStream_t st_dict)
 {
     if (!st_dict) st_dict = st;
-    if (A.prec == LAM_FP32) return run_decode<TF32, false>(A, L, MODE_LOSS, st, st_dict);
-    if (A.prec == LAM_FP8_E4M3) return run_decode<TBF16, true>(A, L, MODE_LOSS, st, st_dict);
-    return run_decode<TBF16, false>(A, L, MODE_LOSS, st, st_dict);
+    if (A.prec == LAM_FP32) return run_decode<TF32, false>(ctx, A, L, MODE_LOSS, st, st_dict);
+    if (A.prec == LAM_FP8_E4M3) return run_decode<TBF16, true>(ctx, A, L, MODE_LOSS, st, st_dict);
+    return run_decode<TBF16, false>(ctx, A, L, MODE_LOSS, st, st_dict);
 }
 
-hipError_t decode_forward_launch(const DecodeArgs& A, const DecodeLayout& L, hipStream_t st)
+hipError_t decode_forward_launch(lam_ctx* ctx, const DecodeArgs& A, const DecodeLayout& L, hipStream_t st)
 {
-    if (A.prec == LAM_FP32) return run_decode<TF32, false>(A, L, MODE_INFER, st, st);
-    if (A.prec == LAM_FP8_E4M3) return run_decode<TBF16, true>(A, L, MODE_INFER, st, st);
-    return run_decode<TBF16, false>(A, L, MODE_INFER, st, st);
+    if (A.prec == LAM_FP32) return run_decode<TF32, false>(ctx, A, L, MODE_INFER, st, st);
+    if (A.prec == LAM_FP8_E4M3) return run_decode<TBF16, true>(ctx, A, L, MODE_INFER, st, st);
+    return run_decode<TBF16, false>(ctx, A, L, MODE_INFER, st, st);
 }
 
-hipError_t decode_backward_launch(const DecodeArgs& A, const DecodeLayout& L, hipStream_t st)
+hipError_t decode_backward_launch(lam_ctx* ctx, const DecodeArgs& A, const DecodeLayout& L, hipStream_t st)
 {
-    if (A.prec == LAM_FP32) return run_decode<TF32, false>(A, L, MODE_ADJ, st, st);
-    if (A.prec == LAM_FP8_E4M3) return run_decode<TBF16, true>(A, L, MODE_ADJ, st, st);
-    return run_decode<TBF16, false>(A, L, MODE_ADJ, st, st);
+    if (A.prec == LAM_FP32) return run_decode<TF32, false>(ctx, A, L, MODE_ADJ, st, st);
+    if (A.prec == LAM_FP8_E4M3) return run_decode<TBF16, true>(ctx, A, L, MODE_ADJ, st, st);
+    return run_decode<TBF16, false>(ctx, A, L, MODE_ADJ, st, st);
 }
 
 }  // namespace lam
@@ -1453,33 +1435,34 @@ static bool dec_ptrs_ok(const float* Q, int n, const float* K, const float* V)
 
 extern "C" {
 
-lam_status lam_decode_workspace_size(int precision, int n, int d, int M, int D, uint64_t* bytes)
+lam_status lam_decode_workspace_size(const lam_ctx* ctx, int precision, int n, int d, int M, int D,
+                                     uint64_t* bytes)
 {
     if (!bytes) return LAM_ERR_INVALID_ARG;
     if (n < 0) return LAM_ERR_INVALID_ARG;
     DecodeLayout L{};
-    if (!decode_layout(precision, n, d, M, D, &L)) return LAM_ERR_UNSUPPORTED;
+    if (!decode_layout(ctx_options(ctx), precision, n, d, M, D, &L)) return LAM_ERR_UNSUPPORTED;
     *bytes = L.bytes;
     return LAM_OK;
 }
 
-static lam_status dec_common(int precision, int n, int d, int M, int D, void* ws, uint64_t ws_bytes,
-                             DecodeLayout* L)
+static lam_status dec_common(const lam_ctx* ctx, int precision, int n, int d, int M, int D, void* ws,
+                             uint64_t ws_bytes, DecodeLayout* L)
 {
-    if (n < 0) return LAM_ERR_INVALID_ARG;
-    if (!decode_layout(precision, n, d, M, D, L)) return LAM_ERR_UNSUPPORTED;
+    if (!ctx_ok(ctx) || n < 0) return LAM_ERR_INVALID_ARG;
+    if (!decode_layout(ctx, precision, n, d, M, D, L)) return LAM_ERR_UNSUPPORTED;
     if (!ws || ws_bytes < L->bytes) return LAM_ERR_INVALID_ARG;
     L->base = ws;
     return LAM_OK;
 }
 
-lam_status lam_decode_loss(int precision, const float* Q, int n, int d, const float* K, const float* V,
+lam_status lam_decode_loss(lam_ctx* ctx, int precision, const float* Q, int n, int d, const float* K, const float* V,
                            int M, int D, const float* target, const float* K0, float lambda_tr,
                            float* loss, float* dQ, float* dK, float* dV, float* row_cos, void* ws,
                            uint64_t ws_bytes, void* stream)
 {
     DecodeLayout L{};
-    lam_status s = dec_common(precision, n, d, M, D, ws, ws_bytes, &L);
+    lam_status s = dec_common(ctx, precision, n, d, M, D, ws, ws_bytes, &L);
     if (s != LAM_OK) return s;
     if (!dec_ptrs_ok(Q, n, K, V) || !loss || !dK || !dV || (n > 0 && !target)) return LAM_ERR_INVALID_ARG;
     if (!a16(target) || !a16(dQ)) return LAM_ERR_INVALID_ARG;
@@ -1488,16 +1471,16 @@ lam_status lam_decode_loss(int precision, const float* Q, int n, int d, const fl
     A.prec = precision; A.n = n; A.d = d; A.M = M; A.D = D;
     A.Q = Q; A.K = K; A.V = V; A.target = target; A.K0 = K0; A.lambda_tr = lambda_tr;
     A.loss = loss; A.dQ = dQ; A.dK = dK; A.dV = dV; A.row_cos = row_cos;
-    return decode_loss_launch(A, L, (hipStream_t)stream) == hipSuccess ? LAM_OK : LAM_ERR_HIP;
+    return decode_loss_launch(ctx, A, L, (hipStream_t)stream) == hipSuccess ? LAM_OK : LAM_ERR_HIP;
 }
 
-lam_status lam_decode_loss_overlap(int precision, const float* Q, int n, int d, const float* K, const float* V,
+lam_status lam_decode_loss_overlap(lam_ctx* ctx, int precision, const float* Q, int n, int d, const float* K, const float* V,
                                    int M, int D, const float* target, const float* K0, float lambda_tr,
                                    float* loss, float* dQ, float* dK, float* dV, float* row_cos, void* ws,
                                    uint64_t ws_bytes, void* stream, void* dict_stream)
 {
     DecodeLayout L{};
-    lam_status s = dec_common(precision, n, d, M, D, ws, ws_bytes, &L);
+    lam_status s = dec_common(ctx, precision, n, d, M, D, ws, ws_bytes, &L);
     if (s != LAM_OK) return s;
     if (!dec_ptrs_ok(Q, n, K, V) || !loss || !dK || !dV || (n > 0 && !target)) return LAM_ERR_INVALID_ARG;
     if (!a16(target) || !a16(dQ)) return LAM_ERR_INVALID_ARG;
@@ -1506,36 +1489,36 @@ lam_status lam_decode_loss_overlap(int precision, const float* Q, int n, int d, 
     A.prec = precision; A.n = n; A.d = d; A.M = M; A.D = D;
     A.Q = Q; A.K = K; A.V = V; A.target = target; A.K0 = K0; A.lambda_tr = lambda_tr;
     A.loss = loss; A.dQ = dQ; A.dK = dK; A.dV = dV; A.row_cos = row_cos;
-    return decode_loss_launch(A, L, (hipStream_t)stream, (hipStream_t)dict_stream) == hipSuccess ? LAM_OK
+    return decode_loss_launch(ctx, A, L, (hipStream_t)stream, (hipStream_t)dict_stream) == hipSuccess ? LAM_OK
                                                                                                    : LAM_ERR_HIP;
 }
 
-lam_status lam_decode_forward(int precision, const float* Q, int n, int d, const float* K, const float* V,
+lam_status lam_decode_forward(lam_ctx* ctx, int precision, const float* Q, int n, int d, const float* K, const float* V,
                               int M, int D, float* F, void* ws, uint64_t ws_bytes, void* stream)
 {
     DecodeLayout L{};
-    lam_status s = dec_common(precision, n, d, M, D, ws, ws_bytes, &L);
+    lam_status s = dec_common(ctx, precision, n, d, M, D, ws, ws_bytes, &L);
     if (s != LAM_OK) return s;
     if (!dec_ptrs_ok(Q, n, K, V) || (n > 0 && !F) || !a16(F)) return LAM_ERR_INVALID_ARG;
     DecodeArgs A{};
     A.prec = precision; A.n = n; A.d = d; A.M = M; A.D = D;
     A.Q = Q; A.K = K; A.V = V; A.F = F;
-    return decode_forward_launch(A, L, (hipStream_t)stream) == hipSuccess ? LAM_OK : LAM_ERR_HIP;
+    return decode_forward_launch(ctx, A, L, (hipStream_t)stream) == hipSuccess ? LAM_OK : LAM_ERR_HIP;
 }
 
-lam_status lam_decode_backward(int precision, const float* Q, int n, int d, const float* K, const float* V,
+lam_status lam_decode_backward(lam_ctx* ctx, int precision, const float* Q, int n, int d, const float* K, const float* V,
                                int M, int D, const float* dF, float* dQ, float* dK, float* dV, void* ws,
                                uint64_t ws_bytes, void* stream)
 {
     DecodeLayout L{};
-    lam_status s = dec_common(precision, n, d, M, D, ws, ws_bytes, &L);
+    lam_status s = dec_common(ctx, precision, n, d, M, D, ws, ws_bytes, &L);
     if (s != LAM_OK) return s;
     if (!dec_ptrs_ok(Q, n, K, V) || !dK || !dV || (n > 0 && !dF) || !a16(dF) || !a16(dQ))
         return LAM_ERR_INVALID_ARG;
     DecodeArgs A{};
     A.prec = precision; A.n = n; A.d = d; A.M = M; A.D = D;
     A.Q = Q; A.K = K; A.V = V; A.dF = dF; A.dQ = dQ; A.dK = dK; A.dV = dV;
-    return decode_backward_launch(A, L, (hipStream_t)stream) == hipSuccess ? LAM_OK : LAM_ERR_HIP;
+    return decode_backward_launch(ctx, A, L, (hipStream_t)stream) == hipSuccess ? LAM_OK : LAM_ERR_HIP;
 }
 
 }  // extern "C"

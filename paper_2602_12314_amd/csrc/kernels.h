@@ -5,9 +5,67 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <atomic>
+#include <mutex>
+#include <string>
+#include <vector>
+
 #include "common.h"
 
 namespace lam {
+
+// Launch timing of one kernel name: recorded (begin, end) event pairs and a
+// pool of free events.
+struct ProfSlot {
+    std::string name;
+    std::vector<hipEvent_t> begin, end;
+    std::vector<hipEvent_t> pool;
+};
+
+}  // namespace lam
+
+// The library context (opaque in the C ABI): the device it was made for, the
+// launch choices an autotuner sets, and the per-device state the launches
+// share (occupancy of the persistent kernels, kernels whose LDS limit was
+// raised, the event that forks the dictionary gradients onto a second stream,
+// the optional per-kernel timers).  The knobs are atomics and the caches sit
+// behind ``mu``, so calls from several host threads on one context are safe.
+struct lam_ctx {
+    int device = 0;
+    std::atomic<int> raster_schedule{2};  // 0 per tile, 1 persistent, 2 persistent for several views
+    std::atomic<int> decode_shape{0};     // 0: 32 pixels x 4 waves, 1: 64 pixels x 8 waves where it fits
+    std::atomic<int> decode_splits{0};    // pixel-range splits of the dictionary GEMMs; 0: sized to the device
+    std::atomic<int> profile_on{0};
+    hipEvent_t fork = nullptr;
+    std::mutex mu;
+    struct Occ {
+        const void* kernel;
+        int threads, blocks;
+    };
+    std::vector<Occ> occ;
+    struct Lds {
+        const void* kernel;
+        size_t bytes;
+    };
+    std::vector<Lds> lds;
+    std::vector<lam::ProfSlot> prof;
+    int cus = 0;
+};
+
+namespace lam {
+
+// True when ``ctx`` is usable from this thread: not null and made for the
+// current HIP device.
+bool ctx_ok(const lam_ctx* ctx);
+// The options of ``ctx``, or the defaults when it is null (the host-only
+// size queries accept a null context).
+const lam_ctx* ctx_options(const lam_ctx* ctx);
+// Workgroups of ``kernel`` with ``threads`` threads resident on the device at
+// once (cached in the context).
+int ctx_resident_blocks(lam_ctx* ctx, const void* kernel, int threads);
+// Raises the dynamic LDS limit of ``kernel`` to at least ``bytes`` once per
+// context (a function attribute of the device).
+hipError_t ctx_ensure_lds(lam_ctx* ctx, const void* kernel, size_t bytes);
 
 // ------------------------------------------------------------- sort / scan
 size_t scan_scratch_words(uint32_t n);
@@ -22,13 +80,13 @@ hipError_t launch_radix_sort(const uint32_t* keys_first, uint32_t* keys_a, uint3
 hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t st);
 
 // ------------------------------------------------------------- profiling
-bool profiling();
-void prof_mark(const char* name, bool is_begin, hipStream_t st);
+void prof_mark(lam_ctx* ctx, const char* name, bool is_begin, hipStream_t st);
 struct ProfScope {
+    lam_ctx* ctx;
     const char* name;
     hipStream_t st;
-    ProfScope(const char* n, hipStream_t s) : name(n), st(s) { prof_mark(name, true, st); }
-    ~ProfScope() { prof_mark(name, false, st); }
+    ProfScope(lam_ctx* c, const char* n, hipStream_t s) : ctx(c), name(n), st(s) { prof_mark(ctx, name, true, st); }
+    ~ProfScope() { prof_mark(ctx, name, false, st); }
 };
 
 // ------------------------------------------------------------- render
@@ -72,9 +130,8 @@ struct RenderLayout {
     float* rec_dz;  // per-record gradient of the rendered depth
 };
 
-hipError_t render_forward_launch(const RenderArgs& A, const RenderLayout& L, hipStream_t st);
-hipError_t render_backward_launch(const RenderArgs& A, const RenderLayout& L, hipStream_t st);
-void set_raster_schedule(int mode);
+hipError_t render_forward_launch(lam_ctx* ctx, const RenderArgs& A, const RenderLayout& L, hipStream_t st);
+hipError_t render_backward_launch(lam_ctx* ctx, const RenderArgs& A, const RenderLayout& L, hipStream_t st);
 
 // ------------------------------------------------------------- decode
 struct DecodeArgs {
@@ -94,16 +151,17 @@ struct DecodeLayout {
     // byte offsets inside the workspace, filled by decode_layout()
     size_t off_kb, off_vb, off_vt, off_kt, off_gf, off_m2, off_ds, off_qt, off_part, off_loss, off_sc;
     int splits, splits_k;
+    bool wide;  // 64-pixel x 8-wave rows workgroups
 };
 
-bool decode_layout(int prec, int n, int d, int M, int D, DecodeLayout* L);
-void set_decode_shape(int mode);
+// The decode block shape and split count come from the context.
+bool decode_layout(const lam_ctx* ctx, int prec, int n, int d, int M, int D, DecodeLayout* L);
 // With st_dict (not null and not st) the dictionary gradients and the loss run
 // on st_dict after the rows kernel on st; the caller joins the two streams.
-hipError_t decode_loss_launch(const DecodeArgs& A, const DecodeLayout& L, hipStream_t st,
+hipError_t decode_loss_launch(lam_ctx* ctx, const DecodeArgs& A, const DecodeLayout& L, hipStream_t st,
                               hipStream_t st_dict = nullptr);
-hipError_t decode_forward_launch(const DecodeArgs& A, const DecodeLayout& L, hipStream_t st);
-hipError_t decode_backward_launch(const DecodeArgs& A, const DecodeLayout& L, hipStream_t st);
+hipError_t decode_forward_launch(lam_ctx* ctx, const DecodeArgs& A, const DecodeLayout& L, hipStream_t st);
+hipError_t decode_backward_launch(lam_ctx* ctx, const DecodeArgs& A, const DecodeLayout& L, hipStream_t st);
 
 // ------------------------------------------------------------- tied decode
 struct TiedArgs {
@@ -120,7 +178,7 @@ struct TiedLayout {
         off_loss;
 };
 
-bool tied_layout(int prec, int n, int ds, int M, int df, TiedLayout* L);
-hipError_t tied_loss_launch(const TiedArgs& T, const TiedLayout& L, void* base, hipStream_t st);
+bool tied_layout(const lam_ctx* ctx, int prec, int n, int ds, int M, int df, TiedLayout* L);
+hipError_t tied_loss_launch(lam_ctx* ctx, const TiedArgs& T, const TiedLayout& L, void* base, hipStream_t st);
 
 }  // namespace lam

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+struct lam_ctx;
+
 namespace lam {
 namespace km {
 
@@ -28,12 +30,12 @@ struct StreamKmLayout {
 bool kmeans_shape_ok(int prec, int D, int k);
 KmLayout kmeans_layout(int prec, int npts, int D, int k);
 StreamKmLayout stream_kmeans_layout(int prec, int n, int D, int Kp, int K, int m);
-hipError_t kmeans_assign_launch(int prec, const float* X, int n, int D, const float* C, int k, const KmLayout& L,
+hipError_t kmeans_assign_launch(lam_ctx* ctx, int prec, const float* X, int n, int D, const float* C, int k, const KmLayout& L,
                                 void* ws, uint32_t* a, float* d2, hipStream_t st);
-hipError_t kmeans_lloyd_launch(int prec, const float* X, const float* w, int n, int D, const float* C0, int k,
+hipError_t kmeans_lloyd_launch(lam_ctx* ctx, int prec, const float* X, const float* w, int n, int D, const float* C0, int k,
                                int iters, float* C, float* W, uint32_t* a_out, const KmLayout& L, void* ws,
                                hipStream_t st);
-hipError_t stream_kmeans_launch(int prec, const float* F, int n, int D, const float* Dprev, const float* wprev,
+hipError_t stream_kmeans_launch(lam_ctx* ctx, int prec, const float* F, int n, int D, const float* Dprev, const float* wprev,
                                 int Kp, int K, const int32_t* seeds_host, int m, int iters_local, int iters_global,
                                 float* Dout, float* Wout, const StreamKmLayout& S, void* ws, hipStream_t st);
 

@@ -560,22 +560,18 @@ KmLayout kmeans_layout(int prec, int npts, int D, int k)
 }
 
 template <class P, int NP, int PIPE>
-static hipError_t launch_assign_np(const float* X, int n, int D, const typename P::T* Cf, const float* cn, int kp,
-                                   int k, float* best_v, uint32_t* a, float* d2, hipStream_t st)
+static hipError_t launch_assign_np(lam_ctx* ctx, const float* X, int n, int D, const typename P::T* Cf,
+                                   const float* cn, int kp, int k, float* best_v, uint32_t* a, float* d2,
+                                   hipStream_t st)
 {
     auto kern = k_km_assign<P, NP, PIPE>;
     const size_t lds_max = (size_t)32 * NP * D * P::kBytes + (size_t)kSlice * 4 + (size_t)2 * 4 * 32 * NP * 4;
-    static size_t lds_set = 0;  // raised only when needed, so captured replays make no call
-    if (lds_max > lds_set) {
-        if (hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_max) !=
-            hipSuccess)
-            return hipErrorInvalidValue;
-        lds_set = lds_max;
-    }
+    hipError_t el = ctx_ensure_lds(ctx, (const void*)kern, lds_max);
+    if (el != hipSuccess) return el;
     const int blocks = (n + 32 * NP - 1) / (32 * NP);
     const int nc = D / 16;
     const int slices = (kp + kSlice - 1) / kSlice;
-    ProfScope ps("kmeans_assign", st);
+    ProfScope ps(ctx, "kmeans_assign", st);
     for (int s = 0; s < slices; ++s) {
         const int kbase = s * kSlice, kcp = std::min(kSlice, kp - kbase);
         const bool last = s == slices - 1;
@@ -588,15 +584,16 @@ static hipError_t launch_assign_np(const float* X, int n, int D, const typename 
 }
 
 template <class P, int NP>
-static hipError_t launch_assign_pipe(const float* X, int n, int D, const typename P::T* Cf, const float* cn,
-                                     int kp, int k, float* best_v, uint32_t* a, float* d2, hipStream_t st)
+static hipError_t launch_assign_pipe(lam_ctx* ctx, const float* X, int n, int D, const typename P::T* Cf,
+                                     const float* cn, int kp, int k, float* best_v, uint32_t* a, float* d2,
+                                     hipStream_t st)
 {
-    if ((D / 16) % 4 == 0) return launch_assign_np<P, NP, 4>(X, n, D, Cf, cn, kp, k, best_v, a, d2, st);
-    return launch_assign_np<P, NP, 2>(X, n, D, Cf, cn, kp, k, best_v, a, d2, st);
+    if ((D / 16) % 4 == 0) return launch_assign_np<P, NP, 4>(ctx, X, n, D, Cf, cn, kp, k, best_v, a, d2, st);
+    return launch_assign_np<P, NP, 2>(ctx, X, n, D, Cf, cn, kp, k, best_v, a, d2, st);
 }
 
 template <class P>
-static hipError_t launch_assign_p(const float* X, int n, int D, const float* C, int k, const KmLayout& L,
+static hipError_t launch_assign_p(lam_ctx* ctx, const float* X, int n, int D, const float* C, int k, const KmLayout& L,
                                   char* base, uint32_t* a, float* d2, hipStream_t st)
 {
     const int kp = (int)align_up((size_t)k, kCentreAlign);
@@ -609,17 +606,17 @@ static hipError_t launch_assign_p(const float* X, int n, int D, const float* C, 
     hipLaunchKernelGGL(k_km_norms, dim3((kp + 3) / 4), dim3(256), 0, st, C, k, kp, D, cn);
     if (n == 0) return hipGetLastError();
     const int bp = tile_points(P::kBytes == 2 ? LAM_BF16 : LAM_FP32, D);
-    if (bp == 64) return launch_assign_pipe<P, 2>(X, n, D, Cf, cn, kp, k, best_v, a, d2, st);
-    return launch_assign_pipe<P, 1>(X, n, D, Cf, cn, kp, k, best_v, a, d2, st);
+    if (bp == 64) return launch_assign_pipe<P, 2>(ctx, X, n, D, Cf, cn, kp, k, best_v, a, d2, st);
+    return launch_assign_pipe<P, 1>(ctx, X, n, D, Cf, cn, kp, k, best_v, a, d2, st);
 }
 
-hipError_t kmeans_assign_launch(int prec, const float* X, int n, int D, const float* C, int k, const KmLayout& L,
+hipError_t kmeans_assign_launch(lam_ctx* ctx, int prec, const float* X, int n, int D, const float* C, int k, const KmLayout& L,
                                 void* ws, uint32_t* a, float* d2, hipStream_t st)
 {
     char* base = static_cast<char*>(ws);
     uint32_t* aa = a ? a : reinterpret_cast<uint32_t*>(base + L.off_a);
-    if (prec == LAM_BF16) return launch_assign_p<PBF16>(X, n, D, C, k, L, base, aa, d2, st);
-    return launch_assign_p<PF32>(X, n, D, C, k, L, base, aa, d2, st);
+    if (prec == LAM_BF16) return launch_assign_p<PBF16>(ctx, X, n, D, C, k, L, base, aa, d2, st);
+    return launch_assign_p<PF32>(ctx, X, n, D, C, k, L, base, aa, d2, st);
 }
 
 template <int CG>
@@ -681,7 +678,7 @@ static hipError_t kmeans_update(const float* X, const float* w, int n, int D, in
     return hipGetLastError();
 }
 
-hipError_t kmeans_lloyd_launch(int prec, const float* X, const float* w, int n, int D, const float* C0, int k,
+hipError_t kmeans_lloyd_launch(lam_ctx* ctx, int prec, const float* X, const float* w, int n, int D, const float* C0, int k,
                                int iters, float* C, float* W, uint32_t* a_out, const KmLayout& L, void* ws,
                                hipStream_t st)
 {
@@ -689,13 +686,13 @@ hipError_t kmeans_lloyd_launch(int prec, const float* X, const float* w, int n, 
     float* cbuf[2] = {reinterpret_cast<float*>(base + L.off_c0), reinterpret_cast<float*>(base + L.off_c1)};
     float* wbuf = reinterpret_cast<float*>(base + L.off_w);
     uint32_t* a = reinterpret_cast<uint32_t*>(base + L.off_a);
-    ProfScope ps("kmeans", st);
+    ProfScope ps(ctx, "kmeans", st);
     const float* cur = C0;
     for (int it = 0; it < iters; ++it) {
         const bool last = it == iters - 1;
         float* next = last ? C : cbuf[it & 1];
         float* wn = (last && W) ? W : wbuf;
-        hipError_t e = kmeans_assign_launch(prec, X, n, D, cur, k, L, ws, a, nullptr, st);
+        hipError_t e = kmeans_assign_launch(ctx, prec, X, n, D, cur, k, L, ws, a, nullptr, st);
         if (e != hipSuccess) return e;
         e = kmeans_update(X, w, n, D, k, cur, next, wn, L, base, st);
         if (e != hipSuccess) return e;
@@ -731,7 +728,7 @@ StreamKmLayout stream_kmeans_layout(int prec, int n, int D, int Kp, int K, int m
     return S;
 }
 
-hipError_t stream_kmeans_launch(int prec, const float* F, int n, int D, const float* Dprev, const float* wprev,
+hipError_t stream_kmeans_launch(lam_ctx* ctx, int prec, const float* F, int n, int D, const float* Dprev, const float* wprev,
                                 int Kp, int K, const int32_t* seeds_host, int m, int iters_local, int iters_global,
                                 float* Dout, float* Wout, const StreamKmLayout& S, void* ws, hipStream_t st)
 {
@@ -749,7 +746,7 @@ hipError_t stream_kmeans_launch(int prec, const float* F, int n, int D, const fl
         e = hipMemcpyAsync(seeds, seeds_host, (size_t)m * 4, hipMemcpyHostToDevice, st);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_km_gather, dim3(m), dim3(128), 0, st, F, D, (const int32_t*)seeds, m, M0);
-        e = kmeans_lloyd_launch(prec, F, nullptr, n, D, M0, m, iters_local, Mc, Mw, nullptr, S.lloyd, ws, st);
+        e = kmeans_lloyd_launch(ctx, prec, F, nullptr, n, D, M0, m, iters_local, Mc, Mw, nullptr, S.lloyd, ws, st);
         if (e != hipSuccess) return e;
     }
     // merged weighted set [D_prev; micro] and the initial centres [D_prev; micro[0 .. K - Kp)]
@@ -768,7 +765,7 @@ hipError_t stream_kmeans_launch(int prec, const float* F, int n, int D, const fl
         e = hipMemcpyAsync(G0 + (size_t)Kp * D, Mc, (size_t)(K - Kp) * row, hipMemcpyDeviceToDevice, st);
         if (e != hipSuccess) return e;
     }
-    return kmeans_lloyd_launch(prec, P, Pw, Kp + m, D, G0, K, iters_global, Dout, Wout, nullptr, S.lloyd, ws, st);
+    return kmeans_lloyd_launch(ctx, prec, P, Pw, Kp + m, D, G0, K, iters_global, Dout, Wout, nullptr, S.lloyd, ws, st);
 }
 
 }  // namespace km
@@ -783,7 +780,7 @@ static bool km_aligned(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 
 extern "C" {
 
-lam_status lam_kmeans_workspace_size(int precision, int n, int D, int k, uint64_t* bytes)
+lam_status lam_kmeans_workspace_size(const lam_ctx* ctx, int precision, int n, int D, int k, uint64_t* bytes)
 {
     if (!bytes || n < 0) return LAM_ERR_INVALID_ARG;
     if (!kmeans_shape_ok(precision, D, k)) return LAM_ERR_UNSUPPORTED;
@@ -791,36 +788,36 @@ lam_status lam_kmeans_workspace_size(int precision, int n, int D, int k, uint64_
     return LAM_OK;
 }
 
-lam_status lam_kmeans_assign(int precision, const float* X, int n, int D, const float* C, int k, int32_t* assign,
+lam_status lam_kmeans_assign(lam_ctx* ctx, int precision, const float* X, int n, int D, const float* C, int k, int32_t* assign,
                              float* d2, void* ws, uint64_t ws_bytes, void* stream)
 {
-    if (n < 0) return LAM_ERR_INVALID_ARG;
+    if (!ctx_ok(ctx) || n < 0) return LAM_ERR_INVALID_ARG;
     if (!kmeans_shape_ok(precision, D, k)) return LAM_ERR_UNSUPPORTED;
     const KmLayout L = kmeans_layout(precision, n, D, k);
     if (!ws || ws_bytes < L.bytes || !C || (n > 0 && (!X || !assign))) return LAM_ERR_INVALID_ARG;
     if (!km_aligned(X) || !km_aligned(C)) return LAM_ERR_INVALID_ARG;
-    return kmeans_assign_launch(precision, X, n, D, C, k, L, ws, reinterpret_cast<uint32_t*>(assign), d2,
+    return kmeans_assign_launch(ctx, precision, X, n, D, C, k, L, ws, reinterpret_cast<uint32_t*>(assign), d2,
                                 (hipStream_t)stream) == hipSuccess
                ? LAM_OK
                : LAM_ERR_HIP;
 }
 
-lam_status lam_kmeans_lloyd(int precision, const float* X, const float* weights, int n, int D, const float* C0,
+lam_status lam_kmeans_lloyd(lam_ctx* ctx, int precision, const float* X, const float* weights, int n, int D, const float* C0,
                             int k, int iters, float* C, float* W, int32_t* assign, void* ws, uint64_t ws_bytes,
                             void* stream)
 {
-    if (n < 0 || iters < 1) return LAM_ERR_INVALID_ARG;
+    if (!ctx_ok(ctx) || n < 0 || iters < 1) return LAM_ERR_INVALID_ARG;
     if (!kmeans_shape_ok(precision, D, k)) return LAM_ERR_UNSUPPORTED;
     const KmLayout L = kmeans_layout(precision, n, D, k);
     if (!ws || ws_bytes < L.bytes || !C0 || !C || (n > 0 && !X)) return LAM_ERR_INVALID_ARG;
     if (!km_aligned(X) || !km_aligned(C0) || !km_aligned(C)) return LAM_ERR_INVALID_ARG;
-    return kmeans_lloyd_launch(precision, X, weights, n, D, C0, k, iters, C, W,
+    return kmeans_lloyd_launch(ctx, precision, X, weights, n, D, C0, k, iters, C, W,
                                reinterpret_cast<uint32_t*>(assign), L, ws, (hipStream_t)stream) == hipSuccess
                ? LAM_OK
                : LAM_ERR_HIP;
 }
 
-lam_status lam_stream_kmeans_workspace_size(int precision, int n, int D, int Kp, int K, int m, uint64_t* bytes)
+lam_status lam_stream_kmeans_workspace_size(const lam_ctx* ctx, int precision, int n, int D, int Kp, int K, int m, uint64_t* bytes)
 {
     if (!bytes || n < 0 || Kp < 0 || m < 0 || m > n || Kp > K || m < K - Kp) return LAM_ERR_INVALID_ARG;
     if (!kmeans_shape_ok(precision, D, std::max(std::max(m, K), 1)) || (size_t)Kp + m > (size_t)1 << 30)
@@ -829,12 +826,12 @@ lam_status lam_stream_kmeans_workspace_size(int precision, int n, int D, int Kp,
     return LAM_OK;
 }
 
-lam_status lam_stream_kmeans(int precision, const float* F, int n, int D, const float* D_prev,
+lam_status lam_stream_kmeans(lam_ctx* ctx, int precision, const float* F, int n, int D, const float* D_prev,
                              const float* w_prev, int Kp, int K, const int32_t* seeds, int m, int iters_local,
                              int iters_global, float* D_out, float* W_out, void* ws, uint64_t ws_bytes,
                              void* stream)
 {
-    if (n < 0 || Kp < 0 || m < 0 || m > n || Kp > K || m < K - Kp || iters_global < 1 ||
+    if (!ctx_ok(ctx) || n < 0 || Kp < 0 || m < 0 || m > n || Kp > K || m < K - Kp || iters_global < 1 ||
         (m > 0 && iters_local < 1))
         return LAM_ERR_INVALID_ARG;
     if (!kmeans_shape_ok(precision, D, std::max(std::max(m, K), 1))) return LAM_ERR_UNSUPPORTED;
@@ -844,7 +841,7 @@ lam_status lam_stream_kmeans(int precision, const float* F, int n, int D, const 
     if (!km_aligned(F) || !km_aligned(D_prev) || !km_aligned(D_out)) return LAM_ERR_INVALID_ARG;
     for (int i = 0; i < m; ++i)
         if (seeds[i] < 0 || seeds[i] >= n) return LAM_ERR_INVALID_ARG;
-    return stream_kmeans_launch(precision, F, n, D, D_prev, w_prev, Kp, K, seeds, m, iters_local, iters_global,
+    return stream_kmeans_launch(ctx, precision, F, n, D, D_prev, w_prev, Kp, K, seeds, m, iters_local, iters_global,
                                 D_out, W_out, S, ws, (hipStream_t)stream) == hipSuccess
                ? LAM_OK
                : LAM_ERR_HIP;

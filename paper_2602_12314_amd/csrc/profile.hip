@@ -1,11 +1,10 @@
 // Optional per-kernel timing with HIP events recorded on the launch stream.
-// Off by default; when on, every instrumented launch is bracketed by two
-// events and lam_profile_read sums their elapsed times per kernel name.
+// Off by default; when a context has it on, every instrumented launch made
+// through that context is bracketed by two events and lam_profile_read sums
+// their elapsed times per kernel name.
 #include <string.h>
 
-#include <mutex>
-#include <string>
-#include <vector>
+#include <algorithm>
 
 #include "common.h"
 #include "kernels.h"
@@ -13,16 +12,7 @@
 namespace lam {
 
 namespace {
-struct Slot {
-    std::string name;
-    std::vector<hipEvent_t> begin, end;  // recorded pairs
-    std::vector<hipEvent_t> pool;        // free events
-};
-std::mutex g_mu;
-bool g_on = false;
-std::vector<Slot> g_slots;
-
-hipEvent_t take_event(Slot& s)
+hipEvent_t take_event(ProfSlot& s)
 {
     if (!s.pool.empty()) {
         hipEvent_t e = s.pool.back();
@@ -34,26 +24,34 @@ hipEvent_t take_event(Slot& s)
     return e;
 }
 
-Slot& slot(const char* name)
+ProfSlot& slot(lam_ctx* ctx, const char* name)
 {
-    for (auto& s : g_slots)
+    for (auto& s : ctx->prof)
         if (s.name == name) return s;
-    g_slots.push_back(Slot{name, {}, {}, {}});
-    return g_slots.back();
+    ctx->prof.push_back(ProfSlot{name, {}, {}, {}});
+    return ctx->prof.back();
 }
 }  // namespace
 
-bool profiling() { return g_on; }
-
-void prof_mark(const char* name, bool is_begin, hipStream_t st)
+void prof_mark(lam_ctx* ctx, const char* name, bool is_begin, hipStream_t st)
 {
-    if (!g_on) return;
-    std::lock_guard<std::mutex> lk(g_mu);
-    Slot& s = slot(name);
+    if (!ctx || !ctx->profile_on.load()) return;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ProfSlot& s = slot(ctx, name);
     hipEvent_t e = take_event(s);
     if (!e) return;
     hipEventRecord(e, st);
     (is_begin ? s.begin : s.end).push_back(e);
+}
+
+void prof_release(lam_ctx* ctx)
+{
+    for (auto& s : ctx->prof) {
+        for (auto e : s.begin) hipEventDestroy(e);
+        for (auto e : s.end) hipEventDestroy(e);
+        for (auto e : s.pool) hipEventDestroy(e);
+    }
+    ctx->prof.clear();
 }
 
 }  // namespace lam
@@ -62,20 +60,20 @@ using namespace lam;
 
 extern "C" {
 
-lam_status lam_profile_enable(int on)
+lam_status lam_profile_enable(lam_ctx* ctx, int on)
 {
-    std::lock_guard<std::mutex> lk(g_mu);
-    g_on = on != 0;
+    if (!ctx) return LAM_ERR_INVALID_ARG;
+    ctx->profile_on.store(on != 0 ? 1 : 0);
     return LAM_OK;
 }
 
-lam_status lam_profile_read(const char* name, double* total_ms, int* count)
+lam_status lam_profile_read(lam_ctx* ctx, const char* name, double* total_ms, int* count)
 {
-    if (!name || !total_ms || !count) return LAM_ERR_INVALID_ARG;
-    std::lock_guard<std::mutex> lk(g_mu);
+    if (!ctx || !name || !total_ms || !count) return LAM_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(ctx->mu);
     *total_ms = 0.0;
     *count = 0;
-    for (auto& s : g_slots) {
+    for (auto& s : ctx->prof) {
         if (s.name != name) continue;
         const size_t n = std::min(s.begin.size(), s.end.size());
         for (size_t i = 0; i < n; ++i) {

@@ -779,41 +779,22 @@ hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t st)
 
 // ------------------------------------------------------------- scheduling
 
-static int g_raster_schedule = 2;  // 0 per tile, 1 persistent, 2 persistent for several views
-
-void set_raster_schedule(int mode) { g_raster_schedule = mode; }
-
-static bool use_persistent(const CamSet& cs)
+// The context's tile schedule: 0 one workgroup per tile, 1 persistent, 2
+// persistent when several views are rendered.
+static bool use_persistent(const lam_ctx* ctx, const CamSet& cs)
 {
-    return g_raster_schedule == 1 || (g_raster_schedule == 2 && cs.n > 1);
+    const int mode = ctx->raster_schedule.load();
+    return mode == 1 || (mode == 2 && cs.n > 1);
 }
 
-// Workgroups of ``kernel`` that fit on the device at once (queried once per
-// kernel and block size).
-static int resident_blocks(const void* kernel, int threads)
-{
-    struct Entry { const void* k; int t, n; };
-    static Entry cache[16];
-    static int used = 0;
-    for (int i = 0; i < used; ++i)
-        if (cache[i].k == kernel && cache[i].t == threads) return cache[i].n;
-    int dev = 0, cus = 0, per = 0;
-    hipGetDevice(&dev);
-    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, 0);
-    const int n = std::max(1, cus * std::max(per, 1));
-    if (used < 16) cache[used++] = Entry{kernel, threads, n};
-    return n;
-}
-
-hipError_t render_forward_launch(const RenderArgs& A, const RenderLayout& L, hipStream_t st)
+hipError_t render_forward_launch(lam_ctx* ctx, const RenderArgs& A, const RenderLayout& L, hipStream_t st)
 {
     const CamSet& cs = L.cams;
     const uint32_t R = (uint32_t)L.records;
     const uint32_t cap = (uint32_t)L.capacity;
     hipError_t e;
     if (A.n > 0) {
-        ProfScope ps("preprocess", st);
+        ProfScope ps(ctx, "preprocess", st);
         hipLaunchKernelGGL(k_preprocess, dim3((A.n + 255) / 256, cs.n), dim3(256), 0, st, cs, A.n,
                            A.means, A.log_scales, A.quats, A.logits, L.rec0, L.rec1, L.foot,
                            L.depth_key, L.ntiles);
@@ -822,7 +803,7 @@ hipError_t render_forward_launch(const RenderArgs& A, const RenderLayout& L, hip
     const uint32_t* tkeys;
     const uint32_t* trecs;
     {
-        ProfScope ps("render_sort", st);
+        ProfScope ps(ctx, "render_sort", st);
         e = launch_radix_sort(L.depth_key, L.depth_a, L.recs_a, L.depth_b, L.recs_b, true, nullptr,
                               R, 32, L.sort_scratch, &in_b, st);
         if (e != hipSuccess) return e;
@@ -848,7 +829,7 @@ hipError_t render_forward_launch(const RenderArgs& A, const RenderLayout& L, hip
                                dim3(256), 0, st, tkeys, (const uint32_t*)L.counters, cap, L.ranges);
     }
     if (cs.total_tiles > 0) {
-        const bool pers = use_persistent(cs);
+        const bool pers = use_persistent(ctx, cs);
         const int threads = cs.tile_w * cs.tile_h;
         const bool rgbd = A.rgbd;
         auto kern = rgbd ? (A.d == 16 ? (pers ? k_raster_fwd<16, true, true> : k_raster_fwd<16, false, true>)
@@ -859,9 +840,9 @@ hipError_t render_forward_launch(const RenderArgs& A, const RenderLayout& L, hip
         if (pers) {
             e = launch_fill_u32(L.counters + 2, 1, 0u, st);
             if (e != hipSuccess) return e;
-            grid = std::min(grid, resident_blocks((const void*)kern, threads));
+            grid = std::min(grid, ctx_resident_blocks(ctx, (const void*)kern, threads));
         }
-        ProfScope ps("raster_fwd", st);
+        ProfScope ps(ctx, "raster_fwd", st);
         hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), 0, st, cs, A.n, (const uint2*)L.ranges,
                            trecs, (const float4*)L.rec0, (const float4*)L.rec1, (const uint2*)L.foot,
                            A.queries, A.Q, A.T_final, L.t_final, L.n_contrib, L.counters + 2, A.colors,
@@ -870,7 +851,7 @@ hipError_t render_forward_launch(const RenderArgs& A, const RenderLayout& L, hip
     return hipGetLastError();
 }
 
-hipError_t render_backward_launch(const RenderArgs& A, const RenderLayout& L, hipStream_t st)
+hipError_t render_backward_launch(lam_ctx* ctx, const RenderArgs& A, const RenderLayout& L, hipStream_t st)
 {
     const CamSet& cs = L.cams;
     hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(L.rec_grad), (size_t)L.records * 6,
@@ -886,7 +867,7 @@ hipError_t render_backward_launch(const RenderArgs& A, const RenderLayout& L, hi
     }
     const uint32_t* trecs = L.tile_in_b ? L.ivals_b : L.ivals_a;
     if (cs.total_tiles > 0) {
-        const bool pers = use_persistent(cs);
+        const bool pers = use_persistent(ctx, cs);
         const int threads = cs.tile_w * cs.tile_h;
         auto kern = rgbd ? (A.d == 16 ? (pers ? k_raster_bwd<16, true, true> : k_raster_bwd<16, false, true>)
                                       : (pers ? k_raster_bwd<32, true, true> : k_raster_bwd<32, false, true>))
@@ -896,9 +877,9 @@ hipError_t render_backward_launch(const RenderArgs& A, const RenderLayout& L, hi
         if (pers) {
             e = launch_fill_u32(L.counters + 3, 1, 0u, st);
             if (e != hipSuccess) return e;
-            grid = std::min(grid, resident_blocks((const void*)kern, threads));
+            grid = std::min(grid, ctx_resident_blocks(ctx, (const void*)kern, threads));
         }
-        ProfScope ps("raster_bwd", st);
+        ProfScope ps(ctx, "raster_bwd", st);
         hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), 0, st, cs, A.n, (const uint2*)L.ranges,
                            trecs, (const float4*)L.rec0, (const float4*)L.rec1, (const uint2*)L.foot,
                            A.queries, (const float*)L.t_final, (const uint32_t*)L.n_contrib, A.dQ,
@@ -906,7 +887,7 @@ hipError_t render_backward_launch(const RenderArgs& A, const RenderLayout& L, hi
                            A.d_rgb, A.d_depth, A.d_colors, L.rec_dz);
     }
     if (A.n > 0) {
-        ProfScope ps("preprocess_bwd", st);
+        ProfScope ps(ctx, "preprocess_bwd", st);
         hipLaunchKernelGGL(k_preprocess_bwd, dim3((A.n + 255) / 256), dim3(256), 0, st, cs, A.n,
                            A.means, A.log_scales, A.quats, A.logits, (const uint32_t*)L.ntiles,
                            (const float*)L.rec_grad, rgbd ? (const float*)L.rec_dz : nullptr, A.d_means,

@@ -337,25 +337,25 @@ using namespace lam;
 
 extern "C" {
 
-lam_status lam_rgbd_l1_workspace_size(int n, uint64_t* bytes)
+lam_status lam_rgbd_l1_workspace_size(const lam_ctx* ctx, int n, uint64_t* bytes)
 {
     if (!bytes || n < 0) return LAM_ERR_INVALID_ARG;
     *bytes = l1_ws_bytes(n);
     return LAM_OK;
 }
 
-lam_status lam_rgbd_l1_loss(const float* rgb, const float* rgb_obs, const float* depth, const float* depth_obs,
+lam_status lam_rgbd_l1_loss(lam_ctx* ctx, const float* rgb, const float* rgb_obs, const float* depth, const float* depth_obs,
                             int n, float lambda_rgb, float lambda_depth, float* loss, float* d_rgb,
                             float* d_depth, void* ws, uint64_t ws_bytes, void* stream)
 {
-    if (n < 0 || !loss || !ws || ws_bytes < l1_ws_bytes(n)) return LAM_ERR_INVALID_ARG;
+    if (!ctx_ok(ctx) || n < 0 || !loss || !ws || ws_bytes < l1_ws_bytes(n)) return LAM_ERR_INVALID_ARG;
     if (n > 0 && (!rgb || !rgb_obs || !depth || !depth_obs || !d_rgb || !d_depth)) return LAM_ERR_INVALID_ARG;
     if (!(lambda_rgb >= 0.0f) || !(lambda_depth >= 0.0f)) return LAM_ERR_INVALID_ARG;
     hipStream_t st = (hipStream_t)stream;
     const int nb = l1_blocks(n);
     float* part = static_cast<float*>(ws);
     float* stats = part + (size_t)nb * 3;
-    ProfScope ps("rgbd_l1", st);
+    ProfScope ps(ctx, "rgbd_l1", st);
     if (n > 0) {
         hipLaunchKernelGGL(k_l1_partials, dim3(nb), dim3(kL1Threads), 0, st, rgb, rgb_obs, depth, depth_obs, n,
                            part);
@@ -375,7 +375,7 @@ lam_status lam_rgbd_l1_loss(const float* rgb, const float* rgb_obs, const float*
 
 extern "C" {
 
-lam_status lam_ssim_workspace_size(const float* cams, int n_cams, uint64_t* bytes)
+lam_status lam_ssim_workspace_size(const lam_ctx* ctx, const float* cams, int n_cams, uint64_t* bytes)
 {
     SsimViews V;
     long long pixels = 0;
@@ -384,12 +384,12 @@ lam_status lam_ssim_workspace_size(const float* cams, int n_cams, uint64_t* byte
     return LAM_OK;
 }
 
-lam_status lam_ssim_loss(const float* rgb, const float* rgb_obs, const float* cams, int n_cams, float lambda,
+lam_status lam_ssim_loss(lam_ctx* ctx, const float* rgb, const float* rgb_obs, const float* cams, int n_cams, float lambda,
                          float* loss, float* d_rgb, int accumulate, void* ws, uint64_t ws_bytes, void* stream)
 {
     SsimViews V;
     long long pixels = 0;
-    if (!ssim_views(cams, n_cams, &V, &pixels)) return LAM_ERR_INVALID_ARG;
+    if (!ctx_ok(ctx) || !ssim_views(cams, n_cams, &V, &pixels)) return LAM_ERR_INVALID_ARG;
     if (!rgb || !rgb_obs || !loss || !d_rgb || !ws || ws_bytes < ssim_ws_bytes(pixels, V.total_tiles))
         return LAM_ERR_INVALID_ARG;
     if (!(lambda >= 0.0f)) return LAM_ERR_INVALID_ARG;
@@ -397,7 +397,7 @@ lam_status lam_ssim_loss(const float* rgb, const float* rgb_obs, const float* ca
     float* part = static_cast<float*>(ws);
     float* tsum = reinterpret_cast<float*>(static_cast<char*>(ws) + ((size_t)pixels * 9 * 4 + 255) / 256 * 256);
     const float inv_total = 1.0f / (3.0f * (float)pixels);
-    ProfScope ps("ssim", st);
+    ProfScope ps(ctx, "ssim", st);
     hipLaunchKernelGGL(k_ssim_fwd, dim3(V.total_tiles), dim3(256), 0, st, V, rgb, rgb_obs, -lambda * inv_total,
                        part, tsum);
     hipLaunchKernelGGL(k_ssim_final, dim3(1), dim3(256), 0, st, (const float*)tsum, V.total_tiles, lambda,

@@ -264,10 +264,10 @@ __global__ __launch_bounds__(256) void k_tied_loss(const float* __restrict__ dec
 // softmax puts its weight on a few atoms, so the E4M3 rounding of D reaches F
 // without the averaging over many atoms that keeps the untied E4M3 decode
 // within its bounds (dQ off by about 5 % against the FP64 loss).
-bool tied_layout(int prec, int n, int ds, int M, int df, TiedLayout* L)
+bool tied_layout(const lam_ctx* ctx, int prec, int n, int ds, int M, int df, TiedLayout* L)
 {
     if (prec != LAM_FP32 && prec != LAM_BF16) return false;
-    if (!decode_layout(prec, n, ds, M, df, &L->dec)) return false;
+    if (!decode_layout(ctx, prec, n, ds, M, df, &L->dec)) return false;
     size_t off = (L->dec.bytes + 255) / 256 * 256;
     auto take = [&](size_t bytes) {
         size_t o = off;
@@ -290,7 +290,7 @@ bool tied_layout(int prec, int n, int ds, int M, int df, TiedLayout* L)
     return true;
 }
 
-hipError_t tied_loss_launch(const TiedArgs& T, const TiedLayout& L, void* base_, hipStream_t st)
+hipError_t tied_loss_launch(lam_ctx* ctx, const TiedArgs& T, const TiedLayout& L, void* base_, hipStream_t st)
 {
     char* base = reinterpret_cast<char*>(base_);
     float* Qs = reinterpret_cast<float*>(base + L.off_qs);
@@ -308,7 +308,7 @@ hipError_t tied_loss_launch(const TiedArgs& T, const TiedLayout& L, void* base_,
     const int n = T.n, ds = T.ds, M = T.M, df = T.df;
     const int pblocks = (n + 255) / 256;
     {
-        ProfScope ps("tied_prep", st);
+        ProfScope ps(ctx, "tied_prep", st);
         if (ds == 16)
             hipLaunchKernelGGL(k_tied_dict<16>, dim3(M + ds), dim3(256), 0, st, T.W, T.D, M, df, K, gD, G);
         else
@@ -329,9 +329,9 @@ hipError_t tied_loss_launch(const TiedArgs& T, const TiedLayout& L, void* base_,
     A.lam_cos = T.lam_cos; A.lam_l2 = T.lam_2; A.logit_scale = 1.0f;
     DecodeLayout DL = L.dec;
     DL.base = base_;
-    hipError_t e = decode_loss_launch(A, DL, st);
+    hipError_t e = decode_loss_launch(ctx, A, DL, st);
     if (e != hipSuccess) return e;
-    ProfScope ps("tied_grads", st);
+    ProfScope ps(ctx, "tied_grads", st);
     const int splits = n > 0 ? pblocks : 0;  // one partial per workgroup of 256 pixels
     if (n > 0) {
         if (ds == 16)
@@ -361,23 +361,24 @@ static bool tied_aligned(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 
 extern "C" {
 
-lam_status lam_decode_tied_workspace_size(int precision, int n, int ds, int M, int df, uint64_t* bytes)
+lam_status lam_decode_tied_workspace_size(const lam_ctx* ctx, int precision, int n, int ds, int M, int df,
+                                          uint64_t* bytes)
 {
     if (!bytes || n < 0) return LAM_ERR_INVALID_ARG;
     TiedLayout L{};
-    if (!tied_layout(precision, n, ds, M, df, &L)) return LAM_ERR_UNSUPPORTED;
+    if (!tied_layout(ctx_options(ctx), precision, n, ds, M, df, &L)) return LAM_ERR_UNSUPPORTED;
     *bytes = L.bytes;
     return LAM_OK;
 }
 
-lam_status lam_decode_tied_loss(int precision, const float* Q, int n, int ds, const float* W, const float* D,
+lam_status lam_decode_tied_loss(lam_ctx* ctx, int precision, const float* Q, int n, int ds, const float* W, const float* D,
                                 int M, int df, const float* target, const float* D0,
                                 const lam_tied_params* params, float* loss, float* dQ, float* dW, float* dD,
                                 void* ws, uint64_t ws_bytes, void* stream)
 {
-    if (n < 0 || !params) return LAM_ERR_INVALID_ARG;
+    if (!ctx_ok(ctx) || n < 0 || !params) return LAM_ERR_INVALID_ARG;
     TiedLayout L{};
-    if (!tied_layout(precision, n, ds, M, df, &L)) return LAM_ERR_UNSUPPORTED;
+    if (!tied_layout(ctx, precision, n, ds, M, df, &L)) return LAM_ERR_UNSUPPORTED;
     if (!ws || ws_bytes < L.bytes) return LAM_ERR_INVALID_ARG;
     if (!W || !D || !D0 || !loss || !dW || !dD || (n > 0 && (!Q || !target))) return LAM_ERR_INVALID_ARG;
     if (!tied_aligned(Q) || !tied_aligned(target) || !tied_aligned(dQ)) return LAM_ERR_INVALID_ARG;
@@ -390,7 +391,7 @@ lam_status lam_decode_tied_loss(int precision, const float* Q, int n, int ds, co
     T.Q = Q; T.W = W; T.D = D; T.target = target; T.D0 = D0;
     T.tau = p.tau; T.lam_cos = p.lambda_cos; T.lam_2 = p.lambda_2; T.lam_D = p.lambda_D; T.delta = p.delta;
     T.loss = loss; T.dQ = dQ; T.dW = dW; T.dD = dD;
-    return tied_loss_launch(T, L, ws, (hipStream_t)stream) == hipSuccess ? LAM_OK : LAM_ERR_HIP;
+    return tied_loss_launch(ctx, T, L, ws, (hipStream_t)stream) == hipSuccess ? LAM_OK : LAM_ERR_HIP;
 }
 
 }  // extern "C"

@@ -69,58 +69,92 @@ def _contig(t):
 
 
 class Renderer:
-    """Render workspace for a fixed camera set, Gaussian count and tile shape."""
+    """Render workspace for a fixed camera set, Gaussian count and tile shape.
+
+    The (Gaussian, tile) pair capacity is sized from the library's own counter:
+    a forward reads it back (a host synchronisation) until one forward has
+    fitted (``check="first"``, the default), or on every forward
+    (``check="always"``).  Later forwards only enqueue work, so a step can be
+    captured in a HIP graph; ``verify()`` reads the overflow flag of the last
+    forward outside the step.  Each forward bumps ``generation``: the state a
+    backward reads is that of the latest forward."""
 
     def __init__(self, cams, n_gauss: int, d: int, tile=(16, 16), capacity: Optional[int] = None,
-                 device="cuda", headroom: float = 1.15):
+                 device="cuda", headroom: float = 1.15, check: str = "first", ctx=None):
+        assert check in ("first", "always")
         self.cams = _lib._cams(cams)
         self.n_gauss, self.d = int(n_gauss), int(d)
         self.tile_w, self.tile_h = int(tile[0]), int(tile[1])
         self.device = torch.device(device)
         self.headroom = headroom
+        self.check_mode = check
+        self.ctx = ctx
         w = self.cams[:, 0].astype(np.int64)
         h = self.cams[:, 1].astype(np.int64)
         self.n_pixels = int((w * h).sum())
         self.capacity = 0
         self.ws = None
+        self.generation = 0
+        self._fitted = False
         self._alloc(capacity if capacity is not None else 0)
 
     def _alloc(self, capacity: int):
         nbytes = _lib.render_workspace_size(self.n_gauss, self.d, self.cams, self.tile_w, self.tile_h,
-                                            capacity)
+                                            capacity, ctx=self.ctx)
         self.ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
         self.capacity = int(capacity)
+        self._fitted = False
 
     def counters(self):
         """BLOCKING: (pairs needed, overflowed) of the last forward."""
-        return _lib.render_counters(self.ws)
+        return _lib.render_counters(self.ws, ctx=self.ctx)
 
-    def forward(self, g: Gaussians, Q=None, T_final=None, check: bool = True):
+    def verify(self):
+        """BLOCKING: raises if the last forward ran out of pair capacity (its
+        output is then incomplete; the next checked forward re-sizes)."""
+        need, over = self.counters()
+        if over:
+            self._fitted = False
+            raise RuntimeError(f"render pair capacity {self.capacity} exceeded ({need} needed): "
+                               "call forward(check=True) to re-size")
+        return need
+
+    def _checked(self, check) -> bool:
+        if check is None:
+            return self.check_mode == "always" or not self._fitted
+        return bool(check)
+
+    def forward(self, g: Gaussians, Q=None, T_final=None, check: Optional[bool] = None):
         if Q is None:
             Q = torch.empty((self.n_pixels, self.d), dtype=torch.float32, device=self.device)
         if T_final is None:
             T_final = torch.empty((self.n_pixels,), dtype=torch.float32, device=self.device)
         gg = Gaussians(*[_contig(t) for t in g.tensors()])
+        check = self._checked(check)
         for _ in range(3):
+            self.generation += 1
             _lib.render_forward(gg, self.cams, self.tile_w, self.tile_h, Q, T_final, self.ws,
-                                self.capacity)
+                                self.capacity, ctx=self.ctx)
             if not check:
                 break
             need, over = self.counters()
             if not over:
+                self._fitted = True
                 break
             self._alloc(int(need * self.headroom) + 4096)
         return Q, T_final
 
     def backward(self, g: Gaussians, dQ: torch.Tensor, out: Optional[Gaussians] = None) -> Gaussians:
+        """Gradients for the upstream dQ of the latest forward (every output is
+        overwritten)."""
         gg = Gaussians(*[_contig(t) for t in g.tensors()])
         if out is None:
-            out = gg.zeros_like()
+            out = Gaussians(*[torch.empty_like(t) for t in gg.tensors()])
         _lib.render_backward(gg, self.cams, self.tile_w, self.tile_h, _contig(dQ), out, self.ws,
-                             self.capacity)
+                             self.capacity, ctx=self.ctx)
         return out
 
-    def forward_rgbd(self, g: Gaussians, colors, check: bool = True):
+    def forward_rgbd(self, g: Gaussians, colors, check: Optional[bool] = None):
         """Q, rgb [P, 3], depth [P], T_final: the query map with colour and depth
         blended in the same pass (Sec. III-A)."""
         P = self.n_pixels
@@ -130,13 +164,16 @@ class Renderer:
         T_final = torch.empty((P,), dtype=torch.float32, device=self.device)
         gg = Gaussians(*[_contig(t) for t in g.tensors()])
         colors = _contig(colors)
+        check = self._checked(check)
         for _ in range(3):
+            self.generation += 1
             _lib.render_rgbd_forward(gg, colors, self.cams, self.tile_w, self.tile_h, Q, rgb, depth, T_final,
-                                     self.ws, self.capacity)
+                                     self.ws, self.capacity, ctx=self.ctx)
             if not check:
                 break
             need, over = self.counters()
             if not over:
+                self._fitted = True
                 break
             self._alloc(int(need * self.headroom) + 4096)
         return Q, rgb, depth, T_final
@@ -144,29 +181,41 @@ class Renderer:
     def backward_rgbd(self, g: Gaussians, colors, dQ, d_rgb, d_depth):
         """Gradients (Gaussians, d_colors) for upstream dQ, d_rgb, d_depth."""
         gg = Gaussians(*[_contig(t) for t in g.tensors()])
-        out = gg.zeros_like()
+        out = Gaussians(*[torch.empty_like(t) for t in gg.tensors()])
         d_colors = torch.empty((self.n_gauss, 3), dtype=torch.float32, device=self.device)
         _lib.render_rgbd_backward(gg, _contig(colors), self.cams, self.tile_w, self.tile_h, _contig(dQ),
-                                  _contig(d_rgb), _contig(d_depth), out, d_colors, self.ws, self.capacity)
+                                  _contig(d_rgb), _contig(d_depth), out, d_colors, self.ws, self.capacity,
+                                  ctx=self.ctx)
         return out, d_colors
 
     def debug_views(self):
         return _lib.render_debug_views(self.ws, self.n_gauss, self.d, self.cams, self.tile_w,
-                                       self.tile_h, self.capacity)
+                                       self.tile_h, self.capacity, ctx=self.ctx)
 
 
 class RenderQueries(torch.autograd.Function):
+    """Eq. 4 as an autograd function.  The backward reads the tile lists and
+    per-pixel state the forward left in the renderer's workspace, so another
+    forward on the same renderer in between is an error (raised, not silently
+    wrong).  After the renderer's capacity has fitted once, neither pass
+    synchronises with the host."""
+
     @staticmethod
     def forward(ctx, renderer: Renderer, means, log_scales, quats, opacity_logits, queries):
         g = Gaussians(means, log_scales, quats, opacity_logits, queries)
         Q, T = renderer.forward(g)
         ctx.renderer = renderer
+        ctx.generation = renderer.generation
         ctx.save_for_backward(means, log_scales, quats, opacity_logits, queries)
         ctx.mark_non_differentiable(T)
         return Q, T
 
     @staticmethod
     def backward(ctx, dQ, dT):
+        if ctx.renderer.generation != ctx.generation:
+            raise RuntimeError("RenderQueries.backward: the renderer ran another forward after this one, "
+                               "so its workspace no longer holds this forward's state; use one Renderer per "
+                               "differentiable render in flight")
         g = Gaussians(*ctx.saved_tensors)
         gr = ctx.renderer.backward(g, dQ)
         return (None,) + gr.tensors()
@@ -175,10 +224,11 @@ class RenderQueries(torch.autograd.Function):
 class Decoder:
     """Decode workspace for fixed (precision, n, d, M, D)."""
 
-    def __init__(self, precision: str, n: int, d: int, M: int, D: int, device="cuda"):
+    def __init__(self, precision: str, n: int, d: int, M: int, D: int, device="cuda", ctx=None):
         self.precision = precision
         self.shape = (int(n), int(d), int(M), int(D))
-        nbytes = _lib.decode_workspace_size(precision, n, d, M, D)
+        self.ctx = ctx
+        nbytes = _lib.decode_workspace_size(precision, n, d, M, D, ctx=ctx)
         self.ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
         self.device = torch.device(device)
 
@@ -195,10 +245,10 @@ class Decoder:
         dV = torch.empty((M, D), dtype=torch.float32, device=dev)
         args = (_contig(Q), _contig(K), _contig(V), _contig(target), None if K0 is None else _contig(K0))
         if dict_stream is None:
-            _lib.decode_loss(self.precision, *args, lambda_tr, loss, dQ, dK, dV, row_cos, self.ws)
+            _lib.decode_loss(self.precision, *args, lambda_tr, loss, dQ, dK, dV, row_cos, self.ws, ctx=self.ctx)
         else:
             _lib.decode_loss_overlap(self.precision, *args, lambda_tr, loss, dQ, dK, dV, row_cos, self.ws,
-                                     dict_stream.cuda_stream)
+                                     dict_stream.cuda_stream, ctx=self.ctx)
             for t in (loss, dK, dV, self.ws) + tuple(a for a in args if a is not None):
                 t.record_stream(dict_stream)
         return loss, dQ, dK, dV
@@ -207,7 +257,7 @@ class Decoder:
         n, d, M, D = self.shape
         if F is None:
             F = torch.empty((n, D), dtype=torch.float32, device=self.device)
-        _lib.decode_forward(self.precision, _contig(Q), _contig(K), _contig(V), F, self.ws)
+        _lib.decode_forward(self.precision, _contig(Q), _contig(K), _contig(V), F, self.ws, ctx=self.ctx)
         return F
 
     def backward(self, Q, K, V, dF, want_dQ=True):
@@ -216,7 +266,7 @@ class Decoder:
         dK = torch.empty((M, d), dtype=torch.float32, device=self.device)
         dV = torch.empty((M, D), dtype=torch.float32, device=self.device)
         _lib.decode_backward(self.precision, _contig(Q), _contig(K), _contig(V), _contig(dF), dQ, dK,
-                             dV, self.ws)
+                             dV, self.ws, ctx=self.ctx)
         return dQ, dK, dV
 
 
@@ -275,10 +325,11 @@ class TiedDecoder:
     """Workspace for the tied decode of n pixel rows (query dimension ds, M atoms,
     feature dimension df)."""
 
-    def __init__(self, precision: str, n: int, ds: int, M: int, df: int, device="cuda"):
+    def __init__(self, precision: str, n: int, ds: int, M: int, df: int, device="cuda", ctx=None):
         self.precision = precision
         self.shape = (int(n), int(ds), int(M), int(df))
-        nbytes = _lib.decode_tied_workspace_size(precision, n, ds, M, df)
+        self.ctx = ctx
+        nbytes = _lib.decode_tied_workspace_size(precision, n, ds, M, df, ctx=ctx)
         self.ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
         self.device = torch.device(device)
 
@@ -291,35 +342,35 @@ class TiedDecoder:
         dW = torch.empty((ds, df), dtype=torch.float32, device=dev)
         dD = torch.empty((M, df), dtype=torch.float32, device=dev)
         _lib.decode_tied_loss(self.precision, _contig(Q), _contig(W), _contig(D), _contig(target), _contig(D0),
-                              params, loss, dQ, dW, dD, self.ws)
+                              params, loss, dQ, dW, dD, self.ws, ctx=self.ctx)
         return loss, dQ, dW, dD
 
 
 PAPER_RGBD_WEIGHTS = dict(lambda_rgb=0.2, lambda_depth=0.1, lambda_ssim=0.8)  # lambda_I1, lambda_d, lambda_I2
 
 
-def rgbd_l1_loss(rgb, rgb_obs, depth, depth_obs, lambda_rgb=0.2, lambda_depth=0.1):
+def rgbd_l1_loss(rgb, rgb_obs, depth, depth_obs, lambda_rgb=0.2, lambda_depth=0.1, ctx=None):
     """(loss, d_rgb, d_depth) of the L1 colour and depth terms (Eq. 7-9)."""
     rgb, rgb_obs, depth, depth_obs = (_contig(t) for t in (rgb, rgb_obs, depth, depth_obs))
     dev = rgb.device
-    ws = torch.empty(_lib.rgbd_l1_workspace_size(depth.shape[0]), dtype=torch.uint8, device=dev)
+    ws = torch.empty(_lib.rgbd_l1_workspace_size(depth.shape[0], ctx=ctx), dtype=torch.uint8, device=dev)
     loss = torch.empty(1, dtype=torch.float32, device=dev)
     d_rgb = torch.empty_like(rgb)
     d_depth = torch.empty_like(depth)
-    _lib.rgbd_l1_loss(rgb, rgb_obs, depth, depth_obs, lambda_rgb, lambda_depth, loss, d_rgb, d_depth, ws)
+    _lib.rgbd_l1_loss(rgb, rgb_obs, depth, depth_obs, lambda_rgb, lambda_depth, loss, d_rgb, d_depth, ws, ctx=ctx)
     return loss, d_rgb, d_depth
 
 
-def ssim_loss(rgb, rgb_obs, cams, lam=0.8, d_rgb=None):
+def ssim_loss(rgb, rgb_obs, cams, lam=0.8, d_rgb=None, ctx=None):
     """(loss, d_rgb) of lam (1 - SSIM) (Eq. 7); with d_rgb given the gradient is
     added to it (e.g. after rgbd_l1_loss)."""
     rgb, rgb_obs = _contig(rgb), _contig(rgb_obs)
-    ws = torch.empty(_lib.ssim_workspace_size(cams), dtype=torch.uint8, device=rgb.device)
+    ws = torch.empty(_lib.ssim_workspace_size(cams, ctx=ctx), dtype=torch.uint8, device=rgb.device)
     loss = torch.empty(1, dtype=torch.float32, device=rgb.device)
     acc = d_rgb is not None
     if d_rgb is None:
         d_rgb = torch.empty_like(rgb)
-    _lib.ssim_loss(rgb, rgb_obs, cams, lam, loss, d_rgb, acc, ws)
+    _lib.ssim_loss(rgb, rgb_obs, cams, lam, loss, d_rgb, acc, ws, ctx=ctx)
     return loss, d_rgb
 
 
@@ -336,8 +387,9 @@ class StreamKMeans:
     global centres and re-clusters to K; returns the new (D, W)."""
 
     def __init__(self, precision: str, K: int, dim: int, iters_local: int = 10, iters_global: int = 10,
-                 seed: int = 0, device="cuda"):
+                 seed: int = 0, device="cuda", ctx=None):
         self.precision = precision
+        self.ctx = ctx
         self.K, self.dim = int(K), int(dim)
         self.iters_local, self.iters_global = int(iters_local), int(iters_global)
         self.device = torch.device(device)
@@ -360,33 +412,34 @@ class StreamKMeans:
         if seeds is None:
             seeds = self.rng.choice(n, size=m, replace=False) if m > 0 else np.zeros(0, np.int64)
         seeds = np.asarray(seeds, dtype=np.int32)
-        ws = self._workspace(_lib.stream_kmeans_workspace_size(self.precision, n, self.dim, Kp, self.K, len(seeds)))
+        ws = self._workspace(_lib.stream_kmeans_workspace_size(self.precision, n, self.dim, Kp, self.K, len(seeds),
+                                                               ctx=self.ctx))
         D_out = torch.empty((self.K, self.dim), dtype=torch.float32, device=self.device)
         W_out = torch.empty(self.K, dtype=torch.float32, device=self.device)
         _lib.stream_kmeans(self.precision, F, self.D if Kp else None, self.W if Kp else None, self.K, seeds,
-                           self.iters_local, self.iters_global, D_out, W_out, ws)
+                           self.iters_local, self.iters_global, D_out, W_out, ws, ctx=self.ctx)
         self.D, self.W = D_out, W_out
         return D_out, W_out
 
 
-def kmeans_assign(precision: str, X, C):
+def kmeans_assign(precision: str, X, C, ctx=None):
     """Nearest centre (int32) and squared distance of every row of X."""
     X, C = _contig(X), _contig(C)
-    ws = torch.empty(max(_lib.kmeans_workspace_size(precision, X.shape[0], X.shape[1], C.shape[0]), 256),
+    ws = torch.empty(max(_lib.kmeans_workspace_size(precision, X.shape[0], X.shape[1], C.shape[0], ctx=ctx), 256),
                      dtype=torch.uint8, device=X.device)
     a = torch.empty(X.shape[0], dtype=torch.int32, device=X.device)
     d2 = torch.empty(X.shape[0], dtype=torch.float32, device=X.device)
-    _lib.kmeans_assign(precision, X, C, a, d2, ws)
+    _lib.kmeans_assign(precision, X, C, a, d2, ws, ctx=ctx)
     return a, d2
 
 
-def kmeans_lloyd(precision: str, X, C0, iters: int, weights=None):
+def kmeans_lloyd(precision: str, X, C0, iters: int, weights=None, ctx=None):
     """``iters`` Lloyd iterations from C0: (C, W, last assignment)."""
     X, C0 = _contig(X), _contig(C0)
-    ws = torch.empty(max(_lib.kmeans_workspace_size(precision, X.shape[0], X.shape[1], C0.shape[0]), 256),
+    ws = torch.empty(max(_lib.kmeans_workspace_size(precision, X.shape[0], X.shape[1], C0.shape[0], ctx=ctx), 256),
                      dtype=torch.uint8, device=X.device)
     C = torch.empty_like(C0)
     W = torch.empty(C0.shape[0], dtype=torch.float32, device=X.device)
     a = torch.empty(X.shape[0], dtype=torch.int32, device=X.device)
-    _lib.kmeans_lloyd(precision, X, None if weights is None else _contig(weights), C0, iters, C, W, a, ws)
+    _lib.kmeans_lloyd(precision, X, None if weights is None else _contig(weights), C0, iters, C, W, a, ws, ctx=ctx)
     return C, W, a

@@ -34,7 +34,7 @@ def test_exports_every_declared_symbol(L):
 
 
 def test_status_strings_and_version(L):
-    assert L.lam_version() == 1
+    assert L.lam_version() == 2
     for code in (0, -1, -2, -3, -4):
         assert _lib.status_string(code)
 
@@ -42,7 +42,7 @@ def test_status_strings_and_version(L):
 def _ws_size(n, d, cams, tw=16, th=16, cap=1000):
     out = C.c_uint64()
     cams = np.ascontiguousarray(cams, np.float32)
-    st = _lib.lib().lam_render_workspace_size(n, d, cams.ctypes.data_as(C.c_void_p), cams.shape[0],
+    st = _lib.lib().lam_render_workspace_size(None, n, d, cams.ctypes.data_as(C.c_void_p), cams.shape[0],
                                               tw, th, cap, C.byref(out))
     return st, out.value
 
@@ -70,41 +70,60 @@ def test_render_workspace_validation(L):
 
 def test_render_forward_rejects_null_inputs(L):
     cams = np.ascontiguousarray(np.stack([scenes.pinhole(64, 48, 50.0).packed()]), np.float32)
-    st = L.lam_render_forward(None, None, None, None, None, 10, 16, cams.ctypes.data_as(C.c_void_p), 1,
+    st = L.lam_render_forward(None, None, None, None, None, None, 10, 16, cams.ctypes.data_as(C.c_void_p), 1,
                               16, 16, None, None, None, 0, 0, None)
     assert st == _lib.LAM_ERR_INVALID_ARG
 
 
 def test_decode_workspace_validation(L):
     ok = C.c_uint64()
-    assert L.lam_decode_workspace_size(1, 1000, 16, 256, 512, C.byref(ok)) == 0 and ok.value > 0
-    assert L.lam_decode_workspace_size(0, 1000, 16, 256, 512, C.byref(ok)) == 0
+    assert L.lam_decode_workspace_size(None, 1, 1000, 16, 256, 512, C.byref(ok)) == 0 and ok.value > 0
+    assert L.lam_decode_workspace_size(None, 0, 1000, 16, 256, 512, C.byref(ok)) == 0
     for args in [(1, 1000, 8, 256, 512), (1, 1000, 16, 0, 512), (1, 1000, 16, 256, 100),
                  (1, 1000, 16, 256, 2048), (1, 1000, 16, 4096, 512), (7, 10, 16, 64, 128)]:
-        assert L.lam_decode_workspace_size(*args, C.byref(ok)) == _lib.LAM_ERR_UNSUPPORTED, args
-    assert L.lam_decode_workspace_size(1, -1, 16, 64, 128, C.byref(ok)) == _lib.LAM_ERR_INVALID_ARG
-    assert L.lam_decode_workspace_size(1, 10, 16, 64, 128, None) == _lib.LAM_ERR_INVALID_ARG
+        assert L.lam_decode_workspace_size(None, *args, C.byref(ok)) == _lib.LAM_ERR_UNSUPPORTED, args
+    assert L.lam_decode_workspace_size(None, 1, -1, 16, 64, 128, C.byref(ok)) == _lib.LAM_ERR_INVALID_ARG
+    assert L.lam_decode_workspace_size(None, 1, 10, 16, 64, 128, None) == _lib.LAM_ERR_INVALID_ARG
 
 
-def test_process_wide_knobs_validate(L):
-    for bad in (-1, 3):
-        assert L.lam_set_raster_schedule(bad) == _lib.LAM_ERR_INVALID_ARG
-    for bad in (-1, 2):
-        assert L.lam_set_decode_shape(bad) == _lib.LAM_ERR_INVALID_ARG
-    assert L.lam_set_decode_shape(1) == 0 and L.lam_set_decode_shape(0) == 0
-    assert L.lam_set_raster_schedule(2) == 0
+def test_context_options_are_validated_before_the_device(L):
+    # lam_create parses its options before it touches the device, so a bad
+    # option is INVALID_ARG with or without a GPU; NULL out is rejected
+    out = C.c_void_p()
+    for bad in (b'{"raster_schedule": 3}', b'{"decode_shape": -1}', b'{"decode_splits": 12}',
+                b'{"decode_splits": 8192}', b'{"tile": 16}', b'{"decode_shape": 1.5}', b'[1]',
+                b'{"decode_shape": 1', b'{"decode_shape": 1} x', b'{decode_shape: 1}'):
+        assert L.lam_create(0, bad, C.byref(out)) == _lib.LAM_ERR_INVALID_ARG, bad
+        assert not out.value
+    assert L.lam_create(0, None, None) == _lib.LAM_ERR_INVALID_ARG
+    assert L.lam_create(-1, b'{}', C.byref(out)) in (_lib.LAM_ERR_INVALID_ARG, _lib.LAM_ERR_HIP)
+    L.lam_destroy(None)  # a no-op
+    v = C.c_int()
+    assert L.lam_ctx_get(None, b"decode_shape", C.byref(v)) == _lib.LAM_ERR_INVALID_ARG
+    assert L.lam_ctx_configure(None, b"{}") == _lib.LAM_ERR_INVALID_ARG
+
+
+def test_launching_calls_need_a_context(L):
+    # the host-only size queries take NULL (the default options); calls that
+    # launch work reject it before touching the device
+    p = C.c_void_p(256)
+    big = C.c_uint64(1 << 40)
+    assert L.lam_decode_forward(None, 1, p, 10, 16, p, p, 64, 128, p, p, big, None) == _lib.LAM_ERR_INVALID_ARG
+    assert L.lam_render_counters(None, p, None, C.byref(C.c_uint64()), C.byref(C.c_int())) == \
+        _lib.LAM_ERR_INVALID_ARG
+    assert L.lam_profile_enable(None, 1) == _lib.LAM_ERR_INVALID_ARG
 
 
 def test_decode_lds_limit_of_fp32(L):
     # the FP32 per-pixel kernel holds 32 rows of max(atoms, D) + 8 FP32 values in LDS
     ok = C.c_uint64()
-    assert L.lam_decode_workspace_size(0, 100, 16, 1024, 1024, C.byref(ok)) == 0
-    assert L.lam_decode_workspace_size(0, 100, 16, 2048, 512, C.byref(ok)) == _lib.LAM_ERR_UNSUPPORTED
-    assert L.lam_decode_workspace_size(1, 100, 16, 2048, 512, C.byref(ok)) == 0
+    assert L.lam_decode_workspace_size(None, 0, 100, 16, 1024, 1024, C.byref(ok)) == 0
+    assert L.lam_decode_workspace_size(None, 0, 100, 16, 2048, 512, C.byref(ok)) == _lib.LAM_ERR_UNSUPPORTED
+    assert L.lam_decode_workspace_size(None, 1, 100, 16, 2048, 512, C.byref(ok)) == 0
 
 
 def test_decode_rejects_small_workspace(L):
-    st = L.lam_decode_loss(1, C.c_void_p(16), 10, 16, C.c_void_p(16), C.c_void_p(16), 64, 128,
+    st = L.lam_decode_loss(None, 1, C.c_void_p(16), 10, 16, C.c_void_p(16), C.c_void_p(16), 64, 128,
                            C.c_void_p(16), C.c_void_p(16), C.c_float(0.1), C.c_void_p(16), None,
                            C.c_void_p(16), C.c_void_p(16), None, C.c_void_p(16), 8, None)
     assert st == _lib.LAM_ERR_INVALID_ARG
@@ -119,51 +138,52 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
 
 def test_tied_decode_validation(L):
     ok = C.c_uint64()
-    assert L.lam_decode_tied_workspace_size(1, 1000, 16, 256, 512, C.byref(ok)) == 0 and ok.value > 0
+    assert L.lam_decode_tied_workspace_size(None, 1, 1000, 16, 256, 512, C.byref(ok)) == 0 and ok.value > 0
     base = ok.value
-    assert L.lam_decode_workspace_size(1, 1000, 16, 256, 512, C.byref(ok)) == 0 and ok.value < base
-    assert L.lam_decode_tied_workspace_size(1, 1000, 8, 256, 512, C.byref(ok)) == _lib.LAM_ERR_UNSUPPORTED
-    assert L.lam_decode_tied_workspace_size(0, 1000, 16, 256, 512, C.byref(ok)) == 0
+    assert L.lam_decode_workspace_size(None, 1, 1000, 16, 256, 512, C.byref(ok)) == 0 and ok.value < base
+    assert L.lam_decode_tied_workspace_size(None, 1, 1000, 8, 256, 512, C.byref(ok)) == _lib.LAM_ERR_UNSUPPORTED
+    assert L.lam_decode_tied_workspace_size(None, 0, 1000, 16, 256, 512, C.byref(ok)) == 0
     # E4M3 is not offered for the tied decode (its dQ misses the E4M3 bound)
-    assert L.lam_decode_tied_workspace_size(2, 1000, 16, 256, 512, C.byref(ok)) == _lib.LAM_ERR_UNSUPPORTED
-    assert L.lam_decode_tied_workspace_size(1, -1, 16, 256, 512, C.byref(ok)) == _lib.LAM_ERR_INVALID_ARG
+    assert L.lam_decode_tied_workspace_size(None, 2, 1000, 16, 256, 512, C.byref(ok)) == _lib.LAM_ERR_UNSUPPORTED
+    assert L.lam_decode_tied_workspace_size(None, 1, -1, 16, 256, 512, C.byref(ok)) == _lib.LAM_ERR_INVALID_ARG
     bad = _lib.TiedParams(0.0, 0.5, 0.5, 0.2, 0.1)  # tau must be positive
     p = C.c_void_p(16)
-    st = L.lam_decode_tied_loss(1, p, 10, 16, p, p, 64, 128, p, p, C.byref(bad), p, None, p, p, p,
+    st = L.lam_decode_tied_loss(None, 1, p, 10, 16, p, p, 64, 128, p, p, C.byref(bad), p, None, p, p, p,
                                 C.c_uint64(1 << 30), None)
     assert st == _lib.LAM_ERR_INVALID_ARG
-    assert L.lam_decode_tied_loss(1, p, 10, 16, p, p, 64, 128, p, p, None, p, None, p, p, p,
+    assert L.lam_decode_tied_loss(None, 1, p, 10, 16, p, p, 64, 128, p, p, None, p, None, p, p, p,
                                   C.c_uint64(1 << 30), None) == _lib.LAM_ERR_INVALID_ARG
     good = _lib.TiedParams(0.1, 0.5, 0.5, 0.2, 0.1)
-    assert L.lam_decode_tied_loss(2, p, 10, 16, p, p, 64, 128, p, p, C.byref(good), p, None, p, p, p,
-                                  C.c_uint64(1 << 30), None) == _lib.LAM_ERR_UNSUPPORTED
+    # a launching call without a context is rejected first
+    assert L.lam_decode_tied_loss(None, 1, p, 10, 16, p, p, 64, 128, p, p, C.byref(good), p, None, p, p, p,
+                                  C.c_uint64(1 << 30), None) == _lib.LAM_ERR_INVALID_ARG
 
 
 def test_kmeans_validation(L):
     ok = C.c_uint64()
-    assert L.lam_kmeans_workspace_size(1, 307200, 512, 1280, C.byref(ok)) == 0 and ok.value > 0
-    assert L.lam_kmeans_workspace_size(0, 100, 1024, 10, C.byref(ok)) == 0       # FP32 up to D = 1024
-    assert L.lam_kmeans_workspace_size(0, 100, 2048, 10, C.byref(ok)) == _lib.LAM_ERR_UNSUPPORTED
-    assert L.lam_kmeans_workspace_size(1, 100, 2048, 10, C.byref(ok)) == 0       # BF16 up to 2048
-    assert L.lam_kmeans_workspace_size(1, 100, 48, 10, C.byref(ok)) == _lib.LAM_ERR_UNSUPPORTED
-    assert L.lam_kmeans_workspace_size(2, 100, 512, 10, C.byref(ok)) == _lib.LAM_ERR_UNSUPPORTED  # no FP8
-    assert L.lam_kmeans_workspace_size(1, 100, 512, 0, C.byref(ok)) == _lib.LAM_ERR_UNSUPPORTED
-    assert L.lam_kmeans_workspace_size(1, -1, 512, 10, C.byref(ok)) == _lib.LAM_ERR_INVALID_ARG
+    assert L.lam_kmeans_workspace_size(None, 1, 307200, 512, 1280, C.byref(ok)) == 0 and ok.value > 0
+    assert L.lam_kmeans_workspace_size(None, 0, 100, 1024, 10, C.byref(ok)) == 0       # FP32 up to D = 1024
+    assert L.lam_kmeans_workspace_size(None, 0, 100, 2048, 10, C.byref(ok)) == _lib.LAM_ERR_UNSUPPORTED
+    assert L.lam_kmeans_workspace_size(None, 1, 100, 2048, 10, C.byref(ok)) == 0       # BF16 up to 2048
+    assert L.lam_kmeans_workspace_size(None, 1, 100, 48, 10, C.byref(ok)) == _lib.LAM_ERR_UNSUPPORTED
+    assert L.lam_kmeans_workspace_size(None, 2, 100, 512, 10, C.byref(ok)) == _lib.LAM_ERR_UNSUPPORTED  # no FP8
+    assert L.lam_kmeans_workspace_size(None, 1, 100, 512, 0, C.byref(ok)) == _lib.LAM_ERR_UNSUPPORTED
+    assert L.lam_kmeans_workspace_size(None, 1, -1, 512, 10, C.byref(ok)) == _lib.LAM_ERR_INVALID_ARG
     p = C.c_void_p(256)
     big = C.c_uint64(1 << 40)
     # iters must be >= 1; misaligned rows are rejected
-    assert L.lam_kmeans_lloyd(1, p, None, 10, 64, p, 4, 0, p, None, None, p, big, None) == _lib.LAM_ERR_INVALID_ARG
-    assert L.lam_kmeans_assign(1, C.c_void_p(260), 10, 64, p, 4, p, None, p, big, None) == _lib.LAM_ERR_INVALID_ARG
-    assert L.lam_kmeans_assign(1, p, 10, 64, p, 4, p, None, p, C.c_uint64(16), None) == _lib.LAM_ERR_INVALID_ARG
+    assert L.lam_kmeans_lloyd(None, 1, p, None, 10, 64, p, 4, 0, p, None, None, p, big, None) == _lib.LAM_ERR_INVALID_ARG
+    assert L.lam_kmeans_assign(None, 1, C.c_void_p(260), 10, 64, p, 4, p, None, p, big, None) == _lib.LAM_ERR_INVALID_ARG
+    assert L.lam_kmeans_assign(None, 1, p, 10, 64, p, 4, p, None, p, C.c_uint64(16), None) == _lib.LAM_ERR_INVALID_ARG
     # stream: m <= n, Kp <= K, m >= K - Kp, seeds inside [0, n)
     for n, Kp, K, m in ((10, 0, 4, 11), (10, 5, 4, 3), (10, 0, 4, 3)):
-        assert L.lam_stream_kmeans_workspace_size(1, n, 64, Kp, K, m, C.byref(ok)) == _lib.LAM_ERR_INVALID_ARG
-    assert L.lam_stream_kmeans_workspace_size(1, 10, 64, 2, 4, 3, C.byref(ok)) == 0
+        assert L.lam_stream_kmeans_workspace_size(None, 1, n, 64, Kp, K, m, C.byref(ok)) == _lib.LAM_ERR_INVALID_ARG
+    assert L.lam_stream_kmeans_workspace_size(None, 1, 10, 64, 2, 4, 3, C.byref(ok)) == 0
     seeds = np.array([0, 3, 10], dtype=np.int32)  # 10 is out of range for n = 10
-    st = L.lam_stream_kmeans(1, p, 10, 64, None, None, 0, 3, seeds.ctypes.data_as(C.c_void_p), 3, 2, 2, p, p, p,
+    st = L.lam_stream_kmeans(None, 1, p, 10, 64, None, None, 0, 3, seeds.ctypes.data_as(C.c_void_p), 3, 2, 2, p, p, p,
                              big, None)
     assert st == _lib.LAM_ERR_INVALID_ARG
     seeds[2] = -1
-    st = L.lam_stream_kmeans(1, p, 10, 64, None, None, 0, 3, seeds.ctypes.data_as(C.c_void_p), 3, 2, 2, p, p, p,
+    st = L.lam_stream_kmeans(None, 1, p, 10, 64, None, None, 0, 3, seeds.ctypes.data_as(C.c_void_p), 3, 2, 2, p, p, p,
                              big, None)
     assert st == _lib.LAM_ERR_INVALID_ARG

@@ -44,9 +44,9 @@ def _cuda(*arrs):
     return [torch.as_tensor(a, device="cuda") for a in arrs]
 
 
-def _decoder(prec, n, d, M, D):
+def _decoder(prec, n, d, M, D, ctx=None):
     from paper_2602_12314_amd import ops
-    return ops.Decoder(prec, n, d, M, D)
+    return ops.Decoder(prec, n, d, M, D, ctx=ctx)
 
 
 def _cos(a, b):
@@ -134,7 +134,7 @@ def test_fp8_meets_min_cosine_and_dQ_bars(shape):
     assert c >= 0.999 and e < 1e-2 and ev < 1e-2
 
 
-# 64-pixel x 8-wave workgroups (lam_set_decode_shape(1)): D = 256 (one D tile
+# 64-pixel x 8-wave workgroups (the context option "decode_shape": 1): D = 256 (one D tile
 # per wave), 512 (two) and 768 (three; FP8 falls back to 32 x 4 there).
 WIDE_SHAPES = [(777, 32, 100, 256), (4096, 16, 256, 512), (333, 32, 512, 768)]
 
@@ -146,14 +146,11 @@ def test_wide_decode_shape(prec, shape):
     n, d, M, D = shape
     say(f"[decode px64] {prec} n={n} d={d} M={M} D={D}")
     Q, K, V, T, K0 = _inputs(3, n, d, M, D)
-    dec = _decoder(prec, n, d, M, D)
-    _lib.set_decode_shape("px64")
-    try:
-        F = to_np(dec.forward(*_cuda(Q, K, V)))
-        loss, dQ, dK, dV = dec.loss_and_grads(*_cuda(Q, K, V, T, K0), 0.1)
-        dQb, dKb, dVb = dec.backward(*_cuda(Q, K, V, T.astype(np.float32) * 0.01))
-    finally:
-        _lib.set_decode_shape("px32")
+    ctx = _lib.Context(options={"decode_shape": "px64"})
+    dec = _decoder(prec, n, d, M, D, ctx=ctx)
+    F = to_np(dec.forward(*_cuda(Q, K, V)))
+    loss, dQ, dK, dV = dec.loss_and_grads(*_cuda(Q, K, V, T, K0), 0.1)
+    dQb, dKb, dVb = dec.backward(*_cuda(Q, K, V, T.astype(np.float32) * 0.01))
     ref = DO.loss_and_grads(Q, K, V, T, K0, 0.1)
     c = _cos(F, ref["F"])
     say(f"  cos min {c.min():.6f} mean {c.mean():.6f}")

@@ -152,15 +152,12 @@ def test_decode_full_size(cfg):
     W = rng.standard_normal((D, 8))
     tr = 2.0 * sp.lambda_tr * (K.astype(np.float64) - K0)
     for shape in ("px32", "px64"):
-        _lib.set_decode_shape(shape)
-        try:
-            dec = ops.Decoder(prec, n, d, M, D)
-            row_cos = torch.empty(n, device="cuda")
-            loss, dQ, dK, dV = dec.loss_and_grads(q, k, v, t, k0, sp.lambda_tr, row_cos=row_cos)
-            F = dec.forward(q, k, v)
-            torch.cuda.synchronize()
-        finally:
-            _lib.set_decode_shape("px32")
+        ctx = _lib.Context(options={"decode_shape": shape})
+        dec = ops.Decoder(prec, n, d, M, D, ctx=ctx)
+        row_cos = torch.empty(n, device="cuda")
+        loss, dQ, dK, dV = dec.loss_and_grads(q, k, v, t, k0, sp.lambda_tr, row_cos=row_cos)
+        F = dec.forward(q, k, v)
+        torch.cuda.synchronize()
         say(f"  decode shape {shape}")
         sel = torch.as_tensor(idx, device="cuda")
         cg = to_np(row_cos)

@@ -155,17 +155,14 @@ def test_persistent_schedule_matches_per_tile(views):
     g = ops.Gaussians.from_numpy(s)
     say(f"[schedule] persistent vs per-tile, {views} view(s)")
     out = {}
-    try:
-        for mode in ("per_tile", "persistent"):
-            _lib.set_raster_schedule(mode)
-            r = ops.Renderer(cams, s.n, 16)
-            Q, T = r.forward(g)
-            dQ = torch.as_tensor(np.random.default_rng(3).standard_normal(tuple(Q.shape)), dtype=torch.float32,
-                                 device="cuda")
-            gr = r.backward(g, dQ)
-            out[mode] = (to_np(Q), to_np(T), [to_np(t) for t in gr.tensors()])
-    finally:
-        _lib.set_raster_schedule("auto")
+    for mode in ("per_tile", "persistent"):
+        ctx = _lib.Context(options={"raster_schedule": mode})
+        r = ops.Renderer(cams, s.n, 16, ctx=ctx)
+        Q, T = r.forward(g)
+        dQ = torch.as_tensor(np.random.default_rng(3).standard_normal(tuple(Q.shape)), dtype=torch.float32,
+                             device="cuda")
+        gr = r.backward(g, dQ)
+        out[mode] = (to_np(Q), to_np(T), [to_np(t) for t in gr.tensors()])
     a, b = out["per_tile"], out["persistent"]
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
     for x, y in zip(a[2], b[2]):
