@@ -74,6 +74,8 @@ extern "C" {
 #define LAM_CAM_FLOATS 22
 #define LAM_MAX_CAMS 16
 #define LAM_VERSION 2
+/* bytes of the static per-GPU scratch of lam_decode_forward_noalloc (8 MiB) */
+#define LAM_NOALLOC_SCRATCH_BYTES (8u << 20)
 
 typedef enum {
     LAM_OK = 0,
@@ -318,6 +320,30 @@ lam_status lam_decode_loss_overlap(lam_ctx* ctx, int precision, const float* Q, 
 lam_status lam_decode_forward(lam_ctx* ctx, int precision, const float* Q, int n, int d, const float* K,
                               const float* V, int M, int D, float* F, void* ws,
                               uint64_t ws_bytes, void* stream);
+
+/* lam_decode_forward for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same kernels and the same F bit for bit, but no workspace
+ * argument.  Its scratch -- the prepared dictionary: K and V converted to the
+ * compute type, V transposed, K permuted for the MFMA layout, the E4M3 row
+ * scales -- lives in a static device array of LAM_NOALLOC_SCRATCH_BYTES per
+ * GPU, held from library load until the process ends.  The dictionary needs
+ *   Mp (d + 2 D + 32) b + 4 (3 Mp + 64) bytes
+ * (each of the five parts rounded up to 256 bytes) with Mp = M rounded up to
+ * 64 and b = 4 (FP32) or 2 (BF16, E4M3).  That holds every supported BF16 and
+ * E4M3 shape except D = 1024 with M > 1920 (d = 32) or M > 1984 (d = 16), and
+ * the FP32 shapes with M <= 960 at D = 1024 (M <= 1024 otherwise, the FP32
+ * limit of lam_decode_forward).  Larger dictionaries return
+ * LAM_ERR_UNSUPPORTED.
+ * Every call on one GPU uses the same array, so calls that overlap on one GPU
+ * (two streams, two host threads, two contexts) race: serialise them.  Each
+ * call rewrites the whole part it reads, so nothing carries over between
+ * calls.  Allocates nothing and makes no host synchronisation.
+ * Errors: LAM_ERR_INVALID_ARG (no context, null or misaligned pointers),
+ * LAM_ERR_UNSUPPORTED (shape, or a dictionary beyond the scratch),
+ * LAM_ERR_HIP. */
+lam_status lam_decode_forward_noalloc(lam_ctx* ctx, int precision, const float* Q, int n, int d, const float* K,
+                                      const float* V, int M, int D, float* F, void* stream);
 
 /* Adjoint of lam_decode_forward: given dF device [n, D] writes dQ [n, d]
  * (nullable), dK [M, d], dV [M, D] (device, overwritten); the softmax is

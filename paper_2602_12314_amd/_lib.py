@@ -68,6 +68,7 @@ def lib():
             "lam_decode_loss_overlap": (i32, [vp, i32, vp, i32, i32, vp, vp, i32, i32, vp, vp, f32, vp, vp, vp, vp,
                                               vp, vp, u64, vp, vp]),
             "lam_decode_forward": (i32, [vp, i32, vp, i32, i32, vp, vp, i32, i32, vp, vp, u64, vp]),
+            "lam_decode_forward_noalloc": (i32, [vp, i32, vp, i32, i32, vp, vp, i32, i32, vp, vp]),
             "lam_decode_backward": (i32, [vp, i32, vp, i32, i32, vp, vp, i32, i32, vp, vp, vp, vp, vp, u64,
                                           vp]),
             "lam_decode_tied_workspace_size": (i32, [vp, i32, i32, i32, i32, i32, pu64]),
@@ -266,6 +267,19 @@ def decode_forward(precision, Q, K, V, F, ws, stream=None, ctx=None):
     check(lib().lam_decode_forward(_ctx(ctx), PRECISIONS.get(precision, precision), _p(Q), n, d, _p(K), _p(V), M, D,
                                    _p(F), _p(ws), ws.numel() * ws.element_size(), _stream(stream)),
           "lam_decode_forward")
+
+
+NOALLOC_SCRATCH_BYTES = 8 << 20  # LAM_NOALLOC_SCRATCH_BYTES
+
+
+def decode_forward_noalloc(precision, Q, K, V, F, stream=None, ctx=None):
+    """lam_decode_forward without a workspace: the dictionary is prepared in
+    the library's static per-GPU scratch (calls on one GPU must not overlap)."""
+    n, d = Q.shape
+    M, D = V.shape
+    check(lib().lam_decode_forward_noalloc(_ctx(ctx), PRECISIONS.get(precision, precision), _p(Q), n, d, _p(K),
+                                           _p(V), M, D, _p(F), _stream(stream)),
+          "lam_decode_forward_noalloc")
 
 
 def decode_backward(precision, Q, K, V, dF, dQ, dK, dV, ws, stream=None, ctx=None):

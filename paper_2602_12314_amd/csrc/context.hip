@@ -5,16 +5,46 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 
 #include "common.h"
 #include "kernels.h"
+
+// Scratch of lam_decode_forward_noalloc: the prepared dictionary (converted
+// K and V, V transposed, K permuted, E4M3 scales).  One copy per GPU, held
+// until the process ends; every call on a GPU shares its copy.  In host code
+// this name is not a device address: launches use the address
+// hipGetSymbolAddress returns, kept per device.
+static __device__ __align__(256) unsigned char scratch[LAM_NOALLOC_SCRATCH_BYTES];
 
 namespace lam {
 
 void prof_release(lam_ctx* ctx);  // profile.hip
 
 namespace {
+
+// Device address of this GPU's ``scratch`` (resolved once per device, with
+// that device current).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxDevices] = {};
+
+hipError_t scratch_address(int device, void** out)
+{
+    *out = nullptr;
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_addr[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_addr[device] = p;
+    }
+    *out = g_scratch_addr[device];
+    return hipSuccess;
+}
 
 // The options a context holds, as parsed and validated from JSON.
 struct Options {
@@ -174,8 +204,11 @@ lam_status lam_create(int device, const char* options_json, lam_ctx** out)
         c->device = device;
         store_options(c, o);
         if (hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
-            hipEventCreateWithFlags(&c->fork, hipEventDisableTiming) != hipSuccess)
+            hipEventCreateWithFlags(&c->fork, hipEventDisableTiming) != hipSuccess ||
+            scratch_address(device, &c->static_scratch) != hipSuccess)
             s = LAM_ERR_HIP;
+        else
+            c->static_scratch_bytes = LAM_NOALLOC_SCRATCH_BYTES;
     }
     if (s != LAM_OK && c) {
         if (c->fork) hipEventDestroy(c->fork);

@@ -1259,6 +1259,31 @@ bool decode_layout(const lam_ctx* ctx, int prec, int n, int d, int M, int D, Dec
     return true;
 }
 
+// The inference decode reads only the prepared dictionary (converted K and V,
+// V transposed, K permuted, the E4M3 scales); this layout packs just those at
+// the front of a buffer.  The per-pixel buffers of the gradient passes are
+// never touched in that mode, so their offsets point at the buffer start.
+bool decode_dict_layout(const lam_ctx* ctx, int prec, int n, int d, int M, int D, DecodeLayout* L)
+{
+    if (!decode_layout(ctx, prec, n, d, M, D, L)) return false;
+    const size_t tb = prec == LAM_FP32 ? 4 : 2;
+    const int Mp = L->Mp;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += (bytes + 255) / 256 * 256;
+        return o;
+    };
+    L->off_kb = take((size_t)Mp * d * tb);
+    L->off_vb = take((size_t)Mp * D * tb);
+    L->off_vt = take((size_t)Mp * D * tb);
+    L->off_kt = take((size_t)32 * Mp * tb);
+    L->off_sc = take(((size_t)3 * Mp + 64) * 4);
+    L->off_m2 = L->off_gf = L->off_ds = L->off_qt = L->off_part = L->off_loss = 0;
+    L->bytes = off;
+    return true;
+}
+
 template <class P, int MODE, bool F8>
 static hipError_t launch_rows(lam_ctx* ctx, const RowsArgs& ra, bool wide, int nb, int D, int d, int Mp, int prec,
                               hipStream_t st)
@@ -1500,6 +1525,21 @@ lam_status lam_decode_forward(lam_ctx* ctx, int precision, const float* Q, int n
     lam_status s = dec_common(ctx, precision, n, d, M, D, ws, ws_bytes, &L);
     if (s != LAM_OK) return s;
     if (!dec_ptrs_ok(Q, n, K, V) || (n > 0 && !F) || !a16(F)) return LAM_ERR_INVALID_ARG;
+    DecodeArgs A{};
+    A.prec = precision; A.n = n; A.d = d; A.M = M; A.D = D;
+    A.Q = Q; A.K = K; A.V = V; A.F = F;
+    return decode_forward_launch(ctx, A, L, (hipStream_t)stream) == hipSuccess ? LAM_OK : LAM_ERR_HIP;
+}
+
+lam_status lam_decode_forward_noalloc(lam_ctx* ctx, int precision, const float* Q, int n, int d, const float* K,
+                                      const float* V, int M, int D, float* F, void* stream)
+{
+    if (!ctx_ok(ctx) || n < 0) return LAM_ERR_INVALID_ARG;
+    DecodeLayout L{};
+    if (!decode_dict_layout(ctx, precision, n, d, M, D, &L)) return LAM_ERR_UNSUPPORTED;
+    if (!ctx->static_scratch || L.bytes > ctx->static_scratch_bytes) return LAM_ERR_UNSUPPORTED;
+    if (!dec_ptrs_ok(Q, n, K, V) || (n > 0 && !F) || !a16(F)) return LAM_ERR_INVALID_ARG;
+    L.base = ctx->static_scratch;
     DecodeArgs A{};
     A.prec = precision; A.n = n; A.d = d; A.M = M; A.D = D;
     A.Q = Q; A.K = K; A.V = V; A.F = F;

@@ -50,6 +50,10 @@ struct lam_ctx {
     std::vector<Lds> lds;
     std::vector<lam::ProfSlot> prof;
     int cus = 0;
+    // this device's copy of the static scratch array of the allocation-free
+    // decode entry point (device address, resolved when the context is made)
+    void* static_scratch = nullptr;
+    size_t static_scratch_bytes = 0;
 };
 
 namespace lam {
