@@ -1,9 +1,11 @@
 """Summaries of rocprofv3 CSV output for the library's kernels.
 
-    python -m paper_2602_12314_amd.profiling stats DIR
+    python -m paper_2602_12314_amd.profiling stats DIR [--by-grid] [--top N]
         per-kernel calls, total and average duration from a
         ``rocprofv3 --kernel-trace --stats --output-format csv -d DIR`` run
-        (markdown table).
+        (markdown table); with --by-grid, from the kernel trace per (kernel,
+        grid size), so that one launch shape's average is not mixed with the
+        same kernel's launches at other sizes.
 
     python -m paper_2602_12314_amd.profiling counters DIR [KERNEL_PREFIX]
         mean value per dispatch of every counter of a ``--pmc`` run, by kernel.
@@ -72,6 +74,16 @@ def kernel_stats(d):
              float(r["AverageNs"]) / 1e3, float(r["Percentage"])) for r in rows]
 
 
+def kernel_stats_by_grid(d):
+    """(kernel, grid threads, calls, total us, average us) from the kernel trace."""
+    acc = defaultdict(list)
+    for r in csv.DictReader(open(_one(d, "*kernel_trace.csv"))):
+        g = int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"])
+        acc[(short(r["Kernel_Name"]), g)].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    rows = [(k, g, len(v), sum(v), sum(v) / len(v)) for (k, g), v in acc.items()]
+    return sorted(rows, key=lambda x: -x[3])
+
+
 def counter_means(d, counter, largest_grid=False):
     """Mean counter value per dispatch, by kernel (with largest_grid, over the
     dispatches of the kernel's largest grid only)."""
@@ -102,6 +114,8 @@ def main(argv=None):
     sub = ap.add_subparsers(dest="cmd", required=True)
     s = sub.add_parser("stats")
     s.add_argument("dir")
+    s.add_argument("--by-grid", action="store_true")
+    s.add_argument("--top", type=int, default=0)
     c = sub.add_parser("counters")
     c.add_argument("dir")
     c.add_argument("prefix", nargs="?", default="")
@@ -115,6 +129,14 @@ def main(argv=None):
     t.add_argument("--largest-grid", action="store_true",
                    help="average only the dispatches of each kernel's largest grid")
     a = ap.parse_args(argv)
+    if a.cmd == "stats" and a.by_grid:
+        rows = kernel_stats_by_grid(a.dir)
+        tot = sum(r[3] for r in rows)
+        print("| kernel | grid (threads) | calls | total us | avg us | % |")
+        print("|---|---|---|---|---|---|")
+        for k, g, calls, t, avg in rows[:a.top or None]:
+            print(f"| {k} | {g} | {calls} | {t:.1f} | {avg:.2f} | {100 * t / tot:.1f} |")
+        return 0
     if a.cmd == "stats":
         print("| kernel | calls | total us | avg us | % |")
         print("|---|---|---|---|---|")

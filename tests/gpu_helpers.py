@@ -16,11 +16,42 @@ def say(*a):
     sys.stdout.flush()
 
 
-def rel_err(x, ref) -> float:
+# An element may be off by at most this many times the L2 bar, relative to the
+# largest reference element: a few badly wrong elements among many correct
+# ones fail a bar that the L2 norm alone would let through.
+ELEM_FACTOR = 10.0
+
+
+class Err(float):
+    """Relative L2 error ||x - ref|| / ||ref|| (the float value) together with
+    the largest element error max |x - ref| / max |ref| (``.elem``).  ``e < bar``
+    holds only when both are within their bars: the L2 error below ``bar`` and
+    the element error below ``ELEM_FACTOR * bar``."""
+
+    def __new__(cls, l2: float, elem: float):
+        o = float.__new__(cls, l2)
+        o.elem = elem
+        return o
+
+    def __lt__(self, bar):
+        return float(self) < bar and self.elem < ELEM_FACTOR * bar
+
+    def __le__(self, bar):
+        return float(self) <= bar and self.elem <= ELEM_FACTOR * bar
+
+    def __format__(self, spec):
+        return f"{float(self):{spec}} (elem {self.elem:{spec}})" if spec else f"{float(self)} (elem {self.elem})"
+
+
+def rel_err(x, ref) -> Err:
     x = np.asarray(x, np.float64)
     ref = np.asarray(ref, np.float64)
     den = np.linalg.norm(ref)
-    return float(np.linalg.norm(x - ref) / den) if den > 0 else float(np.linalg.norm(x))
+    d = np.abs(x - ref)
+    big = float(np.abs(ref).max()) if ref.size else 0.0
+    elem = float(d.max() / big) if d.size and big > 0 else (float(d.max()) if d.size else 0.0)
+    l2 = float(np.linalg.norm(x - ref) / den) if den > 0 else float(np.linalg.norm(x))
+    return Err(l2, elem)
 
 
 def to_np(t):
