@@ -299,6 +299,12 @@ constexpr int pipe_depth()
     return DEEP ? 4 : 2;
 }
 
+// The deep ring where one wave per SIMD is all the registers allow; the
+// 64-pixel block with four D tiles per wave keeps the short ring so that it
+// fits two waves per SIMD (the other wave hides the latency).
+template <bool F8, int NT, int NPG, int NW>
+constexpr bool kDeepRing = (F8 || NT * NPG > 4) && !(NW == 8 && NT * NPG >= 8);
+
 // Workgroup shape of k_dec_rows: NW waves and NPG groups of 32 pixels.  Every
 // wave covers all NPG x 32 pixels of the block and 1 / NW of the D columns
 // (NT = D / (32 NW) tiles of 32) in the F contraction, and the atom tiles
@@ -548,7 +554,7 @@ __global__ __launch_bounds__(NW * kWave) void k_dec_rows(RowsArgs a)
         // ring of PD chunks: chunk c + PD - 1 is loaded while chunk c is multiplied.
         // The loads are unconditional (the last PD chunks are peeled) so that
         // each MFMA waits only for its own fragments.
-        constexpr int PD = pipe_depth<(F8 || NT * NPG > 4)>();
+        constexpr int PD = pipe_depth<kDeepRing<F8, NT, NPG, NW>>();
         Frag ring[PD][NT], bring[PD][NPG];
         auto fetch = [&](int c, Frag* r, Frag* b) {
 #pragma unroll
@@ -601,26 +607,33 @@ __global__ __launch_bounds__(NW * kWave) void k_dec_rows(RowsArgs a)
         return;
     }
 
-    // ---- epilogue: cosine loss gradient (LOSS) or upstream dF (ADJ).  gsc first
-    // holds the target (or dF) rows and is overwritten in place by G = dL/dF / l.
+    // ---- epilogue: cosine loss gradient (LOSS) or upstream dF (ADJ), G = dL/dF / l.
+    // The target (or dF) rows feed the row statistics and, once those are
+    // reduced over the waves, G; they are either held in registers across that
+    // reduction or read a second time (kHold below).
     // (Requesting these rows before the F contraction is slower: loads retire in
     // order, so every fragment wait of the contraction would wait for them.)
     // A pixel past n reads row n - 1, unused since its G is zeroed through ca, cb.
-    float gsc[NT][NPG][16];
-    {
-        const float* rowsrc = MODE == MODE_LOSS ? a.target : a.dF;
+    // The rows are held in registers from the first read (held[]) except in
+    // the 64-pixel block with four D tiles per wave, whose registers only fit
+    // two waves per SIMD when they are read twice (the second read costs
+    // bandwidth: the other shapes are faster holding them).
+    constexpr bool kHold = !(NW == 8 && NT * NPG >= 8);
+    const float* rowsrc = MODE == MODE_LOSS ? a.target : a.dF;
+    auto row_frag = [&](int g, int t, float* x16) {
+        const float* prow = rowsrc + (size_t)(valid[g] ? pxg[g] : a.n - 1) * a.D + 32 * (w * NT + t) + 4 * h;
 #pragma unroll
-        for (int g = 0; g < NPG; ++g) {
-            const float* prow = rowsrc + (size_t)(valid[g] ? pxg[g] : a.n - 1) * a.D;
-#pragma unroll
-            for (int t = 0; t < NT; ++t)
-#pragma unroll
-                for (int g4 = 0; g4 < 4; ++g4) {
-                    const float4 x = *reinterpret_cast<const float4*>(prow + 32 * (w * NT + t) + 8 * g4 + 4 * h);
-                    gsc[t][g][4 * g4] = x.x; gsc[t][g][4 * g4 + 1] = x.y;
-                    gsc[t][g][4 * g4 + 2] = x.z; gsc[t][g][4 * g4 + 3] = x.w;
-                }
+        for (int g4 = 0; g4 < 4; ++g4) {
+            const float4 x = *reinterpret_cast<const float4*>(prow + 8 * g4);
+            x16[4 * g4] = x.x; x16[4 * g4 + 1] = x.y; x16[4 * g4 + 2] = x.z; x16[4 * g4 + 3] = x.w;
         }
+    };
+    float held[kHold ? NT : 1][NPG][16];
+    if constexpr (kHold) {
+#pragma unroll
+        for (int g = 0; g < NPG; ++g)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) row_frag(g, t, held[t][g]);
     }
     float delta[NPG], ca[NPG], cb[NPG];  // G = ca * row + cb * F (zero past n)
 #pragma unroll
@@ -635,13 +648,17 @@ __global__ __launch_bounds__(NW * kWave) void k_dec_rows(RowsArgs a)
         for (int g = 0; g < NPG; ++g) {
             nf[g] = ft[g] = nt[g] = 0.0f;
 #pragma unroll
-            for (int t = 0; t < NT; ++t)
+            for (int t = 0; t < NT; ++t) {
+                float xr[16];
+                if constexpr (!kHold) row_frag(g, t, xr);
+                const float* x = kHold ? held[kHold ? t : 0][g] : xr;
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
                     nf[g] += acc[t][g][r] * acc[t][g][r];
-                    ft[g] += acc[t][g][r] * gsc[t][g][r];
-                    nt[g] += gsc[t][g][r] * gsc[t][g][r];
+                    ft[g] += acc[t][g][r] * x[r];
+                    nt[g] += x[r] * x[r];
                 }
+            }
             nf[g] += __shfl_xor(nf[g], 32, kWave);
             ft[g] += __shfl_xor(ft[g], 32, kWave);
             nt[g] += __shfl_xor(nt[g], 32, kWave);
@@ -683,35 +700,38 @@ __global__ __launch_bounds__(NW * kWave) void k_dec_rows(RowsArgs a)
             }
         }
     }
-    // G in place; delta' = sum_D G F (zero for the pure cosine term up to rounding)
+    __syncthreads();  // everyone is done reading P~ (region X) and the statistics
+    // G from the re-read rows, staged into LDS [px][D]; delta' = sum_D G F (zero
+    // for the pure cosine term up to rounding)
 #pragma unroll
     for (int g = 0; g < NPG; ++g) {
 #pragma unroll
-        for (int t = 0; t < NT; ++t)
+        for (int t = 0; t < NT; ++t) {
+            float x[16];
+            if constexpr (kHold) {
+#pragma unroll
+                for (int r = 0; r < 16; ++r) x[r] = held[kHold ? t : 0][g][r];
+            } else {
+                row_frag(g, t, x);
+            }
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
-                const float gv = ca[g] * gsc[t][g][r] + cb[g] * acc[t][g][r];
+                const float gv = ca[g] * x[r] + cb[g] * acc[t][g][r];
                 delta[g] += gv * acc[t][g][r];
-                gsc[t][g][r] = gv;
+                x[r] = gv;
             }
+#pragma unroll
+            for (int g4 = 0; g4 < 4; ++g4) {
+                const int dr = 32 * (w * NT + t) + 8 * g4 + 4 * h;
+                P::store4(X + (g * kPx + col) * ldg + dr, x[4 * g4], x[4 * g4 + 1], x[4 * g4 + 2], x[4 * g4 + 3]);
+            }
+        }
         delta[g] += __shfl_xor(delta[g], 32, kWave);
     }
-    __syncthreads();  // everyone is done reading P~ (region X) and the statistics
     if (h == 0) {
 #pragma unroll
         for (int g = 0; g < NPG; ++g) rslot(3, w, g)[col] = delta[g];
     }
-    // stage G into LDS [px][D]
-#pragma unroll
-    for (int g = 0; g < NPG; ++g)
-#pragma unroll
-        for (int t = 0; t < NT; ++t)
-#pragma unroll
-            for (int g4 = 0; g4 < 4; ++g4) {
-                const int dr = 32 * (w * NT + t) + 8 * g4 + 4 * h;
-                P::store4(X + (g * kPx + col) * ldg + dr, gsc[t][g][4 * g4], gsc[t][g][4 * g4 + 1],
-                          gsc[t][g][4 * g4 + 2], gsc[t][g][4 * g4 + 3]);
-            }
     __syncthreads();
 #pragma unroll
     for (int g = 0; g < NPG; ++g) {
@@ -762,7 +782,7 @@ __global__ __launch_bounds__(NW * kWave) void k_dec_rows(RowsArgs a)
     // V fragment feeds the NPG pixel groups; the fragments run PG chunks ahead of
     // the MFMAs, and the K fragments of the dS step are requested before the
     // contraction that hides their latency.
-    constexpr int PG = pipe_depth<(F8 || NT * NPG > 4)>();
+    constexpr int PG = pipe_depth<kDeepRing<F8, NT, NPG, NW>>();
     for (int tt = w; tt < ntiles; tt += TT * NW) {
         bool has[TT];
         int tj[TT];
@@ -1190,11 +1210,11 @@ static size_t rows_lds(int prec, int Mp, int D, int NW, int NPG)
 constexpr size_t kMaxLds = 160 * 1024;  // LDS of a gfx950 workgroup
 
 // 64-pixel blocks of 8 waves (each V fragment feeds two MFMAs) where the
-// registers and LDS allow: BF16 with D a multiple of 256 up to 768, E4M3 up to
+// registers and LDS allow: BF16 with D a multiple of 256 up to 1024, E4M3 up to
 // 512 (its wider fragments would spill at 768).
 static bool wide_ok(int prec, int Mp, int D)
 {
-    const int max_nt = prec == LAM_FP8_E4M3 ? 2 : 3;
+    const int max_nt = prec == LAM_FP8_E4M3 ? 2 : 4;
     return prec != LAM_FP32 && D % 256 == 0 && D / 256 <= max_nt && rows_lds(prec, Mp, D, 8, 2) <= kMaxLds;
 }
 
@@ -1303,10 +1323,10 @@ static hipError_t launch_rows(lam_ctx* ctx, const RowsArgs& ra, bool wide, int n
     LAM_ROWS(4, 1, 5, 16) LAM_ROWS(4, 1, 6, 16) LAM_ROWS(4, 1, 7, 16) LAM_ROWS(4, 1, 8, 16)
     LAM_ROWS(4, 1, 1, 32) LAM_ROWS(4, 1, 2, 32) LAM_ROWS(4, 1, 3, 32) LAM_ROWS(4, 1, 4, 32)
     LAM_ROWS(4, 1, 5, 32) LAM_ROWS(4, 1, 6, 32) LAM_ROWS(4, 1, 7, 32) LAM_ROWS(4, 1, 8, 32)
-    if constexpr (P::kBytes == 2) {  // the 64 x 8 shape (wide_ok): BF16 up to 3 D tiles a wave, E4M3 2
+    if constexpr (P::kBytes == 2) {  // the 64 x 8 shape (wide_ok): BF16 up to 4 D tiles a wave, E4M3 2
         LAM_ROWS(8, 2, 1, 16) LAM_ROWS(8, 2, 2, 16) LAM_ROWS(8, 2, 1, 32) LAM_ROWS(8, 2, 2, 32)
         if constexpr (!F8) {
-            LAM_ROWS(8, 2, 3, 16) LAM_ROWS(8, 2, 3, 32)
+            LAM_ROWS(8, 2, 3, 16) LAM_ROWS(8, 2, 3, 32) LAM_ROWS(8, 2, 4, 16) LAM_ROWS(8, 2, 4, 32)
         }
     }
 #undef LAM_ROWS

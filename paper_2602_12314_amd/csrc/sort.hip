@@ -255,6 +255,11 @@ __global__ __launch_bounds__(kTileThreads) void k_radix_hist(const uint32_t* __r
     for (int k = threadIdx.x; k < BINS; k += kTileThreads) hist[(size_t)k * nblocks + blockIdx.x] = h[k];
 }
 
+// Stable scatter of one pass.  The keys of a tile are ranked per digit (wave
+// ballots, then a prefix over the waves), placed in LDS in their sorted order
+// inside the tile, and written out from there: consecutive threads then store
+// consecutive elements of each digit's run, so the global writes are whole
+// runs instead of one scattered element per key.
 template <int DB, int ITEMS>
 __global__ __launch_bounds__(kTileThreads) void k_radix_scatter(
     const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
@@ -264,20 +269,31 @@ __global__ __launch_bounds__(kTileThreads) void k_radix_scatter(
 {
     constexpr int BINS = 1 << DB;
     constexpr int WAVES = kTileThreads / kWave;
-    __shared__ uint32_t cnt[WAVES][BINS];
+    constexpr int TILE = kTileThreads * ITEMS;
+    constexpr int DPT = BINS / kTileThreads;  // digits per thread in the digit scan
+    static_assert(BINS % kTileThreads == 0, "whole digits per thread");
+    // the per-wave digit counts, later (same words) the tile's keys and values
+    // in sorted order
+    constexpr int UWORDS = WAVES * BINS > 2 * TILE ? WAVES * BINS : 2 * TILE;
+    __shared__ uint32_t ubuf[UWORDS];
     __shared__ uint32_t gbase[BINS];
+    __shared__ uint32_t dstart[BINS];  // first local position of each digit
+    __shared__ uint32_t ssh[4];
+    uint32_t(*cnt)[BINS] = reinterpret_cast<uint32_t(*)[BINS]>(ubuf);
+    uint32_t* lk = ubuf;
+    uint32_t* lv = ubuf + TILE;
     const unsigned lane = __lane_id(), w = threadIdx.x / kWave;
-    for (int k = threadIdx.x; k < WAVES * BINS; k += kTileThreads) (&cnt[0][0])[k] = 0;
+    for (int k = threadIdx.x; k < WAVES * BINS; k += kTileThreads) ubuf[k] = 0;
     for (int k = threadIdx.x; k < BINS; k += kTileThreads)
         gbase[k] = offsets[(size_t)k * nblocks + blockIdx.x];
     __syncthreads();
 
     const uint32_t n = load_count(n_dev, n_cap);
-    const uint32_t span = blockIdx.x * (uint32_t)(kTileThreads * ITEMS) + w * (kWave * ITEMS);
+    const uint32_t span = blockIdx.x * (uint32_t)TILE + w * (kWave * ITEMS);
     const unsigned long long lt = (1ull << lane) - 1ull;
     uint32_t key[ITEMS], val[ITEMS], rank[ITEMS];
     // all keys and values of the wave's span are requested before the ranking
-    // (indices clamped into range; entries past n are never written)
+    // (indices clamped into range; entries past n are never placed)
     const uint32_t nl = n > 0 ? n - 1 : 0;
 #pragma unroll
     for (int s = 0; s < ITEMS; ++s) {
@@ -312,8 +328,12 @@ __global__ __launch_bounds__(kTileThreads) void k_radix_scatter(
         if (ok && (peers & lt) == 0ull) cnt[w][dg] = before + (uint32_t)__popcll(peers);
     }
     __syncthreads();
-    // exclusive prefix over the waves, per digit
-    for (int d = threadIdx.x; d < BINS; d += kTileThreads) {
+    // exclusive prefix over the waves per digit, and the tile's digit totals
+    // scanned over the digits (thread t owns digits DPT t .. DPT t + DPT - 1)
+    uint32_t tot[DPT], tsum = 0;
+#pragma unroll
+    for (int j = 0; j < DPT; ++j) {
+        const int d = threadIdx.x * DPT + j;
         uint32_t run = 0;
 #pragma unroll
         for (int k = 0; k < WAVES; ++k) {
@@ -321,16 +341,40 @@ __global__ __launch_bounds__(kTileThreads) void k_radix_scatter(
             cnt[k][d] = run;
             run += c;
         }
+        tot[j] = run;
+        tsum += run;
+    }
+    uint32_t nvalid;
+    uint32_t off = block_excl_scan(tsum, &nvalid, ssh);
+#pragma unroll
+    for (int j = 0; j < DPT; ++j) {
+        dstart[threadIdx.x * DPT + j] = off;
+        off += tot[j];
+    }
+    __syncthreads();
+    // local positions first (they read the counts), then the counts' words
+    // take the sorted keys and values
+#pragma unroll
+    for (int s = 0; s < ITEMS; ++s) {
+        if (rank[s] == 0xFFFFFFFFu) continue;
+        const uint32_t dg = (key[s] >> shift) & (BINS - 1u);
+        rank[s] = dstart[dg] + cnt[w][dg] + rank[s];
     }
     __syncthreads();
 #pragma unroll
     for (int s = 0; s < ITEMS; ++s) {
         if (rank[s] == 0xFFFFFFFFu) continue;
-        const uint32_t dg = (key[s] >> shift) & (BINS - 1u);
-        const uint32_t pos = gbase[dg] + cnt[w][dg] + rank[s];
+        lk[rank[s]] = key[s];
+        lv[rank[s]] = val[s];
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < nvalid; i += kTileThreads) {
+        const uint32_t k = lk[i];
+        const uint32_t dg = (k >> shift) & (BINS - 1u);
+        const uint32_t pos = gbase[dg] + (i - dstart[dg]);
         if (pos < n) {  // always true for a consistent histogram; keeps a bad one in bounds
-            keys_out[pos] = key[s];
-            vals_out[pos] = val[s];
+            keys_out[pos] = k;
+            vals_out[pos] = lv[i];
         }
     }
 }
