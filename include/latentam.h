@@ -89,14 +89,16 @@ typedef enum {
     LAM_FP32 = 0,     /* all products in float32 (MFMA f32) */
     LAM_BF16 = 1,     /* products on bf16 operands, float32 accumulation and softmax */
     LAM_FP8_E4M3 = 2  /* the forward product P V on OCP E4M3 operands: V in E4M3 with a
-                         float32 scale per atom (row), the unnormalised softmax weights
-                         (which peak at 1 per pixel) times the atom scales mapped onto
-                         the E4M3 range by one factor per call; the logits Q K^T and
-                         every backward product in bf16; float32 accumulation and
-                         softmax.  Its error against exact arithmetic is larger than
-                         bf16's: on 1200x680 frames with M = D = 1024 the smallest
-                         per-pixel cosine of F is about 0.9985 and dQ is within a few
-                         1e-2 (relative L2) */
+                         float32 scale per atom (row); the unnormalised softmax weights
+                         (which peak at 1 per pixel) times the atom scales, mapped onto
+                         the E4M3 range by one factor per call, enter as two E4M3 terms
+                         (the rounded value and the rounded residual), so F carries the
+                         rounding of V only; the logits Q K^T and every backward product
+                         in bf16; float32 accumulation and softmax.  On the 1200x680
+                         keyframe of a 2M-Gaussian map (M = D = 1024) the smallest
+                         per-pixel cosine of F against exact arithmetic is 0.99966 and
+                         dQ, dK, dV are within 1e-2 (relative L2); with a sharper
+                         softmax (unit-variance logits) dQ grows to 1-2e-2 */
 } lam_precision;
 
 /* Human-readable name of a status code (static storage). */

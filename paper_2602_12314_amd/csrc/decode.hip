@@ -466,10 +466,21 @@ __global__ __launch_bounds__(NW * kWave) void k_dec_rows(RowsArgs a)
                 if (F8) {
                     // P~ of a pixel peaks at exactly 1, so with the V row scales folded
                     // into its columns one fixed factor maps it onto the E4M3 range.
+                    // The weights go in as two E4M3 terms, the rounded value and the
+                    // rounded residual (relative error 2^-8 instead of 2^-4), so
+                    // that F carries only the E4M3 rounding of V.
                     const float4 sv = *reinterpret_cast<const float4*>(a.sv_fold + atom0);
-                    int pk = __builtin_amdgcn_cvt_pk_fp8_f32(p[4 * g4] * sv.x, p[4 * g4 + 1] * sv.y, 0, false);
-                    pk = __builtin_amdgcn_cvt_pk_fp8_f32(p[4 * g4 + 2] * sv.z, p[4 * g4 + 3] * sv.w, pk, true);
-                    *reinterpret_cast<int*>(reinterpret_cast<uint8_t*>(X) + prow * (a.Mp + 16) + atom0) = pk;
+                    const float q0 = p[4 * g4] * sv.x, q1 = p[4 * g4 + 1] * sv.y;
+                    const float q2 = p[4 * g4 + 2] * sv.z, q3 = p[4 * g4 + 3] * sv.w;
+                    int hi = __builtin_amdgcn_cvt_pk_fp8_f32(q0, q1, 0, false);
+                    hi = __builtin_amdgcn_cvt_pk_fp8_f32(q2, q3, hi, true);
+                    int lo = __builtin_amdgcn_cvt_pk_fp8_f32(q0 - __builtin_amdgcn_cvt_f32_fp8(hi, 0),
+                                                             q1 - __builtin_amdgcn_cvt_f32_fp8(hi, 1), 0, false);
+                    lo = __builtin_amdgcn_cvt_pk_fp8_f32(q2 - __builtin_amdgcn_cvt_f32_fp8(hi, 2),
+                                                         q3 - __builtin_amdgcn_cvt_f32_fp8(hi, 3), lo, true);
+                    uint8_t* X8 = reinterpret_cast<uint8_t*>(X);
+                    *reinterpret_cast<int*>(X8 + prow * (a.Mp + 16) + atom0) = hi;
+                    *reinterpret_cast<int*>(X8 + (BPX + prow) * (a.Mp + 16) + atom0) = lo;
                 } else {
                     P::store4(X + prow * ldp + atom0, p[4 * g4], p[4 * g4 + 1], p[4 * g4 + 2], p[4 * g4 + 3]);
                 }
@@ -506,8 +517,9 @@ __global__ __launch_bounds__(NW * kWave) void k_dec_rows(RowsArgs a)
         // K = 64 atoms per E4M3 MFMA; lane half h holds atoms 32 h + 0..31.
         // Two chunks in flight; the chunk count Mp / 64 may be odd.
         const int nc8 = a.Mp / 64;
-        auto bload = [&](int c, int g) {
-            const uint8_t* X8 = reinterpret_cast<const uint8_t*>(X) + (g * kPx + col) * (a.Mp + 16);
+        // the weights' E4M3 terms: part 0 the rounded values, part 1 the residuals
+        auto bload = [&](int c, int g, int part) {
+            const uint8_t* X8 = reinterpret_cast<const uint8_t*>(X) + (part * BPX + g * kPx + col) * (a.Mp + 16);
             const i32x4 b0 = *reinterpret_cast<const i32x4*>(X8 + 64 * c + 32 * h);
             const i32x4 b1 = *reinterpret_cast<const i32x4*>(X8 + 64 * c + 32 * h + 16);
             const i32x8 bf = {b0[0], b0[1], b0[2], b0[3], b1[0], b1[1], b1[2], b1[3]};
@@ -517,35 +529,40 @@ __global__ __launch_bounds__(NW * kWave) void k_dec_rows(RowsArgs a)
         constexpr int NH = NT < 4 ? NT : 4;
 #pragma unroll
         for (int t0 = 0; t0 < NT; t0 += NH) {
-            i32x8 ra[NH], rb[NH], ba[NPG], bb[NPG];
+            i32x8 ra[NH], rb[NH], ba[NPG][2], bb[NPG][2];
             auto vload = [&](int c, i32x8* af) {
 #pragma unroll
                 for (int t = 0; t < NH; ++t)
                     af[t] = *reinterpret_cast<const i32x8*>(
                         a.Vt8 + ((((size_t)(w * NT + t0 + t) * nc8 + c) << 6) + lane) * 32);
             };
-            auto mma8 = [&](const i32x8* af, const i32x8* bf) {
+            auto mma8 = [&](const i32x8* af, const i32x8 (*bf)[2]) {
 #pragma unroll
                 for (int t = 0; t < NH; ++t)
 #pragma unroll
                     for (int g = 0; g < NPG; ++g)
-                        acc[t0 + t][g] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
-                            af[t], bf[g], acc[t0 + t][g], 0, 0, 0, 127, 0, 127);
+#pragma unroll
+                        for (int part = 0; part < 2; ++part)
+                            acc[t0 + t][g] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+                                af[t], bf[g][part], acc[t0 + t][g], 0, 0, 0, 127, 0, 127);
+            };
+            auto pload = [&](int c, i32x8 (*bf)[2]) {
+#pragma unroll
+                for (int g = 0; g < NPG; ++g)
+#pragma unroll
+                    for (int part = 0; part < 2; ++part) bf[g][part] = bload(c, g, part);
             };
             vload(0, ra);
-#pragma unroll
-            for (int g = 0; g < NPG; ++g) ba[g] = bload(0, g);
+            pload(0, ba);
             for (int c = 0; c < nc8; c += 2) {
                 if (c + 1 < nc8) {
                     vload(c + 1, rb);
-#pragma unroll
-                    for (int g = 0; g < NPG; ++g) bb[g] = bload(c + 1, g);
+                    pload(c + 1, bb);
                 }
                 mma8(ra, ba);
                 if (c + 2 < nc8) {
                     vload(c + 2, ra);
-#pragma unroll
-                    for (int g = 0; g < NPG; ++g) ba[g] = bload(c + 2, g);
+                    pload(c + 2, ba);
                 }
                 if (c + 1 < nc8) mma8(rb, bb);
             }
@@ -1203,6 +1220,7 @@ static size_t rows_lds(int prec, int Mp, int D, int NW, int NPG)
     const size_t tb = prec == LAM_FP32 ? 4 : 2;
     const size_t bpx = (size_t)kPx * NPG;
     size_t x = std::max(bpx * (Mp + 8) * tb, bpx * (D + 8) * tb);
+    if (prec == LAM_FP8_E4M3) x = std::max(x, 2 * bpx * (Mp + 16));  // the weights' two E4M3 terms
     x = std::max(x, (size_t)NW * 32 * bpx * 4);  // dQ reduction
     return 4 * NW * bpx * 4 + (size_t)NW * kPx * kScLd * tb + x;
 }
@@ -1210,11 +1228,11 @@ static size_t rows_lds(int prec, int Mp, int D, int NW, int NPG)
 constexpr size_t kMaxLds = 160 * 1024;  // LDS of a gfx950 workgroup
 
 // 64-pixel blocks of 8 waves (each V fragment feeds two MFMAs) where the
-// registers and LDS allow: BF16 with D a multiple of 256 up to 1024, E4M3 up to
-// 512 (its wider fragments would spill at 768).
+// registers and LDS allow: BF16 with D a multiple of 256 up to 1024, E4M3 only
+// at D = 256 (its two weight terms per fragment would spill from 512 on).
 static bool wide_ok(int prec, int Mp, int D)
 {
-    const int max_nt = prec == LAM_FP8_E4M3 ? 2 : 4;
+    const int max_nt = prec == LAM_FP8_E4M3 ? 1 : 4;
     return prec != LAM_FP32 && D % 256 == 0 && D / 256 <= max_nt && rows_lds(prec, Mp, D, 8, 2) <= kMaxLds;
 }
 
@@ -1323,10 +1341,11 @@ static hipError_t launch_rows(lam_ctx* ctx, const RowsArgs& ra, bool wide, int n
     LAM_ROWS(4, 1, 5, 16) LAM_ROWS(4, 1, 6, 16) LAM_ROWS(4, 1, 7, 16) LAM_ROWS(4, 1, 8, 16)
     LAM_ROWS(4, 1, 1, 32) LAM_ROWS(4, 1, 2, 32) LAM_ROWS(4, 1, 3, 32) LAM_ROWS(4, 1, 4, 32)
     LAM_ROWS(4, 1, 5, 32) LAM_ROWS(4, 1, 6, 32) LAM_ROWS(4, 1, 7, 32) LAM_ROWS(4, 1, 8, 32)
-    if constexpr (P::kBytes == 2) {  // the 64 x 8 shape (wide_ok): BF16 up to 4 D tiles a wave, E4M3 2
-        LAM_ROWS(8, 2, 1, 16) LAM_ROWS(8, 2, 2, 16) LAM_ROWS(8, 2, 1, 32) LAM_ROWS(8, 2, 2, 32)
+    if constexpr (P::kBytes == 2) {  // the 64 x 8 shape (wide_ok): BF16 up to 4 D tiles a wave, E4M3 1
+        LAM_ROWS(8, 2, 1, 16) LAM_ROWS(8, 2, 1, 32)
         if constexpr (!F8) {
-            LAM_ROWS(8, 2, 3, 16) LAM_ROWS(8, 2, 3, 32) LAM_ROWS(8, 2, 4, 16) LAM_ROWS(8, 2, 4, 32)
+            LAM_ROWS(8, 2, 2, 16) LAM_ROWS(8, 2, 2, 32) LAM_ROWS(8, 2, 3, 16) LAM_ROWS(8, 2, 3, 32)
+            LAM_ROWS(8, 2, 4, 16) LAM_ROWS(8, 2, 4, 32)
         }
     }
 #undef LAM_ROWS

@@ -2,8 +2,9 @@
 
 Rounds exactly where the FP8 kernel rounds: BF16 Q and K for the logits, OCP
 E4M3 (3 mantissa bits, bias 7, max 448, subnormals to 2^-9, round to nearest
-even) for V / s^V and for the max-normalised weights times the folded V
-scales; everything else in FP64.  Used to check that the kernel implements the
+even) for V / s^V, and the max-normalised weights times the folded V scales
+as two E4M3 terms (the rounded value plus the rounded residual); everything
+else in FP64.  Used to check that the kernel implements the
 documented quantisation, separately from how far that quantisation is from
 the exact result.
 """
@@ -34,5 +35,7 @@ def fp8_forward(Q, K, V):
     sV = np.abs(np.asarray(V, np.float64)).max(1) / 448.0
     vmax = sV.max()
     V8 = e4m3(np.asarray(V, np.float64) / np.where(sV > 0, sV, 1.0)[:, None])
-    P8 = e4m3(Pt * (sV * 448.0 / vmax)[None, :])
+    q = Pt * (sV * 448.0 / vmax)[None, :]
+    hi = e4m3(q)
+    P8 = hi + e4m3(q - hi)
     return (P8 @ V8) * (vmax / 448.0) / l

@@ -20,13 +20,15 @@ pytestmark = pytest.mark.gpu
 BARS = {"fp32": dict(grad=1e-4, cos=None, F=1e-4), "bf16": dict(grad=1e-2, cos=0.999, F=None),
         "fp8": dict(grad=1e-2, cos=0.999, F=None)}
 
-# FP8 (OCP E4M3, 3 mantissa bits) on F = P V: the mean per-pixel cosine meets
-# 0.999 but the per-pixel minimum and dQ do not (an E4M3 model on the CPU gives
-# the same numbers), and dQ, dV (through the cosine gradient's dependence on F)
-# land at 1-3e-2; those bars are checked in the strict xfail test below.  dK is
-# within the bar except at M = 1, where dS should vanish exactly but the FP8 F
-# and the BF16 backward disagree by the E4M3 rounding of V.
-FP8_MISSES = {"min_cos", "dQ", "dV", "dK"}
+# FP8: V in OCP E4M3 (3 mantissa bits) with a scale per atom, the softmax
+# weights as two E4M3 terms, so F carries V's rounding.  The per-pixel cosine of
+# F meets 0.999 everywhere; dQ meets 1e-2 at the logit spread of rendered query
+# maps (test_fp8_meets_bars_at_rendered_query_scale) but not with the unit
+# Gaussian queries of these shapes, whose sharper softmax puts F close to a few
+# rows of V whose rounding is then not averaged out (1.0-1.9e-2; the strict xfail
+# below).  At M = 1, dS should vanish exactly but the FP8 F and the BF16
+# backward disagree by the E4M3 rounding of V, so dK misses there too.
+FP8_MISSES = {"dQ"}
 
 
 def _inputs(seed, n, d, M, D, qscale=1.0):
@@ -82,14 +84,12 @@ def test_forward_F(prec, shape):
     else:
         c = _cos(F, ref)
         say(f"  cos min {c.min():.6f} p1 {np.percentile(c, 1):.6f} mean {c.mean():.6f}")
+        assert c.min() >= BARS[prec]["cos"]
         if prec == "fp8":
-            assert c.mean() >= BARS[prec]["cos"]
             # the kernel implements the documented E4M3 rounding
             from tests.fp8_model import fp8_forward
             cm = _cos(F, fp8_forward(Q, K, V))
             assert np.percentile(cm, 0.1) >= 1 - 1e-5, cm.min()
-        else:
-            assert c.min() >= BARS[prec]["cos"]
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8"])
@@ -110,28 +110,45 @@ def test_loss_and_grads(prec, shape):
     for name, t in (("dQ", dQ), ("dK", dK), ("dV", dV)):
         e = rel_err(to_np(t), ref[name])
         say(f"  {name} rel err {e:.3e}")
-        if prec == "fp8" and name in FP8_MISSES:
-            assert e < 5 * bar, name  # reported; the bar itself is the xfail test below
+        if prec == "fp8" and (name in FP8_MISSES or (M == 1 and name == "dK")):
+            assert e < 2.5 * bar, name  # reported; the bar itself is the xfail test below
             continue
         assert e < bar, name
 
 
-@pytest.mark.xfail(strict=True, reason="E4M3 has 3 mantissa bits: per-pixel min cosine of F is "
-                   "about 0.9985 and dQ is 1-3e-2 relative (an E4M3 model on the CPU agrees)")
-@pytest.mark.parametrize("shape", [SHAPES[2], SHAPES[5]])
-def test_fp8_meets_min_cosine_and_dQ_bars(shape):
-    n, d, M, D = shape
-    say(f"[decode fp8 bars] n={n} d={d} M={M} D={D}")
-    Q, K, V, T, K0 = _inputs(2, n, d, M, D)
+def _fp8_bars(n, d, M, D, qscale, seed=2):
+    Q, K, V, T, K0 = _inputs(seed, n, d, M, D, qscale=qscale)
     dec = _decoder("fp8", n, d, M, D)
     F = to_np(dec.forward(*_cuda(Q, K, V)))
     loss, dQ, dK, dV = dec.loss_and_grads(*_cuda(Q, K, V, T, K0), 0.1)
     ref = DO.loss_and_grads(Q, K, V, T, K0, 0.1)
     c = _min_cos(F, ref["F"])
-    e = rel_err(to_np(dQ), ref["dQ"])
-    ev = rel_err(to_np(dV), ref["dV"])
-    say(f"  min cos {c:.6f} dQ rel {e:.3e} dV rel {ev:.3e}")
-    assert c >= 0.999 and e < 1e-2 and ev < 1e-2
+    errs = {k: rel_err(to_np(t), ref[k]) for k, t in (("dQ", dQ), ("dK", dK), ("dV", dV))}
+    say(f"  min cos {c:.6f} " + " ".join(f"{k} {v:.3e}" for k, v in errs.items()))
+    assert c >= 0.999
+    for k, v in errs.items():
+        assert v < 1e-2, k
+
+
+@pytest.mark.parametrize("shape", [(4096, 32, 1024, 1024), (3000, 32, 512, 768)])
+def test_fp8_meets_bars_at_rendered_query_scale(shape):
+    """The benchmark spec bars (minimum per-pixel cosine of F >= 0.999, every
+    gradient within 1e-2) for the E4M3 decode at the logit spread of rendered
+    query maps: the queries of the 1200x680 keyframe of the 2M-Gaussian map
+    (a blend of N(0, 1) queries) have a per-component spread of 0.56."""
+    n, d, M, D = shape
+    say(f"[decode fp8 bars, q spread 0.56] n={n} d={d} M={M} D={D}")
+    _fp8_bars(n, d, M, D, qscale=0.56)
+
+
+@pytest.mark.xfail(strict=True, reason="with unit Gaussian queries the softmax is sharper and F sits "
+                   "close to a few rows of V, whose E4M3 rounding (3 mantissa bits) is not averaged out: "
+                   "dQ reaches 1.0-1.6e-2 (the cosine and dK, dV still meet their bars)")
+@pytest.mark.parametrize("shape", [SHAPES[2], SHAPES[5]])
+def test_fp8_meets_bars_with_unit_queries(shape):
+    n, d, M, D = shape
+    say(f"[decode fp8 bars, unit queries] n={n} d={d} M={M} D={D}")
+    _fp8_bars(n, d, M, D, qscale=1.0)
 
 
 # 64-pixel x 8-wave workgroups (the context option "decode_shape": 1): D = 256 (one D tile
@@ -155,12 +172,12 @@ def test_wide_decode_shape(prec, shape):
     ref = DO.loss_and_grads(Q, K, V, T, K0, 0.1)
     c = _cos(F, ref["F"])
     say(f"  cos min {c.min():.6f} mean {c.mean():.6f}")
-    assert (c.mean() if prec == "fp8" else c.min()) >= 0.999
+    assert c.min() >= 0.999
     assert abs(float(loss) - ref["loss"]) / abs(ref["loss"]) < 1e-2
     for name, t in (("dQ", dQ), ("dK", dK), ("dV", dV)):
         e = rel_err(to_np(t), ref[name])
         say(f"  {name} rel err {e:.3e}")
-        assert e < (5e-2 if prec == "fp8" else 1e-2), name
+        assert e < (2.5e-2 if prec == "fp8" and name == "dQ" else 1e-2), name
     refb = dict(zip(("dQ", "dK", "dV"), DO.decode_backward(Q, K, V, T.astype(np.float64) * 0.01)))
     for name, t in (("dQ", dQb), ("dK", dKb), ("dV", dVb)):
         e = rel_err(to_np(t), refb[name])
@@ -313,9 +330,9 @@ def test_paper_dictionary_size_2000(prec):
     ref = DO.loss_and_grads(Q, K, V, T, K0, 0.1)
     c = _cos(F, ref["F"])
     say(f"  F cos min {c.min():.6f} mean {c.mean():.6f}")
-    assert (c.mean() if prec == "fp8" else c.min()) >= 0.999
+    assert c.min() >= 0.999
     assert abs(float(loss) - ref["loss"]) / abs(ref["loss"]) < 1e-2
     for name, t_ in (("dQ", dQ), ("dK", dK), ("dV", dV)):
         e = rel_err(to_np(t_), ref[name])
         say(f"  {name} rel err {e:.3e}")
-        assert e < (5e-2 if prec == "fp8" else 1e-2), name
+        assert e < (2.5e-2 if prec == "fp8" and name == "dQ" else 1e-2), name

@@ -38,7 +38,13 @@ pytestmark = pytest.mark.gpu
 
 WORKLOADS = [2, 3, 4]
 TILE = (8, 32)
-BARS = {"bf16": dict(cos=5e-3, F=0.999, grad=1e-2), "fp8": dict(cos=2e-2, F=0.999, grad=5e-2)}
+# E4M3 with unit Gaussian queries: F meets the cosine bar, dQ lands at 1-2e-2
+# (the sharper softmax of these inputs; see test_gpu_decode.py, where the bar is
+# met at the query spread of rendered maps), so its gradient bar here is 2.5e-2.
+# The dV identity compares the backward's BF16 P V with the returned E4M3 F, so
+# for E4M3 it measures F's rounding (2.8e-2 here), not dV's error: bar 5e-2.
+BARS = {"bf16": dict(cos=5e-3, F=0.999, grad=1e-2, dv_identity=1e-2),
+        "fp8": dict(cos=2e-2, F=0.999, grad=2.5e-2, dv_identity=5e-2)}
 
 
 def _dev(a):
@@ -167,7 +173,7 @@ def test_decode_full_size(cfg):
         say(f"    sampled rows: max |cos err| {ec:.2e}, F cosine min {cF.min():.6f} mean {cF.mean():.6f}, "
             f"dQ rel err {eq:.3e}")
         assert ec < bar["cos"]
-        assert (cF.min() if prec == "bf16" else cF.mean()) >= bar["F"]
+        assert cF.min() >= bar["F"]
         assert eq < bar["grad"]
         # loss: the same per-row cosines, reduced over all n rows
         lref = float((1.0 - cg.astype(np.float64)).mean() + sp.lambda_tr * ((K.astype(np.float64) - K0) ** 2).sum())
@@ -184,5 +190,5 @@ def test_decode_full_size(cfg):
         say(f"    loss identity {el:.2e}, dK identity {ek:.3e}, dV identity {ev:.3e}")
         assert el < 1e-5
         assert ek < bar["grad"]
-        assert ev < bar["grad"]
+        assert ev < bar["dv_identity"]
         del dec, row_cos, loss, dQ, dK, dV, F, dQn
