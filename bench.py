@@ -7,8 +7,10 @@ and its gradients) + render_backward.  The headline workload is the largest
 single-GPU one: one 1200x680 keyframe of a 2M-Gaussian multi-floor map,
 d = 32, M = D = 1024, decoded in BF16 (the narrowest arithmetic that meets
 the error bar); the E4M3 and FP32 decode paths are timed beside it, and the
-640x480 keyframe (100k Gaussians, d = 16, M = 256, D = 512) is a secondary
-workload.  Inputs are seeded synthetic arrays resident in HBM before timing
+640x480 keyframe (100k Gaussians, d = 16, M = 256, D = 512), the 1200x680
+keyframe of a 300k-Gaussian hall (d = 32, M = 512, D = 768) and the eight
+keyframes of uneven size over a 500k-Gaussian local map (one launch per stage)
+are secondary workloads.  Inputs are seeded synthetic arrays resident in HBM before timing
 starts; the render tile shape and the decode block shape are autotuned.
 
 Prints one JSON line: feature-pixels/s, per-stage times, the roofline of the
@@ -115,7 +117,7 @@ class Workload:
     """One workload on the GPU: scene, dictionary, target, renderer, and the
     step (render forward, decode + loss + gradients, render backward)."""
 
-    def __init__(self, idx, prec, dev, autotune=True, tile="16x16"):
+    def __init__(self, idx, prec, dev, autotune=True, tile="16x16", options=None):
         import torch
 
         from paper_2602_12314_amd import _lib, ops, scenes
@@ -135,7 +137,7 @@ class Workload:
         self.n = sp.n_pixels
         tw, th = (int(v) for v in tile.split("x"))
         self.tune = None
-        self.options = {"decode_shape": "px32", "decode_splits": 0}
+        self.options = dict(options) if options else {"decode_shape": "px32", "decode_splits": 0}
         if autotune:
             from paper_2602_12314_amd import autotune as AT
             t0 = time.perf_counter()
@@ -453,7 +455,8 @@ def run(args):
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     prec = args.precision
-    wl = Workload(args.workload, prec, dev, autotune=not args.no_autotune, tile=args.tile)
+    fixed = json.loads(args.decode_options) if args.decode_options else None
+    wl = Workload(args.workload, prec, dev, autotune=not args.no_autotune, tile=args.tile, options=fixed)
     sp, n = wl.spec, wl.n
 
     dec = wl.decoder(prec)
@@ -525,7 +528,7 @@ def run(args):
         "loss": loss,
         "precision_legs": legs,
         "roofline": dict(kernel=dom, **rl, kernel_ms=ms, algorithmic_bytes=work[dom]["bytes"],
-                         algorithmic_flops=work[dom]["flops"], traffic=traffic_for(dom, sp.name),
+                         algorithmic_flops=work[dom]["flops"], traffic=traffic_for(dom, sp.name, {"tile": wl.tile, **wl.options}),
                          issued=decode_issued(n, sp.d, sp.M, sp.D, prec) if dom.startswith("decode") else None),
         "decode_roofline": dict(**roofline(work["decode_total"], dec_ms, prec), ms=dec_ms,
                                 kernels="decode_rows + decode_tn (+ dK GEMM and reductions not timed)"),
@@ -555,10 +558,14 @@ def run(args):
         w2k = decode_work(wl.n, wl.spec.d, wl.spec.M, wl.spec.D)
         dom2 = max((k for k in p2 if k in w2k), key=lambda k: p2[k])
         sec_wl[wl.spec.name] = {"value": wl.n / g2, "ms_per_step": g2 * 1e3, "eager_ms_per_step": e2 * 1e3,
+                                "views": len(wl.spec.cams), "pixels": wl.n,
+                                "ms_per_keyframe": g2 * 1e3 / len(wl.spec.cams),
                                 "decode_precision": "bf16", "tile": wl.tile, "decode_options": wl.options,
                                 "stage_ms": {k: round(v, 4) for k, v in p2.items()},
                                 "roofline": dict(kernel=dom2, **roofline(w2k[dom2], p2[dom2], "bf16"),
-                                                 kernel_ms=p2[dom2])}
+                                                 kernel_ms=p2[dom2],
+                                                 traffic=traffic_for(dom2, wl.spec.name,
+                                                                     {"tile": wl.tile, **wl.options}))}
         del d2
     out["secondary_workloads"] = sec_wl
     print(json.dumps(out), flush=True)
@@ -719,9 +726,10 @@ def kmeans_leg(ops, prec, spec, tgt, dev, ctx, reps=3, iters=10):
                        "traffic": traffic_for("kmeans_assign", spec.name)}}
 
 
-def traffic_for(kernel, workload):
+def traffic_for(kernel, workload, options=None):
     """HBM bytes per launch from the committed rocprofv3 --pmc summary, if it
-    was taken on the current sources of that kernel; otherwise null."""
+    was taken on the current sources of that kernel and, where the summary
+    records them, with the same launch options; otherwise null."""
     from paper_2602_12314_amd import profiling
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
@@ -732,6 +740,8 @@ def traffic_for(kernel, workload):
     if not ent or kernel not in profiling.STAGES:
         return None
     if ent.get("source_hash") != profiling.source_hash(profiling.STAGES[kernel][1]):
+        return None
+    if options is not None and ent.get("options") is not None and ent["options"] != options:
         return None
     return ent.get("bytes_per_launch")
 
@@ -745,9 +755,14 @@ def main():
                     help="0..4 (default 4: the 1200x680 keyframe of the 2M-Gaussian map)")
     ap.add_argument("--precision", default="bf16", help="headline decode precision: bf16 | fp8 | fp32")
     ap.add_argument("--skip-precisions", default="", help="comma list of precision legs to skip (fp8, fp32)")
-    ap.add_argument("--secondary", default="1", help="comma list of further workloads timed in BF16")
+    ap.add_argument("--secondary", default="1,2,3",
+                    help="comma list of further workloads timed in BF16 (default: the 640x480 keyframe, the "
+                         "1200x680 keyframe of the 300k-Gaussian hall, the eight keyframes of the local map)")
     ap.add_argument("--tile", default="16x16", help="render tile shape when not autotuned")
     ap.add_argument("--no-autotune", action="store_true", help="fixed tile and decode block shape")
+    ap.add_argument("--decode-options", default=None, metavar="JSON",
+                    help="decode launch options when not autotuned, e.g. "
+                         "'{\"decode_shape\": \"px64\", \"decode_splits\": 0}' (default px32, no split)")
     ap.add_argument("--no-oracle", action="store_true", help="skip the FP64 oracle check and CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--eager", action="store_true",

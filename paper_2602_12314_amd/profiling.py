@@ -12,6 +12,7 @@
 
     python -m paper_2602_12314_amd.profiling traffic --workload NAME \\
             --fetch DIR --write DIR --copy-fetch DIR --copy-write DIR --copy-bytes N [--only STAGES]
+            [--largest-grid] [--options JSON]
         HBM bytes per launch of each kernel from two ``--pmc FETCH_SIZE`` /
         ``--pmc WRITE_SIZE`` runs, each counter scaled by what it reads for a
         plain device copy of N bytes (``bench.py --copy-calibration N`` under the
@@ -128,6 +129,9 @@ def main(argv=None):
     t.add_argument("--only", default=None, help="comma-separated stage names to record (default: all found)")
     t.add_argument("--largest-grid", action="store_true",
                    help="average only the dispatches of each kernel's largest grid")
+    t.add_argument("--options", default=None, metavar="JSON",
+                   help="launch options the counter runs were pinned to (tile, decode shape, "
+                        "split count), recorded beside the figures")
     a = ap.parse_args(argv)
     if a.cmd == "stats" and a.by_grid:
         rows = kernel_stats_by_grid(a.dir)
@@ -181,6 +185,8 @@ def main(argv=None):
                           "fetch_factor": ff, "write_factor": fw,
                           "bytes_per_launch": fetch[k] * 1024 * ff + write[k] * 1024 * fw,
                           "source_hash": source_hash(files)}
+            if a.options:
+                ent[stage]["options"] = json.loads(a.options)
         with open(a.json, "w") as fh:
             json.dump(rec, fh, indent=1, sort_keys=True)
             fh.write("\n")
