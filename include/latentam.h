@@ -158,7 +158,7 @@ lam_status lam_ctx_get(const lam_ctx* ctx, const char* key, int* value);
  * {64, 128, 256}, both powers of two) and room for ``instance_capacity``
  * (Gaussian, tile) pairs.  Host-only, never blocks.
  * Errors: LAM_ERR_INVALID_ARG (null out, bad camera rows), LAM_ERR_UNSUPPORTED
- * (tile shape, d, more than 2^31 Gaussian-camera records). */
+ * (tile shape, d, 2^30 or more Gaussian-camera records or pairs of capacity). */
 lam_status lam_render_workspace_size(const lam_ctx* ctx, int n_gauss, int d, const float* cams, int n_cams,
                                      int tile_w, int tile_h, uint64_t instance_capacity,
                                      uint64_t* bytes);
@@ -256,13 +256,15 @@ lam_status lam_rgbd_l1_loss(lam_ctx* ctx, const float* rgb, const float* rgb_obs
 
 /* BLOCKING: waits for ``stream`` and reads the counters of the last forward
  * call on ``ws``: the number of (Gaussian, tile) pairs it needed and whether
- * it exceeded the capacity (then returns LAM_ERR_CAPACITY). */
+ * it exceeded the capacity (then returns LAM_ERR_CAPACITY).  Returns
+ * LAM_ERR_HIP if one of the sorts' bounded waits for an earlier tile's counts
+ * ran out (not expected; the binning of that call is then not valid). */
 lam_status lam_render_counters(lam_ctx* ctx, const void* ws, void* stream, uint64_t* instances_needed,
                                int* overflowed);
 
 /* Debug / verification view of the workspace of the last forward call: device
  * pointers to its sorted tile keys and record ids ([count] uint32 each),
- * per-tile [start, end) ranges ([tiles, 2] uint32), per-record depth keys
+ * per-tile [start, end) ranges ([tiles, 2] uint32, (0, 0) for an empty tile), per-record depth keys
  * ([n_cams*N] uint32, 0xFFFFFFFF when culled), per-record footprints
  * ([n_cams*N, 2] uint32: x0 | x1 << 16, y0 | y1 << 16) and per-pixel
  * contributor counts ([P] uint32).  Any output pointer may be NULL.
@@ -420,7 +422,7 @@ lam_status lam_decode_tied_loss(lam_ctx* ctx, int precision, const float* Q, int
  * depend on the launch schedule.
  *
  * Shapes: D a multiple of 32 in [32, 2048] (FP32: up to 1024), 1 <= k <=
- * 65536.  Row arrays (points, centres) are float32 row-major and 16-byte
+ * 65536, fewer than 2^30 points.  Row arrays (points, centres) are float32 row-major and 16-byte
  * aligned.  Otherwise LAM_ERR_UNSUPPORTED (shape) or LAM_ERR_INVALID_ARG. */
 
 /* Workspace bytes for lam_kmeans_assign / lam_kmeans_lloyd with up to n

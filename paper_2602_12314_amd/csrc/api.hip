@@ -78,7 +78,7 @@ lam_status render_layout(int n_gauss, int d, const float* cams, int n_cams, int 
     lam_status s = make_camset(cams, n_cams, tile_w, tile_h, &L->cams, &pixels);
     if (s != LAM_OK) return s;
     const uint64_t R = (uint64_t)n_cams * (uint64_t)n_gauss;
-    if (R >= (1ull << 31) || capacity >= (1ull << 31)) return LAM_ERR_UNSUPPORTED;
+    if (R >= (1ull << 30) || capacity >= (1ull << 30)) return LAM_ERR_UNSUPPORTED;
     L->records = R;
     L->capacity = capacity;
     L->pixels = pixels;
@@ -86,9 +86,9 @@ lam_status render_layout(int n_gauss, int d, const float* cams, int n_cams, int 
     L->tile_bits = tb;
     L->tile_in_b = radix_passes(tb, (uint32_t)capacity) % 2 == 1;
     if (capacity == 0) L->tile_in_b = false;
-    size_t scratch_words = std::max(radix_scratch_words((uint32_t)R),
-                                    radix_scratch_words((uint32_t)capacity));
-    scratch_words = std::max(scratch_words, scan_scratch_words((uint32_t)R));
+    const size_t depth_words = radix_scratch_words(32, (uint32_t)R);
+    const size_t scan_words = scan_scratch_words((uint32_t)R);
+    const size_t tile_words = radix_scratch_words(tb, (uint32_t)capacity);
     char* p = (char*)base;
     uint64_t off = 0;
     auto take = [&](uint64_t bytes) {
@@ -97,6 +97,10 @@ lam_status render_layout(int n_gauss, int d, const float* cams, int n_cams, int 
         return q;
     };
     L->counters = (uint32_t*)take(64);
+    L->sort_scratch = (uint32_t*)take(depth_words * 4);
+    L->scan_scratch = (uint32_t*)take(scan_words * 4);
+    L->tile_scratch = (uint32_t*)take(tile_words * 4);
+    L->zero_end = p ? (uint32_t*)(p + off) : nullptr;
     L->rec0 = (float4*)take(R * 16);
     L->rec1 = (float4*)take(R * 16);
     L->foot = (uint2*)take(R * 8);
@@ -107,7 +111,6 @@ lam_status render_layout(int n_gauss, int d, const float* cams, int n_cams, int 
     L->recs_b = (uint32_t*)take(R * 4);
     L->ntiles = (uint32_t*)take(R * 4);
     L->offsets = (uint32_t*)take(R * 4);
-    L->sort_scratch = (uint32_t*)take(scratch_words * 4);
     L->ikeys_a = (uint32_t*)take(capacity * 4);
     L->ikeys_b = (uint32_t*)take(capacity * 4);
     L->ivals_a = (uint32_t*)take(capacity * 4);
@@ -319,12 +322,13 @@ lam_status lam_render_counters(lam_ctx* ctx, const void* ws, void* stream, uint6
                                int* overflowed)
 {
     if (!ctx_ok(ctx) || !ws || !instances_needed || !overflowed) return LAM_ERR_INVALID_ARG;
-    uint32_t c[2] = {0, 0};
+    uint32_t c[5] = {0, 0, 0, 0, 0};
     if (hipMemcpyAsync(c, ws, sizeof(c), hipMemcpyDeviceToHost, (hipStream_t)stream) != hipSuccess)
         return LAM_ERR_HIP;
     if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return LAM_ERR_HIP;
     *instances_needed = c[0];
     *overflowed = (int)c[1];
+    if (c[4]) return LAM_ERR_HIP;  // a sort wait outlived its bound: the binning is not valid
     return c[1] ? LAM_ERR_CAPACITY : LAM_OK;
 }
 

@@ -72,15 +72,20 @@ int ctx_resident_blocks(lam_ctx* ctx, const void* kernel, int threads);
 hipError_t ctx_ensure_lds(lam_ctx* ctx, const void* kernel, size_t bytes);
 
 // ------------------------------------------------------------- sort / scan
+// The scratch of a scan or a sort must be zero when it starts: the caller
+// clears it (one fill may cover several scratch regions) or passes
+// zero_scratch.  A look-back wait that outlives its bound (never expected)
+// sets *err (a word of the scratch when err is null) and the result is wrong.
 size_t scan_scratch_words(uint32_t n);
-size_t radix_scratch_words(uint32_t n_cap);
+size_t radix_scratch_words(int bits, uint32_t n_cap);  // n_cap below 2^30
 int radix_passes(int bits, uint32_t n_cap);  // passes launch_radix_sort makes for ``bits`` key bits
 hipError_t launch_excl_scan(const uint32_t* in, const uint32_t* idx, uint32_t n, uint32_t* out,
-                            uint32_t* total, uint32_t* scratch, hipStream_t st);
+                            uint32_t* total, uint32_t* over, uint32_t cap, uint32_t* scratch,
+                            bool zero_scratch, uint32_t* err, hipStream_t st);
 hipError_t launch_radix_sort(const uint32_t* keys_first, uint32_t* keys_a, uint32_t* vals_a,
                              uint32_t* keys_b, uint32_t* vals_b, bool iota_first,
                              const uint32_t* n_dev, uint32_t n_cap, int bits, uint32_t* scratch,
-                             bool* in_b, hipStream_t st);
+                             bool zero_scratch, uint32_t* err, bool* in_b, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t st);
 
 // ------------------------------------------------------------- profiling
@@ -117,7 +122,9 @@ struct RenderLayout {
     uint64_t records, capacity, pixels, bytes;
     int tile_bits;
     bool tile_in_b;  // where the sorted (tile, record) pairs end up
-    uint32_t* counters;  // [0] pairs needed, [1] overflow flag
+    // [0] pairs needed, [1] overflow flag, [2] / [3] work counters of the
+    // persistent compositing forward / backward, [4] sort wait error
+    uint32_t* counters;
     float4* rec0;
     float4* rec1;
     uint2* foot;
@@ -125,7 +132,9 @@ struct RenderLayout {
     uint32_t *depth_a, *depth_b, *recs_a, *recs_b;
     uint32_t* ntiles;
     uint32_t* offsets;
-    uint32_t* sort_scratch;
+    // look-back scratch of the depth sort, the pair-count scan and the tile
+    // sort, right after the counters: one fill clears [counters, zero_end)
+    uint32_t *sort_scratch, *scan_scratch, *tile_scratch, *zero_end;
     uint32_t *ikeys_a, *ikeys_b, *ivals_a, *ivals_b;
     uint2* ranges;
     uint32_t* n_contrib;

@@ -514,6 +514,14 @@ static int tile_points(int prec, int D)
 
 static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+// Key bits of the sort by centre index.
+static int kmeans_key_bits(int k)
+{
+    int bits = 1;
+    while ((1 << bits) < k) ++bits;
+    return bits;
+}
+
 bool kmeans_shape_ok(int prec, int D, int k)
 {
     if (prec != LAM_FP32 && prec != LAM_BF16) return false;
@@ -541,7 +549,7 @@ KmLayout kmeans_layout(int prec, int npts, int D, int k)
     L.off_va = take(np * 4);
     L.off_kb = take(np * 4);
     L.off_vb = take(np * 4);
-    L.off_sort = take(radix_scratch_words((uint32_t)np) * 4);
+    L.off_sort = take(radix_scratch_words(kmeans_key_bits(k), (uint32_t)np) * 4);
     L.off_start = take((size_t)k * 4);
     L.off_end = take((size_t)k * 4);
     L.off_head = take(std::max<size_t>(nchunks, 1) * D * 4);
@@ -659,10 +667,9 @@ static hipError_t kmeans_update(const float* X, const float* w, int n, int D, in
     const uint32_t* skeys = a;
     const uint32_t* sidx = nullptr;
     if (n > 0) {
-        int bits = 1;
-        while ((1 << bits) < k) ++bits;
         bool in_b = false;
-        e = launch_radix_sort(a, ka, va, kb, vb, true, ndev, (uint32_t)n, bits, scratch, &in_b, st);
+        e = launch_radix_sort(a, ka, va, kb, vb, true, ndev, (uint32_t)n, kmeans_key_bits(k), scratch, true,
+                              nullptr, &in_b, st);
         if (e != hipSuccess) return e;
         skeys = in_b ? kb : ka;
         sidx = in_b ? vb : va;
@@ -783,7 +790,7 @@ extern "C" {
 lam_status lam_kmeans_workspace_size(const lam_ctx* ctx, int precision, int n, int D, int k, uint64_t* bytes)
 {
     if (!bytes || n < 0) return LAM_ERR_INVALID_ARG;
-    if (!kmeans_shape_ok(precision, D, k)) return LAM_ERR_UNSUPPORTED;
+    if (!kmeans_shape_ok(precision, D, k) || n >= (1 << 30)) return LAM_ERR_UNSUPPORTED;
     *bytes = kmeans_layout(precision, n, D, k).bytes;
     return LAM_OK;
 }
@@ -792,7 +799,7 @@ lam_status lam_kmeans_assign(lam_ctx* ctx, int precision, const float* X, int n,
                              float* d2, void* ws, uint64_t ws_bytes, void* stream)
 {
     if (!ctx_ok(ctx) || n < 0) return LAM_ERR_INVALID_ARG;
-    if (!kmeans_shape_ok(precision, D, k)) return LAM_ERR_UNSUPPORTED;
+    if (!kmeans_shape_ok(precision, D, k) || n >= (1 << 30)) return LAM_ERR_UNSUPPORTED;
     const KmLayout L = kmeans_layout(precision, n, D, k);
     if (!ws || ws_bytes < L.bytes || !C || (n > 0 && (!X || !assign))) return LAM_ERR_INVALID_ARG;
     if (!km_aligned(X) || !km_aligned(C)) return LAM_ERR_INVALID_ARG;
@@ -807,7 +814,7 @@ lam_status lam_kmeans_lloyd(lam_ctx* ctx, int precision, const float* X, const f
                             void* stream)
 {
     if (!ctx_ok(ctx) || n < 0 || iters < 1) return LAM_ERR_INVALID_ARG;
-    if (!kmeans_shape_ok(precision, D, k)) return LAM_ERR_UNSUPPORTED;
+    if (!kmeans_shape_ok(precision, D, k) || n >= (1 << 30)) return LAM_ERR_UNSUPPORTED;
     const KmLayout L = kmeans_layout(precision, n, D, k);
     if (!ws || ws_bytes < L.bytes || !C0 || !C || (n > 0 && !X)) return LAM_ERR_INVALID_ARG;
     if (!km_aligned(X) || !km_aligned(C0) || !km_aligned(C)) return LAM_ERR_INVALID_ARG;
@@ -820,7 +827,7 @@ lam_status lam_kmeans_lloyd(lam_ctx* ctx, int precision, const float* X, const f
 lam_status lam_stream_kmeans_workspace_size(const lam_ctx* ctx, int precision, int n, int D, int Kp, int K, int m, uint64_t* bytes)
 {
     if (!bytes || n < 0 || Kp < 0 || m < 0 || m > n || Kp > K || m < K - Kp) return LAM_ERR_INVALID_ARG;
-    if (!kmeans_shape_ok(precision, D, std::max(std::max(m, K), 1)) || (size_t)Kp + m > (size_t)1 << 30)
+    if (!kmeans_shape_ok(precision, D, std::max(std::max(m, K), 1)) || (size_t)Kp + m >= (size_t)1 << 30)
         return LAM_ERR_UNSUPPORTED;
     *bytes = stream_kmeans_layout(precision, n, D, Kp, K, m).bytes;
     return LAM_OK;

@@ -134,10 +134,15 @@ __global__ __launch_bounds__(256) void k_preprocess(
 }
 
 // One thread per emitted (tile id, record) pair, so Gaussians covering many
-// tiles do not serialise one thread: pair o belongs to the depth-sorted record
-// s with offsets[s] <= o < offsets[s + 1] (binary search; records emitting
-// nothing share their successor's offset and are never found), and is that
-// record's (o - offsets[s])-th tile of its footprint, rows outer.
+// tiles do not serialise one thread.  Pair o belongs to the depth-sorted
+// record s with offsets[s] <= o < offsets[s + 1], and is that record's
+// (o - offsets[s])-th tile of its footprint, rows outer.  A workgroup takes
+// 256 consecutive pairs: every visible record emits at least one pair and
+// culled records (key 0xFFFFFFFF) sort last, so those pairs belong to a run
+// of at most 256 consecutive records.  The run's first record is found by
+// rounds of 256 probes, each narrowing the range 256-fold (three rounds for
+// up to 2^24 records instead of one dependent load per halving), the run's
+// offsets are staged in LDS, and each thread finds its record there.
 __global__ __launch_bounds__(256) void k_emit(CamSet cs, int N, uint32_t R,
                                              const uint32_t* __restrict__ sorted_rec,
                                              const uint32_t* __restrict__ offsets,
@@ -146,36 +151,50 @@ __global__ __launch_bounds__(256) void k_emit(CamSet cs, int N, uint32_t R,
                                              uint32_t* __restrict__ keys,
                                              uint32_t* __restrict__ vals)
 {
+    __shared__ uint32_t run[257];
     const uint32_t total = counters[0] < cap ? counters[0] : cap;
-    for (uint32_t o = blockIdx.x * blockDim.x + threadIdx.x; o < total;
-         o += gridDim.x * blockDim.x) {
-        uint32_t lo = 0, hi = R;  // first s with offsets[s] > o is in (lo, hi]
+    for (uint32_t o0 = blockIdx.x * 256u; o0 < total; o0 += gridDim.x * 256u) {
+        // largest s in [lo, hi) with offsets[s] <= o0 (offsets[0] = 0 <= o0)
+        uint32_t lo = 0, hi = R;
         while (hi - lo > 1) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (offsets[mid] <= o) lo = mid;
-            else hi = mid;
+            const uint32_t stride = (hi - lo + 255) / 256;
+            const uint32_t idx = lo + threadIdx.x * stride;
+            const int le = idx < hi && offsets[idx] <= o0;
+            const uint32_t k = (uint32_t)__syncthreads_count(le);  // a prefix of the probes
+            const uint32_t nlo = lo + (k - 1) * stride;
+            hi = nlo + stride < hi ? nlo + stride : hi;
+            lo = nlo;
         }
-        const uint32_t s = lo;
-        const uint32_t r = sorted_rec[s];
-        const int c = (int)(r / (uint32_t)N);
-        int tbase = 0, tx_n = 1;
-        for (int k = 0; k < cs.n; ++k)
-            if (k == c) { tbase = cs.c[k].tile_base; tx_n = cs.c[k].tiles_x; }
-        const uint2 f = foot[r];
-        const int x0 = (f.x & 0xFFFF) >> cs.tile_shift_x, x1 = (f.x >> 16) >> cs.tile_shift_x;
-        const int y0 = (f.y & 0xFFFF) >> cs.tile_shift_y;
-        const int nx = x1 - x0 + 1;
-        const int k = (int)(o - offsets[s]);
-        const int ty = y0 + k / nx, tx = x0 + k % nx;
-        keys[o] = (uint32_t)(tbase + ty * tx_n + tx);
-        vals[o] = r;
+        const uint32_t s0 = lo;
+        const uint32_t si = s0 + threadIdx.x;
+        run[threadIdx.x] = si < R ? offsets[si] : 0xFFFFFFFFu;
+        if (threadIdx.x == 0) run[256] = s0 + 256 < R ? offsets[s0 + 256] : 0xFFFFFFFFu;
+        __syncthreads();
+        const uint32_t o = o0 + threadIdx.x;
+        if (o < total) {
+            uint32_t a = 0, b = 257;  // largest j with run[j] <= o; run[0] <= o
+            while (b - a > 1) {
+                const uint32_t m = (a + b) >> 1;
+                if (run[m] <= o) a = m;
+                else b = m;
+            }
+            const uint32_t s = s0 + a;
+            const uint32_t r = sorted_rec[s];
+            const int c = (int)(r / (uint32_t)N);
+            int tbase = 0, tx_n = 1;
+            for (int k = 0; k < cs.n; ++k)
+                if (k == c) { tbase = cs.c[k].tile_base; tx_n = cs.c[k].tiles_x; }
+            const uint2 f = foot[r];
+            const int x0 = (f.x & 0xFFFF) >> cs.tile_shift_x, x1 = (f.x >> 16) >> cs.tile_shift_x;
+            const int y0 = (f.y & 0xFFFF) >> cs.tile_shift_y;
+            const int nx = x1 - x0 + 1;
+            const int k = (int)(o - run[a]);
+            const int ty = y0 + k / nx, tx = x0 + k % nx;
+            keys[o] = (uint32_t)(tbase + ty * tx_n + tx);
+            vals[o] = r;
+        }
+        __syncthreads();  // run[] is rewritten by the next chunk
     }
-}
-
-// counters[0] = pairs needed, counters[1] = 1 if they exceed the capacity.
-__global__ void k_check_capacity(uint32_t* counters, uint32_t cap)
-{
-    counters[1] = counters[0] > cap ? 1u : 0u;
 }
 
 __global__ __launch_bounds__(256) void k_fill_u32(uint32_t* p, size_t n, uint32_t v)
@@ -185,15 +204,22 @@ __global__ __launch_bounds__(256) void k_fill_u32(uint32_t* p, size_t n, uint32_
         p[i] = v;
 }
 
+// [start, end) of every tile's list in the tile-sorted pairs, empty tiles
+// included, with no fill first: boundary i (0 <= i <= n) looks at the keys on
+// both sides and, where they differ, ends the tile before, starts the tile
+// after and gives every tile id strictly between them the empty range (0, 0).
 __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ keys,
                                                const uint32_t* __restrict__ counters, uint32_t cap,
-                                               uint2* __restrict__ ranges)
+                                               uint32_t tiles, uint2* __restrict__ ranges)
 {
-    uint32_t n = counters[0] < cap ? counters[0] : cap;
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        const uint32_t t = keys[i];
-        if (i == 0 || keys[i - 1] != t) ranges[t].x = i;
-        if (i + 1 == n || keys[i + 1] != t) ranges[t].y = i + 1;
+    const uint32_t n = counters[0] < cap ? counters[0] : cap;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i <= n; i += gridDim.x * blockDim.x) {
+        const uint32_t a = i > 0 ? keys[i - 1] : 0u;
+        const uint32_t b = i < n ? keys[i] : tiles;
+        if (i > 0 && i < n && a == b) continue;
+        if (i > 0 && a < tiles) ranges[a].y = i;
+        for (uint32_t t = i > 0 ? a + 1 : 0u; t < b && t < tiles; ++t) ranges[t] = make_uint2(0u, 0u);
+        if (i < n && b < tiles) ranges[b].x = i;
     }
 }
 
@@ -792,7 +818,9 @@ hipError_t render_forward_launch(lam_ctx* ctx, const RenderArgs& A, const Render
     const CamSet& cs = L.cams;
     const uint32_t R = (uint32_t)L.records;
     const uint32_t cap = (uint32_t)L.capacity;
-    hipError_t e;
+    // counters and every look-back scratch of the sorts start at zero
+    hipError_t e = launch_fill_u32(L.counters, (size_t)(L.zero_end - L.counters), 0u, st);
+    if (e != hipSuccess) return e;
     if (A.n > 0) {
         ProfScope ps(ctx, "preprocess", st);
         hipLaunchKernelGGL(k_preprocess, dim3((A.n + 255) / 256, cs.n), dim3(256), 0, st, cs, A.n,
@@ -805,28 +833,29 @@ hipError_t render_forward_launch(lam_ctx* ctx, const RenderArgs& A, const Render
     {
         ProfScope ps(ctx, "render_sort", st);
         e = launch_radix_sort(L.depth_key, L.depth_a, L.recs_a, L.depth_b, L.recs_b, true, nullptr,
-                              R, 32, L.sort_scratch, &in_b, st);
+                              R, 32, L.sort_scratch, false, L.counters + 4, &in_b, st);
         if (e != hipSuccess) return e;
         const uint32_t* sorted_rec = in_b ? L.recs_b : L.recs_a;
-        e = launch_excl_scan(L.ntiles, sorted_rec, R, L.offsets, L.counters, L.sort_scratch, st);
+        // pair offsets of the depth-ordered records; the last tile of the scan
+        // writes the pairs needed and the overflow flag
+        e = launch_excl_scan(L.ntiles, sorted_rec, R, L.offsets, L.counters, L.counters + 1, cap,
+                             L.scan_scratch, false, L.counters + 4, st);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_check_capacity, dim3(1), dim3(1), 0, st, L.counters, cap);
         if (R > 0 && cap > 0)
             hipLaunchKernelGGL(k_emit, dim3(std::min<uint32_t>((cap + 255) / 256, 8192u)), dim3(256),
                                0, st, cs, A.n, R, sorted_rec, (const uint32_t*)L.offsets,
                                (const uint2*)L.foot, (const uint32_t*)L.counters, cap, L.ikeys_a,
                                L.ivals_a);
         e = launch_radix_sort(nullptr, L.ikeys_a, L.ivals_a, L.ikeys_b, L.ivals_b, false,
-                              L.counters, cap, L.tile_bits, L.sort_scratch, &in_b, st);
+                              L.counters, cap, L.tile_bits, L.tile_scratch, false, L.counters + 4, &in_b,
+                              st);
         if (e != hipSuccess) return e;
         tkeys = in_b ? L.ikeys_b : L.ikeys_a;
         trecs = in_b ? L.ivals_b : L.ivals_a;
-        e = launch_fill_u32(reinterpret_cast<uint32_t*>(L.ranges), 2 * (size_t)cs.total_tiles, 0u,
-                            st);
-        if (e != hipSuccess) return e;
-        if (cap > 0)
-            hipLaunchKernelGGL(k_ranges, dim3(std::min<uint32_t>((cap + 255) / 256, 8192u)),
-                               dim3(256), 0, st, tkeys, (const uint32_t*)L.counters, cap, L.ranges);
+        if (cs.total_tiles > 0)
+            hipLaunchKernelGGL(k_ranges, dim3(std::min<uint32_t>(cap / 256 + 1, 8192u)), dim3(256), 0, st,
+                               tkeys, (const uint32_t*)L.counters, cap, (uint32_t)cs.total_tiles,
+                               L.ranges);
     }
     if (cs.total_tiles > 0) {
         const bool pers = use_persistent(ctx, cs);
@@ -837,11 +866,8 @@ hipError_t render_forward_launch(lam_ctx* ctx, const RenderArgs& A, const Render
                          : (A.d == 16 ? (pers ? k_raster_fwd<16, true, false> : k_raster_fwd<16, false, false>)
                                       : (pers ? k_raster_fwd<32, true, false> : k_raster_fwd<32, false, false>));
         int grid = cs.total_tiles;
-        if (pers) {
-            e = launch_fill_u32(L.counters + 2, 1, 0u, st);
-            if (e != hipSuccess) return e;
+        if (pers)  // its work counter, counters[2], was cleared with the sort scratch
             grid = std::min(grid, ctx_resident_blocks(ctx, (const void*)kern, threads));
-        }
         ProfScope ps(ctx, "raster_fwd", st);
         hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), 0, st, cs, A.n, (const uint2*)L.ranges,
                            trecs, (const float4*)L.rec0, (const float4*)L.rec1, (const uint2*)L.foot,
