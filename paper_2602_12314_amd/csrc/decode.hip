@@ -983,7 +983,7 @@ __global__ __launch_bounds__(256) void k_dec_tn(const void* At_, int rowsA, cons
 // suffices (a wave can write slot b + 1 while a slower one still reads slot b,
 // and cannot reach slot b + 2 before that wave has passed the barrier of b + 1).
 template <class P, int DQ, int QT>
-__global__ __launch_bounds__(256) void k_dec_dv(const float* __restrict__ Q, int n, const void* Kb_, int M,
+__global__ __launch_bounds__(256, P::kBytes == 2 ? 2 : 1) void k_dec_dv(const float* __restrict__ Q, int n, const void* Kb_, int M,
                                                 const float* __restrict__ m2, float scale_log2, const void* Gt_,
                                                 int Mp, int D, int nblocks, int splits, int tiles_i, int tiles_j,
                                                 float* __restrict__ part)
@@ -1020,24 +1020,32 @@ __global__ __launch_bounds__(256) void k_dec_dv(const float* __restrict__ Q, int
 #pragma unroll
         for (int q = 0; q < QT; ++q) acc[t][q] = f32x16{};
 
-    // one block's operands: Q rows of pixel col (zero past n), the row max of
-    // the lane's 16 pixels, and the G^T fragments of this wave's columns
+    // one block's operands, requested a block ahead: the Q fragments of pixel
+    // col (converted when their loads land; zero past n), the row max of pixel
+    // col (the lane's 16 pixels take theirs by lane shuffles when used), and
+    // the G^T fragments of this wave's columns.  Holding the converted
+    // fragments and one row max per lane instead of the float rows and 16 row
+    // maxima keeps the kernel within two waves per SIMD.
     struct Blk {
-        float4 q[NQ][2];
-        float4 m[4];
+        Frag q[NQ];
+        float m;
         Frag g[QT][2];
     };
     auto load = [&](int blk, Blk& B) {
         const int px = blk * kPx + col;
-        const float* qrow = Q + (size_t)(px < n ? px : n - 1) * DQ;
+        const bool valid = px < n;
+        const float* qrow = Q + (size_t)(valid ? px : n - 1) * DQ;
 #pragma unroll
         for (int c = 0; c < NQ; ++c) {
-            B.q[c][0] = *reinterpret_cast<const float4*>(qrow + 16 * c + 8 * h);
-            B.q[c][1] = *reinterpret_cast<const float4*>(qrow + 16 * c + 8 * h + 4);
-        }
+            const float4 x0 = *reinterpret_cast<const float4*>(qrow + 16 * c + 8 * h);
+            const float4 x1 = *reinterpret_cast<const float4*>(qrow + 16 * c + 8 * h + 4);
+            const float v[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
+            float z[8];
 #pragma unroll
-        for (int g4 = 0; g4 < 4; ++g4)
-            B.m[g4] = *reinterpret_cast<const float4*>(m2 + (size_t)blk * kPx + 8 * g4 + 4 * h);
+            for (int e = 0; e < 8; ++e) z[e] = valid ? v[e] : 0.0f;
+            B.q[c] = P::from_f32(z);
+        }
+        B.m = m2[(size_t)blk * kPx + col];
 #pragma unroll
         for (int q = 0; q < QT; ++q)
 #pragma unroll
@@ -1047,25 +1055,15 @@ __global__ __launch_bounds__(256) void k_dec_dv(const float* __restrict__ Q, int
     auto compute = [&](int blk, const Blk& B) {
         const int slot = blk & 1;
         {
-            const bool valid = blk * kPx + col < n;
-            Frag qf[NQ];
-#pragma unroll
-            for (int c = 0; c < NQ; ++c) {
-                const float v[8] = {B.q[c][0].x, B.q[c][0].y, B.q[c][0].z, B.q[c][0].w,
-                                    B.q[c][1].x, B.q[c][1].y, B.q[c][1].z, B.q[c][1].w};
-                float z[8];
-#pragma unroll
-                for (int e = 0; e < 8; ++e) z[e] = valid ? v[e] : 0.0f;
-                qf[c] = P::from_f32(z);
-            }
-            const float mr[16] = {B.m[0].x, B.m[0].y, B.m[0].z, B.m[0].w, B.m[1].x, B.m[1].y, B.m[1].z, B.m[1].w,
-                                  B.m[2].x, B.m[2].y, B.m[2].z, B.m[2].w, B.m[3].x, B.m[3].y, B.m[3].z, B.m[3].w};
             f32x16 sacc = {};
 #pragma unroll
-            for (int c = 0; c < NQ; ++c) P::mma(sacc, qf[c], kf[c]);
+            for (int c = 0; c < NQ; ++c) P::mma(sacc, B.q[c], kf[c]);
             float p[16];
 #pragma unroll
-            for (int r = 0; r < 16; ++r) p[r] = atom_ok ? exp2_weight(sacc[r] * scale_log2 - mr[r]) : 0.0f;
+            for (int r = 0; r < 16; ++r) {
+                const float mr = __shfl(B.m, crow(r, h), kWave);  // row max of the pixel in row crow(r, h)
+                p[r] = atom_ok ? exp2_weight(sacc[r] * scale_log2 - mr) : 0.0f;
+            }
 #pragma unroll
             for (int k = 0; k < 2; ++k)
                 *reinterpret_cast<Frag*>(&pf[slot][w][k][lane * 8]) = P::from_f32(p + 8 * k);
