@@ -30,6 +30,10 @@ def lib():
         vp, i32, i64 = C.c_void_p, C.c_int, C.c_int64
         _lib.orc_project.restype = i64
         _lib.orc_project.argtypes = [i32, vp, vp, vp, vp, i32, vp] + [vp] * 8
+        _lib.orc_project_decisions64.restype = i64
+        _lib.orc_project_decisions64.argtypes = [i32, vp, vp, vp, vp, i32, vp] + [vp] * 5
+        _lib.orc_exp_cw.restype = None
+        _lib.orc_exp_cw.argtypes = [i64, vp, vp]
         _lib.orc_bin.restype = i64
         _lib.orc_bin.argtypes = [i32, vp, vp, vp, vp, i32, vp, i32, i32, i64, vp, vp, vp, vp]
         _lib.orc_num_tiles.restype = i64
@@ -104,6 +108,27 @@ def project(g: Gaussians, cams):
                            _ptr(out["z"]))
     out["n_visible"] = int(nv)
     return out
+
+
+def project_decisions64(g: Gaussians, cams):
+    """The projection's integer decisions taken in FP64, their margin (pixels,
+    or depth units for the near plane) and the float32 screen mean."""
+    cams = _c(cams)
+    R = cams.shape[0] * g.n
+    out = dict(rect=np.zeros((R, 4), np.int32), depth_key=np.zeros(R, np.uint32), vis=np.zeros(R, np.uint8),
+               margin=np.zeros(R), uv32=np.zeros((R, 2), np.float32))
+    lib().orc_project_decisions64(g.n, *g.geom_args(), cams.shape[0], _ptr(cams), _ptr(out["rect"]),
+                                  _ptr(out["depth_key"]), _ptr(out["vis"]), _ptr(out["margin"]),
+                                  _ptr(out["uv32"]))
+    return out
+
+
+def exp_cw(x):
+    """The float32 exp of the projection (Cody-Waite reduction, Taylor polynomial)."""
+    x = np.ascontiguousarray(x, np.float32)
+    y = np.empty_like(x)
+    lib().orc_exp_cw(x.size, _ptr(x), _ptr(y))
+    return y
 
 
 def bin_sort(g: Gaussians, cams, tw=16, th=16):

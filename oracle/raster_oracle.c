@@ -32,8 +32,14 @@
  *     camera-space z of the Gaussian centre, ties by record index.
  *
  * Everything that decides an integer (culling, radius, footprint, depth key) is
- * computed in FP64 from the float32 inputs, in the operation order written here
- * without contraction; the GPU library computes its projection in FP64 too.
+ * taken in float32 (decide_f32): the projection that decides them is float32
+ * and, where floating point decides an integer, the oracle takes the decision
+ * in that same precision, with every operation written out in a fixed order
+ * and rounded on its own (no contraction; correctly rounded division, square
+ * root and fused multiply-add; exp by the Cody-Waite reduction and Taylor
+ * polynomial of exp_cw).  The continuous values the blend and the adjoint use
+ * (screen mean, conic, opacity, Jacobian) stay FP64 (project_f64), which also
+ * takes the same decisions in FP64 so that tests can compare the two.
  *
  * Records: r = cam * N + i (camera-major).  Pixels: views concatenated in
  * camera order, row-major inside a view.
@@ -79,8 +85,23 @@ typedef struct {
     double A, B, C;          /* conic = inverse of the screen covariance */
     double u, v, o, radius;
     int px0, px1, py0, py1;  /* footprint, inclusive, clipped to the image */
-    uint32_t depth_key;      /* bit pattern of (float)z */
+    uint32_t depth_key;      /* bit pattern of the float32 z */
+    int ok;                  /* the FP64 values are defined (z > 0, |q| > 0, det > 0) */
+    /* the same decisions taken in FP64, and how far they are from flipping:
+     * margin = min(distance of u - r, u + r, v - r, v + r, 3 sqrt(lambda_max)
+     * from the nearest integer in pixels, z - near) */
+    int vis64, r64x0, r64x1, r64y0, r64y1;
+    double radius64, margin64;
+    uint32_t key64;
 } proj_t;
+
+/* Integer decisions of one record, taken in float32. */
+typedef struct {
+    int vis;
+    float radius, u, v, z;
+    int px0, px1, py0, py1;
+    uint32_t key;
+} dec32_t;
 
 static void load_cam(const float* row, cam_t* c)
 {
@@ -116,16 +137,133 @@ static uint32_t f32_bits(double z)
     return u;
 }
 
-static void project_one(const float* mean, const float* ls, const float* quat, float logit,
+/* exp(x) in float32: k = rint(x log2 e), r = (x - k ln2_hi) - k ln2_lo (ln2_hi
+ * with 15 significant bits, so k ln2_hi is exact), the degree-7 Taylor
+ * polynomial of exp(r) by Horner with fused multiply-adds, times 2^k (the
+ * Cody-Waite reduction).  Each step is one correctly rounded float32
+ * operation, so the value is a fixed function of x. */
+static float exp_cw(float x)
+{
+    x = fminf(fmaxf(x, -87.0f), 88.0f);
+    const float k = rintf(x * 1.44269504f);
+    const float r = (x - k * 0.693145751953125f) - k * 1.42860677e-06f;
+    float p = 1.0f / 5040.0f;
+    p = fmaf(p, r, 1.0f / 720.0f);
+    p = fmaf(p, r, 1.0f / 120.0f);
+    p = fmaf(p, r, 1.0f / 24.0f);
+    p = fmaf(p, r, 1.0f / 6.0f);
+    p = fmaf(p, r, 0.5f);
+    p = fmaf(p, r, 1.0f);
+    p = fmaf(p, r, 1.0f);
+    return ldexpf(p, (int)k);
+}
+
+static uint32_t f32_bits_f(float f)
+{
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    return u;
+}
+
+/* The integer decisions of one record from its float32 inputs, in float32:
+ * view transform, scales, normalised quaternion, world and camera covariance,
+ * clamped Jacobian, screen covariance with dilation, radius from the larger
+ * eigenvalue, screen mean, culling and the inclusive pixel footprint, with
+ * every sum taken left to right and every product as written. */
+static void decide_f32(const float* mean, const float* ls, const float* quat, const cam_t* cam, dec32_t* D)
+{
+    memset(D, 0, sizeof *D);
+    float W[3][3], t[3];
+    for (int i = 0; i < 3; ++i) {
+        for (int j = 0; j < 3; ++j) W[i][j] = (float)cam->vm[4 * i + j];
+        t[i] = (float)cam->vm[4 * i + 3];
+    }
+    const float mx = mean[0], my = mean[1], mz = mean[2];
+    const float x = ((W[0][0] * mx + W[0][1] * my) + W[0][2] * mz) + t[0];
+    const float y = ((W[1][0] * mx + W[1][1] * my) + W[1][2] * mz) + t[1];
+    const float z = ((W[2][0] * mx + W[2][1] * my) + W[2][2] * mz) + t[2];
+    D->z = z;
+    if (!(z > 0.2f)) return;
+    float s[3];
+    for (int k = 0; k < 3; ++k) s[k] = exp_cw(ls[k]);
+    const float q0 = quat[0], q1 = quat[1], q2 = quat[2], q3 = quat[3];
+    const float nrm = sqrtf(((q0 * q0 + q1 * q1) + q2 * q2) + q3 * q3);
+    if (!(nrm > 0.0f)) return;
+    const float w = q0 / nrm, qx = q1 / nrm, qy = q2 / nrm, qz = q3 / nrm;
+    const float R[3][3] = {
+        {1.0f - 2.0f * (qy * qy + qz * qz), 2.0f * (qx * qy - w * qz), 2.0f * (qx * qz + w * qy)},
+        {2.0f * (qx * qy + w * qz), 1.0f - 2.0f * (qx * qx + qz * qz), 2.0f * (qy * qz - w * qx)},
+        {2.0f * (qx * qz - w * qy), 2.0f * (qy * qz + w * qx), 1.0f - 2.0f * (qx * qx + qy * qy)}};
+    float S3[3][3], Sc[3][3];
+    for (int p = 0; p < 3; ++p)
+        for (int q = 0; q < 3; ++q) {
+            float acc = 0.0f;
+            for (int k = 0; k < 3; ++k) acc = acc + ((R[p][k] * s[k]) * s[k]) * R[q][k];
+            S3[p][q] = acc;
+        }
+    for (int p = 0; p < 3; ++p)
+        for (int q = 0; q < 3; ++q) {
+            float acc = 0.0f;
+            for (int k = 0; k < 3; ++k)
+                for (int l = 0; l < 3; ++l) acc = acc + (W[p][k] * S3[k][l]) * W[q][l];
+            Sc[p][q] = acc;
+        }
+    const float fx = (float)cam->fx, fy = (float)cam->fy;
+    const float limx = 1.3f * ((float)cam->w / (2.0f * fx));
+    const float limy = 1.3f * ((float)cam->h / (2.0f * fy));
+    float tx = x / z, ty = y / z;
+    tx = tx < -limx ? -limx : (tx > limx ? limx : tx);
+    ty = ty < -limy ? -limy : (ty > limy ? limy : ty);
+    const float J[2][3] = {{fx / z, 0.0f, (-fx * tx) / z}, {0.0f, fy / z, (-fy * ty) / z}};
+    float cov[2][2];
+    for (int p = 0; p < 2; ++p)
+        for (int q = 0; q < 2; ++q) {
+            float acc = 0.0f;
+            for (int k = 0; k < 3; ++k)
+                for (int l = 0; l < 3; ++l) acc = acc + (J[p][k] * Sc[k][l]) * J[q][l];
+            cov[p][q] = acc;
+        }
+    const float a = cov[0][0] + 0.3f, b = cov[0][1], c = cov[1][1] + 0.3f;
+    const float det = a * c - b * b;
+    if (!(det > 0.0f)) return;
+    const float mid = 0.5f * (a + c);
+    const float lam = mid + sqrtf(fmaxf(0.1f, mid * mid - det));
+    const float r = ceilf(3.0f * sqrtf(lam));
+    const float u = (fx * x) / z + (float)cam->cx;
+    const float v = (fy * y) / z + (float)cam->cy;
+    D->radius = r;
+    D->u = u;
+    D->v = v;
+    if (!(u + r >= 0.0f) || !(u - r <= (float)(cam->w - 1)) || !(v + r >= 0.0f) || !(v - r <= (float)(cam->h - 1)))
+        return;
+    const float fx0 = ceilf(u - r), fx1 = floorf(u + r);
+    const float fy0 = ceilf(v - r), fy1 = floorf(v + r);
+    D->px0 = fx0 < 0.0f ? 0 : (int)fx0;
+    D->px1 = fx1 > (float)(cam->w - 1) ? cam->w - 1 : (int)fx1;
+    D->py0 = fy0 < 0.0f ? 0 : (int)fy0;
+    D->py1 = fy1 > (float)(cam->h - 1) ? cam->h - 1 : (int)fy1;
+    if (D->px0 > D->px1 || D->py0 > D->py1) return;
+    D->key = f32_bits_f(z);
+    D->vis = 1;
+}
+
+static double frac_dist(double x) { return fabs(x - nearbyint(x)); }
+
+/* FP64 values of one record (screen mean, conic, opacity and the intermediate
+ * quantities of the adjoint) wherever they are defined, and the same integer
+ * decisions taken in FP64 with their margin. */
+static void project_f64(const float* mean, const float* ls, const float* quat, float logit,
                         const cam_t* cam, proj_t* P)
 {
     memset(P, 0, sizeof *P);
+    P->margin64 = INFINITY;
     const double* V = cam->vm;
     double mx = mean[0], my = mean[1], mz = mean[2];
     P->x = ((V[0] * mx + V[1] * my) + V[2] * mz) + V[3];
     P->y = ((V[4] * mx + V[5] * my) + V[6] * mz) + V[7];
     P->z = ((V[8] * mx + V[9] * my) + V[10] * mz) + V[11];
-    if (!(P->z > ORC_NEAR)) return;
+    P->margin64 = fabs(P->z - ORC_NEAR);
+    if (!(P->z > 0.0)) return;
 
     for (int k = 0; k < 3; ++k) P->s[k] = exp((double)ls[k]);
     for (int k = 0; k < 4; ++k) P->qraw[k] = quat[k];
@@ -186,25 +324,57 @@ static void project_one(const float* mean, const float* ls, const float* quat, f
     P->A = P->c / P->det;
     P->B = -P->b / P->det;
     P->C = P->a / P->det;
-    double mid = 0.5 * (P->a + P->c);
-    double lam = mid + sqrt(fmax(ORC_EIG_FLOOR, mid * mid - P->det));
-    P->radius = ceil(ORC_SIGMA * sqrt(lam));
     P->u = (cam->fx * P->x) / P->z + cam->cx;
     P->v = (cam->fy * P->y) / P->z + cam->cy;
-    double r = P->radius;
+    P->o = 1.0 / (1.0 + exp(-(double)logit));
+    P->ok = 1;
+
+    /* the integer decisions in FP64 */
+    double mid = 0.5 * (P->a + P->c);
+    double lam = mid + sqrt(fmax(ORC_EIG_FLOOR, mid * mid - P->det));
+    double r3 = ORC_SIGMA * sqrt(lam);
+    double r = ceil(r3);
+    P->radius64 = r;
+    double m = fmin(P->margin64, frac_dist(r3));
+    m = fmin(m, fmin(frac_dist(P->u - r), frac_dist(P->u + r)));
+    m = fmin(m, fmin(frac_dist(P->v - r), frac_dist(P->v + r)));
+    P->margin64 = m;
+    if (!(P->z > ORC_NEAR)) return;
     if (!(P->u + r >= 0.0) || !(P->u - r <= cam->w - 1) || !(P->v + r >= 0.0) ||
         !(P->v - r <= cam->h - 1))
         return;
     double fx0 = ceil(P->u - r), fx1 = floor(P->u + r);
     double fy0 = ceil(P->v - r), fy1 = floor(P->v + r);
-    P->px0 = fx0 < 0.0 ? 0 : (int)fx0;
-    P->px1 = fx1 > cam->w - 1 ? cam->w - 1 : (int)fx1;
-    P->py0 = fy0 < 0.0 ? 0 : (int)fy0;
-    P->py1 = fy1 > cam->h - 1 ? cam->h - 1 : (int)fy1;
-    if (P->px0 > P->px1 || P->py0 > P->py1) return;
-    P->o = 1.0 / (1.0 + exp(-(double)logit));
-    P->depth_key = f32_bits(P->z);
+    P->r64x0 = fx0 < 0.0 ? 0 : (int)fx0;
+    P->r64x1 = fx1 > cam->w - 1 ? cam->w - 1 : (int)fx1;
+    P->r64y0 = fy0 < 0.0 ? 0 : (int)fy0;
+    P->r64y1 = fy1 > cam->h - 1 ? cam->h - 1 : (int)fy1;
+    if (P->r64x0 > P->r64x1 || P->r64y0 > P->r64y1) return;
+    P->key64 = f32_bits(P->z);
+    P->vis64 = 1;
+}
+
+/* One record: FP64 values, float32 decisions. */
+static void project_one(const float* mean, const float* ls, const float* quat, float logit,
+                        const cam_t* cam, proj_t* P)
+{
+    project_f64(mean, ls, quat, logit, cam, P);
+    dec32_t D;
+    decide_f32(mean, ls, quat, cam, &D);
+    P->radius = D.radius;
+    /* the FP64 values exist wherever the float32 decision keeps a record: z >
+     * 0.2 in float32 means z > 0 in FP64, and the dilated screen covariance is
+     * positive definite */
+    if (!D.vis || !P->ok) {
+        P->vis = 0;
+        return;
+    }
     P->vis = 1;
+    P->px0 = D.px0;
+    P->px1 = D.px1;
+    P->py0 = D.py0;
+    P->py1 = D.py1;
+    P->depth_key = D.key;
 }
 
 typedef struct {
@@ -461,6 +631,50 @@ int64_t orc_project(int n, const float* means, const float* log_scales, const fl
     }
     scene_free(&S);
     return nv;
+}
+
+/* The integer decisions of every record taken in FP64 (rect64 [R, 4] with -1
+ * rows for culled records, key64, vis64) with their margin (margin64: the
+ * smallest distance, in pixels, of u - r, u + r, v - r, v + r or 3 sqrt(lambda)
+ * from an integer, or of z from the near plane), beside the float32 screen
+ * mean the float32 decisions used (uv32 [R, 2]).  For tests that compare the
+ * float32 decisions with the FP64 ones away from their thresholds.  Outputs may
+ * be NULL. */
+int64_t orc_project_decisions64(int n, const float* means, const float* log_scales, const float* quats,
+                                const float* logits, int n_cams, const float* cams, int32_t* rect64,
+                                uint32_t* key64, uint8_t* vis64, double* margin64, float* uv32)
+{
+    int64_t R = (int64_t)n_cams * n, nv = 0;
+    cam_t* cs = (cam_t*)calloc((size_t)(n_cams > 0 ? n_cams : 1), sizeof(cam_t));
+    for (int c = 0; c < n_cams; ++c) load_cam(cams + (size_t)c * CAM_FLOATS, &cs[c]);
+#pragma omp parallel for schedule(static) reduction(+ : nv)
+    for (int64_t r = 0; r < R; ++r) {
+        const int c = (int)(r / n);
+        const int64_t i = r % n;
+        proj_t P;
+        dec32_t D;
+        project_f64(means + 3 * i, log_scales + 3 * i, quats + 4 * i, logits[i], &cs[c], &P);
+        decide_f32(means + 3 * i, log_scales + 3 * i, quats + 4 * i, &cs[c], &D);
+        nv += P.vis64;
+        if (rect64) {
+            rect64[4 * r] = P.vis64 ? P.r64x0 : -1;
+            rect64[4 * r + 1] = P.vis64 ? P.r64x1 : -1;
+            rect64[4 * r + 2] = P.vis64 ? P.r64y0 : -1;
+            rect64[4 * r + 3] = P.vis64 ? P.r64y1 : -1;
+        }
+        if (key64) key64[r] = P.vis64 ? P.key64 : 0xFFFFFFFFu;
+        if (vis64) vis64[r] = (uint8_t)P.vis64;
+        if (margin64) margin64[r] = P.margin64;
+        if (uv32) { uv32[2 * r] = D.u; uv32[2 * r + 1] = D.v; }
+    }
+    free(cs);
+    return nv;
+}
+
+/* exp_cw of each input (for the tests that pin it against a reference exp). */
+void orc_exp_cw(int64_t n, const float* x, float* y)
+{
+    for (int64_t i = 0; i < n; ++i) y[i] = exp_cw(x[i]);
 }
 
 /* Tile binning.  Returns the instance count; the arrays are filled only when

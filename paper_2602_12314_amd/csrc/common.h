@@ -9,12 +9,13 @@
 namespace lam {
 
 // 3D Gaussian Splatting conventions for Eq. 2 / Eq. 4 (the paper defers the
-// projection and blending details to 3DGS).
-constexpr double kNear = 0.2;          // cull when camera-space z <= kNear
-constexpr double kDilation = 0.3;      // added to the screen covariance diagonal
-constexpr double kFovClamp = 1.3;      // x/z, y/z clamp in the Jacobian, in tan(fov/2) units
-constexpr double kEigFloor = 0.1;      // floor under mid^2 - det
-constexpr double kSigmas = 3.0;        // footprint half-width in standard deviations
+// projection and blending details to 3DGS), as float32 values: the projection
+// is computed in float32.
+constexpr float kNear = 0.2f;          // cull when camera-space z <= kNear
+constexpr float kDilation = 0.3f;      // added to the screen covariance diagonal
+constexpr float kFovClamp = 1.3f;      // x/z, y/z clamp in the Jacobian, in tan(fov/2) units
+constexpr float kEigFloor = 0.1f;      // floor under mid^2 - det
+constexpr float kSigmas = 3.0f;        // footprint half-width in standard deviations
 constexpr float kAlphaMax = 0.99f;     // alpha clamp
 constexpr float kAlphaMin = 1.0f / 255.0f;  // pairs below are skipped
 constexpr float kTStop = 1e-4f;        // stop before transmittance would drop below

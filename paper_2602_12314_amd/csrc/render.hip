@@ -1,7 +1,7 @@
 // Query-map rendering (paper Eq. 2 and Eq. 4) and its adjoint on gfx950.
 //
 // Pipeline of one forward call (one HIP stream, no host synchronisation):
-//   k_preprocess      one thread per (camera, Gaussian) record, FP64 projection:
+//   k_preprocess      one thread per (camera, Gaussian) record, float32 projection:
 //                     screen mean, conic, opacity, integer footprint, depth key
 //   radix sort        records by float32 depth bits (stable: ties by record)
 //   scan + k_emit     (tile id, record) pairs emitted in depth order
@@ -20,9 +20,40 @@ namespace lam {
 
 // ------------------------------------------------------------- preprocess
 
-// Record outputs: rec0 = (u_hi, v_hi, u_lo, v_lo) with u = u_hi + u_lo as a
-// float pair, rec1 = (A, B, C, opacity) with power = -0.5 (A dx^2 + C dy^2) - B dx dy,
-// foot = (x0 | x1 << 16, y0 | y1 << 16) the inclusive pixel footprint.
+// exp(x) in float32 by Cody-Waite reduction and a Taylor polynomial: k =
+// rint(x log2 e), r = (x - k ln2_hi) - k ln2_lo with ln2_hi carrying 15
+// significant bits (so k ln2_hi is exact for |k| < 256), exp(r) to degree 7 by
+// Horner with fused multiply-adds (|r| <= ln2 / 2: truncation below 2^-25),
+// scaled by 2^k.  Every step is a correctly rounded float32 operation, so the
+// result is a fixed function of x, reproducible bit for bit by any IEEE float32
+// implementation of the same steps.
+__device__ inline float exp_cw(float x)
+{
+#pragma clang fp contract(off)
+    x = fminf(fmaxf(x, -87.0f), 88.0f);
+    const float k = rintf(x * 1.44269504f);
+    const float r = (x - k * 0.693145751953125f) - k * 1.42860677e-06f;
+    float p = 1.0f / 5040.0f;
+    p = fmaf(p, r, 1.0f / 720.0f);
+    p = fmaf(p, r, 1.0f / 120.0f);
+    p = fmaf(p, r, 1.0f / 24.0f);
+    p = fmaf(p, r, 1.0f / 6.0f);
+    p = fmaf(p, r, 0.5f);
+    p = fmaf(p, r, 1.0f);
+    p = fmaf(p, r, 1.0f);
+    return ldexpf(p, (int)k);
+}
+
+// Record outputs: rec0 = (u, v, 0, 0) (the last two words, a low-order part
+// of the screen mean, are zero for a float32 projection), rec1 = (A, B, C,
+// opacity) with power = -0.5 (A dx^2 + C dy^2) - B dx dy, foot = (x0 | x1 << 16,
+// y0 | y1 << 16) the inclusive pixel footprint.
+//
+// The projection is float32 with every operation written out and rounded on
+// its own (no contraction; division and square root correctly rounded;
+// exp_cw above), in the order below, so that the integer decisions it takes
+// (culling, radius, footprint, depth key) are a fixed function of the float32
+// inputs.
 __global__ __launch_bounds__(256) void k_preprocess(
     CamSet cs, int N, const float* __restrict__ means, const float* __restrict__ log_scales,
     const float* __restrict__ quats, const float* __restrict__ logits, float4* __restrict__ rec0,
@@ -35,85 +66,84 @@ __global__ __launch_bounds__(256) void k_preprocess(
     const Cam& cam = cs.c[blockIdx.y];
     const size_t r = (size_t)blockIdx.y * N + i;
 
-    const double mx = means[3 * i], my = means[3 * i + 1], mz = means[3 * i + 2];
-    double Wm[3][3], t[3];
+    const float mx = means[3 * i], my = means[3 * i + 1], mz = means[3 * i + 2];
+    float Wm[3][3], t[3];
     for (int a = 0; a < 3; ++a) {
-        for (int b = 0; b < 3; ++b) Wm[a][b] = (double)cam.vm[4 * a + b];
-        t[a] = (double)cam.vm[4 * a + 3];
+        for (int b = 0; b < 3; ++b) Wm[a][b] = cam.vm[4 * a + b];
+        t[a] = cam.vm[4 * a + 3];
     }
-    const double x = ((Wm[0][0] * mx + Wm[0][1] * my) + Wm[0][2] * mz) + t[0];
-    const double y = ((Wm[1][0] * mx + Wm[1][1] * my) + Wm[1][2] * mz) + t[1];
-    const double z = ((Wm[2][0] * mx + Wm[2][1] * my) + Wm[2][2] * mz) + t[2];
+    const float x = ((Wm[0][0] * mx + Wm[0][1] * my) + Wm[0][2] * mz) + t[0];
+    const float y = ((Wm[1][0] * mx + Wm[1][1] * my) + Wm[1][2] * mz) + t[1];
+    const float z = ((Wm[2][0] * mx + Wm[2][1] * my) + Wm[2][2] * mz) + t[2];
 
     bool vis = z > kNear;
-    double s[3], qn[4];
-    double nrm = 0.0;
+    float s[3], qn[4];
     if (vis) {
-        for (int k = 0; k < 3; ++k) s[k] = exp((double)log_scales[3 * i + k]);
-        double q0 = quats[4 * i], q1 = quats[4 * i + 1], q2 = quats[4 * i + 2], q3 = quats[4 * i + 3];
-        nrm = sqrt(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
-        vis = nrm > 0.0;
+        for (int k = 0; k < 3; ++k) s[k] = exp_cw(log_scales[3 * i + k]);
+        const float q0 = quats[4 * i], q1 = quats[4 * i + 1], q2 = quats[4 * i + 2], q3 = quats[4 * i + 3];
+        const float nrm = sqrtf(((q0 * q0 + q1 * q1) + q2 * q2) + q3 * q3);
+        vis = nrm > 0.0f;
         qn[0] = q0 / nrm; qn[1] = q1 / nrm; qn[2] = q2 / nrm; qn[3] = q3 / nrm;
     }
-    double a = 0, b = 0, c = 0, det = 0, u = 0, v = 0, radius = 0;
+    float a = 0, b = 0, c = 0, det = 0, u = 0, v = 0, radius = 0;
     if (vis) {
-        const double w = qn[0], qx = qn[1], qy = qn[2], qz = qn[3];
-        double Rg[3][3] = {
-            {1.0 - 2.0 * (qy * qy + qz * qz), 2.0 * (qx * qy - w * qz), 2.0 * (qx * qz + w * qy)},
-            {2.0 * (qx * qy + w * qz), 1.0 - 2.0 * (qx * qx + qz * qz), 2.0 * (qy * qz - w * qx)},
-            {2.0 * (qx * qz - w * qy), 2.0 * (qy * qz + w * qx), 1.0 - 2.0 * (qx * qx + qy * qy)}};
-        double S3[3][3], Sc[3][3];
+        const float w = qn[0], qx = qn[1], qy = qn[2], qz = qn[3];
+        const float Rg[3][3] = {
+            {1.0f - 2.0f * (qy * qy + qz * qz), 2.0f * (qx * qy - w * qz), 2.0f * (qx * qz + w * qy)},
+            {2.0f * (qx * qy + w * qz), 1.0f - 2.0f * (qx * qx + qz * qz), 2.0f * (qy * qz - w * qx)},
+            {2.0f * (qx * qz - w * qy), 2.0f * (qy * qz + w * qx), 1.0f - 2.0f * (qx * qx + qy * qy)}};
+        float S3[3][3], Sc[3][3];
         for (int p = 0; p < 3; ++p)
             for (int q = 0; q < 3; ++q) {
-                double acc = 0.0;
-                for (int k = 0; k < 3; ++k) acc += Rg[p][k] * s[k] * s[k] * Rg[q][k];
+                float acc = 0.0f;
+                for (int k = 0; k < 3; ++k) acc = acc + ((Rg[p][k] * s[k]) * s[k]) * Rg[q][k];
                 S3[p][q] = acc;
             }
         for (int p = 0; p < 3; ++p)
             for (int q = 0; q < 3; ++q) {
-                double acc = 0.0;
+                float acc = 0.0f;
                 for (int k = 0; k < 3; ++k)
-                    for (int l = 0; l < 3; ++l) acc += Wm[p][k] * S3[k][l] * Wm[q][l];
+                    for (int l = 0; l < 3; ++l) acc = acc + (Wm[p][k] * S3[k][l]) * Wm[q][l];
                 Sc[p][q] = acc;
             }
-        const double fx = cam.fx, fy = cam.fy;
-        const double limx = kFovClamp * (cam.w / (2.0 * fx));
-        const double limy = kFovClamp * (cam.h / (2.0 * fy));
-        double tx = x / z, ty = y / z;
+        const float fx = cam.fx, fy = cam.fy;
+        const float limx = kFovClamp * ((float)cam.w / (2.0f * fx));
+        const float limy = kFovClamp * ((float)cam.h / (2.0f * fy));
+        float tx = x / z, ty = y / z;
         tx = tx < -limx ? -limx : (tx > limx ? limx : tx);
         ty = ty < -limy ? -limy : (ty > limy ? limy : ty);
-        const double J[2][3] = {{fx / z, 0.0, -fx * tx / z}, {0.0, fy / z, -fy * ty / z}};
-        double cov[2][2];
+        const float J[2][3] = {{fx / z, 0.0f, (-fx * tx) / z}, {0.0f, fy / z, (-fy * ty) / z}};
+        float cov[2][2];
         for (int p = 0; p < 2; ++p)
             for (int q = 0; q < 2; ++q) {
-                double acc = 0.0;
+                float acc = 0.0f;
                 for (int k = 0; k < 3; ++k)
-                    for (int l = 0; l < 3; ++l) acc += J[p][k] * Sc[k][l] * J[q][l];
+                    for (int l = 0; l < 3; ++l) acc = acc + (J[p][k] * Sc[k][l]) * J[q][l];
                 cov[p][q] = acc;
             }
         a = cov[0][0] + kDilation;
         b = cov[0][1];
         c = cov[1][1] + kDilation;
         det = a * c - b * b;
-        vis = det > 0.0;
+        vis = det > 0.0f;
         if (vis) {
-            const double mid = 0.5 * (a + c);
-            const double lam = mid + sqrt(fmax(kEigFloor, mid * mid - det));
-            radius = ceil(kSigmas * sqrt(lam));
-            u = (fx * x) / z + (double)cam.cx;
-            v = (fy * y) / z + (double)cam.cy;
-            vis = (u + radius >= 0.0) && (u - radius <= (double)(cam.w - 1)) &&
-                  (v + radius >= 0.0) && (v - radius <= (double)(cam.h - 1));
+            const float mid = 0.5f * (a + c);
+            const float lam = mid + sqrtf(fmaxf(kEigFloor, mid * mid - det));
+            radius = ceilf(kSigmas * sqrtf(lam));
+            u = (fx * x) / z + cam.cx;
+            v = (fy * y) / z + cam.cy;
+            vis = (u + radius >= 0.0f) && (u - radius <= (float)(cam.w - 1)) && (v + radius >= 0.0f) &&
+                  (v - radius <= (float)(cam.h - 1));
         }
     }
     int x0 = 0, x1 = -1, y0 = 0, y1 = -1;
     if (vis) {
-        const double fx0 = ceil(u - radius), fx1 = floor(u + radius);
-        const double fy0 = ceil(v - radius), fy1 = floor(v + radius);
-        x0 = fx0 < 0.0 ? 0 : (int)fx0;
-        x1 = fx1 > cam.w - 1 ? cam.w - 1 : (int)fx1;
-        y0 = fy0 < 0.0 ? 0 : (int)fy0;
-        y1 = fy1 > cam.h - 1 ? cam.h - 1 : (int)fy1;
+        const float fx0 = ceilf(u - radius), fx1 = floorf(u + radius);
+        const float fy0 = ceilf(v - radius), fy1 = floorf(v + radius);
+        x0 = fx0 < 0.0f ? 0 : (int)fx0;
+        x1 = fx1 > (float)(cam.w - 1) ? cam.w - 1 : (int)fx1;
+        y0 = fy0 < 0.0f ? 0 : (int)fy0;
+        y1 = fy1 > (float)(cam.h - 1) ? cam.h - 1 : (int)fy1;
         vis = x0 <= x1 && y0 <= y1;
     }
     if (!vis) {
@@ -122,12 +152,11 @@ __global__ __launch_bounds__(256) void k_preprocess(
         foot[r] = make_uint2(0u, 0u);
         return;
     }
-    const float uh = (float)u, vh = (float)v;
-    rec0[r] = make_float4(uh, vh, (float)(u - (double)uh), (float)(v - (double)vh));
-    const double o = 1.0 / (1.0 + exp(-(double)logits[i]));
-    rec1[r] = make_float4((float)(c / det), (float)(-b / det), (float)(a / det), (float)o);
+    rec0[r] = make_float4(u, v, 0.0f, 0.0f);
+    const float o = 1.0f / (1.0f + exp_cw(-logits[i]));
+    rec1[r] = make_float4(c / det, -b / det, a / det, o);
     foot[r] = make_uint2((uint32_t)x0 | ((uint32_t)x1 << 16), (uint32_t)y0 | ((uint32_t)y1 << 16));
-    depth_key[r] = __float_as_uint((float)z);
+    depth_key[r] = __float_as_uint(z);
     const int nx = (x1 >> cs.tile_shift_x) - (x0 >> cs.tile_shift_x) + 1;
     const int ny = (y1 >> cs.tile_shift_y) - (y0 >> cs.tile_shift_y) + 1;
     ntiles[r] = (uint32_t)(nx * ny);

@@ -457,3 +457,54 @@ def test_transmittance_non_increasing_along_every_walk():
         assert wk["T_final"][i] == T[-1] * (1.0 - a[-1])
         assert wk["T_final"][i] >= 1e-4 and wk["T_final"][i] <= T[-1]
         np.testing.assert_allclose(wk["T_final"][i], np.prod(1.0 - a), rtol=1e-12)
+
+
+def test_exp_cw_within_one_ulp_of_exp():
+    # The float32 exp of the projection (Cody-Waite reduction and a degree-7
+    # Taylor polynomial) against the FP64 exp, over the range log-scales and
+    # opacity logits take and beyond: within one float32 ulp, exact at 0.
+    rng = np.random.default_rng(5)
+    x = np.concatenate([np.linspace(-30.0, 20.0, 200001, dtype=np.float32),
+                        rng.uniform(-87.0, 88.0, 100000).astype(np.float32)])
+    y = R.exp_cw(x).astype(np.float64)
+    ref = np.exp(x.astype(np.float64))
+    ulp = np.spacing(ref.astype(np.float32)).astype(np.float64)
+    assert np.max(np.abs(y - ref) / ulp) <= 1.0
+    assert R.exp_cw(np.zeros(1))[0] == 1.0
+
+
+@pytest.mark.parametrize("idx", [1, 2, 4])
+def test_float32_decisions_match_fp64_away_from_thresholds(idx):
+    # The integer decisions of the projection (culling, radius, footprint,
+    # depth key) are taken in float32, the precision of the projection they
+    # belong to.  Taken again in FP64 they must agree wherever FP64 puts them
+    # farther from a threshold than float32 rounding can move them (1e-3 px,
+    # or 1e-3 of depth at the near plane), and the float32 depth z must lie
+    # within the rounding bound of a four-term float32 sum, 4 u (|w0 mx| +
+    # |w1 my| + |w2 mz| + |t|), of the FP64 z.
+    sp = scenes.spec(idx)
+    s = scenes.make_scene(sp, seed=0, with_target=False)
+    g = R.Gaussians.of(s)
+    p32 = R.project(g, s.cams)
+    p64 = R.project_decisions64(g, s.cams)
+    v32, v64 = p32["vis"] == 1, p64["vis"] == 1
+    safe = p64["margin"] > 1e-3
+    assert np.array_equal(v32[safe], v64[safe])
+    both = v32 & v64
+    differ = both & np.any(p32["rect"] != p64["rect"], axis=1)
+    assert not np.any(differ & safe)
+    n_flip = int(np.count_nonzero((v32 != v64) | differ))
+    print(f"[decisions] {sp.name}: {int(v32.sum())} visible, {n_flip} records with another rect or "
+          f"visibility in FP64 (all within {p64['margin'][(v32 != v64) | differ].max(initial=0.0):.2e} px "
+          f"of a threshold)")
+    assert n_flip <= 1e-3 * max(int(v32.sum()), 1)
+    cams = np.asarray(s.cams, np.float64)
+    n = g.n
+    z32 = p32["depth_key"][both].view(np.float32).astype(np.float64)
+    rec = np.nonzero(both)[0]
+    c, i = rec // n, rec % n
+    vm = cams[c, 6:22].reshape(-1, 4, 4)
+    m = g.means.astype(np.float64)[i]
+    terms = np.abs(vm[:, 2, :3] * m).sum(1) + np.abs(vm[:, 2, 3])
+    u = 2.0 ** -24
+    assert np.all(np.abs(z32 - p32["z"][both]) <= 4 * u / (1 - 4 * u) * terms)
