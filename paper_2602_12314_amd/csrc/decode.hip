@@ -626,15 +626,16 @@ __global__ __launch_bounds__(NW * kWave) void k_dec_rows(RowsArgs a)
 
     // ---- epilogue: cosine loss gradient (LOSS) or upstream dF (ADJ), G = dL/dF / l.
     // The target (or dF) rows feed the row statistics and, once those are
-    // reduced over the waves, G; they are either held in registers across that
-    // reduction or read a second time (kHold below).
+    // reduced over the waves, G.  All rows are held in registers from one read
+    // (kHold), except in the 64-pixel block with four D tiles per wave, whose
+    // registers fit two waves per SIMD only without them: that shape reduces
+    // the statistics one 32-pixel group at a time (one barrier each) and reads
+    // the group's rows again right after, while they are still in L2 (a
+    // 128 KB working set per workgroup instead of 256 KB read twice far
+    // apart).
     // (Requesting these rows before the F contraction is slower: loads retire in
     // order, so every fragment wait of the contraction would wait for them.)
     // A pixel past n reads row n - 1, unused since its G is zeroed through ca, cb.
-    // The rows are held in registers from the first read (held[]) except in
-    // the 64-pixel block with four D tiles per wave, whose registers only fit
-    // two waves per SIMD when they are read twice (the second read costs
-    // bandwidth: the other shapes are faster holding them).
     constexpr bool kHold = !(NW == 8 && NT * NPG >= 8);
     const float* rowsrc = MODE == MODE_LOSS ? a.target : a.dF;
     auto row_frag = [&](int g, int t, float* x16) {
@@ -645,13 +646,6 @@ __global__ __launch_bounds__(NW * kWave) void k_dec_rows(RowsArgs a)
             x16[4 * g4] = x.x; x16[4 * g4 + 1] = x.y; x16[4 * g4 + 2] = x.z; x16[4 * g4 + 3] = x.w;
         }
     };
-    float held[kHold ? NT : 1][NPG][16];
-    if constexpr (kHold) {
-#pragma unroll
-        for (int g = 0; g < NPG; ++g)
-#pragma unroll
-            for (int t = 0; t < NT; ++t) row_frag(g, t, held[t][g]);
-    }
     float delta[NPG], ca[NPG], cb[NPG];  // G = ca * row + cb * F (zero past n)
 #pragma unroll
     for (int g = 0; g < NPG; ++g) {
@@ -659,91 +653,133 @@ __global__ __launch_bounds__(NW * kWave) void k_dec_rows(RowsArgs a)
         ca[g] = valid[g] ? invl[g] : 0.0f;
         cb[g] = 0.0f;
     }
-    if (MODE == MODE_LOSS) {
-        float nf[NPG], ft[NPG], nt[NPG];
-#pragma unroll
-        for (int g = 0; g < NPG; ++g) {
-            nf[g] = ft[g] = nt[g] = 0.0f;
-#pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                float xr[16];
-                if constexpr (!kHold) row_frag(g, t, xr);
-                const float* x = kHold ? held[kHold ? t : 0][g] : xr;
-#pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    nf[g] += acc[t][g][r] * acc[t][g][r];
-                    ft[g] += acc[t][g][r] * x[r];
-                    nt[g] += x[r] * x[r];
-                }
-            }
-            nf[g] += __shfl_xor(nf[g], 32, kWave);
-            ft[g] += __shfl_xor(ft[g], 32, kWave);
-            nt[g] += __shfl_xor(nt[g], 32, kWave);
-        }
-        __syncthreads();  // every wave is done reading the row sums of pass 2
-        if (h == 0) {
-#pragma unroll
-            for (int g = 0; g < NPG; ++g) {
-                rslot(0, w, g)[col] = nf[g];
-                rslot(1, w, g)[col] = ft[g];
-                rslot(2, w, g)[col] = nt[g];
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int g = 0; g < NPG; ++g) {
-            float sf = 0.f, st = 0.f, stt = 0.f;
-#pragma unroll
-            for (int ww = 0; ww < NW; ++ww) {
-                sf += rslot(0, ww, g)[col];
-                st += rslot(1, ww, g)[col];
-                stt += rslot(2, ww, g)[col];
-            }
-            const float raw = sqrtf(sf) * sqrtf(stt);
-            const float den = fmaxf(raw, 1e-8f);
-            const float cs = st / den;
-            // dL/dF = lam_cos (-(1/n) (T / den - c F / |F|^2)) + lam_l2 (2/n) (F - T),
-            // then divided by l
-            const float l2 = 2.0f * a.lam_l2 * a.inv_n;
-            ca[g] = valid[g] ? (-a.lam_cos * a.inv_n / den - l2) * invl[g] : 0.0f;
-            cb[g] = valid[g] ? (((raw > 1e-8f && sf > 0.f) ? a.lam_cos * a.inv_n * cs / sf : 0.0f) + l2) * invl[g]
-                             : 0.0f;
-            if (w == g && h == 0) {
-                if (a.row_cos && valid[g]) a.row_cos[pxg[g]] = cs;
-                // sum of the pixel losses over the valid pixels of 32-pixel block g
-                float lp = valid[g] ? a.lam_cos * (1.0f - cs) + a.lam_l2 * (sf - 2.0f * st + stt) : 0.0f;
-                for (int o = 16; o >= 1; o >>= 1) lp += __shfl_xor(lp, o, kWave);
-                if (col == 0) a.loss_part[blk * NPG + g] = lp;
-            }
-        }
-    }
-    __syncthreads();  // everyone is done reading P~ (region X) and the statistics
-    // G from the re-read rows, staged into LDS [px][D]; delta' = sum_D G F (zero
-    // for the pure cosine term up to rounding)
-#pragma unroll
-    for (int g = 0; g < NPG; ++g) {
+    // row statistics of pixel group g over this wave's D tiles, into its
+    // slots; rows(t, x) yields the group's rows of D tile t
+    auto stats_put = [&](int g, auto&& rows) {
+        float nf = 0.0f, ft = 0.0f, nt = 0.0f;
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
             float x[16];
-            if constexpr (kHold) {
-#pragma unroll
-                for (int r = 0; r < 16; ++r) x[r] = held[kHold ? t : 0][g][r];
-            } else {
-                row_frag(g, t, x);
-            }
+            rows(t, x);
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
-                const float gv = ca[g] * x[r] + cb[g] * acc[t][g][r];
-                delta[g] += gv * acc[t][g][r];
-                x[r] = gv;
+                nf += acc[t][g][r] * acc[t][g][r];
+                ft += acc[t][g][r] * x[r];
+                nt += x[r] * x[r];
+            }
+        }
+        nf += __shfl_xor(nf, 32, kWave);
+        ft += __shfl_xor(ft, 32, kWave);
+        nt += __shfl_xor(nt, 32, kWave);
+        if (h == 0) {
+            rslot(0, w, g)[col] = nf;
+            rslot(1, w, g)[col] = ft;
+            rslot(2, w, g)[col] = nt;
+        }
+    };
+    // the reduced statistics of group g: the cosine, the loss and ca, cb
+    auto stats_take = [&](int g) {
+        float sf = 0.f, st = 0.f, stt = 0.f;
+#pragma unroll
+        for (int ww = 0; ww < NW; ++ww) {
+            sf += rslot(0, ww, g)[col];
+            st += rslot(1, ww, g)[col];
+            stt += rslot(2, ww, g)[col];
+        }
+        const float raw = sqrtf(sf) * sqrtf(stt);
+        const float den = fmaxf(raw, 1e-8f);
+        const float cs = st / den;
+        // dL/dF = lam_cos (-(1/n) (T / den - c F / |F|^2)) + lam_l2 (2/n) (F - T),
+        // then divided by l
+        const float l2 = 2.0f * a.lam_l2 * a.inv_n;
+        ca[g] = valid[g] ? (-a.lam_cos * a.inv_n / den - l2) * invl[g] : 0.0f;
+        cb[g] = valid[g] ? (((raw > 1e-8f && sf > 0.f) ? a.lam_cos * a.inv_n * cs / sf : 0.0f) + l2) * invl[g]
+                         : 0.0f;
+        if (w == g && h == 0) {
+            if (a.row_cos && valid[g]) a.row_cos[pxg[g]] = cs;
+            // sum of the pixel losses over the valid pixels of 32-pixel block g
+            float lp = valid[g] ? a.lam_cos * (1.0f - cs) + a.lam_l2 * (sf - 2.0f * st + stt) : 0.0f;
+            for (int o = 16; o >= 1; o >>= 1) lp += __shfl_xor(lp, o, kWave);
+            if (col == 0) a.loss_part[blk * NPG + g] = lp;
+        }
+    };
+    // G of group g from its rows, staged into LDS [px][D]; delta' = sum_D G F
+    // (zero for the pure cosine term up to rounding)
+    auto stage_g = [&](int g, auto&& rows) {
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            float x[16], gv[16];
+            rows(t, x);
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                gv[r] = ca[g] * x[r] + cb[g] * acc[t][g][r];
+                delta[g] += gv[r] * acc[t][g][r];
             }
 #pragma unroll
             for (int g4 = 0; g4 < 4; ++g4) {
                 const int dr = 32 * (w * NT + t) + 8 * g4 + 4 * h;
-                P::store4(X + (g * kPx + col) * ldg + dr, x[4 * g4], x[4 * g4 + 1], x[4 * g4 + 2], x[4 * g4 + 3]);
+                P::store4(X + (g * kPx + col) * ldg + dr, gv[4 * g4], gv[4 * g4 + 1], gv[4 * g4 + 2], gv[4 * g4 + 3]);
             }
         }
         delta[g] += __shfl_xor(delta[g], 32, kWave);
+    };
+    if constexpr (kHold) {
+        float held[NPG][NT][16];
+#pragma unroll
+        for (int g = 0; g < NPG; ++g)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) row_frag(g, t, held[g][t]);
+        if (MODE == MODE_LOSS) {
+            float nf[NPG], ft[NPG], nt[NPG];
+#pragma unroll
+            for (int g = 0; g < NPG; ++g) {
+                nf[g] = ft[g] = nt[g] = 0.0f;
+#pragma unroll
+                for (int t = 0; t < NT; ++t)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        nf[g] += acc[t][g][r] * acc[t][g][r];
+                        ft[g] += acc[t][g][r] * held[g][t][r];
+                        nt[g] += held[g][t][r] * held[g][t][r];
+                    }
+                nf[g] += __shfl_xor(nf[g], 32, kWave);
+                ft[g] += __shfl_xor(ft[g], 32, kWave);
+                nt[g] += __shfl_xor(nt[g], 32, kWave);
+            }
+            __syncthreads();  // every wave is done reading the row sums of pass 2
+            if (h == 0) {
+#pragma unroll
+                for (int g = 0; g < NPG; ++g) {
+                    rslot(0, w, g)[col] = nf[g];
+                    rslot(1, w, g)[col] = ft[g];
+                    rslot(2, w, g)[col] = nt[g];
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int g = 0; g < NPG; ++g) stats_take(g);
+        }
+        __syncthreads();  // everyone is done reading P~ (region X) and the statistics
+#pragma unroll
+        for (int g = 0; g < NPG; ++g) {
+            auto rows = [&](int t, float* x) {
+#pragma unroll
+                for (int r = 0; r < 16; ++r) x[r] = held[g][t][r];
+            };
+            stage_g(g, rows);
+        }
+    } else {
+        __syncthreads();  // as above
+#pragma unroll
+        for (int g = 0; g < NPG; ++g) {
+            auto rows = [&](int t, float* x) { row_frag(g, t, x); };
+            if (MODE == MODE_LOSS) {
+                stats_put(g, rows);
+                __syncthreads();
+                stats_take(g);
+            }
+            stage_g(g, rows);
+        }
     }
     if (h == 0) {
 #pragma unroll

@@ -54,13 +54,23 @@ __device__ inline float exp_cw(float x)
 // exp_cw above), in the order below, so that the integer decisions it takes
 // (culling, radius, footprint, depth key) are a fixed function of the float32
 // inputs.
+//
+// The launch also clears the forward's counters and look-back scratch
+// (zero[0 .. zero_words)), which the sorts after it need at zero: one launch
+// fewer than a separate fill.
 __global__ __launch_bounds__(256) void k_preprocess(
     CamSet cs, int N, const float* __restrict__ means, const float* __restrict__ log_scales,
     const float* __restrict__ quats, const float* __restrict__ logits, float4* __restrict__ rec0,
     float4* __restrict__ rec1, uint2* __restrict__ foot, uint32_t* __restrict__ depth_key,
-    uint32_t* __restrict__ ntiles)
+    uint32_t* __restrict__ ntiles, uint32_t* __restrict__ zero, size_t zero_words)
 {
 #pragma clang fp contract(off)
+    {
+        const size_t nthreads = (size_t)gridDim.x * gridDim.y * blockDim.x;
+        for (size_t k = ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * blockDim.x + threadIdx.x; k < zero_words;
+             k += nthreads)
+            zero[k] = 0u;
+    }
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
     const Cam& cam = cs.c[blockIdx.y];
@@ -847,14 +857,18 @@ hipError_t render_forward_launch(lam_ctx* ctx, const RenderArgs& A, const Render
     const CamSet& cs = L.cams;
     const uint32_t R = (uint32_t)L.records;
     const uint32_t cap = (uint32_t)L.capacity;
-    // counters and every look-back scratch of the sorts start at zero
-    hipError_t e = launch_fill_u32(L.counters, (size_t)(L.zero_end - L.counters), 0u, st);
-    if (e != hipSuccess) return e;
-    if (A.n > 0) {
+    // counters and every look-back scratch of the sorts start at zero (cleared
+    // by the projection launch when there is one)
+    hipError_t e = hipSuccess;
+    const size_t zero_words = (size_t)(L.zero_end - L.counters);
+    if (A.n > 0 && cs.n > 0) {
         ProfScope ps(ctx, "preprocess", st);
         hipLaunchKernelGGL(k_preprocess, dim3((A.n + 255) / 256, cs.n), dim3(256), 0, st, cs, A.n,
                            A.means, A.log_scales, A.quats, A.logits, L.rec0, L.rec1, L.foot,
-                           L.depth_key, L.ntiles);
+                           L.depth_key, L.ntiles, L.counters, zero_words);
+    } else {
+        e = launch_fill_u32(L.counters, zero_words, 0u, st);
+        if (e != hipSuccess) return e;
     }
     bool in_b = false;
     const uint32_t* tkeys;
