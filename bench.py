@@ -741,7 +741,13 @@ def traffic_for(kernel, workload, options=None):
         return None
     if ent.get("source_hash") != profiling.source_hash(profiling.STAGES[kernel][1]):
         return None
-    if options is not None and ent.get("options") is not None and ent["options"] != options:
+    # only the options that change the kernel's bytes must match: the decode
+    # block shape for the rows kernel, also the split count for the dV partials,
+    # the tile shape for the compositing kernels
+    keys = {"decode_rows": ("decode_shape",), "decode_tn": ("decode_shape", "decode_splits"),
+            "raster_fwd": ("tile",), "raster_bwd": ("tile",)}.get(kernel, ())
+    rec_opts = ent.get("options") or {}
+    if options is not None and any(k in rec_opts and rec_opts[k] != options.get(k) for k in keys):
         return None
     return ent.get("bytes_per_launch")
 
