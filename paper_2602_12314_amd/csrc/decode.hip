@@ -303,7 +303,7 @@ constexpr int pipe_depth()
 // 64-pixel block with four D tiles per wave keeps the short ring so that it
 // fits two waves per SIMD (the other wave hides the latency).
 template <bool F8, int NT, int NPG, int NW>
-constexpr bool kDeepRing = (F8 || NT * NPG > 4) && !(NW == 8 && NT * NPG >= 8);
+constexpr bool kDeepRing = (F8 || NT * NPG > 4) && !(NW == 8 && (NT * NPG >= 8 || (F8 && NT >= 2)));
 
 // Workgroup shape of k_dec_rows: NW waves and NPG groups of 32 pixels.  Every
 // wave covers all NPG x 32 pixels of the block and 1 / NW of the D columns
@@ -525,11 +525,18 @@ __global__ __launch_bounds__(NW * kWave) void k_dec_rows(RowsArgs a)
             const i32x8 bf = {b0[0], b0[1], b0[2], b0[3], b1[0], b1[1], b1[2], b1[3]};
             return bf;
         };
-        // at most four D tiles per sweep over the atoms keeps the ring at 64 registers
-        constexpr int NH = NT < 4 ? NT : 4;
+        // the D tiles of a sweep over the atoms: a divisor of NT, at most four
+        // (the ring then holds at most 64 registers); the 64-pixel block takes
+        // at most two per sweep and loads the weights' fragments from LDS just
+        // before their MFMAs (one buffer, the other wave of the SIMD covering
+        // the LDS latency), which keeps it within two waves per SIMD
+        constexpr bool kWideF8 = NW == 8;
+        constexpr int NH = kWideF8 ? (NT % 2 == 0 ? 2 : 1)
+                                   : (NT % 4 == 0 ? 4 : (NT % 3 == 0 ? 3 : (NT % 2 == 0 ? 2 : 1)));
+        static_assert(NT % NH == 0, "whole sweeps");
 #pragma unroll
         for (int t0 = 0; t0 < NT; t0 += NH) {
-            i32x8 ra[NH], rb[NH], ba[NPG][2], bb[NPG][2];
+            i32x8 ra[NH], rb[NH], ba[kWideF8 ? 1 : NPG][2], bb[kWideF8 ? 1 : NPG][2];
             auto vload = [&](int c, i32x8* af) {
 #pragma unroll
                 for (int t = 0; t < NH; ++t)
@@ -552,19 +559,44 @@ __global__ __launch_bounds__(NW * kWave) void k_dec_rows(RowsArgs a)
 #pragma unroll
                     for (int part = 0; part < 2; ++part) bf[g][part] = bload(c, g, part);
             };
-            vload(0, ra);
-            pload(0, ba);
-            for (int c = 0; c < nc8; c += 2) {
-                if (c + 1 < nc8) {
-                    vload(c + 1, rb);
-                    pload(c + 1, bb);
+            if constexpr (kWideF8) {
+                // one E4M3 term of both pixel groups at a time
+                auto mma8p = [&](int c, const i32x8* af) {
+#pragma unroll
+                    for (int part = 0; part < 2; ++part) {
+                        i32x8 bp[NPG];
+#pragma unroll
+                        for (int g = 0; g < NPG; ++g) bp[g] = bload(c, g, part);
+#pragma unroll
+                        for (int t = 0; t < NH; ++t)
+#pragma unroll
+                            for (int g = 0; g < NPG; ++g)
+                                acc[t0 + t][g] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+                                    af[t], bp[g], acc[t0 + t][g], 0, 0, 0, 127, 0, 127);
+                    }
+                };
+                vload(0, ra);
+                for (int c = 0; c < nc8; c += 2) {
+                    if (c + 1 < nc8) vload(c + 1, rb);
+                    mma8p(c, ra);
+                    if (c + 2 < nc8) vload(c + 2, ra);
+                    if (c + 1 < nc8) mma8p(c + 1, rb);
                 }
-                mma8(ra, ba);
-                if (c + 2 < nc8) {
-                    vload(c + 2, ra);
-                    pload(c + 2, ba);
+            } else {
+                vload(0, ra);
+                pload(0, ba);
+                for (int c = 0; c < nc8; c += 2) {
+                    if (c + 1 < nc8) {
+                        vload(c + 1, rb);
+                        pload(c + 1, bb);
+                    }
+                    mma8(ra, ba);
+                    if (c + 2 < nc8) {
+                        vload(c + 2, ra);
+                        pload(c + 2, ba);
+                    }
+                    if (c + 1 < nc8) mma8(rb, bb);
                 }
-                if (c + 1 < nc8) mma8(rb, bb);
             }
         }
     } else {
@@ -1266,7 +1298,7 @@ constexpr size_t kMaxLds = 160 * 1024;  // LDS of a gfx950 workgroup
 // at D = 256 (its two weight terms per fragment would spill from 512 on).
 static bool wide_ok(int prec, int Mp, int D)
 {
-    const int max_nt = prec == LAM_FP8_E4M3 ? 1 : 4;
+    const int max_nt = 4;
     return prec != LAM_FP32 && D % 256 == 0 && D / 256 <= max_nt && rows_lds(prec, Mp, D, 8, 2) <= kMaxLds;
 }
 
@@ -1375,12 +1407,10 @@ static hipError_t launch_rows(lam_ctx* ctx, const RowsArgs& ra, bool wide, int n
     LAM_ROWS(4, 1, 5, 16) LAM_ROWS(4, 1, 6, 16) LAM_ROWS(4, 1, 7, 16) LAM_ROWS(4, 1, 8, 16)
     LAM_ROWS(4, 1, 1, 32) LAM_ROWS(4, 1, 2, 32) LAM_ROWS(4, 1, 3, 32) LAM_ROWS(4, 1, 4, 32)
     LAM_ROWS(4, 1, 5, 32) LAM_ROWS(4, 1, 6, 32) LAM_ROWS(4, 1, 7, 32) LAM_ROWS(4, 1, 8, 32)
-    if constexpr (P::kBytes == 2) {  // the 64 x 8 shape (wide_ok): BF16 up to 4 D tiles a wave, E4M3 1
+    if constexpr (P::kBytes == 2) {  // the 64 x 8 shape (wide_ok): up to 4 D tiles a wave
         LAM_ROWS(8, 2, 1, 16) LAM_ROWS(8, 2, 1, 32)
-        if constexpr (!F8) {
-            LAM_ROWS(8, 2, 2, 16) LAM_ROWS(8, 2, 2, 32) LAM_ROWS(8, 2, 3, 16) LAM_ROWS(8, 2, 3, 32)
-            LAM_ROWS(8, 2, 4, 16) LAM_ROWS(8, 2, 4, 32)
-        }
+        LAM_ROWS(8, 2, 2, 16) LAM_ROWS(8, 2, 2, 32) LAM_ROWS(8, 2, 3, 16) LAM_ROWS(8, 2, 3, 32)
+        LAM_ROWS(8, 2, 4, 16) LAM_ROWS(8, 2, 4, 32)
     }
 #undef LAM_ROWS
     return hipErrorInvalidValue;
