@@ -123,8 +123,8 @@ typedef struct lam_ctx lam_ctx;
  *   "decode_shape"     workgroup shape of the per-pixel decode kernel:
  *                      0 = 32 pixels with 4 waves (default); 1 = 64 pixels
  *                      with 8 waves, each V fragment feeding two pixel groups
- *                      (BF16 with D a multiple of 256 up to 768, E4M3 up to
- *                      512; other shapes keep 0).  Results agree to rounding
+ *                      (BF16 and E4M3 with D a multiple of 256 up to 1024;
+ *                      other shapes keep 0).  Results agree to rounding
  *                      (the per-pixel sums over the waves split differently).
  *   "decode_splits"    pixel-range splits of the dV GEMM (the larger of the
  *                      two dictionary-gradient GEMMs; a multiple of 8 in

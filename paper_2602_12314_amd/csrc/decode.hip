@@ -349,24 +349,29 @@ __global__ __launch_bounds__(NW * kWave) void k_dec_rows(RowsArgs a)
     const T* Vt = reinterpret_cast<const T*>(a.Vt);
     const T* Ktp = reinterpret_cast<const T*>(a.Ktp);
 
-    // query fragments (B operand of S^T = K Q^T): Q[px][16 c + 8 h + t]
+    // query fragments (B operand of S^T = K Q^T): Q[px][16 c + 8 h + t].  They
+    // are loaded again for the dP loop rather than held across the F
+    // contraction, whose registers they would take (the rows are in L2).
     Frag qf[NPG][NQ];
+    auto load_qf = [&]() {
 #pragma unroll
-    for (int g = 0; g < NPG; ++g)
+        for (int g = 0; g < NPG; ++g)
 #pragma unroll
-        for (int c = 0; c < NQ; ++c) {
-            float v[8];
-            if (valid[g]) {
-                const float4* qp = reinterpret_cast<const float4*>(a.Q + (size_t)pxg[g] * DQ + 16 * c + 8 * h);
-                const float4 x0 = qp[0], x1 = qp[1];
-                v[0] = x0.x; v[1] = x0.y; v[2] = x0.z; v[3] = x0.w;
-                v[4] = x1.x; v[5] = x1.y; v[6] = x1.z; v[7] = x1.w;
-            } else {
+            for (int c = 0; c < NQ; ++c) {
+                float v[8];
+                if (valid[g]) {
+                    const float4* qp = reinterpret_cast<const float4*>(a.Q + (size_t)pxg[g] * DQ + 16 * c + 8 * h);
+                    const float4 x0 = qp[0], x1 = qp[1];
+                    v[0] = x0.x; v[1] = x0.y; v[2] = x0.z; v[3] = x0.w;
+                    v[4] = x1.x; v[5] = x1.y; v[6] = x1.z; v[7] = x1.w;
+                } else {
 #pragma unroll
-                for (int t = 0; t < 8; ++t) v[t] = 0.0f;
+                    for (int t = 0; t < 8; ++t) v[t] = 0.0f;
+                }
+                qf[g][c] = P::from_f32(v);
             }
-            qf[g][c] = P::from_f32(v);
-        }
+    };
+    load_qf();
     // Q^T of 32-pixel block g for the dK reduction, written by wave g (rows >= d zero)
     if (MODE != MODE_INFER) {
 #pragma unroll
@@ -834,6 +839,7 @@ __global__ __launch_bounds__(NW * kWave) void k_dec_rows(RowsArgs a)
     }
 
     // ---- per atom tile: dP = G V^T, dS = P~ (dP - delta) / sqrt(d), dQ^T += K^T dS^T
+    load_qf();
     f32x16 dq[NPG];
 #pragma unroll
     for (int g = 0; g < NPG; ++g) dq[g] = f32x16{};
