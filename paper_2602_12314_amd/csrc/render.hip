@@ -176,12 +176,15 @@ __global__ __launch_bounds__(256) void k_preprocess(
 // tiles do not serialise one thread.  Pair o belongs to the depth-sorted
 // record s with offsets[s] <= o < offsets[s + 1], and is that record's
 // (o - offsets[s])-th tile of its footprint, rows outer.  A workgroup takes
-// 256 consecutive pairs: every visible record emits at least one pair and
-// culled records (key 0xFFFFFFFF) sort last, so those pairs belong to a run
-// of at most 256 consecutive records.  The run's first record is found by
+// chunks of 256 consecutive pairs, a contiguous range of them: every visible
+// record emits at least one pair and culled records (key 0xFFFFFFFF) sort
+// last, so a chunk's pairs belong to a run of at most 256 consecutive
+// records.  The run's offsets are staged in LDS and each thread finds its
+// record there.  The first record of the workgroup's first chunk is found by
 // rounds of 256 probes, each narrowing the range 256-fold (three rounds for
-// up to 2^24 records instead of one dependent load per halving), the run's
-// offsets are staged in LDS, and each thread finds its record there.
+// up to 2^24 records instead of one dependent load per halving); that of each
+// later chunk is read off the staged run of the chunk before it, unless the
+// run ends first (then the probes again).
 __global__ __launch_bounds__(256) void k_emit(CamSet cs, int N, uint32_t R,
                                              const uint32_t* __restrict__ sorted_rec,
                                              const uint32_t* __restrict__ offsets,
@@ -191,20 +194,32 @@ __global__ __launch_bounds__(256) void k_emit(CamSet cs, int N, uint32_t R,
                                              uint32_t* __restrict__ vals)
 {
     __shared__ uint32_t run[257];
+    __shared__ uint32_t next_s0;
     const uint32_t total = counters[0] < cap ? counters[0] : cap;
-    for (uint32_t o0 = blockIdx.x * 256u; o0 < total; o0 += gridDim.x * 256u) {
-        // largest s in [lo, hi) with offsets[s] <= o0 (offsets[0] = 0 <= o0)
-        uint32_t lo = 0, hi = R;
-        while (hi - lo > 1) {
-            const uint32_t stride = (hi - lo + 255) / 256;
-            const uint32_t idx = lo + threadIdx.x * stride;
-            const int le = idx < hi && offsets[idx] <= o0;
-            const uint32_t k = (uint32_t)__syncthreads_count(le);  // a prefix of the probes
-            const uint32_t nlo = lo + (k - 1) * stride;
-            hi = nlo + stride < hi ? nlo + stride : hi;
-            lo = nlo;
+    const uint32_t nchunks = (total + 255) / 256;
+    const uint32_t per = (nchunks + gridDim.x - 1) / gridDim.x;
+    const uint32_t c0 = blockIdx.x * per;
+    const uint32_t c1 = c0 + per < nchunks ? c0 + per : nchunks;
+    bool known = false;  // next_s0 holds the first record of chunk c
+    for (uint32_t c = c0; c < c1; ++c) {
+        const uint32_t o0 = c * 256u;
+        uint32_t s0;
+        if (known) {
+            s0 = next_s0;
+        } else {
+            // largest s in [lo, hi) with offsets[s] <= o0 (offsets[0] = 0 <= o0)
+            uint32_t lo = 0, hi = R;
+            while (hi - lo > 1) {
+                const uint32_t stride = (hi - lo + 255) / 256;
+                const uint32_t idx = lo + threadIdx.x * stride;
+                const int le = idx < hi && offsets[idx] <= o0;
+                const uint32_t k = (uint32_t)__syncthreads_count(le);  // a prefix of the probes
+                const uint32_t nlo = lo + (k - 1) * stride;
+                hi = nlo + stride < hi ? nlo + stride : hi;
+                lo = nlo;
+            }
+            s0 = lo;
         }
-        const uint32_t s0 = lo;
         const uint32_t si = s0 + threadIdx.x;
         run[threadIdx.x] = si < R ? offsets[si] : 0xFFFFFFFFu;
         if (threadIdx.x == 0) run[256] = s0 + 256 < R ? offsets[s0 + 256] : 0xFFFFFFFFu;
@@ -219,10 +234,10 @@ __global__ __launch_bounds__(256) void k_emit(CamSet cs, int N, uint32_t R,
             }
             const uint32_t s = s0 + a;
             const uint32_t r = sorted_rec[s];
-            const int c = (int)(r / (uint32_t)N);
+            const int cam = (int)(r / (uint32_t)N);
             int tbase = 0, tx_n = 1;
             for (int k = 0; k < cs.n; ++k)
-                if (k == c) { tbase = cs.c[k].tile_base; tx_n = cs.c[k].tiles_x; }
+                if (k == cam) { tbase = cs.c[k].tile_base; tx_n = cs.c[k].tiles_x; }
             const uint2 f = foot[r];
             const int x0 = (f.x & 0xFFFF) >> cs.tile_shift_x, x1 = (f.x >> 16) >> cs.tile_shift_x;
             const int y0 = (f.y & 0xFFFF) >> cs.tile_shift_y;
@@ -232,7 +247,20 @@ __global__ __launch_bounds__(256) void k_emit(CamSet cs, int N, uint32_t R,
             keys[o] = (uint32_t)(tbase + ty * tx_n + tx);
             vals[o] = r;
         }
-        __syncthreads();  // run[] is rewritten by the next chunk
+        // the next chunk's first record: the largest j with run[j] <= o0 + 256,
+        // if the run reaches past that pair (run[256] > o0 + 256)
+        const uint32_t on = o0 + 256u;
+        known = run[256] > on;
+        if (known && threadIdx.x == 0) {
+            uint32_t a = 0, b = 257;
+            while (b - a > 1) {
+                const uint32_t m = (a + b) >> 1;
+                if (run[m] <= on) a = m;
+                else b = m;
+            }
+            next_s0 = s0 + a;
+        }
+        __syncthreads();  // run[] is rewritten by the next chunk; next_s0 is read
     }
 }
 
