@@ -322,7 +322,7 @@ __global__ __launch_bounds__(NW * kWave) void k_dec_rows(RowsArgs a)
     extern __shared__ __align__(16) char smem[];
     // LDS: red [4][NW][BPX] floats of per-pixel statistics, the waves' dS
     // staging tiles [NW][32][kScLd], then region X (P~ [BPX][Mp+8], later
-    // G [BPX][D+8], later the dQ reduction [NW][32][BPX] floats)
+    // G [BPX][D+8], later the dQ reduction [NW][32][BPX + 2] floats)
     const int w = threadIdx.x / kWave;
     const int lane = threadIdx.x % kWave;
     float* red = reinterpret_cast<float*>(smem);
@@ -931,17 +931,21 @@ __global__ __launch_bounds__(NW * kWave) void k_dec_rows(RowsArgs a)
     }
     if (!a.dQ) return;
     __syncthreads();  // region X (G) no longer read
+    // [NW][32][BPX + 2] floats: with the two-float pad the reads below, 32
+    // lanes of one pixel at consecutive k, fall on banks 2 k + p, distinct over
+    // the wave (unpadded, a pixel's 32 lanes would share one bank)
+    constexpr int RLD = BPX + 2;
     float* dqr = reinterpret_cast<float*>(X);
 #pragma unroll
     for (int g = 0; g < NPG; ++g)
 #pragma unroll
-        for (int r = 0; r < 16; ++r) dqr[(w * 32 + crow(r, h)) * BPX + g * kPx + col] = dq[g][r];
+        for (int r = 0; r < 16; ++r) dqr[(w * 32 + crow(r, h)) * RLD + g * kPx + col] = dq[g][r];
     __syncthreads();
     for (int i = threadIdx.x; i < BPX * DQ; i += NTH) {
         const int p = i / DQ, k = i % DQ;
         float v = 0.0f;
 #pragma unroll
-        for (int ww = 0; ww < NW; ++ww) v += dqr[(ww * 32 + k) * BPX + p];
+        for (int ww = 0; ww < NW; ++ww) v += dqr[(ww * 32 + k) * RLD + p];
         const int gp = blk * BPX + p;
         if (gp < a.n) a.dQ[(size_t)gp * DQ + k] = v;
     }
@@ -1293,15 +1297,14 @@ static size_t rows_lds(int prec, int Mp, int D, int NW, int NPG)
     const size_t bpx = (size_t)kPx * NPG;
     size_t x = std::max(bpx * (Mp + 8) * tb, bpx * (D + 8) * tb);
     if (prec == LAM_FP8_E4M3) x = std::max(x, 2 * bpx * (Mp + 16));  // the weights' two E4M3 terms
-    x = std::max(x, (size_t)NW * 32 * bpx * 4);  // dQ reduction
+    x = std::max(x, (size_t)NW * 32 * (bpx + 2) * 4);  // dQ reduction
     return 4 * NW * bpx * 4 + (size_t)NW * kPx * kScLd * tb + x;
 }
 
 constexpr size_t kMaxLds = 160 * 1024;  // LDS of a gfx950 workgroup
 
 // 64-pixel blocks of 8 waves (each V fragment feeds two MFMAs) where the
-// registers and LDS allow: BF16 with D a multiple of 256 up to 1024, E4M3 only
-// at D = 256 (its two weight terms per fragment would spill from 512 on).
+// registers and LDS allow: BF16 and E4M3 with D a multiple of 256 up to 1024.
 static bool wide_ok(int prec, int Mp, int D)
 {
     const int max_nt = 4;
