@@ -870,10 +870,16 @@ __global__ __launch_bounds__(NW * kWave) void k_dec_rows(RowsArgs a)
         }
     };
     // TT atom tiles per iteration share each G fragment read from LDS, and each
-    // V fragment feeds the NPG pixel groups; the fragments run PG chunks ahead of
-    // the MFMAs, and the K fragments of the dS step are requested before the
-    // contraction that hides their latency.
-    constexpr int PG = pipe_depth<kDeepRing<F8, NT, NPG, NW>>();
+    // V fragment feeds the NPG pixel groups; the V fragments (from L2) run PV
+    // chunks ahead of the MFMAs and the G fragments (from LDS) PGD chunks, and
+    // the K fragments of the dS step are requested before the contraction that
+    // hides their latency.  The 8-wave block has registers to spare in this
+    // loop (not in the F contraction), so its V ring is 8 chunks deep: the two
+    // MFMAs of a chunk are far shorter than an L2 round trip.  Its D is a
+    // multiple of 256, so the 16-wide chunk count ncd is a multiple of PV.
+    constexpr int PV = NW == 8 ? 8 : pipe_depth<kDeepRing<F8, NT, NPG, NW>>();
+    constexpr int PGD = NW == 8 ? 2 : PV;
+    static_assert(PGD >= 2 && PV % PGD == 0, "G ring within the V ring");
     for (int tt = w; tt < ntiles; tt += TT * NW) {
         bool has[TT];
         int tj[TT];
@@ -896,10 +902,12 @@ __global__ __launch_bounds__(NW * kWave) void k_dec_rows(RowsArgs a)
         for (int j = 0; j < TT; ++j)
 #pragma unroll
             for (int g = 0; g < NPG; ++g) dp[j][g] = f32x16{};
-        Frag rv[PG][TT], gb[PG][NPG];
-        auto fetch = [&](int c, Frag* v, Frag* gg) {
+        Frag rv[PV][TT], gb[PGD][NPG];
+        auto vfetch = [&](int c, Frag* v) {
 #pragma unroll
             for (int j = 0; j < TT; ++j) v[j] = load_frag<P>(Vb, tj[j], c, ncd, lane);
+        };
+        auto gfetch = [&](int c, Frag* gg) {
 #pragma unroll
             for (int g = 0; g < NPG; ++g) gg[g] = P::load(X + (g * kPx + col) * ldg + 16 * c + 8 * h);
         };
@@ -910,18 +918,23 @@ __global__ __launch_bounds__(NW * kWave) void k_dec_rows(RowsArgs a)
                 for (int g = 0; g < NPG; ++g) P::mma(dp[j][g], v[j], gg[g]);
         };
 #pragma unroll
-        for (int s = 0; s < PG - 1; ++s) fetch(s, rv[s], gb[s]);
-        for (int c0 = 0; c0 < ncd - PG; c0 += PG) {
+        for (int s = 0; s < PV - 1; ++s) vfetch(s, rv[s]);
 #pragma unroll
-            for (int s = 0; s < PG; ++s) {
-                const int sl = (s + PG - 1) % PG;
-                fetch(c0 + s + PG - 1, rv[sl], gb[sl]);
-                mma(rv[s], gb[s]);
+        for (int s = 0; s < PGD - 1; ++s) gfetch(s, gb[s]);
+        for (int c0 = 0; c0 < ncd - PV; c0 += PV) {
+#pragma unroll
+            for (int s = 0; s < PV; ++s) {
+                vfetch(c0 + s + PV - 1, rv[(s + PV - 1) % PV]);
+                gfetch(c0 + s + PGD - 1, gb[(s + PGD - 1) % PGD]);
+                mma(rv[s], gb[s % PGD]);
             }
         }
-        fetch(ncd - 1, rv[PG - 1], gb[PG - 1]);
+        vfetch(ncd - 1, rv[PV - 1]);
 #pragma unroll
-        for (int s = 0; s < PG; ++s) mma(rv[s], gb[s]);
+        for (int s = 0; s < PV; ++s) {
+            if (s + PGD - 1 < PV) gfetch(ncd - PV + s + PGD - 1, gb[(s + PGD - 1) % PGD]);
+            mma(rv[s], gb[s % PGD]);
+        }
 #pragma unroll
         for (int j = 0; j < TT; ++j)
             if (has[j]) {
