@@ -20,6 +20,13 @@
         the figures into FILE keyed by workload and the bench's stage names,
         together with the hash of the kernel sources they were taken on.
 
+    python -m paper_2602_12314_amd.profiling timeline DIR [--step K]
+        the launches of one step of a ``--kernel-trace`` run in start order,
+        from the K-th projection launch (``k_preprocess``; default the third
+        from last) to the next: start and end relative to the step's first
+        launch and the duration, in microseconds.  Launches on the two streams
+        of a step interleave, so overlapping rows show what ran beside what.
+
 Counter values are KiB per dispatch (rocprofv3's derived FETCH_SIZE and
 WRITE_SIZE).
 """
@@ -120,6 +127,9 @@ def main(argv=None):
     c = sub.add_parser("counters")
     c.add_argument("dir")
     c.add_argument("prefix", nargs="?", default="")
+    tl = sub.add_parser("timeline")
+    tl.add_argument("dir")
+    tl.add_argument("--step", type=int, default=-3)
     t = sub.add_parser("traffic")
     t.add_argument("--workload", required=True)
     for k in ("fetch", "write", "copy-fetch", "copy-write"):
@@ -146,6 +156,24 @@ def main(argv=None):
         print("|---|---|---|---|---|")
         for k, calls, tot, avg, pct in kernel_stats(a.dir):
             print(f"| {k} | {calls} | {tot:.1f} | {avg:.2f} | {pct:.1f} |")
+        return 0
+    if a.cmd == "timeline":
+        rows = sorted(csv.DictReader(open(_one(a.dir, "*kernel_trace.csv"))), key=lambda r: int(r["Start_Timestamp"]))
+        pre = [i for i, r in enumerate(rows) if short(r["Kernel_Name"]) == "k_preprocess"]
+        if len(pre) < 2:
+            raise SystemExit("fewer than two k_preprocess launches in the trace")
+        k = a.step % len(pre)
+        if k + 1 >= len(pre):
+            raise SystemExit("the chosen step has no following k_preprocess launch")
+        i, j = pre[k], pre[k + 1]
+        t0 = int(rows[i]["Start_Timestamp"])
+        print("| start us | end us | duration us | kernel | grid (threads) |")
+        print("|---|---|---|---|---|")
+        for r in rows[i:j]:
+            s0, e0 = int(r["Start_Timestamp"]) - t0, int(r["End_Timestamp"]) - t0
+            print(f"| {s0 / 1e3:.2f} | {e0 / 1e3:.2f} | {(e0 - s0) / 1e3:.2f} | {short(r['Kernel_Name'])} "
+                  f"| {r['Grid_Size_X']} |")
+        print(f"\nnext step's projection starts at {(int(rows[j]['Start_Timestamp']) - t0) / 1e3:.2f} us")
         return 0
     if a.cmd == "counters":
         acc = defaultdict(lambda: defaultdict(list))
