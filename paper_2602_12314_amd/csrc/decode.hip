@@ -299,9 +299,11 @@ constexpr int pipe_depth()
     return DEEP ? 4 : 2;
 }
 
-// The deep ring where one wave per SIMD is all the registers allow; the
-// 64-pixel block with four D tiles per wave keeps the short ring so that it
-// fits two waves per SIMD (the other wave hides the latency).
+// Depth of the uniform rings (the F contraction's V^T and weight fragments
+// together, and the 32-pixel block's dP loop): deep where one wave per SIMD
+// is all the registers allow.  The 64-pixel block keeps two waves per SIMD:
+// it takes the short ring where a deep one would not fit, and its dP loop and
+// its F contraction at four D tiles a wave have rings of their own.
 template <bool F8, int NT, int NPG, int NW>
 constexpr bool kDeepRing = (F8 || NT * NPG > 4) && !(NW == 8 && (NT * NPG >= 8 || (F8 && NT >= 2)));
 
@@ -608,32 +610,64 @@ __global__ __launch_bounds__(NW * kWave) void k_dec_rows(RowsArgs a)
         // ring of PD chunks: chunk c + PD - 1 is loaded while chunk c is multiplied.
         // The loads are unconditional (the last PD chunks are peeled) so that
         // each MFMA waits only for its own fragments.
-        constexpr int PD = pipe_depth<kDeepRing<F8, NT, NPG, NW>>();
-        Frag ring[PD][NT], bring[PD][NPG];
-        auto fetch = [&](int c, Frag* r, Frag* b) {
+        if constexpr (NW == 8 && NT * NPG >= 8) {
+            // the 64-pixel block with four D tiles a wave, whose uniform ring
+            // could only be two deep: V^T chunks four deep instead, and the
+            // weights' fragments read from LDS just before their MFMAs (the
+            // SIMD's other wave covers that latency), as in the E4M3 product
+            constexpr int PF = 4;
+            Frag vr[PF][NT];
+            auto vget = [&](int c, Frag* r) {
 #pragma unroll
-            for (int t = 0; t < NT; ++t) r[t] = load_frag<P>(Vt, w * NT + t, c, nca, lane);
+                for (int t = 0; t < NT; ++t) r[t] = load_frag<P>(Vt, w * NT + t, c, nca, lane);
+            };
 #pragma unroll
-            for (int g = 0; g < NPG; ++g) b[g] = P::load(X + (g * kPx + col) * ldp + 16 * c + 8 * h);
-        };
-        auto mma = [&](const Frag* r, const Frag* b) {
+            for (int s = 0; s < PF - 1; ++s)
+                if (s < nca) vget(s, vr[s]);
+            for (int c0 = 0; c0 < nca; c0 += PF) {
 #pragma unroll
-            for (int t = 0; t < NT; ++t)
+                for (int s = 0; s < PF; ++s) {
+                    const int c = c0 + s;
+                    if (c < nca) {
+                        if (c + PF - 1 < nca) vget(c + PF - 1, vr[(s + PF - 1) % PF]);
+                        Frag b[NPG];
 #pragma unroll
-                for (int g = 0; g < NPG; ++g) P::mma(acc[t][g], r[t], b[g]);
-        };
+                        for (int g = 0; g < NPG; ++g) b[g] = P::load(X + (g * kPx + col) * ldp + 16 * c + 8 * h);
 #pragma unroll
-        for (int s = 0; s < PD - 1; ++s) fetch(s, ring[s], bring[s]);
-        for (int c0 = 0; c0 < nca - PD; c0 += PD) {
+                        for (int t = 0; t < NT; ++t)
 #pragma unroll
-            for (int s = 0; s < PD; ++s) {
-                fetch(c0 + s + PD - 1, ring[(s + PD - 1) % PD], bring[(s + PD - 1) % PD]);
-                mma(ring[s], bring[s]);
+                            for (int g = 0; g < NPG; ++g) P::mma(acc[t][g], vr[s][t], b[g]);
+                    }
+                }
             }
-        }
-        fetch(nca - 1, ring[PD - 1], bring[PD - 1]);
+        } else {
+            constexpr int PD = pipe_depth<kDeepRing<F8, NT, NPG, NW>>();
+            Frag ring[PD][NT], bring[PD][NPG];
+            auto fetch = [&](int c, Frag* r, Frag* b) {
 #pragma unroll
-        for (int s = 0; s < PD; ++s) mma(ring[s], bring[s]);
+                for (int t = 0; t < NT; ++t) r[t] = load_frag<P>(Vt, w * NT + t, c, nca, lane);
+#pragma unroll
+                for (int g = 0; g < NPG; ++g) b[g] = P::load(X + (g * kPx + col) * ldp + 16 * c + 8 * h);
+            };
+            auto mma = [&](const Frag* r, const Frag* b) {
+#pragma unroll
+                for (int t = 0; t < NT; ++t)
+#pragma unroll
+                    for (int g = 0; g < NPG; ++g) P::mma(acc[t][g], r[t], b[g]);
+            };
+#pragma unroll
+            for (int s = 0; s < PD - 1; ++s) fetch(s, ring[s], bring[s]);
+            for (int c0 = 0; c0 < nca - PD; c0 += PD) {
+#pragma unroll
+                for (int s = 0; s < PD; ++s) {
+                    fetch(c0 + s + PD - 1, ring[(s + PD - 1) % PD], bring[(s + PD - 1) % PD]);
+                    mma(ring[s], bring[s]);
+                }
+            }
+            fetch(nca - 1, ring[PD - 1], bring[PD - 1]);
+#pragma unroll
+            for (int s = 0; s < PD; ++s) mma(ring[s], bring[s]);
+        }
     }
 #pragma unroll
     for (int g = 0; g < NPG; ++g) {
