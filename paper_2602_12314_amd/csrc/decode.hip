@@ -323,7 +323,8 @@ __global__ __launch_bounds__(NW * kWave) void k_dec_rows(RowsArgs a)
     constexpr int TT = NPG == 1 ? 2 : 1;  // atom tiles per dP iteration
     extern __shared__ __align__(16) char smem[];
     // LDS: red [4][NW][BPX] floats of per-pixel statistics, the waves' dS
-    // staging tiles [NW][32][kScLd], then region X (P~ [BPX][Mp+8], later
+    // staging tiles [NW][32][kScLd] (before the dP loop the E4M3 V scales
+    // [Mp] floats), then region X (P~ [BPX][Mp+8], later
     // G [BPX][D+8], later the dQ reduction [NW][32][BPX + 2] floats)
     const int w = threadIdx.x / kWave;
     const int lane = threadIdx.x % kWave;
@@ -414,6 +415,14 @@ __global__ __launch_bounds__(NW * kWave) void k_dec_rows(RowsArgs a)
         }
     };
 
+    // The E4M3 weights' per-atom V scales, read once per atom tile in pass 2,
+    // staged in the dS scratch region (unused before the dP loop; pass 1's
+    // barriers come first), which holds the largest Mp (2048) floats.
+    static_assert(!F8 || NW * kPx * kScLd * sizeof(T) >= 2048 * sizeof(float), "V scales fit the dS scratch");
+    float* svs = reinterpret_cast<float*>(smem + 4 * NW * BPX * sizeof(float));
+    if (F8) {
+        for (int i = threadIdx.x; i < a.Mp; i += NTH) svs[i] = a.sv_fold[i];
+    }
     // ---- pass 1: row max of the logits (in log2 units)
     float mx[NPG];
 #pragma unroll
@@ -476,7 +485,7 @@ __global__ __launch_bounds__(NW * kWave) void k_dec_rows(RowsArgs a)
                     // The weights go in as two E4M3 terms, the rounded value and the
                     // rounded residual (relative error 2^-8 instead of 2^-4), so
                     // that F carries only the E4M3 rounding of V.
-                    const float4 sv = *reinterpret_cast<const float4*>(a.sv_fold + atom0);
+                    const float4 sv = *reinterpret_cast<const float4*>(svs + atom0);
                     const float q0 = p[4 * g4] * sv.x, q1 = p[4 * g4 + 1] * sv.y;
                     const float q2 = p[4 * g4 + 2] * sv.z, q3 = p[4 * g4 + 3] * sv.w;
                     int hi = __builtin_amdgcn_cvt_pk_fp8_f32(q0, q1, 0, false);
