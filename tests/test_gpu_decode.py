@@ -152,8 +152,10 @@ def test_fp8_meets_bars_with_unit_queries(shape):
 
 
 # 64-pixel x 8-wave workgroups (the context option "decode_shape": 1): D = 256 (one D tile
-# per wave), 512 (two), 768 (three) and 1024 (four), in BF16 and E4M3.
-WIDE_SHAPES = [(777, 32, 100, 256), (4096, 16, 256, 512), (333, 32, 512, 768), (1000, 32, 1000, 1024)]
+# per wave), 512 (two), 768 (three) and 1024 (four, at d = 32 and d = 16, the latter with
+# 300 atoms: padded atom tiles and an odd count of 64-atom E4M3 chunks), in BF16 and E4M3.
+WIDE_SHAPES = [(777, 32, 100, 256), (4096, 16, 256, 512), (333, 32, 512, 768), (1000, 32, 1000, 1024),
+               (2048, 16, 300, 1024)]
 
 
 @pytest.mark.parametrize("prec", ["bf16", "fp8"])
