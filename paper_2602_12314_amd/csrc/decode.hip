@@ -616,9 +616,6 @@ __global__ __launch_bounds__(NW * kWave) void k_dec_rows(RowsArgs a)
             }
         }
     } else {
-        // ring of PD chunks: chunk c + PD - 1 is loaded while chunk c is multiplied.
-        // The loads are unconditional (the last PD chunks are peeled) so that
-        // each MFMA waits only for its own fragments.
         if constexpr (NW == 8 && NT * NPG >= 8) {
             // the 64-pixel block with four D tiles a wave, whose uniform ring
             // could only be two deep: V^T chunks four deep instead, and the
@@ -650,6 +647,9 @@ __global__ __launch_bounds__(NW * kWave) void k_dec_rows(RowsArgs a)
                 }
             }
         } else {
+            // ring of PD chunks: chunk c + PD - 1 is loaded while chunk c is
+            // multiplied.  The loads are unconditional (the last PD chunks are
+            // peeled) so that each MFMA waits only for its own fragments.
             constexpr int PD = pipe_depth<kDeepRing<F8, NT, NPG, NW>>();
             Frag ring[PD][NT], bring[PD][NPG];
             auto fetch = [&](int c, Frag* r, Frag* b) {
