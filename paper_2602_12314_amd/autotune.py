@@ -138,10 +138,28 @@ def _name(opt: dict) -> str:
     return f"{opt['decode_shape']}/splits={opt['decode_splits']}"
 
 
+# A split count other than the library's own rule (0) is taken only when it is
+# clearly faster.  Timed alone, the split counts of the dV GEMM differ by about
+# the run-to-run noise (1-2 %), while in the training step the dV grid also sets
+# how the dictionary gradients share the GPU with the compositing backward on
+# the second stream, which this timing does not see.
+SPLIT_TOL = 0.02
+
+
+def pick_decode_options(cands, times: dict, tol: float = SPLIT_TOL) -> dict:
+    """The fastest candidate, except that the fastest one with the library's
+    split rule (decode_splits 0) wins when it is within ``tol`` of it."""
+    t = lambda o: times[_name(o)]
+    best = min(cands, key=t)
+    rule = [o for o in cands if o["decode_splits"] == 0 and t(o) <= t(best) * (1.0 + tol)]
+    return dict(min(rule, key=t)) if rule else dict(best)
+
+
 def best_decode_options(precision: str, n: int, d: int, M: int, D: int, use_cache: bool = True,
                         reps: int = 5, candidates=None) -> Tuple[dict, dict]:
-    """Fastest decode options for these sizes: ({"decode_shape", "decode_splits"},
-    {candidate name: ms}).  Pass the options to ``Context(options=...)``."""
+    """Fastest decode options for these sizes (see pick_decode_options):
+    ({"decode_shape", "decode_splits"}, {candidate name: ms}).  Pass the
+    options to ``Context(options=...)``."""
     key = f"{_arch()}|decode|{precision}|n={n}|d={d}|M={M}|D={D}"
     db = _load() if use_cache else {}
     if use_cache and key in db and "options" in db[key]:
@@ -151,7 +169,7 @@ def best_decode_options(precision: str, n: int, d: int, M: int, D: int, use_cach
     times = {}
     for opt in cands:
         times[_name(opt)] = time_decode_options(precision, n, d, M, D, opt, reps=reps, inputs=inputs)
-    best = min(cands, key=lambda o: times[_name(o)])
+    best = pick_decode_options(cands, times)
     if use_cache:
         db[key] = {"options": dict(best), "ms": times}
         _store(db)
